@@ -1,0 +1,164 @@
+"""CPU FP64 oracle for the L1 time-stepping scheme (test infrastructure).
+
+TEST INFRASTRUCTURE ONLY: the test suite, the smoke check and the CPU-baseline
+leg of the benchmark may import this package; the product library never does.
+It shares no code with the HIP path.
+
+The arithmetic lives in ``oracle.c`` (plain C, FP64, O(M N^2) forward time
+stepping -- the paper's "direct method" for the block lower-triangular Toeplitz
+system of Scheme 4, section 3); this module only marshals numpy arrays.
+
+Parity status of each function (what pins it, in tests/test_oracle_*.py):
+  weights   -- decimal references, invariants, row sums, digamma vs scipy
+  solve     -- closed forms, single-mode reduction, dense LU brute force,
+               Table 9 and Table 7 of the paper, convergence rates
+  apply     -- dense brute force
+  adjoint   -- dot test, central differences in f and in gamma
+  mode      -- closed form on linear-in-time data, dense brute force
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+_dp = ctypes.POINTER(ctypes.c_double)
+_lib = None
+
+
+def build(force: bool = False) -> str:
+    """Compile liboracle.so with gcc (OpenMP, -O2, no fast-math)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    build()
+    lib = ctypes.CDLL(_LIB)
+    i64, d, i32 = ctypes.c_int64, ctypes.c_double, ctypes.c_int
+    lib.oracle_digamma.restype = d
+    lib.oracle_digamma.argtypes = [d]
+    lib.oracle_threads.restype = i32
+    lib.oracle_weights.restype = i32
+    lib.oracle_weights.argtypes = [d, d, i64] + [_dp] * 8
+    lib.oracle_solve.restype = i32
+    lib.oracle_solve.argtypes = [d, d, d, d, i64, i64, i64, _dp, _dp, _dp, _dp, i32]
+    lib.oracle_apply.restype = i32
+    lib.oracle_apply.argtypes = [d, d, d, d, i64, i64, _dp, _dp, i32]
+    lib.oracle_adjoint.restype = i32
+    lib.oracle_adjoint.argtypes = [d, d, d, d, i64, i64, _dp, _dp, _dp, _dp, _dp, _dp, i32]
+    lib.oracle_mode.restype = i32
+    lib.oracle_mode.argtypes = [d, d, i64, d, _dp, d, d, _dp]
+    _lib = lib
+    return lib
+
+
+def _ptr(x):
+    if x is None:
+        return None
+    return x.ctypes.data_as(_dp)
+
+
+def _f64(x, shape=None):
+    if x is None:
+        return None
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    if shape is not None and x.shape != shape:
+        x = x.reshape(shape)
+    return x
+
+
+def _check(rc, what):
+    if rc != 0:
+        raise ValueError("oracle %s failed with status %d" % (what, rc))
+
+
+def threads() -> int:
+    return int(_load().oracle_threads())
+
+
+def digamma(x: float) -> float:
+    return float(_load().oracle_digamma(float(x)))
+
+
+def weights(gamma: float, T: float, N: int) -> dict:
+    """b_k, a_m, rho_n, psi_n and their gamma-derivatives (length N each)."""
+    lib = _load()
+    out = {k: np.zeros(N) for k in ("b", "a", "rho", "psi", "da", "drho", "dpsi")}
+    scal = np.zeros(2)
+    rc = lib.oracle_weights(gamma, T, N, *(_ptr(out[k]) for k in ("b", "a", "rho", "psi", "da", "drho", "dpsi")),
+                            _ptr(scal))
+    _check(rc, "weights")
+    out["coef"], out["dcoef"] = float(scal[0]), float(scal[1])
+    return out
+
+
+def solve(gamma, T, x0, x1, M, N, f, u0=None, phi=None, nsteps=None, nthreads=0):
+    """Forward time stepping; returns U [N][M] (rows >= nsteps are zero)."""
+    lib = _load()
+    f = _f64(f, (N, M))
+    u0 = _f64(u0, (M,))
+    phi = _f64(phi, (M,))
+    u = np.zeros((N, M))
+    rc = lib.oracle_solve(gamma, T, x0, x1, M, N, N if nsteps is None else nsteps,
+                          _ptr(f), _ptr(u0), _ptr(phi), _ptr(u), nthreads)
+    _check(rc, "solve")
+    return u
+
+
+def apply(gamma, T, x0, x1, M, N, u, nthreads=0):
+    """y = A u for the block lower-triangular system (without the u0/phi terms)."""
+    lib = _load()
+    u = _f64(u, (N, M))
+    y = np.zeros((N, M))
+    _check(lib.oracle_apply(gamma, T, x0, x1, M, N, _ptr(u), _ptr(y), nthreads), "apply")
+    return y
+
+
+def adjoint(gamma, T, x0, x1, M, N, g, u, u0=None, phi=None, nthreads=0):
+    """Returns (Lambda = dL/dF [N][M], dL/dgamma) for upstream gradient g = dL/dU."""
+    lib = _load()
+    g = _f64(g, (N, M))
+    u = _f64(u, (N, M))
+    u0 = _f64(u0, (M,))
+    phi = _f64(phi, (M,))
+    lam = np.zeros((N, M))
+    dg = ctypes.c_double(0.0)
+    rc = lib.oracle_adjoint(gamma, T, x0, x1, M, N, _ptr(g), _ptr(u), _ptr(u0), _ptr(phi),
+                            _ptr(lam), ctypes.byref(dg), nthreads)
+    _check(rc, "adjoint")
+    return lam, float(dg.value)
+
+
+def mode(gamma, T, N, lam, g, v0=0.0, phihat=0.0):
+    """Scalar recurrence of one sine mode with eigenvalue lam (length-N result)."""
+    lib = _load()
+    g = _f64(g, (N,))
+    v = np.zeros(N)
+    _check(lib.oracle_mode(gamma, T, N, lam, _ptr(g), v0, phihat, _ptr(v)), "mode")
+    return v
+
+
+def grid(x0, x1, M, T, N):
+    """x_i (i=1..M) and t_n (n=1..N) of the uniform grid used by every routine."""
+    h = (x1 - x0) / (M + 1)
+    tau = T / N
+    return x0 + h * np.arange(1, M + 1), tau * np.arange(1, N + 1), h, tau
+
+
+def eig_K(M, j, x0=0.0, x1=1.0):
+    """Eigenvalue of K = h^-2 tridiag(-1,2,-1) for the sine mode sin(j pi (x-x0)/(x1-x0))."""
+    h = (x1 - x0) / (M + 1)
+    return 4.0 / (h * h) * np.sin(j * np.pi * h / (2.0 * (x1 - x0))) ** 2

@@ -1,0 +1,392 @@
+/*
+ * oracle.c -- plain CPU FP64 reference for the L1 time-stepping scheme.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+ * CPU-baseline leg of the benchmark may load this library.  The product path
+ * (the HIP library) shares no code with it and never calls it.
+ *
+ * What it computes (Liu, Cheng, Li, Wang, "Fast procedures for Caputo
+ * fractional ordinary and partial differential equations"):
+ *
+ *   Time-fractional diffusion, 0<gamma<1 (Scheme 4, eq. e19/e20):
+ *     mu = tau^-gamma / Gamma(2-gamma),  b_k = G_k = (k+1)^(1-gamma) - k^(1-gamma)
+ *     a_0 = mu,  a_m = mu (b_m - b_{m-1}),  rho_n = -mu b_{n-1},  psi_n = 0,
+ *     F^n = f(x_i, t_n).
+ *     The u^0 term of e19 is read as the telescoping L1 term -mu b_{n-1} u^0
+ *     (the printed "+G_n u^0" would make the Caputo derivative of a constant
+ *     non-zero).
+ *
+ *   Diffusion-wave, 1<gamma<2 (time part of Scheme 3, eq. e15-e17, and the
+ *   Toeplitz matrix of the "new procedure" for Scheme 3):
+ *     c = tau^-gamma / Gamma(3-gamma),  b_k = M_k = (k+1)^(2-gamma) - k^(2-gamma),
+ *     b_{-1} = b_{-2} = 0,
+ *     a_m = c (b_{m-2} - 2 b_{m-1} + b_m),  rho_n = c (b_{n-2} - b_{n-1}),
+ *     psi_n = c tau b_{n-1},  F^n = f(x_i, t_{n-1/2});
+ *     the spatial term is taken at t_n, as in e16/e17.
+ *
+ *   Both regimes give, for n = 1..N, with K = h^-2 tridiag(-1,2,-1):
+ *     (a_0 I + K) U^n + sum_{j=1}^{n-1} a_{n-j} U^j = F^n - rho_n u^0 + psi_n phi
+ *   and this file solves it by plain forward time stepping (the paper's
+ *   "direct method" of section 3, O(M N^2) work), one Thomas solve per step.
+ *
+ * Layout: time-major [N][M] row-major, entry (n-1)*M + (i-1) is (x_i, t_n),
+ * h = (x1-x0)/(M+1), x_i = x0 + i h, tau = T/N.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORACLE_OK 0
+#define ORACLE_EARG (-1)
+#define ORACLE_ENOMEM (-2)
+
+/* Digamma from the asymptotic (Stirling-type) series, Abramowitz & Stegun
+ * 6.3.18, after shifting the argument above 10 with psi(x) = psi(x+1) - 1/x
+ * (A&S 6.3.5).  Used for d(mu)/d(gamma) = mu (-ln tau + psi(2-gamma)). */
+double oracle_digamma(double x)
+{
+    double acc = 0.0;
+    while (x < 10.0) {
+        acc -= 1.0 / x;
+        x += 1.0;
+    }
+    double r = 1.0 / x, r2 = r * r;
+    /* Bernoulli-number terms B_2k / (2k x^2k), k = 1..7 */
+    double series = r2 * (1.0 / 12.0
+                  - r2 * (1.0 / 120.0
+                  - r2 * (1.0 / 252.0
+                  - r2 * (1.0 / 240.0
+                  - r2 * (1.0 / 132.0
+                  - r2 * (691.0 / 32760.0
+                  - r2 * (1.0 / 12.0)))))));
+    return acc + log(x) - 0.5 * r - series;
+}
+
+static int regime_of(double gamma)
+{
+    if (gamma > 0.0 && gamma < 1.0) return 0;   /* diffusion */
+    if (gamma > 1.0 && gamma < 2.0) return 1;   /* diffusion-wave */
+    return -1;
+}
+
+/* b_k = (k+1)^p - k^p evaluated without cancellation:
+ * (k+1)^p - k^p = k^p ((1+1/k)^p - 1) = k^p expm1(p log1p(1/k)). */
+static double bk(int64_t k, double p)
+{
+    if (k < 0) return 0.0;
+    if (k == 0) return 1.0;
+    double kd = (double)k;
+    return pow(kd, p) * expm1(p * log1p(1.0 / kd));
+}
+
+/* d b_k / d p = ln(k+1)(k+1)^p - ln(k) k^p = ln(k) b_k + log1p(1/k) (k+1)^p,
+ * a sum of two non-negative terms. */
+static double dbk_dp(int64_t k, double p)
+{
+    if (k <= 0) return 0.0;
+    double kd = (double)k;
+    return log(kd) * bk(k, p) + log1p(1.0 / kd) * pow(kd + 1.0, p);
+}
+
+/*
+ * Weights of the discrete system for gamma in (0,1) or (1,2).
+ * Arrays have length N; index m holds a_m (m = 0..N-1), index n-1 holds
+ * rho_n and psi_n (n = 1..N), index k holds b_k.  Derivative arrays (d/dgamma)
+ * may be NULL.  scal[0] = mu or c, scal[1] = its gamma derivative.
+ */
+int oracle_weights(double gamma, double T, int64_t N,
+                   double *b, double *a, double *rho, double *psi,
+                   double *da, double *drho, double *dpsi, double *scal)
+{
+    int reg = regime_of(gamma);
+    if (reg < 0 || !(T > 0.0) || N < 1) return ORACLE_EARG;
+    double tau = T / (double)N;
+    double p = (reg == 0) ? 1.0 - gamma : 2.0 - gamma;
+    double g = (reg == 0) ? 2.0 - gamma : 3.0 - gamma;     /* Gamma argument */
+    double coef = pow(tau, -gamma) / tgamma(g);
+    double dcoef = coef * (-log(tau) + oracle_digamma(g));
+    if (scal) { scal[0] = coef; scal[1] = dcoef; }
+
+    /* b_k for k = -2..N (shifted by 2) and d b_k / d gamma = -d b_k / d p */
+    double *B = (double *)malloc(sizeof(double) * (size_t)(N + 3));
+    double *dB = (double *)malloc(sizeof(double) * (size_t)(N + 3));
+    if (!B || !dB) { free(B); free(dB); return ORACLE_ENOMEM; }
+    for (int64_t k = -2; k <= N; ++k) {
+        B[k + 2] = bk(k, p);
+        dB[k + 2] = -dbk_dp(k, p);
+    }
+#define BB(k) B[(k) + 2]
+#define DB(k) dB[(k) + 2]
+    for (int64_t k = 0; k < N; ++k)
+        if (b) b[k] = BB(k);
+    for (int64_t m = 0; m < N; ++m) {
+        double am, dam;
+        if (reg == 0) {
+            /* a_0 = mu G_0, a_m = mu (G_m - G_{m-1}) */
+            double d1 = BB(m) - BB(m - 1), dd1 = DB(m) - DB(m - 1);
+            am = coef * d1;
+            dam = dcoef * d1 + coef * dd1;
+        } else {
+            double d2 = BB(m - 2) - 2.0 * BB(m - 1) + BB(m);
+            double dd2 = DB(m - 2) - 2.0 * DB(m - 1) + DB(m);
+            am = coef * d2;
+            dam = dcoef * d2 + coef * dd2;
+        }
+        if (a) a[m] = am;
+        if (da) da[m] = dam;
+    }
+    for (int64_t n = 1; n <= N; ++n) {
+        double r, dr, s, ds;
+        if (reg == 0) {
+            r = -coef * BB(n - 1);
+            dr = -dcoef * BB(n - 1) - coef * DB(n - 1);
+            s = 0.0;
+            ds = 0.0;
+        } else {
+            r = coef * (BB(n - 2) - BB(n - 1));
+            dr = dcoef * (BB(n - 2) - BB(n - 1)) + coef * (DB(n - 2) - DB(n - 1));
+            s = coef * tau * BB(n - 1);
+            ds = tau * (dcoef * BB(n - 1) + coef * DB(n - 1));
+        }
+        if (rho) rho[n - 1] = r;
+        if (drho) drho[n - 1] = dr;
+        if (psi) psi[n - 1] = s;
+        if (dpsi) dpsi[n - 1] = ds;
+    }
+#undef BB
+#undef DB
+    free(B);
+    free(dB);
+    return ORACLE_OK;
+}
+
+/* Factor the constant tridiagonal block A0 = a0 I + K once (Thomas, no
+ * pivoting; A0 is symmetric and strictly diagonally dominant because a0 > 0).
+ * cp[i] = modified super-diagonal, inv[i] = 1/pivot. */
+static void thomas_factor(int64_t M, double diag, double off, double *cp, double *inv)
+{
+    double prev = 0.0;
+    for (int64_t i = 0; i < M; ++i) {
+        double piv = diag - off * prev;
+        inv[i] = 1.0 / piv;
+        cp[i] = off * inv[i];
+        prev = cp[i];
+    }
+}
+
+/* Solve A0 x = r in place (r overwritten by x). */
+static void thomas_solve(int64_t M, double off, const double *cp, const double *inv, double *r)
+{
+    for (int64_t i = 0; i < M; ++i) {
+        double prev = (i > 0) ? r[i - 1] : 0.0;
+        r[i] = (r[i] - off * prev) * inv[i];
+    }
+    for (int64_t i = M - 2; i >= 0; --i)
+        r[i] -= cp[i] * r[i + 1];
+}
+
+static void set_threads(int nthreads)
+{
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+    (void)nthreads;
+#endif
+}
+
+int oracle_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+/*
+ * Forward time stepping for n = 1..nsteps (nsteps <= N; the grid and the
+ * weights are those of the full N-step problem).
+ *   f   [N][M]  source sampled at t_n (gamma<1) or t_{n-1/2} (gamma>1)
+ *   u0  [M]     initial value (NULL = 0)
+ *   phi [M]     initial velocity, used for gamma>1 only (NULL = 0)
+ *   u   [N][M]  output; rows >= nsteps are left untouched
+ */
+int oracle_solve(double gamma, double T, double x0, double x1, int64_t M, int64_t N,
+                 int64_t nsteps, const double *f, const double *u0, const double *phi,
+                 double *u, int nthreads)
+{
+    if (regime_of(gamma) < 0 || !(T > 0.0) || !(x1 > x0) || M < 1 || N < 1 || !f || !u)
+        return ORACLE_EARG;
+    if (nsteps < 0 || nsteps > N) return ORACLE_EARG;
+    set_threads(nthreads);
+    double h = (x1 - x0) / (double)(M + 1);
+    double e = 1.0 / (h * h);
+    double *a = (double *)malloc(sizeof(double) * (size_t)N);
+    double *rho = (double *)malloc(sizeof(double) * (size_t)N);
+    double *psi = (double *)malloc(sizeof(double) * (size_t)N);
+    double *cp = (double *)malloc(sizeof(double) * (size_t)M);
+    double *inv = (double *)malloc(sizeof(double) * (size_t)M);
+    if (!a || !rho || !psi || !cp || !inv) {
+        free(a); free(rho); free(psi); free(cp); free(inv);
+        return ORACLE_ENOMEM;
+    }
+    oracle_weights(gamma, T, N, NULL, a, rho, psi, NULL, NULL, NULL, NULL);
+    thomas_factor(M, a[0] + 2.0 * e, -e, cp, inv);
+
+    for (int64_t n = 1; n <= nsteps; ++n) {
+        double *r = u + (size_t)(n - 1) * (size_t)M;
+        const double *fn = f + (size_t)(n - 1) * (size_t)M;
+        /* right-hand side: F^n - rho_n u^0 + psi_n phi - sum_j a_{n-j} U^j */
+        /* blocks of 256 points; each block runs over all earlier rows j in
+         * order, so rows are read contiguously */
+        #pragma omp parallel for schedule(static)
+        for (int64_t i0 = 0; i0 < M; i0 += 256) {
+            int64_t i1 = (i0 + 256 < M) ? i0 + 256 : M;
+            for (int64_t i = i0; i < i1; ++i) {
+                double s = fn[i];
+                if (u0) s -= rho[n - 1] * u0[i];
+                if (phi) s += psi[n - 1] * phi[i];
+                r[i] = s;
+            }
+            for (int64_t j = 1; j < n; ++j) {
+                const double *uj = u + (size_t)(j - 1) * (size_t)M;
+                double w = a[n - j];
+                for (int64_t i = i0; i < i1; ++i) r[i] -= w * uj[i];
+            }
+        }
+        thomas_solve(M, -e, cp, inv, r);
+    }
+    free(a); free(rho); free(psi); free(cp); free(inv);
+    return ORACLE_OK;
+}
+
+/*
+ * Operator apply y = A u of the whole block lower-triangular system:
+ *   y^n = (a_0 I + K) U^n + sum_{j=1}^{n-1} a_{n-j} U^j.
+ */
+int oracle_apply(double gamma, double T, double x0, double x1, int64_t M, int64_t N,
+                 const double *u, double *y, int nthreads)
+{
+    if (regime_of(gamma) < 0 || !(T > 0.0) || !(x1 > x0) || M < 1 || N < 1 || !u || !y)
+        return ORACLE_EARG;
+    set_threads(nthreads);
+    double h = (x1 - x0) / (double)(M + 1);
+    double e = 1.0 / (h * h);
+    double *a = (double *)malloc(sizeof(double) * (size_t)N);
+    if (!a) return ORACLE_ENOMEM;
+    oracle_weights(gamma, T, N, NULL, a, NULL, NULL, NULL, NULL, NULL, NULL);
+    for (int64_t n = 1; n <= N; ++n) {
+        const double *un = u + (size_t)(n - 1) * (size_t)M;
+        double *yn = y + (size_t)(n - 1) * (size_t)M;
+        #pragma omp parallel for schedule(static)
+        for (int64_t i = 0; i < M; ++i) {
+            double left = (i > 0) ? un[i - 1] : 0.0;
+            double right = (i + 1 < M) ? un[i + 1] : 0.0;
+            double s = (a[0] + 2.0 * e) * un[i] - e * (left + right);
+            for (int64_t j = 1; j < n; ++j)
+                s += a[n - j] * u[(size_t)(j - 1) * (size_t)M + (size_t)i];
+            yn[i] = s;
+        }
+    }
+    free(a);
+    return ORACLE_OK;
+}
+
+/*
+ * Adjoint of the solve.  Given G = dL/dU [N][M] and the forward solution
+ * U [N][M], computes Lambda = A^{-T} G (= dL/dF, since F enters the
+ * right-hand side with identity) by backward time stepping
+ *   (a_0 I + K) Lambda^n = G^n - sum_{j=n+1}^{N} a_{j-n} Lambda^j,  n = N..1,
+ * and dL/dgamma = sum_n <Lambda^n, -rho'_n u^0 + psi'_n phi>
+ *               - sum_n sum_{j<=n} a'_{n-j} <Lambda^n, U^j>,
+ * with f, u^0 and phi held fixed.
+ */
+int oracle_adjoint(double gamma, double T, double x0, double x1, int64_t M, int64_t N,
+                   const double *g, const double *u, const double *u0, const double *phi,
+                   double *lam, double *dLdgamma, int nthreads)
+{
+    if (regime_of(gamma) < 0 || !(T > 0.0) || !(x1 > x0) || M < 1 || N < 1 || !g || !u || !lam)
+        return ORACLE_EARG;
+    set_threads(nthreads);
+    double h = (x1 - x0) / (double)(M + 1);
+    double e = 1.0 / (h * h);
+    size_t NN = (size_t)N;
+    double *a = (double *)malloc(sizeof(double) * NN);
+    double *da = (double *)malloc(sizeof(double) * NN);
+    double *drho = (double *)malloc(sizeof(double) * NN);
+    double *dpsi = (double *)malloc(sizeof(double) * NN);
+    double *cp = (double *)malloc(sizeof(double) * (size_t)M);
+    double *inv = (double *)malloc(sizeof(double) * (size_t)M);
+    if (!a || !da || !drho || !dpsi || !cp || !inv) {
+        free(a); free(da); free(drho); free(dpsi); free(cp); free(inv);
+        return ORACLE_ENOMEM;
+    }
+    oracle_weights(gamma, T, N, NULL, a, NULL, NULL, da, drho, dpsi, NULL);
+    thomas_factor(M, a[0] + 2.0 * e, -e, cp, inv);
+
+    for (int64_t n = N; n >= 1; --n) {
+        double *r = lam + (size_t)(n - 1) * (size_t)M;
+        const double *gn = g + (size_t)(n - 1) * (size_t)M;
+        #pragma omp parallel for schedule(static)
+        for (int64_t i0 = 0; i0 < M; i0 += 256) {
+            int64_t i1 = (i0 + 256 < M) ? i0 + 256 : M;
+            for (int64_t i = i0; i < i1; ++i) r[i] = gn[i];
+            for (int64_t j = n + 1; j <= N; ++j) {
+                const double *lj = lam + (size_t)(j - 1) * (size_t)M;
+                double w = a[j - n];
+                for (int64_t i = i0; i < i1; ++i) r[i] -= w * lj[i];
+            }
+        }
+        thomas_solve(M, -e, cp, inv, r);
+    }
+
+    if (dLdgamma) {
+        double total = 0.0;
+        for (int64_t n = 1; n <= N; ++n) {
+            const double *ln = lam + (size_t)(n - 1) * (size_t)M;
+            double acc = 0.0;
+            #pragma omp parallel for schedule(static) reduction(+:acc)
+            for (int64_t i = 0; i < M; ++i) {
+                double s = 0.0;
+                if (u0) s -= drho[n - 1] * u0[i];
+                if (phi) s += dpsi[n - 1] * phi[i];
+                for (int64_t j = 1; j <= n; ++j)
+                    s -= da[n - j] * u[(size_t)(j - 1) * (size_t)M + (size_t)i];
+                acc += ln[i] * s;
+            }
+            total += acc;
+        }
+        *dLdgamma = total;
+    }
+    free(a); free(da); free(drho); free(dpsi); free(cp); free(inv);
+    return ORACLE_OK;
+}
+
+/*
+ * Scalar recurrence of one spatial sine mode.  If the source is g(t) s_j and
+ * the initial data are v0 s_j, phihat s_j, with s_j(i) = sin(j pi x_i) an exact
+ * eigenvector of K with eigenvalue lam, the discrete solution is v^n s_j with
+ *   (a_0 + lam) v^n = g^n - rho_n v0 + psi_n phihat - sum_{j<n} a_{n-j} v^j.
+ */
+int oracle_mode(double gamma, double T, int64_t N, double lam, const double *g,
+                double v0, double phihat, double *v)
+{
+    if (regime_of(gamma) < 0 || !(T > 0.0) || N < 1 || !g || !v) return ORACLE_EARG;
+    double *a = (double *)malloc(sizeof(double) * (size_t)N);
+    double *rho = (double *)malloc(sizeof(double) * (size_t)N);
+    double *psi = (double *)malloc(sizeof(double) * (size_t)N);
+    if (!a || !rho || !psi) { free(a); free(rho); free(psi); return ORACLE_ENOMEM; }
+    oracle_weights(gamma, T, N, NULL, a, rho, psi, NULL, NULL, NULL, NULL);
+    double d = a[0] + lam;
+    for (int64_t n = 1; n <= N; ++n) {
+        double s = g[n - 1] - rho[n - 1] * v0 + psi[n - 1] * phihat;
+        for (int64_t j = 1; j < n; ++j) s -= a[n - j] * v[j - 1];
+        v[n - 1] = s / d;
+    }
+    free(a); free(rho); free(psi);
+    return ORACLE_OK;
+}
