@@ -1,0 +1,247 @@
+#!/usr/bin/env python3
+"""Throughput of the fracsolve hot path on one MI355X.
+
+A step is one full solve (right-hand-side assembly, every leaf and every
+level product) of one synthetic instance already resident in HBM.  Default
+workload: time-fractional diffusion, gamma = 0.3, M = 4096 interior points,
+N = 65536 time steps, manufactured t^2 sin(pi x) source plus 8 seeded random
+modes a_j t^p_j sin(j pi x), float64.  The printed value is M*N unknowns per
+second over the timed steps.  The error is checked against the oracle
+through single-mode reduction (every source mode's discrete solution is
+v_j^n sin(j pi x_i), with v_j from the oracle's scalar recurrence).
+
+roofline: the single-pass FFT level kernel with the largest total time,
+timed live with HIP events around each launch on the solver's stream during
+one extra solve; achieved = its algorithmic bytes (24 B per X-row entry:
+read X, read and write Y) / its time, against the 8 TB/s HBM peak.
+cpu_baseline: the oracle (plain time stepping) on the same workload for the
+first --cpu-steps steps at full width; its wall time is scaled by
+(N / steps)^2 (the history work is quadratic in the step count) to the full
+run and reported as unknowns per second.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "M·N unknowns solved/sec at stated err vs FP64 oracle; mixed/batched vs plain FP64"
+HBM_PEAK_GBS = 8000.0
+
+# single-pass FFT kernel instantiations (k_fft.hip): n -> template text
+FFT64_NAMES = {
+    8: "k_fft2<double, 4, 2, 8, 0>", 16: "k_fft2<double, 4, 4, 8, 0>", 32: "k_fft2<double, 8, 4, 8, 0>",
+    64: "k_fft2<double, 8, 8, 8, 0>", 128: "k_fft2<double, 16, 8, 8, 0>", 256: "k_fft2<double, 16, 16, 8, 0>",
+    512: "k_fft2<double, 32, 16, 8, 0>", 1024: "k_fft2<double, 32, 32, 8, 0>",
+    2048: "k_fft3<double, 16, 16, 8, 4, 0>", 4096: "k_fft3<double, 16, 16, 16, 2, 0>",
+    8192: "k_fft3<double, 32, 16, 16, 1, 0>",
+}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def build_instance(args):
+    from paper_1710_11593_amd import workloads as wl
+
+    if args.config == "c2":
+        inst = wl.c2(gamma=args.gamma if args.gamma else 0.3, seed=2, M=args.M or 4096, N=args.N or 65536,
+                     build=False)
+        desc = "diffusion gamma=%g, M=%d, N=%d, manufactured t^2 sin(pi x) + 8 seeded modes" % (
+            inst.gamma, inst.M, inst.N)
+    elif args.config == "c3":
+        inst = wl.c3(M=args.M or 2048, N=args.N or 131072, build=False)
+        desc = "diffusion-wave gamma=1.5, M=%d, N=%d, u=(t^2+1) sin(pi x)" % (inst.M, inst.N)
+    elif args.config == "c1":
+        inst = wl.c1()
+        inst.f = None
+        desc = "diffusion gamma=0.5, M=64, N=256, u=t^2 sin(pi x)"
+    else:
+        raise SystemExit("unknown --config %s" % args.config)
+    return inst, desc
+
+
+def modal_factors(inst):
+    """(js, G [N][k], u0 coefficient per mode, phi coefficient per mode)."""
+    import numpy as np
+
+    from paper_1710_11593_amd import workloads as wl
+
+    series = wl.modal_time_series(inst)
+    js = sorted(series)
+    G = np.stack([series[j][0] for j in js], axis=1)
+    return js, G, [series[j][1] for j in js], [series[j][2] for j in js]
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", default="c2")
+    ap.add_argument("--gamma", type=float, default=0.0)
+    ap.add_argument("--M", type=int, default=0)
+    ap.add_argument("--N", type=int, default=0)
+    ap.add_argument("--precision", default="fp64")
+    ap.add_argument("--refine", type=int, default=1)
+    ap.add_argument("--leaf", type=int, default=0)
+    ap.add_argument("--crossover", type=int, default=0)
+    ap.add_argument("--cpu-steps", type=int, default=4096)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-check", action="store_true")
+    ap.add_argument("--out", default="")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path (instances would shard "
+              "across GPUs without communication; a single instance does not).  Use --gpus 1.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import oracle
+    from paper_1710_11593_amd import binding, workloads as wl
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    inst, desc = build_instance(args)
+    M, N, gamma = inst.M, inst.N, inst.gamma
+    log("bench: %s, precision %s" % (desc, args.precision))
+
+    # inputs: f = G S with G [N][k] the per-mode time series and S [k][M] the sines
+    js, G, c_u0, c_phi = modal_factors(inst)
+    x, _, h, tau = wl.grid(M, N)
+    S = np.stack([np.sin(j * math.pi * x) for j in js])
+    Gd = torch.from_numpy(G).to(dev)
+    Sd = torch.from_numpy(S).to(dev)
+    f = (Gd @ Sd).contiguous()
+    u0 = torch.from_numpy(np.asarray(c_u0) @ S).to(dev)
+    phi = torch.from_numpy(np.asarray(c_phi) @ S).to(dev)
+    u = torch.empty_like(f)
+    torch.cuda.synchronize()
+
+    prec = args.precision
+    solver = binding.Solver([dict(gamma=gamma, M=M, N=N)], precision=prec,
+                            refine_steps=(args.refine if prec != "fp64" else 0), leaf=args.leaf,
+                            crossover=args.crossover)
+    wave = gamma > 1.0
+
+    def step():
+        solver.solve([f], [u0], [phi] if wave else None, out=[u])
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms = (t1 - t0) * 1e3 / args.steps
+    value = M * N / (ms / 1e3)
+    log("bench: %.3f ms per solve, %.4g unknowns/s" % (ms, value))
+
+    # accuracy vs the oracle through single-mode reduction
+    err = None
+    if not args.no_check:
+        from concurrent.futures import ThreadPoolExecutor
+
+        lam = [4.0 / h ** 2 * math.sin(j * math.pi * h / 2) ** 2 for j in js]
+        with ThreadPoolExecutor(max_workers=len(js)) as ex:
+            vs = list(ex.map(lambda k: oracle.mode(gamma, inst.T, N, lam[k], G[:, k], c_u0[k], c_phi[k]),
+                             range(len(js))))
+        V = torch.from_numpy(np.stack(vs, axis=1)).to(dev)
+        ref = V @ Sd
+        err = float((u - ref).abs().max() / ref.abs().max())
+        del ref, V
+        log("bench: max-norm relative error vs oracle (mode reduction): %.3e" % err)
+
+    # per-kernel timing during one more solve
+    solver.set_timing_level(2)
+    step()
+    torch.cuda.synchronize()
+    ks = solver.kernel_stats()
+    solver.set_timing_level(0)
+    st = solver.stats()
+    groups = sorted(ks, key=lambda r: -r["ms"])
+    for g in groups[:12]:
+        log("  %-10s s=%-6d launches=%-6d %9.3f ms  %8.1f GB/s" % (
+            g["kind"], g["s"], g["launches"], g["ms"], g["bytes"] / (g["ms"] * 1e-3) / 1e9 if g["ms"] else 0))
+    fft_kind = "fft_f64" if prec == "fp64" else "fft_f32"
+    single = [g for g in ks if g["kind"] == fft_kind and 2 * g["s"] <= (8192 if prec == "fp64" else 16384)]
+    roof = None
+    if single:
+        dom = max(single, key=lambda r: r["ms"])
+        per_launch_ms = dom["ms"] / dom["launches"]
+        per_launch_bytes = dom["bytes"] / dom["launches"]
+        achieved = per_launch_bytes / (per_launch_ms * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": FFT64_NAMES.get(2 * dom["s"], "fft level s=%d" % dom["s"]) if prec == "fp64"
+                else "fft_f32 s=%d" % dom["s"],
+                "level_s": dom["s"], "launches": dom["launches"], "avg_us": round(per_launch_ms * 1e3, 2),
+                "bytes_per_launch": per_launch_bytes}
+    leaf = [g for g in ks if g["kind"] == "leaf"]
+    leaf_ms = sum(g["ms"] for g in leaf)
+
+    # CPU baseline: the oracle on the first cpu_steps steps at full width
+    cpu = None
+    if not args.no_cpu_baseline:
+        n_s = min(args.cpu_steps, N)
+        fh = (G[:n_s] @ S)
+        fpad = np.zeros((N, M)) if n_s < N else fh
+        if n_s < N:
+            fpad[:n_s] = fh
+        th = oracle.threads()
+        c0 = time.perf_counter()
+        oracle.solve(gamma, inst.T, 0.0, 1.0, M, N, fpad, u0=np.asarray(c_u0) @ S,
+                     phi=(np.asarray(c_phi) @ S) if wave else None, nsteps=n_s)
+        c1 = time.perf_counter()
+        t_full = (c1 - c0) * (N / n_s) ** 2
+        cpu = {"value": M * N / t_full, "unit": "unknowns/s", "cores": th, "kind": "oracle",
+               "sample": "first %d of %d time steps at full M=%d (%.2f s wall); time scaled by (N/%d)^2 to the "
+                         "full run" % (n_s, N, M, c1 - c0, n_s)}
+        log("bench: oracle sample %.2f s on %d threads -> %.4g unknowns/s (full-run estimate)" % (
+            c1 - c0, th, cpu["value"]))
+
+    line = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "unknowns/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if prec == "fp64" else ("f32+f64" if prec == "fp32" else "bf16x3+f64"),
+        "data": "synthetic",
+        "config": {"workload": "%s: %s" % (args.config, desc), "M": M, "N": N, "gamma": gamma,
+                   "precision": prec, "leaf": st["leaf"], "crossover": st["crossover"],
+                   "refine_steps": args.refine if prec != "fp64" else 0},
+        "error_vs_oracle": err,
+        "leaf_us_per_step": round(leaf_ms * 1e3 / N, 4) if leaf else None,
+        "kernels_per_solve": st["kernels"],
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    s = json.dumps(line)
+    print(s, flush=True)
+    if args.out:
+        with open(args.out, "w") as fh_:
+            fh_.write(s + "\n")
+    solver.close()
+
+
+if __name__ == "__main__":
+    main()

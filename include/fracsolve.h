@@ -1,0 +1,208 @@
+/*
+ * fracsolve.h -- C ABI of the MI355X (gfx950) divide-and-conquer solver for
+ * the L1 time-stepping system of Caputo time-fractional equations.
+ *
+ * Problem (Liu, Cheng, Li, Wang, "Fast procedures for Caputo fractional
+ * ordinary and partial differential equations", section 3):
+ *   0<gamma<1: D_t^gamma u = u_xx + f on (x0,x1) x (0,T], u(x,0) = u0,
+ *              homogeneous Dirichlet data (eq. e18), discretised by Scheme 4
+ *              (eq. e19/e20);
+ *   1<gamma<2: the same with u_t(x,0) = phi, discretised in time by the
+ *              L1-type formula of eq. e15-e17 (source at t_{n-1/2}, spatial
+ *              term at t_n).
+ * With U^n the values at the M interior points x_i = x0 + i h,
+ * h = (x1-x0)/(M+1), tau = T/N, both regimes give the block lower-triangular
+ * Toeplitz system (time-major form of eq. e21)
+ *   (a_0 I + K) U^n + sum_{j=1}^{n-1} a_{n-j} U^j = F^n - rho_n u0 + psi_n phi,
+ *   n = 1..N,  K = h^-2 tridiag(-1, 2, -1),
+ * with a_m, rho_n, psi_n the L1 weights of section 3 (G_k for 0<gamma<1,
+ * M_k and W_j = M_{j-2} - 2 M_{j-1} + M_j for 1<gamma<2).  The library solves
+ * it exactly (up to rounding) in O(M N log^2 N) work: recursive halving in
+ * time, tridiagonal solves of the diagonal block, and Toeplitz-block
+ * products for the off-diagonal blocks done as FFT convolutions (the
+ * circulant embedding of section 3.1) or as dense products below a
+ * crossover size.
+ *
+ * Conventions for every entry point
+ *   - Arrays are float64.  Fields are time-major [N][M], row-major: element
+ *     (n-1)*M + (i-1) is the value at (x_i, t_n).  u0 and phi are [M].
+ *   - Field pointers (f, u0, phi, u, g, dL_df) are DEVICE pointers to memory
+ *     on the current HIP device (e.g. torch tensors' data_ptr()).  Weight
+ *     outputs of fracsolve_weights are HOST pointers.
+ *   - A handle holds `count` independent instances (count >= 1); field
+ *     arguments are host arrays of `count` device pointers, one per instance.
+ *   - The caller owns every buffer passed in; the library keeps no pointer
+ *     after a call returns.  The handle owns its weights, spectra, factor
+ *     tables and workspace, and frees them in fracsolve_destroy.
+ *   - Work is enqueued on the stream given at create time (NULL = the null
+ *     stream); fracsolve_solve / fracsolve_apply / fracsolve_adjoint return
+ *     after enqueueing, except where stated.  Results are valid after the
+ *     stream is synchronised.  A handle must not be used from two threads at
+ *     once.
+ *   - Errors: every function returns FRACSOLVE_OK (0) or a negative status.
+ *     Argument errors are detected before any device work.  The text of the
+ *     last error is available from fracsolve_last_error(h) (or with h = NULL
+ *     for errors of fracsolve_create).
+ */
+#ifndef FRACSOLVE_H
+#define FRACSOLVE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fracsolve_ctx *fracsolve_t;
+
+enum {
+    FRACSOLVE_OK = 0,
+    FRACSOLVE_E_ARG = -1,      /* invalid argument (nothing was enqueued)   */
+    FRACSOLVE_E_NOMEM = -2,    /* device or host allocation failed           */
+    FRACSOLVE_E_DEVICE = -3,   /* no usable device, or a HIP call failed     */
+    FRACSOLVE_E_NUMERIC = -4,  /* non-finite value found where checked       */
+    FRACSOLVE_E_STATE = -5     /* call not valid in the handle's state       */
+};
+
+/* Arithmetic of the off-diagonal Toeplitz-block products.  Weights, the
+ * tridiagonal solves of the diagonal blocks and the refinement residual are
+ * float64 in every mode. */
+enum {
+    FRACSOLVE_FP64 = 0,   /* all products in float64                          */
+    FRACSOLVE_FP32 = 1,   /* products in float32, history accumulated in f32  */
+    FRACSOLVE_BF16X3 = 2  /* dense products as three bf16 MFMA products with
+                             fp32 accumulation (hi*hi + hi*lo + lo*hi); FFT
+                             products in float32                              */
+};
+
+typedef struct {
+    double gamma;   /* fractional order, in (0,1) or (1,2); 1 is rejected      */
+    double T;       /* final time, > 0                                         */
+    double x0, x1;  /* spatial interval, x1 > x0                               */
+    int64_t M;      /* interior points, 1 <= M <= 4096                         */
+    int64_t N;      /* time steps, N >= 1 (padded internally to a power of 2;
+                       exact, because the system is causal)                   */
+} fracsolve_problem;
+
+typedef struct {
+    int32_t precision;    /* FRACSOLVE_FP64 / FP32 / BF16X3                    */
+    int32_t refine_steps; /* iterative-refinement steps against the float64
+                             operator for FP32 / BF16X3 (0 = none; FP64 ignores
+                             it)                                               */
+    int32_t leaf;         /* leaf size L (4, 8 or 16); 0 = default             */
+    int32_t crossover;    /* largest half-block size s done as a dense product;
+                             FFT above it.  0 = tuned default, < 0 = FFT at
+                             every level                                       */
+    void *stream;         /* hipStream_t for all work; NULL = null stream      */
+} fracsolve_options;
+
+/*
+ * Create a handle for `count` instances (probs[0..count-1]).  Validates every
+ * problem (gamma in (0,1) or (1,2), T > 0, x1 > x0, 1 <= M <= 4096, N >= 1),
+ * computes the weights (section 3: G_k / M_k in cancellation-free form),
+ * the FFT spectra of the Toeplitz column for every FFT level (circulant
+ * embedding, section 3.1) and the factor tables of a_0 I + K, on the device.
+ * opts may be NULL (defaults).  On success *out receives the handle.
+ * Errors: E_ARG (bad argument; the message names the instance and field),
+ * E_DEVICE (no HIP device), E_NOMEM.
+ */
+int fracsolve_create(const fracsolve_problem *probs, int32_t count,
+                     const fracsolve_options *opts, fracsolve_t *out);
+
+/*
+ * Copy instance `inst`'s weights to host arrays of length N (any may be NULL):
+ *   b[k]    = G_k or M_k,                    k = 0..N-1
+ *   a[m]    = Toeplitz column a_m,           m = 0..N-1  (a_0 = diagonal shift)
+ *   rho[n-1], psi[n-1] = u0 and phi coefficients of step n, n = 1..N
+ *   da, drho, dpsi = derivatives of a, rho, psi with respect to gamma.
+ * Synchronises the handle's stream.  Errors: E_ARG, E_DEVICE.
+ */
+int fracsolve_weights(fracsolve_t h, int32_t inst, double *b, double *a, double *rho,
+                      double *psi, double *da, double *drho, double *dpsi);
+
+/*
+ * Solve every instance: u[k] <- solution U [N][M] for source f[k] [N][M]
+ * (sampled at t_n for gamma<1, at t_{n-1/2} for gamma>1) and initial data
+ * u0[k], phi[k] ([M]; phi is ignored for gamma<1).  u0 or phi (the outer
+ * array, or any entry) may be NULL, meaning zero.  u[k] may equal f[k]
+ * (in place).  u[k] is used as workspace during the call.
+ * Errors: E_ARG (NULL f or u), E_DEVICE, E_NOMEM.
+ */
+int fracsolve_solve(fracsolve_t h, const double *const *f, const double *const *u0,
+                    const double *const *phi, double *const *u);
+
+/*
+ * Operator apply in float64: y[k] <- A u[k], the left-hand side of the block
+ * system (no u0/phi terms), i.e. y^n = (a_0 I + K) U^n + sum_{j<n} a_{n-j} U^j.
+ * Errors: E_ARG, E_DEVICE.
+ */
+int fracsolve_apply(fracsolve_t h, const double *const *u, double *const *y);
+
+/*
+ * Adjoint of fracsolve_solve for a loss L(U): given g[k] = dL/dU [N][M] and
+ * the forward solution u[k], writes dL_df[k] = A^{-T} g[k] [N][M] (the
+ * reverse-time, block upper-triangular Toeplitz solve; f enters the
+ * right-hand side with identity, so this is dL/df) and, if dL_dgamma is not
+ * NULL, dL_dgamma[k] = sum_n <dL_df^n, -rho'_n u0 + psi'_n phi>
+ *                       - sum_n sum_{j<=n} a'_{n-j} <dL_df^n, U^j>
+ * (f, u0 and phi held fixed; primes are gamma-derivatives).  dL_dgamma is a
+ * host array of `count` doubles; when it is requested the call synchronises
+ * the stream before returning.  dL_df[k] may equal g[k].
+ * Errors: E_ARG, E_DEVICE, E_NOMEM.
+ */
+int fracsolve_adjoint(fracsolve_t h, const double *const *g, const double *const *u,
+                      const double *const *u0, const double *const *phi,
+                      double *const *dL_df, double *dL_dgamma);
+
+/*
+ * Timing and plan details of the last call, for reporting.  Fields are -1
+ * when not measured.  Filled only if timing was enabled with
+ * fracsolve_set_timing(h, 1) before the call (it adds events and a
+ * synchronisation).
+ */
+typedef struct {
+    int32_t leaf;              /* leaf size used by instance 0                 */
+    int32_t crossover;         /* dense/FFT crossover s* of instance 0         */
+    int32_t levels;            /* recursion levels of instance 0               */
+    int32_t kernels;           /* kernel launches of the last call             */
+    double ms_total;           /* wall time of the last call (events)          */
+    double ms_leaf;            /* summed leaf-kernel time                      */
+    double ms_dense;           /* summed dense-update time                     */
+    double ms_fft;             /* summed FFT-update time                       */
+    double residual_norm;      /* max |r| of the last refinement residual      */
+} fracsolve_stats;
+
+/* on = 0: off; 1: total time and residual norm; 2: also per-kernel-group
+ * times (an event pair around every launch; adds overhead). */
+int fracsolve_set_timing(fracsolve_t h, int32_t on);
+int fracsolve_get_stats(fracsolve_t h, fracsolve_stats *out);
+
+/* Per-kernel-group timing of the last call (timing level 2).  One record per
+ * (kind, s): kind 0 = leaf solves (s = leaf size), 1 = dense float64 level
+ * products, 2 = dense float32, 3 = FFT float64, 4 = FFT float32 (s = level
+ * half-size).  bytes = algorithmic HBM bytes of those launches (reads of X
+ * and of the right-hand side, read+write of Y, solution writes).  Writes at
+ * most cap records to out and their number to *count. */
+typedef struct {
+    int32_t kind;
+    int32_t s;
+    int32_t launches;
+    int32_t tasks;
+    double ms;
+    double bytes;
+} fracsolve_kernel_stat;
+
+int fracsolve_kernel_stats(fracsolve_t h, fracsolve_kernel_stat *out, int32_t cap, int32_t *count);
+
+/* Release every device and host resource of the handle.  NULL-safe. */
+void fracsolve_destroy(fracsolve_t h);
+
+/* Text of the last error on h (or of the last failed create when h is NULL).
+ * The string stays valid until the next call on the same handle. */
+const char *fracsolve_last_error(fracsolve_t h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FRACSOLVE_H */

@@ -1,0 +1,277 @@
+"""Python binding of the fracsolve C ABI (include/fracsolve.h).
+
+Argument marshalling only: every step of the solve runs in the HIP library
+csrc/libfracsolve.so.  Fields are torch float64 CUDA tensors of shape [N, M]
+(time-major, row n-1 = t_n); their device pointers are handed to the library,
+which enqueues its work on torch's current stream.  If the library has not
+been built this module raises; there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Sequence
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIBPATH = os.path.join(HERE, "csrc", "libfracsolve.so")
+
+FRACSOLVE_OK = 0
+STATUS = {0: "OK", -1: "E_ARG", -2: "E_NOMEM", -3: "E_DEVICE", -4: "E_NUMERIC", -5: "E_STATE"}
+PRECISION = {"fp64": 0, "fp32": 1, "bf16x3": 2}
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [("gamma", ctypes.c_double), ("T", ctypes.c_double), ("x0", ctypes.c_double),
+                ("x1", ctypes.c_double), ("M", ctypes.c_int64), ("N", ctypes.c_int64)]
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int32), ("refine_steps", ctypes.c_int32), ("leaf", ctypes.c_int32),
+                ("crossover", ctypes.c_int32), ("stream", ctypes.c_void_p)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("leaf", ctypes.c_int32), ("crossover", ctypes.c_int32), ("levels", ctypes.c_int32),
+                ("kernels", ctypes.c_int32), ("ms_total", ctypes.c_double), ("ms_leaf", ctypes.c_double),
+                ("ms_dense", ctypes.c_double), ("ms_fft", ctypes.c_double), ("residual_norm", ctypes.c_double)]
+
+
+class KernelStat(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("s", ctypes.c_int32), ("launches", ctypes.c_int32),
+                ("tasks", ctypes.c_int32), ("ms", ctypes.c_double), ("bytes", ctypes.c_double)]
+
+
+KIND_NAMES = {0: "leaf", 1: "dense_f64", 2: "dense_f32", 3: "fft_f64", 4: "fft_f32"}
+
+EXPORTS = ["fracsolve_create", "fracsolve_weights", "fracsolve_solve", "fracsolve_apply", "fracsolve_adjoint",
+           "fracsolve_set_timing", "fracsolve_get_stats", "fracsolve_kernel_stats", "fracsolve_destroy",
+           "fracsolve_last_error"]
+
+_lib = None
+
+
+class FracsolveError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s: %s" % (STATUS.get(code, code), msg))
+        self.code = code
+
+
+def lib():
+    """Load the HIP library (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIBPATH):
+        raise RuntimeError("fracsolve HIP library not built: %s is missing (run __graft_entry__.build())" % LIBPATH)
+    L = ctypes.CDLL(LIBPATH)
+    dp = ctypes.POINTER(ctypes.c_double)
+    vpp = ctypes.POINTER(ctypes.c_void_p)
+    L.fracsolve_create.restype = ctypes.c_int
+    L.fracsolve_create.argtypes = [ctypes.POINTER(Problem), ctypes.c_int32, ctypes.POINTER(Options),
+                                   ctypes.POINTER(ctypes.c_void_p)]
+    L.fracsolve_weights.restype = ctypes.c_int
+    L.fracsolve_weights.argtypes = [ctypes.c_void_p, ctypes.c_int32] + [dp] * 7
+    L.fracsolve_solve.restype = ctypes.c_int
+    L.fracsolve_solve.argtypes = [ctypes.c_void_p, vpp, vpp, vpp, vpp]
+    L.fracsolve_apply.restype = ctypes.c_int
+    L.fracsolve_apply.argtypes = [ctypes.c_void_p, vpp, vpp]
+    L.fracsolve_adjoint.restype = ctypes.c_int
+    L.fracsolve_adjoint.argtypes = [ctypes.c_void_p, vpp, vpp, vpp, vpp, vpp, dp]
+    L.fracsolve_set_timing.restype = ctypes.c_int
+    L.fracsolve_set_timing.argtypes = [ctypes.c_void_p, ctypes.c_int32]
+    L.fracsolve_get_stats.restype = ctypes.c_int
+    L.fracsolve_get_stats.argtypes = [ctypes.c_void_p, ctypes.POINTER(Stats)]
+    L.fracsolve_kernel_stats.restype = ctypes.c_int
+    L.fracsolve_kernel_stats.argtypes = [ctypes.c_void_p, ctypes.POINTER(KernelStat), ctypes.c_int32,
+                                         ctypes.POINTER(ctypes.c_int32)]
+    L.fracsolve_destroy.restype = None
+    L.fracsolve_destroy.argtypes = [ctypes.c_void_p]
+    L.fracsolve_last_error.restype = ctypes.c_char_p
+    L.fracsolve_last_error.argtypes = [ctypes.c_void_p]
+    _lib = L
+    return L
+
+
+def _ptrs(tensors, required=True, name="field"):
+    """Host array of device pointers (None entries -> NULL)."""
+    if tensors is None:
+        return None
+    arr = (ctypes.c_void_p * len(tensors))()
+    for k, t in enumerate(tensors):
+        if t is None:
+            if required:
+                raise ValueError("%s[%d] is None" % (name, k))
+            arr[k] = None
+            continue
+        if not t.is_cuda or t.dtype.__str__() != "torch.float64" or not t.is_contiguous():
+            raise ValueError("%s[%d] must be a contiguous float64 CUDA tensor" % (name, k))
+        arr[k] = t.data_ptr()
+    return ctypes.cast(arr, ctypes.POINTER(ctypes.c_void_p))
+
+
+class Solver:
+    """One handle over `len(problems)` instances (see fracsolve_create)."""
+
+    def __init__(self, problems: Sequence[dict], precision="fp64", refine_steps=0, leaf=0, crossover=0,
+                 stream=None):
+        L = lib()
+        self._lib = L
+        self.problems = [dict(p) for p in problems]
+        arr = (Problem * len(problems))()
+        for k, p in enumerate(problems):
+            arr[k] = Problem(float(p["gamma"]), float(p.get("T", 1.0)), float(p.get("x0", 0.0)),
+                             float(p.get("x1", 1.0)), int(p["M"]), int(p["N"]))
+        if stream is None:
+            import torch
+
+            stream = torch.cuda.current_stream().cuda_stream
+        self.stream = stream
+        opts = Options(PRECISION[precision] if isinstance(precision, str) else int(precision), int(refine_steps),
+                       int(leaf), int(crossover), ctypes.c_void_p(stream))
+        h = ctypes.c_void_p()
+        rc = L.fracsolve_create(arr, len(problems), ctypes.byref(opts), ctypes.byref(h))
+        if rc != FRACSOLVE_OK:
+            raise FracsolveError(rc, L.fracsolve_last_error(None).decode())
+        self.h = h
+
+    def _check(self, rc):
+        if rc != FRACSOLVE_OK:
+            raise FracsolveError(rc, self._lib.fracsolve_last_error(self.h).decode())
+
+    def close(self):
+        if getattr(self, "h", None):
+            self._lib.fracsolve_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def weights(self, inst=0):
+        import numpy as np
+
+        N = self.problems[inst]["N"]
+        out = {k: np.zeros(N) for k in ("b", "a", "rho", "psi", "da", "drho", "dpsi")}
+        dp = ctypes.POINTER(ctypes.c_double)
+        args = [out[k].ctypes.data_as(dp) for k in ("b", "a", "rho", "psi", "da", "drho", "dpsi")]
+        self._check(self._lib.fracsolve_weights(self.h, inst, *args))
+        return out
+
+    def solve(self, f, u0=None, phi=None, out=None):
+        """f: list (one per instance) of [N,M] tensors; returns the list of solutions."""
+        import torch
+
+        f = list(f)
+        if out is None:
+            out = [torch.empty_like(x) for x in f]
+        u0p = _ptrs(u0, required=False, name="u0") if u0 is not None else None
+        php = _ptrs(phi, required=False, name="phi") if phi is not None else None
+        self._check(self._lib.fracsolve_solve(self.h, _ptrs(f, name="f"), u0p, php, _ptrs(out, name="u")))
+        return out
+
+    def apply(self, u, out=None):
+        import torch
+
+        u = list(u)
+        if out is None:
+            out = [torch.empty_like(x) for x in u]
+        self._check(self._lib.fracsolve_apply(self.h, _ptrs(u, name="u"), _ptrs(out, name="y")))
+        return out
+
+    def adjoint(self, g, u=None, u0=None, phi=None, out=None, want_gamma=True):
+        import torch
+
+        g = list(g)
+        if out is None:
+            out = [torch.empty_like(x) for x in g]
+        dg = (ctypes.c_double * len(g))() if want_gamma else None
+        rc = self._lib.fracsolve_adjoint(
+            self.h, _ptrs(g, name="g"), _ptrs(u, name="u") if u is not None else None,
+            _ptrs(u0, required=False, name="u0") if u0 is not None else None,
+            _ptrs(phi, required=False, name="phi") if phi is not None else None, _ptrs(out, name="dL_df"),
+            ctypes.cast(dg, ctypes.POINTER(ctypes.c_double)) if want_gamma else None)
+        self._check(rc)
+        return out, (list(dg) if want_gamma else None)
+
+    def set_timing(self, on=True):
+        self._check(self._lib.fracsolve_set_timing(self.h, 1 if on else 0))
+
+    def kernel_stats(self):
+        """Per-(kind, level) launch count, time and algorithmic bytes of the last call (timing level 2)."""
+        cap = 256
+        arr = (KernelStat * cap)()
+        n = ctypes.c_int32(0)
+        self._check(self._lib.fracsolve_kernel_stats(self.h, arr, cap, ctypes.byref(n)))
+        return [dict(kind=KIND_NAMES[arr[k].kind], s=arr[k].s, launches=arr[k].launches, tasks=arr[k].tasks,
+                     ms=arr[k].ms, bytes=arr[k].bytes) for k in range(min(n.value, cap))]
+
+    def set_timing_level(self, level):
+        self._check(self._lib.fracsolve_set_timing(self.h, int(level)))
+
+    def stats(self):
+        s = Stats()
+        self._check(self._lib.fracsolve_get_stats(self.h, ctypes.byref(s)))
+        return {k: getattr(s, k) for k, _ in Stats._fields_}
+
+
+_solver_cache = {}
+
+
+def _cached_solver(gamma, T, x0, x1, M, N, precision, refine_steps):
+    key = (float(gamma), T, x0, x1, M, N, precision, refine_steps)
+    s = _solver_cache.get(key)
+    if s is None:
+        if len(_solver_cache) > 8:
+            _solver_cache.clear()
+        s = Solver([dict(gamma=float(gamma), T=T, x0=x0, x1=x1, M=M, N=N)], precision=precision,
+                   refine_steps=refine_steps)
+        _solver_cache[key] = s
+    return s
+
+
+def _make_function():
+    import torch
+
+    class FracSolve(torch.autograd.Function):
+        """u = solve(f; gamma) with u0, phi fixed data.
+
+        forward(f [N,M], gamma (0-dim tensor), u0 [M] or None, phi [M] or None,
+                T=1, x0=0, x1=1) -> u [N,M]
+        backward: dL/df by the reverse-time adjoint solve, dL/dgamma through
+        the gamma-derivatives of the weights (both computed by the library).
+        """
+
+        @staticmethod
+        def forward(ctx, f, gamma, u0=None, phi=None, T=1.0, x0=0.0, x1=1.0):
+            N, M = f.shape
+            s = _cached_solver(float(gamma), T, x0, x1, M, N, "fp64", 0)
+            f = f.contiguous()
+            u = s.solve([f], [u0] if u0 is not None else None, [phi] if phi is not None else None)[0]
+            ctx.solver = s
+            ctx.save_for_backward(u, u0 if u0 is not None else None, phi if phi is not None else None)
+            ctx.has = (u0 is not None, phi is not None)
+            return u
+
+        @staticmethod
+        def backward(ctx, grad_u):
+            u, u0, phi = ctx.saved_tensors
+            s = ctx.solver
+            g = grad_u.contiguous()
+            lam, dg = s.adjoint([g], [u], [u0] if ctx.has[0] else None, [phi] if ctx.has[1] else None)
+            dgamma = torch.tensor(dg[0], dtype=torch.float64, device=grad_u.device)
+            return lam[0], dgamma, None, None, None, None, None
+
+    return FracSolve
+
+
+_fn = None
+
+
+def frac_solve(f, gamma, u0=None, phi=None, T=1.0, x0=0.0, x1=1.0):
+    """Differentiable solve (see FracSolve)."""
+    global _fn
+    if _fn is None:
+        _fn = _make_function()
+    return _fn.apply(f, gamma, u0, phi, T, x0, x1)

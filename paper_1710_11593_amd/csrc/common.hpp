@@ -1,0 +1,106 @@
+// Shared declarations of the fracsolve HIP library: task descriptors passed
+// to the kernels, small complex helpers and the launcher prototypes.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fs {
+
+template <typename T>
+struct cplx {
+    T x, y;
+};
+
+template <typename T>
+__device__ __forceinline__ cplx<T> cadd(cplx<T> a, cplx<T> b) { return {a.x + b.x, a.y + b.y}; }
+template <typename T>
+__device__ __forceinline__ cplx<T> csub(cplx<T> a, cplx<T> b) { return {a.x - b.x, a.y - b.y}; }
+template <typename T>
+__device__ __forceinline__ cplx<T> cmul(cplx<T> a, cplx<T> b)
+{
+    return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+// a * conj(b)
+template <typename T>
+__device__ __forceinline__ cplx<T> cmulc(cplx<T> a, cplx<T> b)
+{
+    return {a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y};
+}
+
+// One leaf of the recursion: rows [lo, lo+nrows) of one instance, solved by
+// forward substitution in time with a tridiagonal solve per row.
+struct LeafTask {
+    double *u;          // field [N][M]: right-hand side in, solution out
+    const double *a;    // Toeplitz column a_0..a_{L-1}
+    const double *fac;  // factor table of a_0 I + K (see k_leaf.hip)
+    const float *hist;  // float32 history accumulator [N][M] or null
+    float *x32;         // float32 shadow of solved rows or null
+    int64_t M;
+    int64_t lo;
+    int32_t nrows;
+    int32_t pad;
+};
+
+// One off-diagonal Toeplitz-block product:
+//   Y[ylo + p] += alpha * sum_{q<s} w[s + p - q] X[xlo + q],   p < ny <= s,
+// for all M columns.  The rows of X and Y are rows of [*][M] arrays.
+template <typename T>
+struct UpdTask {
+    const T *x;
+    T *y;
+    const double *w;             // Toeplitz column (dense products)
+    const cplx<T> *spec;         // DFT_{2s} of w[0..2s) (FFT products)
+    int64_t M;
+    int64_t xlo, ylo;
+    int32_t s;
+    int32_t ny;
+    double alpha;
+};
+
+// Launchers (defined in the .hip files; all enqueue on `st`).
+hipError_t launch_weights(hipStream_t st, int regime, double p, double coef, double dcoef, double tau,
+                          int64_t N, double *b, double *a, double *rho, double *psi, double *da,
+                          double *drho, double *dpsi);
+hipError_t launch_rhs(hipStream_t st, const double *f, const double *u0, const double *phi,
+                      const double *rho, const double *psi, double *u, int64_t M, int64_t N);
+hipError_t launch_rhs_scale(hipStream_t st, double *y, const double *u0, const double *phi,
+                            const double *rho, const double *psi, int64_t M, int64_t N);
+
+// Leaf configuration chosen from M.
+struct LeafCfg {
+    int nt;   // threads per workgroup
+    int pt;   // rows per thread
+    int S;    // PCR stages = log2(2 nt)
+};
+LeafCfg leaf_config(int64_t M);
+size_t leaf_table_doubles(const LeafCfg &c);
+hipError_t launch_leaf_factor(hipStream_t st, const LeafCfg &c, int64_t M, double a0, double e, double *fac);
+hipError_t launch_leaf(hipStream_t st, const LeafCfg &c, int L, const LeafTask *d_tasks, int ntasks, bool mixed);
+
+hipError_t launch_twiddles(hipStream_t st, int64_t nmax, cplx<double> *w64, cplx<float> *w32);
+
+template <typename T>
+hipError_t launch_gemm_update(hipStream_t st, const UpdTask<T> *d_tasks, int ntasks, int s, int64_t maxM);
+template <typename T>
+hipError_t launch_fft_update_ex(hipStream_t st, const UpdTask<T> *d_tasks, int ntasks, int s, int64_t maxM,
+                                const cplx<T> *tw, int64_t nmax, cplx<T> *zs, size_t zs_elems);
+hipError_t launch_spectrum(hipStream_t st, const double *w, int s, cplx<double> *spec64, cplx<float> *spec32,
+                           const cplx<double> *tw, int64_t nmax, cplx<double> *scratch);
+int fft_max_single_pass(bool fp32);
+
+hipError_t launch_diag_apply(hipStream_t st, const double *x, double *y, const double *a, double e, int64_t M,
+                             int64_t N, int L);
+hipError_t launch_copy_reverse(hipStream_t st, const double *src, double *dst, int64_t M, int64_t N);
+hipError_t launch_axpy(hipStream_t st, double *y, const double *x, double alpha, int64_t n);
+hipError_t launch_sub(hipStream_t st, double *r, const double *b, const double *y, int64_t n);
+hipError_t launch_to_f32(hipStream_t st, const double *x, float *y, int64_t n);
+hipError_t launch_zero(hipStream_t st, void *p, size_t bytes);
+hipError_t launch_dot_partial(hipStream_t st, const double *x, const double *y, int64_t n, double *partial,
+                              int nblocks);
+hipError_t launch_gamma_rhs_terms(hipStream_t st, const double *lam, const double *u0, const double *phi,
+                                  const double *drho, const double *dpsi, int64_t M, int64_t N, double *partial,
+                                  int nblocks);
+hipError_t launch_absmax_partial(hipStream_t st, const double *x, int64_t n, double *partial, int nblocks);
+
+}  // namespace fs

@@ -1,0 +1,926 @@
+// Host runtime of the fracsolve library: handle, planner, the recursive
+// (divide-and-conquer in time) driver and the C ABI of include/fracsolve.h.
+//
+// The block lower-triangular Toeplitz system (time-major form of eq. e21)
+//   (a_0 I + K) U^n + sum_{j<n} a_{n-j} U^j = R^n
+// is solved by recursive halving of [0, Np), Np = 2^k >= N:
+//   solve(lo, 2s): solve(lo, s); Y[lo+s, lo+2s) -= T_s X[lo, lo+s); solve(lo+s, s)
+// with T_s[p][q] = a_{s+p-q}; leaves of L rows are solved by k_leaf.  Run in
+// depth-first order, leaf k is followed by exactly one level product of
+// half-size s = L * lowbit(k+1).  Rows at or beyond N are never touched
+// (the system is causal, so padding N up to Np is exact).
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/fracsolve.h"
+#include "common.hpp"
+
+using namespace fs;
+
+namespace {
+
+std::string g_create_error;
+
+struct Inst {
+    fracsolve_problem p;
+    int regime = 0;  // 0 diffusion, 1 diffusion-wave
+    double tau = 0, h = 0, e = 0, coef = 0, dcoef = 0, pexp = 0;
+    int64_t M = 0, N = 0, Np = 0;
+    LeafCfg lc{};
+    double *b = nullptr, *a = nullptr, *rho = nullptr, *psi = nullptr;
+    double *da = nullptr, *drho = nullptr, *dpsi = nullptr;
+    double *fac = nullptr;
+    // spectra of a and of da for every FFT level, indexed by log2(s)
+    std::vector<int64_t> spec_off;
+    cplx<double> *spec64 = nullptr, *dspec64 = nullptr;
+    cplx<float> *spec32 = nullptr;
+    // workspaces (allocated on first use)
+    double *R = nullptr;      // saved right-hand side (refinement)
+    double *W = nullptr;      // residual / correction / reversed field
+    double *V = nullptr;      // operator apply output
+    float *hist32 = nullptr;  // float32 history accumulator
+    float *x32 = nullptr;     // float32 shadow of solved rows
+};
+
+double digamma_host(double x)
+{
+    // psi(x) for x > 0: recurrence psi(x) = psi(x+1) - 1/x up to x >= 12,
+    // then the asymptotic expansion ln x - 1/(2x) - sum B_2k/(2k x^2k)
+    // (Abramowitz & Stegun 6.3.5 and 6.3.18).
+    double r = 0.0;
+    while (x < 12.0) {
+        r -= 1.0 / x;
+        x += 1.0;
+    }
+    const double B[] = {1.0 / 6, -1.0 / 30, 1.0 / 42, -1.0 / 30, 5.0 / 66, -691.0 / 2730, 7.0 / 6};
+    double x2 = 1.0 / (x * x), pw = x2, s = 0.0;
+    for (int k = 1; k <= 7; ++k) {
+        s += B[k - 1] / (2.0 * k) * pw;
+        pw *= x2;
+    }
+    return r + std::log(x) - 0.5 / x - s;
+}
+
+bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
+int64_t next_pow2(int64_t v)
+{
+    int64_t p = 1;
+    while (p < v) p <<= 1;
+    return p;
+}
+int ilog2i(int64_t v)
+{
+    int r = 0;
+    while ((1LL << r) < v) ++r;
+    return r;
+}
+
+}  // namespace
+
+struct fracsolve_ctx {
+    std::vector<Inst> inst;
+    fracsolve_options opts{};
+    hipStream_t st = nullptr;
+    int device = 0;
+    int L = 8;
+    int crossover = 64;
+    int64_t nmax = 0;
+    cplx<double> *tw64 = nullptr;
+    cplx<float> *tw32 = nullptr;
+    // descriptor staging: pinned host copy and device copy
+    void *h_desc = nullptr, *d_desc = nullptr;
+    size_t desc_cap = 0, desc_used = 0;
+    hipEvent_t desc_ready = nullptr;
+    // multi-pass FFT scratch
+    void *zs = nullptr;
+    size_t zs_bytes = 0;
+    double *partial = nullptr;  // reduction partials
+    std::string err;
+    int timing = 0;
+    fracsolve_stats stats{};
+    std::vector<hipEvent_t> evpool;
+    struct Rec {
+        int kind, s, ntasks;
+        double bytes;
+        size_t ev;
+    };
+    std::vector<Rec> recs;
+    std::vector<fracsolve_kernel_stat> kstats;
+    int kernels = 0;
+    std::vector<double *> allocs;
+};
+
+namespace {
+
+int fail(fracsolve_ctx *h, int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (h)
+        h->err = buf;
+    else
+        g_create_error = buf;
+    return code;
+}
+
+#define HIPCHK(h, expr)                                                                           \
+    do {                                                                                          \
+        hipError_t _e = (expr);                                                                   \
+        if (_e != hipSuccess)                                                                     \
+            return fail((h), FRACSOLVE_E_DEVICE, "%s failed: %s", #expr, hipGetErrorString(_e)); \
+    } while (0)
+
+template <typename T>
+int dalloc(fracsolve_ctx *h, T **p, size_t count)
+{
+    void *q = nullptr;
+    size_t bytes = count * sizeof(T);
+    if (bytes == 0) bytes = 16;
+    if (hipMalloc(&q, bytes) != hipSuccess) {
+        hipGetLastError();
+        return fail(h, FRACSOLVE_E_NOMEM, "device allocation of %zu bytes failed", bytes);
+    }
+    h->allocs.push_back((double *)q);
+    *p = (T *)q;
+    return FRACSOLVE_OK;
+}
+
+// ---- descriptor staging: all task descriptors of one call go to the device
+// in one copy; kernels receive pointers into the device copy.
+struct DescBuilder {
+    fracsolve_ctx *h;
+    std::vector<char> host;
+    size_t add(const void *p, size_t bytes)
+    {
+        size_t off = (host.size() + 15) & ~(size_t)15;
+        host.resize(off + bytes);
+        memcpy(host.data() + off, p, bytes);
+        return off;
+    }
+};
+
+int desc_upload(fracsolve_ctx *h, const DescBuilder &db)
+{
+    size_t need = db.host.size();
+    if (need == 0) return FRACSOLVE_OK;
+    if (h->desc_ready) HIPCHK(h, hipEventSynchronize(h->desc_ready));
+    if (need > h->desc_cap) {
+        HIPCHK(h, hipStreamSynchronize(h->st));
+        if (h->h_desc) hipHostFree(h->h_desc);
+        if (h->d_desc) hipFree(h->d_desc);
+        h->h_desc = h->d_desc = nullptr;
+        size_t cap = std::max(need, (size_t)1 << 20);
+        HIPCHK(h, hipHostMalloc(&h->h_desc, cap, hipHostMallocDefault));
+        HIPCHK(h, hipMalloc(&h->d_desc, cap));
+        h->desc_cap = cap;
+    }
+    memcpy(h->h_desc, db.host.data(), need);
+    HIPCHK(h, hipMemcpyAsync(h->d_desc, h->h_desc, need, hipMemcpyHostToDevice, h->st));
+    HIPCHK(h, hipEventRecord(h->desc_ready, h->st));
+    return FRACSOLVE_OK;
+}
+
+template <typename T>
+const T *dptr(fracsolve_ctx *h, size_t off)
+{
+    return (const T *)((const char *)h->d_desc + off);
+}
+
+// ---- one call = a list of launch records built on the host, then replayed.
+enum OpKind { OP_LEAF, OP_GEMM64, OP_GEMM32, OP_FFT64, OP_FFT32 };
+struct Op {
+    OpKind kind;
+    size_t off;   // descriptor offset
+    int ntasks;
+    int s;        // level half-size (updates) or leaf config index
+    int64_t maxM;
+    LeafCfg lc;
+    bool mixed;
+    double bytes = 0.0;  // algorithmic HBM bytes of the launch
+};
+
+int get_event(fracsolve_ctx *h, size_t idx, hipEvent_t *ev)
+{
+    while (h->evpool.size() <= idx) {
+        hipEvent_t e;
+        HIPCHK(h, hipEventCreate(&e));
+        h->evpool.push_back(e);
+    }
+    *ev = h->evpool[idx];
+    return FRACSOLVE_OK;
+}
+
+int run_ops(fracsolve_ctx *h, const std::vector<Op> &ops)
+{
+    for (const Op &op : ops) {
+        hipError_t e = hipSuccess;
+        size_t evi = 0;
+        if (h->timing >= 2) {
+            evi = 2 * h->recs.size();
+            hipEvent_t e0;
+            int rc = get_event(h, evi, &e0);
+            if (rc) return rc;
+            rc = get_event(h, evi + 1, &e0);
+            if (rc) return rc;
+            HIPCHK(h, hipEventRecord(h->evpool[evi], h->st));
+        }
+        switch (op.kind) {
+            case OP_LEAF:
+                e = launch_leaf(h->st, op.lc, h->L, dptr<LeafTask>(h, op.off), op.ntasks, op.mixed);
+                break;
+            case OP_GEMM64:
+                e = launch_gemm_update<double>(h->st, dptr<UpdTask<double>>(h, op.off), op.ntasks, op.s, op.maxM);
+                break;
+            case OP_GEMM32:
+                e = launch_gemm_update<float>(h->st, dptr<UpdTask<float>>(h, op.off), op.ntasks, op.s, op.maxM);
+                break;
+            case OP_FFT64:
+                e = launch_fft_update_ex<double>(h->st, dptr<UpdTask<double>>(h, op.off), op.ntasks, op.s, op.maxM,
+                                                 h->tw64, h->nmax, (cplx<double> *)h->zs,
+                                                 h->zs_bytes / sizeof(cplx<double>));
+                break;
+            case OP_FFT32:
+                e = launch_fft_update_ex<float>(h->st, dptr<UpdTask<float>>(h, op.off), op.ntasks, op.s, op.maxM,
+                                                h->tw32, h->nmax, (cplx<float> *)h->zs,
+                                                h->zs_bytes / sizeof(cplx<float>));
+                break;
+        }
+        if (e != hipSuccess) return fail(h, FRACSOLVE_E_DEVICE, "kernel launch failed: %s", hipGetErrorString(e));
+        h->kernels++;
+        if (h->timing >= 2) {
+            HIPCHK(h, hipEventRecord(h->evpool[evi + 1], h->st));
+            int kind = op.kind == OP_LEAF ? 0 : op.kind == OP_GEMM64 ? 1 : op.kind == OP_GEMM32 ? 2
+                     : op.kind == OP_FFT64 ? 3 : 4;
+            h->recs.push_back({kind, op.kind == OP_LEAF ? h->L : op.s, op.ntasks, op.bytes, evi});
+        }
+    }
+    return FRACSOLVE_OK;
+}
+
+// Algorithmic HBM bytes of one level product: read the s rows of X, read and
+// write the ny rows of Y (M columns each).
+template <typename T>
+double upd_bytes(const UpdTask<T> &t, double elem)
+{
+    return ((double)t.s + 2.0 * (double)t.ny) * (double)t.M * elem;
+}
+
+// Field views of one recursive solve.
+struct Field {
+    double *u;        // right-hand side in / solution out [N][M]
+    float *hist32;    // mixed: history accumulator (zeroed by caller)
+    float *x32;       // mixed: float32 shadow of solved rows
+};
+
+// Build the launch list of the recursive solve of every instance in `sel`
+// (lockstep over leaf index).  prec: FRACSOLVE_FP64 or FRACSOLVE_FP32.
+void build_solve(fracsolve_ctx *h, const std::vector<int> &sel, const std::vector<Field> &fld, int prec,
+                 DescBuilder &db, std::vector<Op> &ops)
+{
+    const int L = h->L;
+    const bool mixed = (prec != FRACSOLVE_FP64);
+    int64_t K = 0;
+    for (int i : sel) K = std::max(K, h->inst[i].Np / L);
+    for (int64_t k = 0; k < K; ++k) {
+        // leaves, one launch per leaf configuration
+        std::vector<std::pair<int, LeafTask>> lt;
+        for (size_t q = 0; q < sel.size(); ++q) {
+            const Inst &in = h->inst[sel[q]];
+            int64_t lo = k * L;
+            if (lo >= in.N) continue;
+            LeafTask t{};
+            t.u = fld[q].u;
+            t.a = in.a;
+            t.fac = in.fac;
+            t.hist = mixed ? fld[q].hist32 : nullptr;
+            t.x32 = mixed ? fld[q].x32 : nullptr;
+            t.M = in.M;
+            t.lo = lo;
+            t.nrows = (int)std::min<int64_t>(L, in.N - lo);
+            lt.push_back({in.lc.nt * 100 + in.lc.pt, t});
+        }
+        std::sort(lt.begin(), lt.end(), [](const auto &x, const auto &y) { return x.first < y.first; });
+        for (size_t b = 0; b < lt.size();) {
+            size_t e = b;
+            while (e < lt.size() && lt[e].first == lt[b].first) ++e;
+            std::vector<LeafTask> v;
+            for (size_t j = b; j < e; ++j) v.push_back(lt[j].second);
+            size_t off = db.add(v.data(), v.size() * sizeof(LeafTask));
+            LeafCfg lc{lt[b].first / 100, lt[b].first % 100, 0};
+            lc.S = ilog2i(2 * lc.nt);
+            Op op{OP_LEAF, off, (int)v.size(), 0, 0, lc, mixed};
+            for (auto &t : v) op.bytes += (double)t.nrows * (double)t.M * (mixed ? 24.0 : 16.0);
+            ops.push_back(op);
+            b = e;
+        }
+        // level product after leaf k
+        if (k + 1 >= K) break;
+        int64_t kk = k + 1;
+        int64_t s = (int64_t)L * (kk & -kk);
+        int64_t mid = kk * L, lo = mid - s;
+        std::vector<UpdTask<double>> t64;
+        std::vector<UpdTask<float>> t32;
+        int64_t maxM = 0;
+        std::vector<int> users;
+        for (size_t q = 0; q < sel.size(); ++q) {
+            const Inst &in = h->inst[sel[q]];
+            if (mid >= in.N) continue;
+            int lev = ilog2i(s);
+            bool fft = s > h->crossover;
+            if (!mixed) {
+                UpdTask<double> t{};
+                t.x = fld[q].u;
+                t.y = fld[q].u;
+                t.w = in.a;
+                t.spec = fft ? in.spec64 + in.spec_off[lev] : nullptr;
+                t.M = in.M;
+                t.xlo = lo;
+                t.ylo = mid;
+                t.s = (int)s;
+                t.ny = (int)std::min<int64_t>(s, in.N - mid);
+                t.alpha = -1.0;
+                t64.push_back(t);
+            } else {
+                UpdTask<float> t{};
+                t.x = fld[q].x32;
+                t.y = fld[q].hist32;
+                t.w = in.a;
+                t.spec = fft ? in.spec32 + in.spec_off[lev] : nullptr;
+                t.M = in.M;
+                t.xlo = lo;
+                t.ylo = mid;
+                t.s = (int)s;
+                t.ny = (int)std::min<int64_t>(s, in.N - mid);
+                t.alpha = -1.0;
+                t32.push_back(t);
+            }
+            maxM = std::max(maxM, in.M);
+        }
+        bool fft = s > h->crossover;
+        bool multipass = 2 * s > fft_max_single_pass(mixed);
+        if (!mixed && !t64.empty()) {
+            if (fft && multipass) {
+                for (auto &t : t64) {
+                    Op op{OP_FFT64, db.add(&t, sizeof t), 1, (int)s, t.M, {}, false};
+                    op.bytes = upd_bytes(t, 8);
+                    ops.push_back(op);
+                }
+            } else {
+                size_t off = db.add(t64.data(), t64.size() * sizeof(t64[0]));
+                Op op{fft ? OP_FFT64 : OP_GEMM64, off, (int)t64.size(), (int)s, maxM, {}, false};
+                for (auto &t : t64) op.bytes += upd_bytes(t, 8);
+                ops.push_back(op);
+            }
+        }
+        if (mixed && !t32.empty()) {
+            if (fft && multipass) {
+                for (auto &t : t32) {
+                    Op op{OP_FFT32, db.add(&t, sizeof t), 1, (int)s, t.M, {}, true};
+                    op.bytes = upd_bytes(t, 4);
+                    ops.push_back(op);
+                }
+            } else {
+                size_t off = db.add(t32.data(), t32.size() * sizeof(t32[0]));
+                Op op{fft ? OP_FFT32 : OP_GEMM32, off, (int)t32.size(), (int)s, maxM, {}, true};
+                for (auto &t : t32) op.bytes += upd_bytes(t, 4);
+                ops.push_back(op);
+            }
+        }
+    }
+}
+
+// Build the launch list of the off-diagonal part of an operator apply
+// y += alpha * (sum over level tiles) for one instance and weights (a or da).
+void build_apply_levels(fracsolve_ctx *h, const Inst &in, const double *x, double *y, bool deriv, DescBuilder &db,
+                        std::vector<Op> &ops)
+{
+    const int L = h->L;
+    for (int64_t s = L; s < in.Np; s *= 2) {
+        int lev = ilog2i(s);
+        bool fft = s > h->crossover;
+        bool multipass = 2 * s > fft_max_single_pass(false);
+        std::vector<UpdTask<double>> tv;
+        for (int64_t lo = 0; lo + s < in.N; lo += 2 * s) {
+            UpdTask<double> t{};
+            t.x = x;
+            t.y = y;
+            t.w = deriv ? in.da : in.a;
+            t.spec = fft ? (deriv ? in.dspec64 : in.spec64) + in.spec_off[lev] : nullptr;
+            t.M = in.M;
+            t.xlo = lo;
+            t.ylo = lo + s;
+            t.s = (int)s;
+            t.ny = (int)std::min<int64_t>(s, in.N - (lo + s));
+            t.alpha = 1.0;
+            tv.push_back(t);
+        }
+        if (tv.empty()) continue;
+        if (fft && multipass) {
+            for (auto &t : tv) {
+                Op op{OP_FFT64, db.add(&t, sizeof t), 1, (int)s, in.M, {}, false};
+                op.bytes = upd_bytes(t, 8);
+                ops.push_back(op);
+            }
+        } else {
+            size_t off = db.add(tv.data(), tv.size() * sizeof(tv[0]));
+            Op op{fft ? OP_FFT64 : OP_GEMM64, off, (int)tv.size(), (int)s, in.M, {}, false};
+            for (auto &t : tv) op.bytes += upd_bytes(t, 8);
+            ops.push_back(op);
+        }
+    }
+}
+
+int ensure(fracsolve_ctx *h, double **p, int64_t n)
+{
+    if (*p) return FRACSOLVE_OK;
+    return dalloc(h, p, (size_t)n);
+}
+int ensuref(fracsolve_ctx *h, float **p, int64_t n)
+{
+    if (*p) return FRACSOLVE_OK;
+    return dalloc(h, p, (size_t)n);
+}
+
+// Recursive solve of the assembled right-hand sides in fld (u in place).
+int dc_solve(fracsolve_ctx *h, const std::vector<int> &sel, const std::vector<Field> &fld, int prec)
+{
+    if (prec != FRACSOLVE_FP64) {
+        for (size_t q = 0; q < sel.size(); ++q) {
+            const Inst &in = h->inst[sel[q]];
+            HIPCHK(h, launch_zero(h->st, fld[q].hist32, sizeof(float) * (size_t)(in.M * in.N)));
+            h->kernels++;
+        }
+    }
+    DescBuilder db{h, {}};
+    std::vector<Op> ops;
+    build_solve(h, sel, fld, prec, db, ops);
+    int rc = desc_upload(h, db);
+    if (rc) return rc;
+    return run_ops(h, ops);
+}
+
+// y = A x in float64 (deriv: y = (dA/dgamma) x, i.e. weights a' and no K).
+// x and y are distinct [N][M] device arrays of instance i.
+int apply_op(fracsolve_ctx *h, int i, const double *x, double *y, bool deriv)
+{
+    Inst &in = h->inst[i];
+    HIPCHK(h, launch_diag_apply(h->st, x, y, deriv ? in.da : in.a, deriv ? 0.0 : in.e, in.M, in.N, h->L));
+    h->kernels++;
+    DescBuilder db{h, {}};
+    std::vector<Op> ops;
+    build_apply_levels(h, in, x, y, deriv, db, ops);
+    int rc = desc_upload(h, db);
+    if (rc) return rc;
+    return run_ops(h, ops);
+}
+
+// sum of a device reduction written as per-block partials
+int finish_sum(fracsolve_ctx *h, int nb, double *out)
+{
+    std::vector<double> hp(nb);
+    HIPCHK(h, hipMemcpyAsync(hp.data(), h->partial, sizeof(double) * nb, hipMemcpyDeviceToHost, h->st));
+    HIPCHK(h, hipStreamSynchronize(h->st));
+    double s = 0.0;
+    for (double v : hp) s += v;
+    *out = s;
+    return FRACSOLVE_OK;
+}
+
+int finish_max(fracsolve_ctx *h, int nb, double *out)
+{
+    std::vector<double> hp(nb);
+    HIPCHK(h, hipMemcpyAsync(hp.data(), h->partial, sizeof(double) * nb, hipMemcpyDeviceToHost, h->st));
+    HIPCHK(h, hipStreamSynchronize(h->st));
+    double s = 0.0;
+    for (double v : hp) s = std::max(s, v);
+    *out = s;
+    return FRACSOLVE_OK;
+}
+
+constexpr int kRedBlocks = 1024;
+
+int validate_problem(const fracsolve_problem &p, int k)
+{
+    char what[64];
+    snprintf(what, sizeof what, "instance %d", k);
+    if (!(p.gamma > 0.0 && p.gamma < 2.0) || p.gamma == 1.0 || !std::isfinite(p.gamma))
+        return fail(nullptr, FRACSOLVE_E_ARG, "%s: gamma must lie in (0,1) or (1,2), got %g", what, p.gamma);
+    if (!(p.T > 0.0) || !std::isfinite(p.T))
+        return fail(nullptr, FRACSOLVE_E_ARG, "%s: T must be positive, got %g", what, p.T);
+    if (!(p.x1 > p.x0) || !std::isfinite(p.x0) || !std::isfinite(p.x1))
+        return fail(nullptr, FRACSOLVE_E_ARG, "%s: need x1 > x0, got [%g, %g]", what, p.x0, p.x1);
+    if (p.M < 1 || p.M > 4096)
+        return fail(nullptr, FRACSOLVE_E_ARG, "%s: M must lie in [1, 4096], got %lld", what, (long long)p.M);
+    if (p.N < 1 || p.N > (1LL << 24))
+        return fail(nullptr, FRACSOLVE_E_ARG, "%s: N must lie in [1, 2^24], got %lld", what, (long long)p.N);
+    return FRACSOLVE_OK;
+}
+
+void free_all(fracsolve_ctx *h)
+{
+    for (double *p : h->allocs) hipFree(p);
+    h->allocs.clear();
+    if (h->h_desc) hipHostFree(h->h_desc);
+    if (h->d_desc) hipFree(h->d_desc);
+    if (h->zs) hipFree(h->zs);
+    if (h->desc_ready) hipEventDestroy(h->desc_ready);
+    h->h_desc = h->d_desc = h->zs = nullptr;
+    h->desc_ready = nullptr;
+}
+
+int setup_instance(fracsolve_ctx *h, Inst &in)
+{
+    const fracsolve_problem &p = in.p;
+    in.regime = (p.gamma < 1.0) ? 0 : 1;
+    in.M = p.M;
+    in.N = p.N;
+    in.Np = std::max<int64_t>(next_pow2(p.N), h->L);
+    in.tau = p.T / (double)p.N;
+    in.h = (p.x1 - p.x0) / (double)(p.M + 1);
+    in.e = 1.0 / (in.h * in.h);
+    in.pexp = (in.regime == 0) ? 1.0 - p.gamma : 2.0 - p.gamma;
+    double garg = (in.regime == 0) ? 2.0 - p.gamma : 3.0 - p.gamma;
+    in.coef = std::pow(in.tau, -p.gamma) / std::tgamma(garg);
+    in.dcoef = in.coef * (-std::log(in.tau) + digamma_host(garg));
+    in.lc = leaf_config(in.M);
+    if (in.lc.pt == 16 && h->L > 8)
+        return fail(h, FRACSOLVE_E_ARG, "leaf size %d is not available for M = %lld (use 4 or 8)", h->L,
+                    (long long)in.M);
+
+    // weights: length Np plus slack for the dense kernel's window reads
+    const int64_t WL = in.Np + 2048;
+    int rc;
+    if ((rc = dalloc(h, &in.b, WL)) || (rc = dalloc(h, &in.a, WL)) || (rc = dalloc(h, &in.rho, WL)) ||
+        (rc = dalloc(h, &in.psi, WL)) || (rc = dalloc(h, &in.da, WL)) || (rc = dalloc(h, &in.drho, WL)) ||
+        (rc = dalloc(h, &in.dpsi, WL)))
+        return rc;
+    for (double *q : {in.b, in.a, in.rho, in.psi, in.da, in.drho, in.dpsi})
+        HIPCHK(h, launch_zero(h->st, q, sizeof(double) * (size_t)WL));
+    HIPCHK(h, launch_weights(h->st, in.regime, in.pexp, in.coef, in.dcoef, in.tau, in.Np, in.b, in.a, in.rho,
+                             in.psi, in.da, in.drho, in.dpsi));
+
+    // factor table of a_0 I + K
+    if ((rc = dalloc(h, &in.fac, leaf_table_doubles(in.lc)))) return rc;
+    HIPCHK(h, launch_leaf_factor(h->st, in.lc, in.M, in.coef, in.e, in.fac));
+
+    // spectra of a and a' for every level s in [L, Np/2] (all levels, so that
+    // the crossover can be changed and the apply can use the FFT route)
+    int nlev = ilog2i(in.Np) + 1;
+    in.spec_off.assign(nlev, -1);
+    int64_t total = 0;
+    for (int64_t s = h->L; s < in.Np; s *= 2) {
+        in.spec_off[ilog2i(s)] = total;
+        total += 2 * s;
+    }
+    if ((rc = dalloc(h, &in.spec64, total)) || (rc = dalloc(h, &in.dspec64, total)) ||
+        (rc = dalloc(h, &in.spec32, total)))
+        return rc;
+    cplx<double> *scr = nullptr;
+    if ((rc = dalloc(h, &scr, 2 * in.Np))) return rc;
+    for (int64_t s = h->L; s < in.Np; s *= 2) {
+        int64_t off = in.spec_off[ilog2i(s)];
+        HIPCHK(h, launch_spectrum(h->st, in.a, (int)s, in.spec64 + off, in.spec32 + off, h->tw64, h->nmax, scr));
+        HIPCHK(h, launch_spectrum(h->st, in.da, (int)s, in.dspec64 + off, nullptr, h->tw64, h->nmax, scr));
+    }
+    return FRACSOLVE_OK;
+}
+
+int check_fields(fracsolve_ctx *h, const void *const *arr, const char *name, bool required)
+{
+    if (!arr) {
+        if (required) return fail(h, FRACSOLVE_E_ARG, "%s is NULL", name);
+        return FRACSOLVE_OK;
+    }
+    if (required)
+        for (size_t k = 0; k < h->inst.size(); ++k)
+            if (!arr[k]) return fail(h, FRACSOLVE_E_ARG, "%s[%zu] is NULL", name, k);
+    return FRACSOLVE_OK;
+}
+
+const double *opt_ptr(const double *const *arr, size_t k) { return arr ? arr[k] : nullptr; }
+
+// Refinement and solve driver for all instances.
+int solve_all(fracsolve_ctx *h, const double *const *f, const double *const *u0, const double *const *phi,
+              double *const *u)
+{
+    const size_t cnt = h->inst.size();
+    const int prec = h->opts.precision;
+    std::vector<int> sel(cnt);
+    for (size_t k = 0; k < cnt; ++k) sel[k] = (int)k;
+    int rc;
+    // right-hand sides R = F - rho u0 + psi phi, written into u
+    for (size_t k = 0; k < cnt; ++k) {
+        Inst &in = h->inst[k];
+        const double *ph = (in.regime == 1) ? opt_ptr(phi, k) : nullptr;
+        HIPCHK(h, launch_rhs(h->st, f[k], opt_ptr(u0, k), ph, in.rho, in.psi, u[k], in.M, in.N));
+        h->kernels++;
+    }
+    if (prec == FRACSOLVE_FP64) {
+        std::vector<Field> fld(cnt);
+        for (size_t k = 0; k < cnt; ++k) fld[k] = {u[k], nullptr, nullptr};
+        return dc_solve(h, sel, fld, FRACSOLVE_FP64);
+    }
+    // mixed: float32 products, float64 leaves; then refinement steps
+    std::vector<Field> fld(cnt);
+    for (size_t k = 0; k < cnt; ++k) {
+        Inst &in = h->inst[k];
+        int64_t n = in.M * in.N;
+        if ((rc = ensuref(h, &in.hist32, n)) || (rc = ensuref(h, &in.x32, n))) return rc;
+        if (h->opts.refine_steps > 0) {
+            if ((rc = ensure(h, &in.R, n)) || (rc = ensure(h, &in.W, n)) || (rc = ensure(h, &in.V, n))) return rc;
+            HIPCHK(h, hipMemcpyAsync(in.R, u[k], sizeof(double) * n, hipMemcpyDeviceToDevice, h->st));
+        }
+        fld[k] = {u[k], in.hist32, in.x32};
+    }
+    if ((rc = dc_solve(h, sel, fld, FRACSOLVE_FP32))) return rc;
+    for (int step = 0; step < h->opts.refine_steps; ++step) {
+        // W = R - A U ; solve A D = W (mixed) ; U += D
+        for (size_t k = 0; k < cnt; ++k) {
+            Inst &in = h->inst[k];
+            if ((rc = apply_op(h, (int)k, u[k], in.V, false))) return rc;
+            HIPCHK(h, launch_sub(h->st, in.W, in.R, in.V, in.M * in.N));
+            h->kernels++;
+            fld[k] = {in.W, in.hist32, in.x32};
+        }
+        if (h->timing) {
+            Inst &in0 = h->inst[0];
+            HIPCHK(h, launch_absmax_partial(h->st, in0.W, in0.M * in0.N, h->partial, kRedBlocks));
+            if ((rc = finish_max(h, kRedBlocks, &h->stats.residual_norm))) return rc;
+        }
+        if ((rc = dc_solve(h, sel, fld, FRACSOLVE_FP32))) return rc;
+        for (size_t k = 0; k < cnt; ++k) {
+            Inst &in = h->inst[k];
+            HIPCHK(h, launch_axpy(h->st, u[k], in.W, 1.0, in.M * in.N));
+            h->kernels++;
+        }
+    }
+    return FRACSOLVE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int fracsolve_create(const fracsolve_problem *probs, int32_t count, const fracsolve_options *opts, fracsolve_t *out)
+{
+    if (!out) return fail(nullptr, FRACSOLVE_E_ARG, "out is NULL");
+    *out = nullptr;
+    if (!probs) return fail(nullptr, FRACSOLVE_E_ARG, "probs is NULL");
+    if (count < 1) return fail(nullptr, FRACSOLVE_E_ARG, "count must be >= 1, got %d", (int)count);
+    for (int k = 0; k < count; ++k) {
+        int rc = validate_problem(probs[k], k);
+        if (rc) return rc;
+    }
+    fracsolve_options o{};
+    if (opts) o = *opts;
+    if (o.precision < FRACSOLVE_FP64 || o.precision > FRACSOLVE_BF16X3)
+        return fail(nullptr, FRACSOLVE_E_ARG, "unknown precision %d", (int)o.precision);
+    if (o.refine_steps < 0 || o.refine_steps > 8)
+        return fail(nullptr, FRACSOLVE_E_ARG, "refine_steps must lie in [0, 8], got %d", (int)o.refine_steps);
+    if (o.leaf != 0 && o.leaf != 4 && o.leaf != 8 && o.leaf != 16)
+        return fail(nullptr, FRACSOLVE_E_ARG, "leaf must be 0, 4, 8 or 16, got %d", (int)o.leaf);
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) {
+        hipGetLastError();
+        return fail(nullptr, FRACSOLVE_E_DEVICE, "no HIP device available");
+    }
+    fracsolve_ctx *h = new fracsolve_ctx();
+    h->opts = o;
+    h->st = (hipStream_t)o.stream;
+    if (hipGetDevice(&h->device) != hipSuccess) {
+        delete h;
+        return fail(nullptr, FRACSOLVE_E_DEVICE, "hipGetDevice failed");
+    }
+    h->L = o.leaf ? o.leaf : 8;
+    // dense products are limited to s <= 1024 (k_gemm.hip)
+    h->crossover = (o.crossover > 0) ? std::min(o.crossover, 1024) : (o.crossover < 0 ? 0 : 64);
+    int64_t npmax = 0;
+    for (int k = 0; k < count; ++k) npmax = std::max(npmax, std::max<int64_t>(next_pow2(probs[k].N), h->L));
+    h->nmax = std::max<int64_t>(npmax, 16384);
+    int rc = FRACSOLVE_OK;
+    if (hipEventCreateWithFlags(&h->desc_ready, hipEventDisableTiming) != hipSuccess) rc = FRACSOLVE_E_DEVICE;
+    if (!rc) rc = dalloc(h, &h->tw64, h->nmax);
+    if (!rc) rc = dalloc(h, &h->tw32, h->nmax);
+    if (!rc) rc = dalloc(h, &h->partial, kRedBlocks);
+    if (!rc && launch_twiddles(h->st, h->nmax, h->tw64, h->tw32) != hipSuccess)
+        rc = fail(h, FRACSOLVE_E_DEVICE, "twiddle kernel launch failed");
+    h->inst.resize(count);
+    for (int k = 0; k < count && !rc; ++k) {
+        h->inst[k].p = probs[k];
+        rc = setup_instance(h, h->inst[k]);
+    }
+    // multi-pass scratch: only when some FFT level exceeds the single-pass size
+    if (!rc) {
+        bool need = false;
+        for (auto &in : h->inst)
+            if (in.Np > fft_max_single_pass(false)) need = true;
+        if (need) {
+            h->zs_bytes = (size_t)256 << 20;
+            if (hipMalloc(&h->zs, h->zs_bytes) != hipSuccess) {
+                hipGetLastError();
+                rc = fail(h, FRACSOLVE_E_NOMEM, "multi-pass scratch allocation failed");
+            }
+        }
+    }
+    if (!rc) {
+        hipError_t e = hipStreamSynchronize(h->st);
+        if (e != hipSuccess) rc = fail(h, FRACSOLVE_E_DEVICE, "setup failed: %s", hipGetErrorString(e));
+    }
+    if (rc) {
+        g_create_error = h->err.empty() ? g_create_error : h->err;
+        free_all(h);
+        delete h;
+        return rc;
+    }
+    h->stats.leaf = h->L;
+    h->stats.crossover = h->crossover;
+    h->stats.levels = ilog2i(h->inst[0].Np / h->L);
+    *out = h;
+    return FRACSOLVE_OK;
+}
+
+int fracsolve_weights(fracsolve_t h, int32_t inst, double *b, double *a, double *rho, double *psi, double *da,
+                      double *drho, double *dpsi)
+{
+    if (!h) return fail(nullptr, FRACSOLVE_E_ARG, "handle is NULL");
+    if (inst < 0 || inst >= (int32_t)h->inst.size())
+        return fail(h, FRACSOLVE_E_ARG, "instance %d out of range [0, %zu)", (int)inst, h->inst.size());
+    Inst &in = h->inst[inst];
+    size_t bytes = sizeof(double) * (size_t)in.N;
+    std::pair<double *, double *> pr[] = {{b, in.b},   {a, in.a},   {rho, in.rho}, {psi, in.psi},
+                                          {da, in.da}, {drho, in.drho}, {dpsi, in.dpsi}};
+    for (auto &x : pr)
+        if (x.first) HIPCHK(h, hipMemcpyAsync(x.first, x.second, bytes, hipMemcpyDeviceToHost, h->st));
+    HIPCHK(h, hipStreamSynchronize(h->st));
+    return FRACSOLVE_OK;
+}
+
+static int timed_begin(fracsolve_ctx *h, hipEvent_t *ev)
+{
+    h->kernels = 0;
+    h->recs.clear();
+    h->kstats.clear();
+    if (!h->timing) return FRACSOLVE_OK;
+    HIPCHK(h, hipEventCreate(&ev[0]));
+    HIPCHK(h, hipEventCreate(&ev[1]));
+    HIPCHK(h, hipEventRecord(ev[0], h->st));
+    return FRACSOLVE_OK;
+}
+
+static int timed_end(fracsolve_ctx *h, hipEvent_t *ev, int rc)
+{
+    h->stats.kernels = h->kernels;
+    if (!h->timing) return rc;
+    if (!rc) {
+        float ms = 0.0f;
+        if (hipEventRecord(ev[1], h->st) == hipSuccess && hipEventSynchronize(ev[1]) == hipSuccess &&
+            hipEventElapsedTime(&ms, ev[0], ev[1]) == hipSuccess)
+            h->stats.ms_total = ms;
+    }
+    hipEventDestroy(ev[0]);
+    hipEventDestroy(ev[1]);
+    if (!rc && h->timing >= 2) {
+        for (const auto &r : h->recs) {
+            float ms = 0.0f;
+            if (hipEventElapsedTime(&ms, h->evpool[r.ev], h->evpool[r.ev + 1]) != hipSuccess) continue;
+            fracsolve_kernel_stat *ks = nullptr;
+            for (auto &k : h->kstats)
+                if (k.kind == r.kind && k.s == r.s) ks = &k;
+            if (!ks) {
+                h->kstats.push_back({r.kind, r.s, 0, 0, 0.0, 0.0});
+                ks = &h->kstats.back();
+            }
+            ks->launches += 1;
+            ks->tasks += r.ntasks;
+            ks->ms += ms;
+            ks->bytes += r.bytes;
+        }
+    }
+    return rc;
+}
+
+int fracsolve_solve(fracsolve_t h, const double *const *f, const double *const *u0, const double *const *phi,
+                    double *const *u)
+{
+    if (!h) return fail(nullptr, FRACSOLVE_E_ARG, "handle is NULL");
+    int rc;
+    if ((rc = check_fields(h, (const void *const *)f, "f", true))) return rc;
+    if ((rc = check_fields(h, (const void *const *)u, "u", true))) return rc;
+    hipEvent_t ev[2];
+    if ((rc = timed_begin(h, ev))) return rc;
+    rc = solve_all(h, f, u0, phi, u);
+    return timed_end(h, ev, rc);
+}
+
+int fracsolve_apply(fracsolve_t h, const double *const *u, double *const *y)
+{
+    if (!h) return fail(nullptr, FRACSOLVE_E_ARG, "handle is NULL");
+    int rc;
+    if ((rc = check_fields(h, (const void *const *)u, "u", true))) return rc;
+    if ((rc = check_fields(h, (const void *const *)y, "y", true))) return rc;
+    for (size_t k = 0; k < h->inst.size(); ++k)
+        if ((const void *)u[k] == (const void *)y[k]) return fail(h, FRACSOLVE_E_ARG, "u[%zu] and y[%zu] alias", k, k);
+    hipEvent_t ev[2];
+    if ((rc = timed_begin(h, ev))) return rc;
+    for (size_t k = 0; k < h->inst.size() && !rc; ++k) rc = apply_op(h, (int)k, u[k], y[k], false);
+    return timed_end(h, ev, rc);
+}
+
+int fracsolve_adjoint(fracsolve_t h, const double *const *g, const double *const *u, const double *const *u0,
+                      const double *const *phi, double *const *dL_df, double *dL_dgamma)
+{
+    if (!h) return fail(nullptr, FRACSOLVE_E_ARG, "handle is NULL");
+    int rc;
+    if ((rc = check_fields(h, (const void *const *)g, "g", true))) return rc;
+    if ((rc = check_fields(h, (const void *const *)dL_df, "dL_df", true))) return rc;
+    if (dL_dgamma && (rc = check_fields(h, (const void *const *)u, "u", true))) return rc;
+    hipEvent_t ev[2];
+    if ((rc = timed_begin(h, ev))) return rc;
+    const size_t cnt = h->inst.size();
+    std::vector<int> sel(cnt);
+    std::vector<Field> fld(cnt);
+    for (size_t k = 0; k < cnt && !rc; ++k) {
+        Inst &in = h->inst[k];
+        sel[k] = (int)k;
+        if ((rc = ensure(h, &in.W, in.M * in.N))) break;
+        // reversed time: lambda~^m = lambda^{N-1-m} solves the same lower-triangular system
+        if (launch_copy_reverse(h->st, g[k], in.W, in.M, in.N) != hipSuccess) {
+            rc = fail(h, FRACSOLVE_E_DEVICE, "launch failed");
+            break;
+        }
+        fld[k] = {in.W, nullptr, nullptr};
+    }
+    if (!rc) rc = dc_solve(h, sel, fld, FRACSOLVE_FP64);
+    for (size_t k = 0; k < cnt && !rc; ++k) {
+        Inst &in = h->inst[k];
+        if (launch_copy_reverse(h->st, in.W, dL_df[k], in.M, in.N) != hipSuccess)
+            rc = fail(h, FRACSOLVE_E_DEVICE, "launch failed");
+    }
+    if (!rc && dL_dgamma) {
+        for (size_t k = 0; k < cnt && !rc; ++k) {
+            Inst &in = h->inst[k];
+            if ((rc = ensure(h, &in.V, in.M * in.N))) break;
+            // V = (dA/dgamma) U
+            if ((rc = apply_op(h, (int)k, u[k], in.V, true))) break;
+            double t1 = 0.0, t2 = 0.0;
+            HIPCHK(h, launch_dot_partial(h->st, dL_df[k], in.V, in.M * in.N, h->partial, kRedBlocks));
+            if ((rc = finish_sum(h, kRedBlocks, &t1))) break;
+            const double *ph = (in.regime == 1) ? opt_ptr(phi, k) : nullptr;
+            HIPCHK(h, launch_gamma_rhs_terms(h->st, dL_df[k], opt_ptr(u0, k), ph, in.drho, in.dpsi, in.M, in.N,
+                                             h->partial, kRedBlocks));
+            if ((rc = finish_sum(h, kRedBlocks, &t2))) break;
+            dL_dgamma[k] = t2 - t1;
+        }
+    }
+    return timed_end(h, ev, rc);
+}
+
+int fracsolve_set_timing(fracsolve_t h, int32_t on)
+{
+    if (!h) return fail(nullptr, FRACSOLVE_E_ARG, "handle is NULL");
+    h->timing = on;
+    return FRACSOLVE_OK;
+}
+
+int fracsolve_get_stats(fracsolve_t h, fracsolve_stats *out)
+{
+    if (!h || !out) return fail(h, FRACSOLVE_E_ARG, "NULL argument");
+    *out = h->stats;
+    return FRACSOLVE_OK;
+}
+
+int fracsolve_kernel_stats(fracsolve_t h, fracsolve_kernel_stat *out, int32_t cap, int32_t *count)
+{
+    if (!h || !count || (cap > 0 && !out)) return fail(h, FRACSOLVE_E_ARG, "NULL argument");
+    int32_t n = (int32_t)h->kstats.size();
+    for (int32_t k = 0; k < n && k < cap; ++k) out[k] = h->kstats[k];
+    *count = n;
+    return FRACSOLVE_OK;
+}
+
+void fracsolve_destroy(fracsolve_t h)
+{
+    if (!h) return;
+    hipStreamSynchronize(h->st);
+    for (hipEvent_t e : h->evpool) hipEventDestroy(e);
+    h->evpool.clear();
+    free_all(h);
+    delete h;
+}
+
+const char *fracsolve_last_error(fracsolve_t h)
+{
+    if (!h) return g_create_error.c_str();
+    return h->err.c_str();
+}
+
+}  // extern "C"

@@ -1,0 +1,605 @@
+// FFT route for the off-diagonal Toeplitz-block products (section 3.1: a
+// Toeplitz matrix is embedded in a circulant of twice its size, which the
+// DFT diagonalises).  For a level with half-block size s and n = 2s:
+//   z = IDFT_n( H_s . DFT_n(x) ),  H_s = DFT_n(w_0..w_{n-1}),
+// x = the s rows of X zero-padded to n, and Y[ylo + p] += alpha z[s + p]/n
+// for p < s (those outputs see no wrap-around).  Two real columns are packed
+// into one complex column (x = X[:,2c] + i X[:,2c+1]); the kernel is real, so
+// real and imaginary parts of z belong to the two columns.
+//
+// Single pass (n <= 8192 in float64): one workgroup owns CC complex columns
+// and the whole length-n transform in LDS.  n = n1 n2 (n3) is split
+// Cooley-Tukey style, q = q1 n2 n3 + q2 n3 + q3, k = k1 + n1 k2 + n1 n2 k3;
+// each digit transform runs in registers and LDS only transposes between
+// digits.  The first stage reads X straight from HBM and skips the zero half
+// (q1 >= n1/2); the middle digit does DFT -> multiply by H -> inverse DFT in
+// registers; the last stage writes only the outputs q1 >= n1/2 to Y.
+//
+// Multi-pass (n = N1 * n_in, n_in the single-pass size): pass 1 does the
+// N1-point digit from HBM into a column-chunk scratch buffer, pass 2 runs
+// the single-pass machinery over the n_in inner points (with the full
+// spectrum) in place, pass 3 does the inverse N1-point digit into Y.
+#include "common.hpp"
+
+namespace fs {
+
+// ---------------------------------------------------------------- twiddles
+// w[j] = exp(-2 pi i j / nmax), j < nmax, in float64 and float32.
+__global__ void k_twiddles(int64_t nmax, cplx<double> *w64, cplx<float> *w32)
+{
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < nmax; j += (int64_t)gridDim.x * blockDim.x) {
+        double sn, cs;
+        sincospi(-2.0 * (double)j / (double)nmax, &sn, &cs);
+        w64[j] = {cs, sn};
+        if (w32) w32[j] = {(float)cs, (float)sn};
+    }
+}
+
+hipError_t launch_twiddles(hipStream_t st, int64_t nmax, cplx<double> *w64, cplx<float> *w32)
+{
+    int64_t nb = (nmax + 255) / 256;
+    if (nb > 4096) nb = 4096;
+    hipLaunchKernelGGL(k_twiddles, dim3((unsigned)nb), dim3(256), 0, st, nmax, w64, w32);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------ in-register DFTs
+template <int X>
+struct lg2 {
+    static constexpr int v = 1 + lg2<X / 2>::v;
+};
+template <>
+struct lg2<1> {
+    static constexpr int v = 0;
+};
+
+__host__ __device__ constexpr int bitrev(int i, int bits)
+{
+    int r = 0;
+    for (int b = 0; b < bits; ++b) r |= ((i >> b) & 1) << (bits - 1 - b);
+    return r;
+}
+
+// Radix-2 decimation-in-time DFT of length R held in registers; natural
+// order in and out.  Forward uses exp(-2 pi i jk/R), inverse its conjugate
+// (unnormalised).  tw is the exp(-2 pi i j/nmax) table.  HALFZERO: inputs
+// R/2..R-1 are zero and are not read.
+template <int R, bool INV, bool HALFZERO, typename T>
+__device__ __forceinline__ void dft_reg(cplx<T> (&v)[R], const cplx<T> *__restrict__ tw, int64_t nmax)
+{
+    constexpr int B = lg2<R>::v;
+    cplx<T> w[R];
+    if (HALFZERO) {
+        // first butterfly stage pairs w[2m] with w[2m+1] = x[bitrev(2m)+R/2] = 0
+#pragma unroll
+        for (int m = 0; m < R / 2; ++m) {
+            cplx<T> a = v[bitrev(2 * m, B)];
+            w[2 * m] = a;
+            w[2 * m + 1] = a;
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < R; ++i) w[i] = v[bitrev(i, B)];
+#pragma unroll
+        for (int m = 0; m < R / 2; ++m) {
+            cplx<T> a = w[2 * m], b = w[2 * m + 1];
+            w[2 * m] = cadd(a, b);
+            w[2 * m + 1] = csub(a, b);
+        }
+    }
+#pragma unroll
+    for (int len = 4; len <= R; len <<= 1) {
+        const int half = len / 2;
+        const int64_t ts = nmax / len;
+#pragma unroll
+        for (int st = 0; st < R; st += len) {
+#pragma unroll
+            for (int j = 0; j < half; ++j) {
+                cplx<T> a = w[st + j], b = w[st + j + half];
+                if (j == 0) {
+                } else if (4 * j == len) {
+                    // multiply by -i (forward) or +i (inverse)
+                    b = INV ? cplx<T>{-b.y, b.x} : cplx<T>{b.y, -b.x};
+                } else {
+                    cplx<T> t = tw[j * ts];
+                    b = INV ? cmulc(b, t) : cmul(b, t);
+                }
+                w[st + j] = cadd(a, b);
+                w[st + j + half] = csub(a, b);
+            }
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < R; ++i) v[i] = w[i];
+}
+
+template <typename T>
+__device__ __forceinline__ cplx<T> twiddle(const cplx<T> *__restrict__ tw, int64_t idx, bool inv)
+{
+    cplx<T> t = tw[idx];
+    if (inv) t.y = -t.y;
+    return t;
+}
+
+// Loads of the two packed real columns; zero beyond M.
+template <typename T>
+__device__ __forceinline__ cplx<T> load_pair(const T *__restrict__ row, int64_t col, int64_t M)
+{
+    cplx<T> v;
+    v.x = (col < M) ? row[col] : (T)0;
+    v.y = (col + 1 < M) ? row[col + 1] : (T)0;
+    return v;
+}
+
+template <typename T>
+__device__ __forceinline__ void add_pair(T *__restrict__ row, int64_t col, int64_t M, cplx<T> v, T scale)
+{
+    if (col < M) row[col] += scale * v.x;
+    if (col + 1 < M) row[col + 1] += scale * v.y;
+}
+
+// Source/destination of the first and last digit.
+//  UPDATE mode: X rows from global memory (zero upper half), Y rows out.
+//  INNER mode (multi-pass pass 2): complex scratch Z, layout
+//    Z[(k1g * Mc + c) * n + q]   (q contiguous), full input, full output.
+enum { MODE_UPDATE = 0, MODE_INNER = 1 };
+
+// ---------------------------------------------------- two-digit kernel
+// n = N1 N2, q = q1 N2 + q2, k = k1 + N1 k2.
+// LDS layout of element (k1 or q1, q2 or k2, c): k1*(N2*CC+1) + q2*CC + c.
+template <typename T, int N1, int N2, int CC, int MODE>
+__global__ __launch_bounds__(256) void k_fft2(const UpdTask<T> *__restrict__ tasks, const cplx<T> *__restrict__ tw,
+                                              int64_t nmax, cplx<T> *__restrict__ zs, int64_t Mc, int N1g)
+{
+    constexpr int n = N1 * N2;
+    constexpr int RS = N2 * CC + 1;
+    __shared__ cplx<T> sd[N1 * RS];
+    const UpdTask<T> tk = tasks[MODE == MODE_UPDATE ? blockIdx.z : 0];
+    const int64_t M = tk.M;
+    const int t = threadIdx.x;
+    const int64_t cgrp = (int64_t)blockIdx.x * CC;  // first complex column of this workgroup
+    if (MODE == MODE_UPDATE && 2 * cgrp >= M) return;
+    const int64_t tws = nmax / n;
+    // spectrum index: spec[k1g + N1g * k]
+    const int k1g = (MODE == MODE_INNER) ? blockIdx.y : 0;
+    const int sstride = (MODE == MODE_INNER) ? N1g : 1;
+
+    // stage A: digit q1 -> k1 (forward), twiddle, to LDS
+    for (int it = t; it < CC * N2; it += 256) {
+        const int c = it % CC, q2 = it / CC;
+        cplx<T> v[N1];
+        if (MODE == MODE_UPDATE) {
+            const int64_t col = 2 * (cgrp + c);
+            const T *__restrict__ xb = tk.x + tk.xlo * M;
+#pragma unroll
+            for (int q1 = 0; q1 < N1 / 2; ++q1) v[q1] = load_pair(xb + (int64_t)(q1 * N2 + q2) * M, col, M);
+            dft_reg<N1, false, true>(v, tw, nmax);
+        } else {
+            const bool cv = cgrp + c < Mc;
+            const cplx<T> *__restrict__ zb = zs + ((int64_t)k1g * Mc + cgrp + c) * n;
+#pragma unroll
+            for (int q1 = 0; q1 < N1; ++q1) v[q1] = cv ? zb[q1 * N2 + q2] : cplx<T>{0, 0};
+            dft_reg<N1, false, false>(v, tw, nmax);
+        }
+#pragma unroll
+        for (int k1 = 1; k1 < N1; ++k1) v[k1] = cmul(v[k1], twiddle(tw, (int64_t)(q2 * k1) * tws, false));
+#pragma unroll
+        for (int k1 = 0; k1 < N1; ++k1) sd[k1 * RS + q2 * CC + c] = v[k1];
+    }
+    __syncthreads();
+    // stage B: digit q2 -> k2, multiply by the spectrum, back k2 -> q2
+    for (int it = t; it < CC * N1; it += 256) {
+        const int c = it % CC, k1 = it / CC;
+        cplx<T> v[N2];
+#pragma unroll
+        for (int q2 = 0; q2 < N2; ++q2) v[q2] = sd[k1 * RS + q2 * CC + c];
+        dft_reg<N2, false, false>(v, tw, nmax);
+#pragma unroll
+        for (int k2 = 0; k2 < N2; ++k2) v[k2] = cmul(v[k2], tk.spec[k1g + (int64_t)sstride * (k1 + N1 * k2)]);
+        dft_reg<N2, true, false>(v, tw, nmax);
+#pragma unroll
+        for (int q2 = 0; q2 < N2; ++q2) sd[k1 * RS + q2 * CC + c] = v[q2];
+    }
+    __syncthreads();
+    // stage C: conjugate twiddle, digit k1 -> q1 (inverse), out
+    for (int it = t; it < CC * N2; it += 256) {
+        const int c = it % CC, q2 = it / CC;
+        cplx<T> v[N1];
+#pragma unroll
+        for (int k1 = 0; k1 < N1; ++k1) {
+            cplx<T> e = sd[k1 * RS + q2 * CC + c];
+            v[k1] = (k1 == 0) ? e : cmul(e, twiddle(tw, (int64_t)(q2 * k1) * tws, true));
+        }
+        dft_reg<N1, true, false>(v, tw, nmax);
+        if (MODE == MODE_UPDATE) {
+            const int64_t col = 2 * (cgrp + c);
+            const T scale = (T)(tk.alpha / (double)n);
+            T *__restrict__ yb = tk.y + tk.ylo * M;
+#pragma unroll
+            for (int q1 = N1 / 2; q1 < N1; ++q1) {
+                const int p = (q1 - N1 / 2) * N2 + q2;
+                if (p < tk.ny) add_pair(yb + (int64_t)p * M, col, M, v[q1], scale);
+            }
+        } else if (cgrp + c < Mc) {
+            cplx<T> *__restrict__ zb = zs + ((int64_t)k1g * Mc + cgrp + c) * n;
+#pragma unroll
+            for (int q1 = 0; q1 < N1; ++q1) zb[q1 * N2 + q2] = v[q1];
+        }
+    }
+}
+
+// -------------------------------------------------- three-digit kernel
+// n = N1 N2 N3, q = q1 N2 N3 + q2 N3 + q3, k = k1 + N1 k2 + N1 N2 k3.
+// LDS layout of element (a = k1|q1, b = q2|k2, d = q3|k3, c):
+//   (a*N2 + b)*(N3*CC + 1) + d*CC + c.
+template <typename T, int N1, int N2, int N3, int CC, int MODE>
+__global__ __launch_bounds__(256) void k_fft3(const UpdTask<T> *__restrict__ tasks, const cplx<T> *__restrict__ tw,
+                                              int64_t nmax, cplx<T> *__restrict__ zs, int64_t Mc, int N1g)
+{
+    constexpr int n = N1 * N2 * N3;
+    constexpr int RS = N3 * CC + 1;
+    __shared__ cplx<T> sd[N1 * N2 * RS];
+    const UpdTask<T> tk = tasks[MODE == MODE_UPDATE ? blockIdx.z : 0];
+    const int64_t M = tk.M;
+    const int t = threadIdx.x;
+    const int64_t cgrp = (int64_t)blockIdx.x * CC;
+    if (MODE == MODE_UPDATE && 2 * cgrp >= M) return;
+    const int64_t tws = nmax / n;
+    const int k1g = (MODE == MODE_INNER) ? blockIdx.y : 0;
+    const int sstride = (MODE == MODE_INNER) ? N1g : 1;
+    auto at = [&](int a, int b, int d, int c) { return (a * N2 + b) * RS + d * CC + c; };
+
+    // A: q1 -> k1, twiddle by W_n^{(q2 N3 + q3) k1}
+    for (int it = t; it < CC * N2 * N3; it += 256) {
+        const int c = it % CC, r = it / CC, q3 = r % N3, q2 = r / N3;
+        cplx<T> v[N1];
+        if (MODE == MODE_UPDATE) {
+            const int64_t col = 2 * (cgrp + c);
+            const T *__restrict__ xb = tk.x + tk.xlo * M;
+#pragma unroll
+            for (int q1 = 0; q1 < N1 / 2; ++q1) v[q1] = load_pair(xb + (int64_t)(q1 * N2 * N3 + r) * M, col, M);
+            dft_reg<N1, false, true>(v, tw, nmax);
+        } else {
+            const bool cv = cgrp + c < Mc;
+            const cplx<T> *__restrict__ zb = zs + ((int64_t)k1g * Mc + cgrp + c) * n;
+#pragma unroll
+            for (int q1 = 0; q1 < N1; ++q1) v[q1] = cv ? zb[q1 * N2 * N3 + r] : cplx<T>{0, 0};
+            dft_reg<N1, false, false>(v, tw, nmax);
+        }
+#pragma unroll
+        for (int k1 = 1; k1 < N1; ++k1) v[k1] = cmul(v[k1], twiddle(tw, (int64_t)(r * k1) * tws, false));
+#pragma unroll
+        for (int k1 = 0; k1 < N1; ++k1) sd[at(k1, q2, q3, c)] = v[k1];
+    }
+    __syncthreads();
+    // B: q2 -> k2, twiddle by W_{N2 N3}^{q3 k2} = W_n^{q3 k2 N1}
+    for (int it = t; it < CC * N1 * N3; it += 256) {
+        const int c = it % CC, r = it / CC, q3 = r % N3, k1 = r / N3;
+        cplx<T> v[N2];
+#pragma unroll
+        for (int q2 = 0; q2 < N2; ++q2) v[q2] = sd[at(k1, q2, q3, c)];
+        dft_reg<N2, false, false>(v, tw, nmax);
+#pragma unroll
+        for (int k2 = 1; k2 < N2; ++k2) v[k2] = cmul(v[k2], twiddle(tw, (int64_t)(q3 * k2 * N1) * tws, false));
+#pragma unroll
+        for (int k2 = 0; k2 < N2; ++k2) sd[at(k1, k2, q3, c)] = v[k2];
+    }
+    __syncthreads();
+    // C: q3 -> k3, spectrum, k3 -> q3
+    for (int it = t; it < CC * N1 * N2; it += 256) {
+        const int c = it % CC, r = it / CC, k2 = r % N2, k1 = r / N2;
+        cplx<T> v[N3];
+#pragma unroll
+        for (int q3 = 0; q3 < N3; ++q3) v[q3] = sd[at(k1, k2, q3, c)];
+        dft_reg<N3, false, false>(v, tw, nmax);
+#pragma unroll
+        for (int k3 = 0; k3 < N3; ++k3)
+            v[k3] = cmul(v[k3], tk.spec[k1g + (int64_t)sstride * (k1 + N1 * k2 + N1 * N2 * k3)]);
+        dft_reg<N3, true, false>(v, tw, nmax);
+#pragma unroll
+        for (int q3 = 0; q3 < N3; ++q3) sd[at(k1, k2, q3, c)] = v[q3];
+    }
+    __syncthreads();
+    // D: conjugate twiddle, k2 -> q2
+    for (int it = t; it < CC * N1 * N3; it += 256) {
+        const int c = it % CC, r = it / CC, q3 = r % N3, k1 = r / N3;
+        cplx<T> v[N2];
+#pragma unroll
+        for (int k2 = 0; k2 < N2; ++k2) {
+            cplx<T> e = sd[at(k1, k2, q3, c)];
+            v[k2] = (k2 == 0) ? e : cmul(e, twiddle(tw, (int64_t)(q3 * k2 * N1) * tws, true));
+        }
+        dft_reg<N2, true, false>(v, tw, nmax);
+#pragma unroll
+        for (int q2 = 0; q2 < N2; ++q2) sd[at(k1, q2, q3, c)] = v[q2];
+    }
+    __syncthreads();
+    // E: conjugate twiddle, k1 -> q1, out
+    for (int it = t; it < CC * N2 * N3; it += 256) {
+        const int c = it % CC, r = it / CC, q3 = r % N3, q2 = r / N3;
+        cplx<T> v[N1];
+#pragma unroll
+        for (int k1 = 0; k1 < N1; ++k1) {
+            cplx<T> e = sd[at(k1, q2, q3, c)];
+            v[k1] = (k1 == 0) ? e : cmul(e, twiddle(tw, (int64_t)(r * k1) * tws, true));
+        }
+        dft_reg<N1, true, false>(v, tw, nmax);
+        if (MODE == MODE_UPDATE) {
+            const int64_t col = 2 * (cgrp + c);
+            const T scale = (T)(tk.alpha / (double)n);
+            T *__restrict__ yb = tk.y + tk.ylo * M;
+#pragma unroll
+            for (int q1 = N1 / 2; q1 < N1; ++q1) {
+                const int p = (q1 - N1 / 2) * N2 * N3 + r;
+                if (p < tk.ny) add_pair(yb + (int64_t)p * M, col, M, v[q1], scale);
+            }
+        } else if (cgrp + c < Mc) {
+            cplx<T> *__restrict__ zb = zs + ((int64_t)k1g * Mc + cgrp + c) * n;
+#pragma unroll
+            for (int q1 = 0; q1 < N1; ++q1) zb[q1 * N2 * N3 + r] = v[q1];
+        }
+    }
+}
+
+// ------------------------------------------------ multi-pass outer digit
+// Pass 1: for complex column c of the chunk and inner index q2 < nin:
+//   v[k1] = W_n^{q2 k1} sum_{q1 < N1/2} x[q1 nin + q2] W_N1^{q1 k1}
+//   Z[(k1 * Mc + c) * nin + q2] = v[k1]
+// Workgroup: 16 complex columns x 16 inner indices; LDS transposes so that
+// X reads are row-contiguous and Z writes are q2-contiguous.
+template <typename T, int N1>
+__global__ __launch_bounds__(256) void k_mp_pass1(const UpdTask<T> *__restrict__ tasks, const cplx<T> *__restrict__ tw,
+                                                  int64_t nmax, cplx<T> *__restrict__ zs, int64_t c0, int64_t Mc,
+                                                  int nin)
+{
+    __shared__ cplx<T> sb[N1][16][17];
+    const UpdTask<T> tk = tasks[0];
+    const int64_t M = tk.M;
+    const int64_t n = (int64_t)N1 * nin;
+    const int64_t tws = nmax / n;
+    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+    const int64_t cl = (int64_t)blockIdx.x * 16 + tx;  // complex column within chunk
+    const int q2 = blockIdx.y * 16 + ty;
+    cplx<T> v[N1];
+    const int64_t col = 2 * (c0 + cl);
+    const T *__restrict__ xb = tk.x + tk.xlo * M;
+#pragma unroll
+    for (int q1 = 0; q1 < N1 / 2; ++q1)
+        v[q1] = (cl < Mc) ? load_pair(xb + ((int64_t)q1 * nin + q2) * M, col, M) : cplx<T>{0, 0};
+    dft_reg<N1, false, true>(v, tw, nmax);
+#pragma unroll
+    for (int k1 = 0; k1 < N1; ++k1) {
+        cplx<T> e = (k1 == 0) ? v[k1] : cmul(v[k1], twiddle(tw, (int64_t)q2 * k1 * tws, false));
+        sb[k1][tx][ty] = e;
+    }
+    __syncthreads();
+    // write: thread (ty -> column, tx -> q2)
+    const int64_t cw = (int64_t)blockIdx.x * 16 + ty;
+    const int qw = blockIdx.y * 16 + tx;
+    if (cw < Mc) {
+#pragma unroll
+        for (int k1 = 0; k1 < N1; ++k1) zs[((int64_t)k1 * Mc + cw) * nin + qw] = sb[k1][ty][tx];
+    }
+}
+
+// Pass 3: v[k1] = Z[(k1 * Mc + c) * nin + q2] conj(W_n^{q2 k1}); inverse N1-point
+// DFT over k1; outputs q1 >= N1/2 go to Y row (q1 - N1/2) nin + q2.
+template <typename T, int N1>
+__global__ __launch_bounds__(256) void k_mp_pass3(const UpdTask<T> *__restrict__ tasks, const cplx<T> *__restrict__ tw,
+                                                  int64_t nmax, const cplx<T> *__restrict__ zs, int64_t c0,
+                                                  int64_t Mc, int nin)
+{
+    __shared__ cplx<T> sb[N1][16][17];
+    const UpdTask<T> tk = tasks[0];
+    const int64_t M = tk.M;
+    const int64_t n = (int64_t)N1 * nin;
+    const int64_t tws = nmax / n;
+    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+    // read: thread (ty -> column, tx -> q2), q2-contiguous
+    const int64_t cr = (int64_t)blockIdx.x * 16 + ty;
+    const int qr = blockIdx.y * 16 + tx;
+#pragma unroll
+    for (int k1 = 0; k1 < N1; ++k1)
+        sb[k1][ty][tx] = (cr < Mc) ? zs[((int64_t)k1 * Mc + cr) * nin + qr] : cplx<T>{0, 0};
+    __syncthreads();
+    const int64_t cl = (int64_t)blockIdx.x * 16 + tx;
+    const int q2 = blockIdx.y * 16 + ty;
+    cplx<T> v[N1];
+#pragma unroll
+    for (int k1 = 0; k1 < N1; ++k1) {
+        cplx<T> e = sb[k1][tx][ty];
+        v[k1] = (k1 == 0) ? e : cmul(e, twiddle(tw, (int64_t)q2 * k1 * tws, true));
+    }
+    dft_reg<N1, true, false>(v, tw, nmax);
+    if (cl < Mc) {
+        const int64_t col = 2 * (c0 + cl);
+        const T scale = (T)(tk.alpha / (double)n);
+        T *__restrict__ yb = tk.y + tk.ylo * M;
+#pragma unroll
+        for (int q1 = N1 / 2; q1 < N1; ++q1) {
+            const int64_t p = (int64_t)(q1 - N1 / 2) * nin + q2;
+            if (p < tk.ny) add_pair(yb + p * M, col, M, v[q1], scale);
+        }
+    }
+}
+
+// ------------------------------------------------------ spectra (setup)
+// Radix-2 Stockham pass over a global complex buffer of length n:
+//   for j < n/2, k = j mod Ns: a = x[j], b = x[j + n/2] W_{2Ns}^k,
+//   y[(j/Ns)*2Ns + k] = a + b,  y[(j/Ns)*2Ns + k + Ns] = a - b.
+// After log2(n) passes y = DFT_n(x) in natural order.
+__global__ void k_stockham_pass(const cplx<double> *__restrict__ x, cplx<double> *__restrict__ y, int64_t n,
+                                int64_t Ns, const cplx<double> *__restrict__ tw, int64_t nmax)
+{
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n / 2; j += (int64_t)gridDim.x * blockDim.x) {
+        int64_t k = j % Ns;
+        cplx<double> a = x[j], b = x[j + n / 2];
+        if (k) b = cmul(b, tw[k * (nmax / (2 * Ns))]);
+        int64_t o = (j / Ns) * 2 * Ns + k;
+        y[o] = cadd(a, b);
+        y[o + Ns] = csub(a, b);
+    }
+}
+
+__global__ void k_real_to_cplx(const double *__restrict__ w, int64_t n, cplx<double> *__restrict__ out)
+{
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x)
+        out[j] = {w[j], 0.0};
+}
+
+__global__ void k_spec_store(const cplx<double> *__restrict__ in, int64_t n, cplx<double> *__restrict__ s64,
+                             cplx<float> *__restrict__ s32)
+{
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x) {
+        cplx<double> v = in[j];
+        if (s64) s64[j] = v;
+        if (s32) s32[j] = {(float)v.x, (float)v.y};
+    }
+}
+
+// spec = DFT_{2s}(w[0..2s)); scratch holds 2*2s complex entries.
+hipError_t launch_spectrum(hipStream_t st, const double *w, int s, cplx<double> *spec64, cplx<float> *spec32,
+                           const cplx<double> *tw, int64_t nmax, cplx<double> *scratch)
+{
+    const int64_t n = 2 * (int64_t)s;
+    cplx<double> *b0 = scratch, *b1 = scratch + n;
+    unsigned nb = (unsigned)((n + 255) / 256);
+    if (nb > 4096) nb = 4096;
+    hipLaunchKernelGGL(k_real_to_cplx, dim3(nb), dim3(256), 0, st, w, n, b0);
+    cplx<double> *src = b0, *dst = b1;
+    for (int64_t Ns = 1; Ns < n; Ns *= 2) {
+        hipLaunchKernelGGL(k_stockham_pass, dim3(nb), dim3(256), 0, st, src, dst, n, Ns, tw, nmax);
+        cplx<double> *tmp = src;
+        src = dst;
+        dst = tmp;
+    }
+    hipLaunchKernelGGL(k_spec_store, dim3(nb), dim3(256), 0, st, src, n, spec64, spec32);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------ dispatch
+// Single-pass factorisations and complex columns per workgroup.
+template <typename T, int MODE>
+static hipError_t single_pass(hipStream_t st, const UpdTask<T> *d_tasks, int ntasks, int n, int64_t ncols_c,
+                              const cplx<T> *tw, int64_t nmax, cplx<T> *zs, int64_t Mc, int N1g, int nk1)
+{
+    auto grid = [&](int CC) {
+        unsigned gx = (unsigned)((ncols_c + CC - 1) / CC);
+        return (MODE == MODE_UPDATE) ? dim3(gx, 1, (unsigned)ntasks) : dim3(gx, (unsigned)nk1, 1);
+    };
+#define FS_F2(N1_, N2_, CC_)                                                                                     \
+    case N1_ * N2_:                                                                                              \
+        hipLaunchKernelGGL((k_fft2<T, N1_, N2_, CC_, MODE>), grid(CC_), dim3(256), 0, st, d_tasks, tw, nmax, zs, \
+                           Mc, N1g);                                                                             \
+        return hipGetLastError();
+#define FS_F3(N1_, N2_, N3_, CC_)                                                                                 \
+    case N1_ * N2_ * N3_:                                                                                         \
+        hipLaunchKernelGGL((k_fft3<T, N1_, N2_, N3_, CC_, MODE>), grid(CC_), dim3(256), 0, st, d_tasks, tw, nmax, \
+                           zs, Mc, N1g);                                                                          \
+        return hipGetLastError();
+    if constexpr (sizeof(T) == 8) {
+        switch (n) {
+            FS_F2(4, 2, 8)
+            FS_F2(4, 4, 8)
+            FS_F2(8, 4, 8)
+            FS_F2(8, 8, 8)
+            FS_F2(16, 8, 8)
+            FS_F2(16, 16, 8)
+            FS_F2(32, 16, 8)
+            FS_F2(32, 32, 8)
+            FS_F3(16, 16, 8, 4)
+            FS_F3(16, 16, 16, 2)
+            FS_F3(32, 16, 16, 1)
+            default:
+                return hipErrorInvalidValue;
+        }
+    } else {
+        switch (n) {
+            FS_F2(4, 2, 8)
+            FS_F2(4, 4, 8)
+            FS_F2(8, 4, 8)
+            FS_F2(8, 8, 8)
+            FS_F2(16, 8, 8)
+            FS_F2(16, 16, 8)
+            FS_F2(32, 16, 8)
+            FS_F2(32, 32, 8)
+            FS_F3(16, 16, 8, 8)
+            FS_F3(16, 16, 16, 4)
+            FS_F3(32, 16, 16, 2)
+            FS_F3(32, 32, 16, 1)
+            default:
+                return hipErrorInvalidValue;
+        }
+    }
+#undef FS_F2
+#undef FS_F3
+}
+
+int fft_max_single_pass(bool fp32) { return fp32 ? 16384 : 8192; }
+
+template <typename T>
+static hipError_t multipass(hipStream_t st, const UpdTask<T> *d_task, int n, int64_t M, const cplx<T> *tw,
+                            int64_t nmax, cplx<T> *zs, size_t zs_elems)
+{
+    const int nin = fft_max_single_pass(sizeof(T) == 4);
+    const int N1 = n / nin;
+    const int64_t Mc_all = (M + 1) / 2;
+    int64_t chunk = (int64_t)(zs_elems / (size_t)n);
+    if (chunk >= Mc_all) {
+        chunk = Mc_all;
+    } else {
+        chunk = (chunk / 16) * 16;
+        if (chunk < 16) return hipErrorInvalidValue;
+    }
+    for (int64_t c0 = 0; c0 < Mc_all; c0 += chunk) {
+        int64_t Mc = (Mc_all - c0 < chunk) ? Mc_all - c0 : chunk;
+        dim3 g13((unsigned)((Mc + 15) / 16), (unsigned)(nin / 16));
+#define FS_P1(N1_) \
+    case N1_: hipLaunchKernelGGL((k_mp_pass1<T, N1_>), g13, dim3(256), 0, st, d_task, tw, nmax, zs, c0, Mc, nin); break;
+        switch (N1) {
+            FS_P1(2)
+            FS_P1(4)
+            FS_P1(8)
+            FS_P1(16)
+            default:
+                return hipErrorInvalidValue;
+        }
+#undef FS_P1
+        hipError_t e = single_pass<T, MODE_INNER>(st, d_task, 1, nin, Mc, tw, nmax, zs, Mc, N1, N1);
+        if (e != hipSuccess) return e;
+#define FS_P3(N1_) \
+    case N1_: hipLaunchKernelGGL((k_mp_pass3<T, N1_>), g13, dim3(256), 0, st, d_task, tw, nmax, zs, c0, Mc, nin); break;
+        switch (N1) {
+            FS_P3(2)
+            FS_P3(4)
+            FS_P3(8)
+            FS_P3(16)
+            default:
+                return hipErrorInvalidValue;
+        }
+#undef FS_P3
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+// Entry: tasks of one level (all with the same s).  Multi-pass levels take
+// exactly one task and need the scratch buffer zs (zs_elems complex entries).
+template <typename T>
+hipError_t launch_fft_update_ex(hipStream_t st, const UpdTask<T> *d_tasks, int ntasks, int s, int64_t maxM,
+                                const cplx<T> *tw, int64_t nmax, cplx<T> *zs, size_t zs_elems)
+{
+    const int n = 2 * s;
+    if (n <= fft_max_single_pass(sizeof(T) == 4))
+        return single_pass<T, MODE_UPDATE>(st, d_tasks, ntasks, n, (maxM + 1) / 2, tw, nmax, nullptr, 0, 1, 1);
+    if (ntasks != 1) return hipErrorInvalidValue;
+    return multipass<T>(st, d_tasks, n, maxM, tw, nmax, zs, zs_elems);
+}
+
+template hipError_t launch_fft_update_ex<double>(hipStream_t, const UpdTask<double> *, int, int, int64_t,
+                                                const cplx<double> *, int64_t, cplx<double> *, size_t);
+template hipError_t launch_fft_update_ex<float>(hipStream_t, const UpdTask<float> *, int, int, int64_t,
+                                               const cplx<float> *, int64_t, cplx<float> *, size_t);
+
+}  // namespace fs

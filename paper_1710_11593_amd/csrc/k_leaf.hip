@@ -1,0 +1,314 @@
+// Leaf of the time recursion: L consecutive time steps of one instance,
+//   (a_0 I + K) U^n = R^n - (history already accumulated) - sum_{lo<=j<n} a_{n-j} U^j,
+// one workgroup per leaf.  The diagonal block a_0 I + K (eq. e20's matrix A
+// with uniform diagonal 2/h^2 + a_0) is constant, so it is factored once per
+// handle by k_leaf_factor and every step only runs the right-hand-side part:
+//
+//  1. each thread owns PT consecutive rows and eliminates inside its block
+//     (a modified Thomas sweep forward and back) so that every row is
+//     expressed through the block's first and last unknowns;
+//  2. the first/last rows of all blocks form a tridiagonal system of 2*NT
+//     unknowns, solved by parallel cyclic reduction (PCR) across the
+//     workgroup, log2(2 NT) stages through LDS;
+//  3. interior rows are recovered from the two block-end values.
+//
+// The in-leaf history is pushed forward: after U^n is solved each thread
+// subtracts a_{m-n} U^n from the right-hand sides of the later rows m of the
+// leaf, which it keeps in registers.
+//
+// Rows beyond M (padding up to NT*PT) are identity rows decoupled from the
+// real ones.
+#include "common.hpp"
+
+namespace fs {
+
+template <int X>
+struct ilog2 {
+    static constexpr int value = 1 + ilog2<X / 2>::value;
+};
+template <>
+struct ilog2<1> {
+    static constexpr int value = 0;
+};
+
+// Factor-table layout (doubles), for NT threads, PT rows per thread, S stages:
+//   local coefficient c (0:rF 1:aF 2:gB 3:aR 4:cR), row k, thread t at
+//       (c*PT + k)*NT + t
+//   invD0 of thread t at 5*PT*NT + t
+//   PCR coefficient c (0:inv 1:p 2:q) of stage s and reduced row j at
+//       5*PT*NT + NT + (s*3 + c)*(2*NT) + j
+template <int NT, int PT>
+struct LeafLayout {
+    static constexpr int S = ilog2<2 * NT>::value;
+    static constexpr int R2 = 2 * NT;
+    static constexpr size_t local(int c, int k, int t) { return (size_t)(c * PT + k) * NT + t; }
+    static constexpr size_t invd0(int t) { return (size_t)5 * PT * NT + t; }
+    static constexpr size_t pcr_base() { return (size_t)5 * PT * NT + NT; }
+    static constexpr size_t pcr(int s, int c, int j) { return pcr_base() + (size_t)(s * 3 + c) * R2 + j; }
+    static constexpr size_t total() { return pcr_base() + (size_t)3 * S * R2; }
+};
+
+template <int NT, int PT>
+__global__ __launch_bounds__(NT) void k_leaf_factor(int64_t M, double a0, double e, double *__restrict__ fac)
+{
+    using LY = LeafLayout<NT, PT>;
+    constexpr int S = LY::S, R2 = LY::R2;
+    __shared__ double sL[R2], sU[R2];
+    const int t = threadIdx.x;
+    const int64_t i0 = (int64_t)t * PT;
+    auto Aof = [&](int64_t i) { return (i < M && i > 0) ? -e : 0.0; };
+    auto Bof = [&](int64_t i) { return (i < M) ? a0 + 2.0 * e : 1.0; };
+    auto Cof = [&](int64_t i) { return (i < M - 1) ? -e : 0.0; };
+
+    double al[PT], ga[PT], rF[PT], aF[PT], aR[PT], cR[PT];
+    for (int k = 0; k < PT; ++k) {
+        int64_t i = i0 + k;
+        double A = Aof(i), B = Bof(i), C = Cof(i);
+        if (k < 2) {
+            rF[k] = 1.0 / B;
+            aF[k] = 0.0;
+            al[k] = A * rF[k];
+            ga[k] = C * rF[k];
+        } else {
+            double den = B - A * ga[k - 1];
+            rF[k] = 1.0 / den;
+            aF[k] = A * rF[k];
+            al[k] = -A * al[k - 1] * rF[k];
+            ga[k] = C * rF[k];
+        }
+        aR[k] = 0.0;
+        cR[k] = 0.0;
+    }
+    double Lf, Uf, invD0 = 1.0;
+    if (PT == 2) {
+        Lf = al[0];
+        Uf = ga[0];
+    } else {
+        aR[PT - 2] = al[PT - 2];
+        cR[PT - 2] = ga[PT - 2];
+        for (int k = PT - 3; k >= 1; --k) {
+            aR[k] = al[k] - ga[k] * aR[k + 1];
+            cR[k] = -ga[k] * cR[k + 1];
+        }
+        double D0 = 1.0 - ga[0] * aR[1];
+        invD0 = 1.0 / D0;
+        Lf = al[0] * invD0;
+        Uf = -ga[0] * cR[1] * invD0;
+    }
+    double Ll = al[PT - 1], Ul = ga[PT - 1];
+    for (int k = 0; k < PT; ++k) {
+        fac[LY::local(0, k, t)] = rF[k];
+        fac[LY::local(1, k, t)] = aF[k];
+        fac[LY::local(2, k, t)] = ga[k];
+        fac[LY::local(3, k, t)] = aR[k];
+        fac[LY::local(4, k, t)] = cR[k];
+    }
+    fac[LY::invd0(t)] = invD0;
+
+    // PCR on the reduced rows j = 2t (first) and 2t+1 (last), normalised to a
+    // unit diagonal: L_j x_{j-d} + x_j + U_j x_{j+d} = D_j.
+    double Lj[2] = {Lf, Ll}, Uj[2] = {Uf, Ul};
+    for (int s = 0; s < S; ++s) {
+        const int d = 1 << s;
+        sL[2 * t] = Lj[0];
+        sL[2 * t + 1] = Lj[1];
+        sU[2 * t] = Uj[0];
+        sU[2 * t + 1] = Uj[1];
+        __syncthreads();
+        double nL[2], nU[2];
+        for (int h = 0; h < 2; ++h) {
+            int j = 2 * t + h;
+            double Lm = (j - d >= 0) ? sL[j - d] : 0.0;
+            double Um = (j - d >= 0) ? sU[j - d] : 0.0;
+            double Lp = (j + d < R2) ? sL[j + d] : 0.0;
+            double Up = (j + d < R2) ? sU[j + d] : 0.0;
+            double den = 1.0 - Lj[h] * Um - Uj[h] * Lp;
+            double inv = 1.0 / den;
+            fac[LY::pcr(s, 0, j)] = inv;
+            fac[LY::pcr(s, 1, j)] = Lj[h] * inv;
+            fac[LY::pcr(s, 2, j)] = Uj[h] * inv;
+            nL[h] = -Lj[h] * Lm * inv;
+            nU[h] = -Uj[h] * Up * inv;
+        }
+        __syncthreads();
+        Lj[0] = nL[0];
+        Lj[1] = nL[1];
+        Uj[0] = nU[0];
+        Uj[1] = nU[1];
+    }
+}
+
+template <int NT, int PT, int L, bool MIXED>
+__global__ __launch_bounds__(NT) void k_leaf(const LeafTask *__restrict__ tasks)
+{
+    using LY = LeafLayout<NT, PT>;
+    constexpr int S = LY::S, R2 = LY::R2;
+    __shared__ double sP[3 * S * R2];
+    __shared__ double sX[2][R2];
+
+    const LeafTask tk = tasks[blockIdx.x];
+    const int t = threadIdx.x;
+    const double *__restrict__ fac = tk.fac;
+    const int64_t M = tk.M;
+    const int64_t c0 = (int64_t)t * PT;
+    const int nrows = tk.nrows;
+    double *__restrict__ u = tk.u + tk.lo * M;
+
+    for (int i = t; i < 3 * S * R2; i += NT) sP[i] = fac[LY::pcr_base() + i];
+
+    double rF[PT], aF[PT], gB[PT], aR[PT], cR[PT];
+#pragma unroll
+    for (int k = 0; k < PT; ++k) {
+        rF[k] = fac[LY::local(0, k, t)];
+        aF[k] = fac[LY::local(1, k, t)];
+        gB[k] = fac[LY::local(2, k, t)];
+        aR[k] = fac[LY::local(3, k, t)];
+        cR[k] = fac[LY::local(4, k, t)];
+    }
+    const double invD0 = fac[LY::invd0(t)];
+    double aw[L];
+#pragma unroll
+    for (int m = 0; m < L; ++m) aw[m] = (m > 0) ? tk.a[m] : 0.0;
+
+    double acc[L][PT];
+#pragma unroll
+    for (int r = 0; r < L; ++r) {
+#pragma unroll
+        for (int k = 0; k < PT; ++k) {
+            int64_t i = c0 + k;
+            double v = 0.0;
+            if (r < nrows && i < M) {
+                v = u[(int64_t)r * M + i];
+                if (MIXED) v += (double)tk.hist[(tk.lo + r) * M + i];
+            }
+            acc[r][k] = v;
+        }
+    }
+    __syncthreads();
+
+    int buf = 0;
+#pragma unroll
+    for (int r = 0; r < L; ++r) {
+        if (r < nrows) {
+            double dp[PT], dpp[PT];
+            dp[0] = rF[0] * acc[r][0];
+            dp[1] = rF[1] * acc[r][1];
+#pragma unroll
+            for (int k = 2; k < PT; ++k) dp[k] = rF[k] * acc[r][k] - aF[k] * dp[k - 1];
+            double Df, Dl;
+            if (PT == 2) {
+                Df = dp[0];
+                Dl = dp[1];
+            } else {
+                dpp[PT - 2] = dp[PT - 2];
+#pragma unroll
+                for (int k = PT - 3; k >= 1; --k) dpp[k] = dp[k] - gB[k] * dpp[k + 1];
+                Df = (dp[0] - gB[0] * dpp[1]) * invD0;
+                Dl = dp[PT - 1];
+            }
+#pragma unroll
+            for (int s = 0; s < S; ++s) {
+                const int d = 1 << s;
+                const int j0 = 2 * t, j1 = 2 * t + 1;
+                sX[buf][j0] = Df;
+                sX[buf][j1] = Dl;
+                __syncthreads();
+                double f_m = (j0 - d >= 0) ? sX[buf][j0 - d] : 0.0;
+                double f_p = (j0 + d < R2) ? sX[buf][j0 + d] : 0.0;
+                double l_m = (j1 - d >= 0) ? sX[buf][j1 - d] : 0.0;
+                double l_p = (j1 + d < R2) ? sX[buf][j1 + d] : 0.0;
+                const double *P = sP + s * 3 * R2;
+                Df = P[j0] * Df - P[R2 + j0] * f_m - P[2 * R2 + j0] * f_p;
+                Dl = P[j1] * Dl - P[R2 + j1] * l_m - P[2 * R2 + j1] * l_p;
+                buf ^= 1;
+            }
+            double x[PT];
+            x[0] = Df;
+            x[PT - 1] = Dl;
+#pragma unroll
+            for (int k = 1; k < PT - 1; ++k) x[k] = dpp[k] - aR[k] * Df - cR[k] * Dl;
+#pragma unroll
+            for (int k = 0; k < PT; ++k) {
+                int64_t i = c0 + k;
+                if (i < M) {
+                    u[(int64_t)r * M + i] = x[k];
+                    if (MIXED) tk.x32[(tk.lo + r) * M + i] = (float)x[k];
+                }
+            }
+#pragma unroll
+            for (int f = r + 1; f < L; ++f) {
+#pragma unroll
+                for (int k = 0; k < PT; ++k) acc[f][k] -= aw[f - r] * x[k];
+            }
+        }
+    }
+}
+
+LeafCfg leaf_config(int64_t M)
+{
+    if (M <= 128) return {64, 2, 7};
+    if (M <= 256) return {128, 2, 8};
+    if (M <= 512) return {256, 2, 9};
+    if (M <= 1024) return {256, 4, 9};
+    if (M <= 2048) return {256, 8, 9};
+    return {256, 16, 9};
+}
+
+size_t leaf_table_doubles(const LeafCfg &c)
+{
+    return (size_t)5 * c.pt * c.nt + c.nt + (size_t)3 * c.S * 2 * c.nt;
+}
+
+hipError_t launch_leaf_factor(hipStream_t st, const LeafCfg &c, int64_t M, double a0, double e, double *fac)
+{
+#define FS_FACT(NT_, PT_)                                                                                  \
+    if (c.nt == NT_ && c.pt == PT_) {                                                                      \
+        hipLaunchKernelGGL((k_leaf_factor<NT_, PT_>), dim3(1), dim3(NT_), 0, st, M, a0, e, fac);           \
+        return hipGetLastError();                                                                          \
+    }
+    FS_FACT(64, 2)
+    FS_FACT(128, 2)
+    FS_FACT(256, 2)
+    FS_FACT(256, 4)
+    FS_FACT(256, 8)
+    FS_FACT(256, 16)
+#undef FS_FACT
+    return hipErrorInvalidValue;
+}
+
+template <int NT, int PT, int L>
+static hipError_t leaf_go(hipStream_t st, bool mixed, const LeafTask *d_tasks, int ntasks)
+{
+    if (mixed)
+        hipLaunchKernelGGL((k_leaf<NT, PT, L, true>), dim3(ntasks), dim3(NT), 0, st, d_tasks);
+    else
+        hipLaunchKernelGGL((k_leaf<NT, PT, L, false>), dim3(ntasks), dim3(NT), 0, st, d_tasks);
+    return hipGetLastError();
+}
+
+hipError_t launch_leaf(hipStream_t st, const LeafCfg &c, int L, const LeafTask *d_tasks, int ntasks, bool mixed)
+{
+#define FS_LEAF(NT_, PT_, L_) \
+    if (c.nt == NT_ && c.pt == PT_ && L == L_) return leaf_go<NT_, PT_, L_>(st, mixed, d_tasks, ntasks);
+    FS_LEAF(64, 2, 4)
+    FS_LEAF(64, 2, 8)
+    FS_LEAF(64, 2, 16)
+    FS_LEAF(128, 2, 4)
+    FS_LEAF(128, 2, 8)
+    FS_LEAF(128, 2, 16)
+    FS_LEAF(256, 2, 4)
+    FS_LEAF(256, 2, 8)
+    FS_LEAF(256, 2, 16)
+    FS_LEAF(256, 4, 4)
+    FS_LEAF(256, 4, 8)
+    FS_LEAF(256, 4, 16)
+    FS_LEAF(256, 8, 4)
+    FS_LEAF(256, 8, 8)
+    FS_LEAF(256, 8, 16)
+    FS_LEAF(256, 16, 4)
+    FS_LEAF(256, 16, 8)
+#undef FS_LEAF
+    return hipErrorInvalidValue;
+}
+
+}  // namespace fs

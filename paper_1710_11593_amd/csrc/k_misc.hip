@@ -1,0 +1,242 @@
+// Streaming kernels of the solver: right-hand-side assembly, the diagonal
+// (within-leaf) part of the operator apply, time reversal, reductions.
+#include "common.hpp"
+
+namespace fs {
+
+static inline unsigned nblocks_for(int64_t n, int bs)
+{
+    int64_t nb = (n + bs - 1) / bs;
+    if (nb > 65535LL * 64) nb = 65535LL * 64;
+    return (unsigned)nb;
+}
+
+// u[n][i] = f[n][i] - rho_n u0[i] + psi_n phi[i]   (right-hand side of step n+1)
+__global__ void k_rhs(const double *__restrict__ f, const double *__restrict__ u0, const double *__restrict__ phi,
+                      const double *__restrict__ rho, const double *__restrict__ psi, double *__restrict__ u,
+                      int64_t M, int64_t total)
+{
+    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        int64_t n = idx / M, i = idx - n * M;
+        double v = f[idx];
+        if (u0) v -= rho[n] * u0[i];
+        if (phi) v += psi[n] * phi[i];
+        u[idx] = v;
+    }
+}
+
+hipError_t launch_rhs(hipStream_t st, const double *f, const double *u0, const double *phi, const double *rho,
+                      const double *psi, double *u, int64_t M, int64_t N)
+{
+    int64_t total = M * N;
+    hipLaunchKernelGGL(k_rhs, dim3(nblocks_for(total, 256)), dim3(256), 0, st, f, u0, phi, rho, psi, u, M, total);
+    return hipGetLastError();
+}
+
+// y[n][i] += rho_n u0[i] - psi_n phi[i]  (moves the initial-data terms back to
+// the left-hand side; used to form residuals against the assembled RHS)
+__global__ void k_rhs_scale(double *__restrict__ y, const double *__restrict__ u0, const double *__restrict__ phi,
+                            const double *__restrict__ rho, const double *__restrict__ psi, int64_t M, int64_t total)
+{
+    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        int64_t n = idx / M, i = idx - n * M;
+        double v = y[idx];
+        if (u0) v += rho[n] * u0[i];
+        if (phi) v -= psi[n] * phi[i];
+        y[idx] = v;
+    }
+}
+
+hipError_t launch_rhs_scale(hipStream_t st, double *y, const double *u0, const double *phi, const double *rho,
+                            const double *psi, int64_t M, int64_t N)
+{
+    int64_t total = M * N;
+    hipLaunchKernelGGL(k_rhs_scale, dim3(nblocks_for(total, 256)), dim3(256), 0, st, y, u0, phi, rho, psi, M, total);
+    return hipGetLastError();
+}
+
+// Diagonal part of the operator apply, leaf by leaf:
+//   y^n = (a_0 I + K) x^n + sum_{lo <= j < n} a_{n-j} x^j,  lo = L floor(n/L),
+// with K = e tridiag(-1,2,-1) (e = 0 drops K: used for the gamma-derivative
+// of the operator, whose K part does not depend on gamma).
+// The off-diagonal blocks between leaves are added by the level products.
+__global__ void k_diag_apply(const double *__restrict__ x, double *__restrict__ y, const double *__restrict__ a,
+                             double e, int64_t M, int64_t N, int L)
+{
+    const double a0 = a[0];
+    int64_t total = M * N;
+    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        int64_t n = idx / M, i = idx - n * M;
+        const double *xn = x + n * M;
+        double left = (i > 0) ? xn[i - 1] : 0.0;
+        double right = (i + 1 < M) ? xn[i + 1] : 0.0;
+        double v = (a0 + 2.0 * e) * xn[i] - e * (left + right);
+        int64_t lo = (n / L) * L;
+        for (int64_t j = lo; j < n; ++j) v += a[n - j] * x[j * M + i];
+        y[idx] = v;
+    }
+}
+
+hipError_t launch_diag_apply(hipStream_t st, const double *x, double *y, const double *a, double e, int64_t M,
+                             int64_t N, int L)
+{
+    int64_t total = M * N;
+    hipLaunchKernelGGL(k_diag_apply, dim3(nblocks_for(total, 256)), dim3(256), 0, st, x, y, a, e, M, N, L);
+    return hipGetLastError();
+}
+
+// dst[N-1-n][i] = src[n][i]
+__global__ void k_copy_reverse(const double *__restrict__ src, double *__restrict__ dst, int64_t M, int64_t N)
+{
+    int64_t total = M * N;
+    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        int64_t n = idx / M, i = idx - n * M;
+        dst[(N - 1 - n) * M + i] = src[idx];
+    }
+}
+
+hipError_t launch_copy_reverse(hipStream_t st, const double *src, double *dst, int64_t M, int64_t N)
+{
+    int64_t total = M * N;
+    hipLaunchKernelGGL(k_copy_reverse, dim3(nblocks_for(total, 256)), dim3(256), 0, st, src, dst, M, N);
+    return hipGetLastError();
+}
+
+__global__ void k_axpy(double *__restrict__ y, const double *__restrict__ x, double alpha, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        y[i] += alpha * x[i];
+}
+
+hipError_t launch_axpy(hipStream_t st, double *y, const double *x, double alpha, int64_t n)
+{
+    hipLaunchKernelGGL(k_axpy, dim3(nblocks_for(n, 256)), dim3(256), 0, st, y, x, alpha, n);
+    return hipGetLastError();
+}
+
+// r = b - y
+__global__ void k_sub(double *__restrict__ r, const double *__restrict__ b, const double *__restrict__ y, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        r[i] = b[i] - y[i];
+}
+
+hipError_t launch_sub(hipStream_t st, double *r, const double *b, const double *y, int64_t n)
+{
+    hipLaunchKernelGGL(k_sub, dim3(nblocks_for(n, 256)), dim3(256), 0, st, r, b, y, n);
+    return hipGetLastError();
+}
+
+__global__ void k_to_f32(const double *__restrict__ x, float *__restrict__ y, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        y[i] = (float)x[i];
+}
+
+hipError_t launch_to_f32(hipStream_t st, const double *x, float *y, int64_t n)
+{
+    hipLaunchKernelGGL(k_to_f32, dim3(nblocks_for(n, 256)), dim3(256), 0, st, x, y, n);
+    return hipGetLastError();
+}
+
+// Zero fill by a kernel (kept out of memset so that captured graphs replay it
+// as an ordinary kernel node).
+__global__ void k_zero(uint32_t *__restrict__ p, int64_t nwords)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nwords; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0u;
+}
+
+hipError_t launch_zero(hipStream_t st, void *p, size_t bytes)
+{
+    int64_t nw = (int64_t)(bytes / 4);
+    if (nw == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_zero, dim3(nblocks_for(nw, 256)), dim3(256), 0, st, (uint32_t *)p, nw);
+    return hipGetLastError();
+}
+
+template <int BS>
+__device__ double block_sum(double v)
+{
+    __shared__ double red[BS];
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int o = BS / 2; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    return red[0];
+}
+
+// partial[b] = sum over the block's grid-stride share of x[i] y[i]
+__global__ void k_dot_partial(const double *__restrict__ x, const double *__restrict__ y, int64_t n,
+                              double *__restrict__ partial)
+{
+    double s = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        s += x[i] * y[i];
+    double t = block_sum<256>(s);
+    if (threadIdx.x == 0) partial[blockIdx.x] = t;
+}
+
+hipError_t launch_dot_partial(hipStream_t st, const double *x, const double *y, int64_t n, double *partial,
+                              int nblocks)
+{
+    hipLaunchKernelGGL(k_dot_partial, dim3(nblocks), dim3(256), 0, st, x, y, n, partial);
+    return hipGetLastError();
+}
+
+// partial[b] = sum_n sum_i lam[n][i] (-rho'_n u0[i] + psi'_n phi[i])
+__global__ void k_gamma_rhs_terms(const double *__restrict__ lam, const double *__restrict__ u0,
+                                  const double *__restrict__ phi, const double *__restrict__ drho,
+                                  const double *__restrict__ dpsi, int64_t M, int64_t total,
+                                  double *__restrict__ partial)
+{
+    double s = 0.0;
+    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        int64_t n = idx / M, i = idx - n * M;
+        double v = 0.0;
+        if (u0) v -= drho[n] * u0[i];
+        if (phi) v += dpsi[n] * phi[i];
+        s += lam[idx] * v;
+    }
+    double t = block_sum<256>(s);
+    if (threadIdx.x == 0) partial[blockIdx.x] = t;
+}
+
+hipError_t launch_gamma_rhs_terms(hipStream_t st, const double *lam, const double *u0, const double *phi,
+                                  const double *drho, const double *dpsi, int64_t M, int64_t N, double *partial,
+                                  int nblocks)
+{
+    hipLaunchKernelGGL(k_gamma_rhs_terms, dim3(nblocks), dim3(256), 0, st, lam, u0, phi, drho, dpsi, M, M * N,
+                       partial);
+    return hipGetLastError();
+}
+
+__global__ void k_absmax_partial(const double *__restrict__ x, int64_t n, double *__restrict__ partial)
+{
+    __shared__ double red[256];
+    double s = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        s = fmax(s, fabs(x[i]));
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + o]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+hipError_t launch_absmax_partial(hipStream_t st, const double *x, int64_t n, double *partial, int nblocks)
+{
+    hipLaunchKernelGGL(k_absmax_partial, dim3(nblocks), dim3(256), 0, st, x, n, partial);
+    return hipGetLastError();
+}
+
+}  // namespace fs
