@@ -93,6 +93,45 @@ static double dbk_dp(int64_t k, double p)
 }
 
 /*
+ * The Toeplitz column is a finite difference of k^p: for m >= 1
+ *   0<gamma<1:  b_m - b_{m-1}             = (m+1)^p - 2 m^p + (m-1)^p
+ *   1<gamma<2:  b_{m-2} - 2 b_{m-1} + b_m = (m+1)^p - 3 m^p + 3 (m-1)^p - (m-2)^p
+ * (section 3: G_k - G_{k-1}, and W_j = M_{j-2} - 2 M_{j-1} + M_j).  Formed as
+ * differences of rounded b_k these lose about m (resp. m^2) in relative
+ * accuracy.  For large m they are summed instead from the binomial expansion
+ * of (1 + j/m)^p, an exact identity: with x = 1/m and C(p,k) the binomial
+ * coefficients,
+ *   sum_j c_j (1 + j x)^p = sum_{k>=0} C(p,k) x^k sum_j c_j j^k,
+ * where the inner sums vanish for k < order of the difference.
+ */
+static double diff_series(int64_t m, double p, int order)
+{
+    /* offsets j and coefficients c_j of the difference operator */
+    const double j2[3] = {1.0, 0.0, -1.0}, c2[3] = {1.0, -2.0, 1.0};
+    const double j3[4] = {1.0, 0.0, -1.0, -2.0}, c3[4] = {1.0, -3.0, 3.0, -1.0};
+    const double *jj = (order == 2) ? j2 : j3, *cc = (order == 2) ? c2 : c3;
+    int nj = (order == 2) ? 3 : 4;
+    double x = 1.0 / (double)m;
+    double binom = 1.0; /* C(p,k) x^k */
+    double sum = 0.0;
+    double jk[4] = {1.0, 1.0, 1.0, 1.0}; /* j^k, updated by one product per k */
+    for (int k = 1; k <= 200; ++k) {
+        binom *= (p - (double)(k - 1)) / (double)k * x;
+        double inner = 0.0;
+        for (int q = 0; q < nj; ++q) {
+            jk[q] *= jj[q];
+            inner += cc[q] * jk[q];
+        }
+        double term = binom * inner;
+        sum += term;
+        /* |inner| <= sum_j |c_j| |j|^k <= 8 * 2^k; stop once that bound on the
+         * remaining terms is negligible (single terms can vanish exactly) */
+        if (k > order && fabs(binom) * 8.0 * pow(2.0, (double)k) <= 1e-18 * fabs(sum)) break;
+    }
+    return pow((double)m, p) * sum;
+}
+
+/*
  * Weights of the discrete system for gamma in (0,1) or (1,2).
  * Arrays have length N; index m holds a_m (m = 0..N-1), index n-1 holds
  * rho_n and psi_n (n = 1..N), index k holds b_k.  Derivative arrays (d/dgamma)
@@ -127,11 +166,13 @@ int oracle_weights(double gamma, double T, int64_t N,
         double am, dam;
         if (reg == 0) {
             /* a_0 = mu G_0, a_m = mu (G_m - G_{m-1}) */
-            double d1 = BB(m) - BB(m - 1), dd1 = DB(m) - DB(m - 1);
+            double d1 = (m >= 4) ? diff_series(m, p, 2) : BB(m) - BB(m - 1);
+            double dd1 = DB(m) - DB(m - 1);
             am = coef * d1;
             dam = dcoef * d1 + coef * dd1;
         } else {
-            double d2 = BB(m - 2) - 2.0 * BB(m - 1) + BB(m);
+            /* a_m = c W_m, W_m = M_{m-2} - 2 M_{m-1} + M_m (W_0 = 1, W_1 = M_1 - 2) */
+            double d2 = (m >= 4) ? diff_series(m, p, 3) : BB(m - 2) - 2.0 * BB(m - 1) + BB(m);
             double dd2 = DB(m - 2) - 2.0 * DB(m - 1) + DB(m);
             am = coef * d2;
             dam = dcoef * d2 + coef * dd2;

@@ -42,6 +42,27 @@ def test_b_against_decimal(orc, gamma):
     assert worst <= 4.0 * EPS, worst
 
 
+@pytest.mark.parametrize("gamma", [0.1, 0.3, 0.5, 0.7, 0.9, 1.1, 1.5, 1.9])
+def test_a_relative_against_decimal(orc, gamma):
+    """a_m to a few ulps RELATIVE to a_m itself, at every sampled m (the
+    differences are formed without cancellation)."""
+    N = 131072
+    w = orc.weights(gamma, 1.0, N)
+    coef = w["coef"]
+    pd = Decimal(repr((1.0 - gamma) if gamma < 1 else (2.0 - gamma)))
+    worst = 0.0
+    for m in SAMPLE_K:
+        if m >= N:
+            continue
+        if gamma < 1:
+            d = dec_b(m, pd) - (dec_b(m - 1, pd) if m >= 1 else Decimal(0))
+        else:
+            d = dec_b(m - 2, pd) - 2 * dec_b(m - 1, pd) + dec_b(m, pd)
+        rel = abs((Decimal(repr(float(w["a"][m]))) - Decimal(repr(coef)) * d) / (Decimal(repr(coef)) * d))
+        worst = max(worst, float(rel))
+    assert worst <= 64 * EPS, worst
+
+
 @pytest.mark.parametrize("gamma", [0.1, 0.5, 0.9, 1.1, 1.5, 1.9])
 def test_a_against_decimal(orc, gamma):
     """a_m = coef * (first or second difference of b), to a few eps of b."""
