@@ -93,6 +93,9 @@ typedef struct {
     int32_t crossover;    /* largest half-block size s done as a dense product;
                              FFT above it.  0 = tuned default, < 0 = FFT at
                              every level                                       */
+    int32_t leaf_solver;  /* tridiagonal solve of a_0 I + K in the leaves:
+                             0 = closed-form inverse by parallel scan (default),
+                             1 = block Thomas + parallel cyclic reduction      */
     void *stream;         /* hipStream_t for all work; NULL = null stream      */
 } fracsolve_options;
 

@@ -188,7 +188,8 @@ int oracle_weights(double gamma, double T, int64_t N,
             s = 0.0;
             ds = 0.0;
         } else {
-            r = coef * (BB(n - 2) - BB(n - 1));
+            /* rho_n = c (M_{n-2} - M_{n-1}) = -c ((n)^p - 2 (n-1)^p + (n-2)^p) */
+            r = (n - 1 >= 4) ? -coef * diff_series(n - 1, p, 2) : coef * (BB(n - 2) - BB(n - 1));
             dr = dcoef * (BB(n - 2) - BB(n - 1)) + coef * (DB(n - 2) - DB(n - 1));
             s = coef * tau * BB(n - 1);
             ds = tau * (dcoef * BB(n - 1) + coef * DB(n - 1));

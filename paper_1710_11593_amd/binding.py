@@ -27,7 +27,7 @@ class Problem(ctypes.Structure):
 
 class Options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("refine_steps", ctypes.c_int32), ("leaf", ctypes.c_int32),
-                ("crossover", ctypes.c_int32), ("stream", ctypes.c_void_p)]
+                ("crossover", ctypes.c_int32), ("leaf_solver", ctypes.c_int32), ("stream", ctypes.c_void_p)]
 
 
 class Stats(ctypes.Structure):
@@ -113,7 +113,7 @@ class Solver:
     """One handle over `len(problems)` instances (see fracsolve_create)."""
 
     def __init__(self, problems: Sequence[dict], precision="fp64", refine_steps=0, leaf=0, crossover=0,
-                 stream=None):
+                 leaf_solver=0, stream=None):
         L = lib()
         self._lib = L
         self.problems = [dict(p) for p in problems]
@@ -127,7 +127,7 @@ class Solver:
             stream = torch.cuda.current_stream().cuda_stream
         self.stream = stream
         opts = Options(PRECISION[precision] if isinstance(precision, str) else int(precision), int(refine_steps),
-                       int(leaf), int(crossover), ctypes.c_void_p(stream))
+                       int(leaf), int(crossover), int(leaf_solver), ctypes.c_void_p(stream))
         h = ctypes.c_void_p()
         rc = L.fracsolve_create(arr, len(problems), ctypes.byref(opts), ctypes.byref(h))
         if rc != FRACSOLVE_OK:

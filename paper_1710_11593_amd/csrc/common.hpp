@@ -49,14 +49,20 @@ template <typename T>
 struct UpdTask {
     const T *x;
     T *y;
-    const double *w;             // Toeplitz column (dense products)
-    const cplx<T> *spec;         // DFT_{2s} of w[0..2s) (FFT products)
+    const double *w;             // Toeplitz column (dense products, corner band)
+    const cplx<T> *spec;         // DFT_{2s} of w with the corner band removed (FFT products)
+    const double *xc;            // float64 views of X and Y for the corner band of
+    double *yc;                  // the FFT route (equal to x, y in float64 mode)
     int64_t M;
     int64_t xlo, ylo;
     int32_t s;
     int32_t ny;
     double alpha;
 };
+
+// Width of the near-corner band of a level product that the FFT route adds
+// exactly instead of through the spectrum (see k_fft.hip).
+__host__ __device__ inline int corner_width(int s) { return s < 32 ? s : 32; }
 
 // Launchers (defined in the .hip files; all enqueue on `st`).
 hipError_t launch_weights(hipStream_t st, int regime, double p, double coef, double dcoef, double tau,
@@ -77,6 +83,12 @@ LeafCfg leaf_config(int64_t M);
 size_t leaf_table_doubles(const LeafCfg &c);
 hipError_t launch_leaf_factor(hipStream_t st, const LeafCfg &c, int64_t M, double a0, double e, double *fac);
 hipError_t launch_leaf(hipStream_t st, const LeafCfg &c, int L, const LeafTask *d_tasks, int ntasks, bool mixed);
+// scan-form leaf (closed-form semiseparable inverse of a_0 I + K)
+LeafCfg scan_config(int64_t M);
+size_t scan_table_doubles(const LeafCfg &c);
+hipError_t launch_scan_factor(hipStream_t st, const LeafCfg &c, int64_t M, double a0, double e, double *tab);
+hipError_t launch_leaf_scan(hipStream_t st, const LeafCfg &c, int L, const LeafTask *d_tasks, int ntasks,
+                            bool mixed);
 
 hipError_t launch_twiddles(hipStream_t st, int64_t nmax, cplx<double> *w64, cplx<float> *w32);
 

@@ -33,6 +33,7 @@ struct Inst {
     double tau = 0, h = 0, e = 0, coef = 0, dcoef = 0, pexp = 0;
     int64_t M = 0, N = 0, Np = 0;
     LeafCfg lc{};
+    bool scan = true;  // leaf solver: closed-form scan (true) or block Thomas + PCR
     double *b = nullptr, *a = nullptr, *rho = nullptr, *psi = nullptr;
     double *da = nullptr, *drho = nullptr, *dpsi = nullptr;
     double *fac = nullptr;
@@ -112,6 +113,15 @@ struct fracsolve_ctx {
     };
     std::vector<Rec> recs;
     std::vector<fracsolve_kernel_stat> kstats;
+    // replay of recorded launch sequences (hipGraph) on an internal stream
+    bool use_graph = false;
+    hipStream_t gst = nullptr;
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    struct GraphEntry {
+        uint64_t key;
+        hipGraphExec_t exec;
+    };
+    std::vector<GraphEntry> graphs;
     int kernels = 0;
     std::vector<double *> allocs;
 };
@@ -175,6 +185,9 @@ int desc_upload(fracsolve_ctx *h, const DescBuilder &db)
     if (h->desc_ready) HIPCHK(h, hipEventSynchronize(h->desc_ready));
     if (need > h->desc_cap) {
         HIPCHK(h, hipStreamSynchronize(h->st));
+        if (h->gst) HIPCHK(h, hipStreamSynchronize(h->gst));
+        for (auto &g : h->graphs) hipGraphExecDestroy(g.exec);
+        h->graphs.clear();
         if (h->h_desc) hipHostFree(h->h_desc);
         if (h->d_desc) hipFree(h->d_desc);
         h->h_desc = h->d_desc = nullptr;
@@ -196,7 +209,7 @@ const T *dptr(fracsolve_ctx *h, size_t off)
 }
 
 // ---- one call = a list of launch records built on the host, then replayed.
-enum OpKind { OP_LEAF, OP_GEMM64, OP_GEMM32, OP_FFT64, OP_FFT32 };
+enum OpKind { OP_LEAF, OP_LEAF_SCAN, OP_GEMM64, OP_GEMM32, OP_FFT64, OP_FFT32 };
 struct Op {
     OpKind kind;
     size_t off;   // descriptor offset
@@ -237,6 +250,9 @@ int run_ops(fracsolve_ctx *h, const std::vector<Op> &ops)
             case OP_LEAF:
                 e = launch_leaf(h->st, op.lc, h->L, dptr<LeafTask>(h, op.off), op.ntasks, op.mixed);
                 break;
+            case OP_LEAF_SCAN:
+                e = launch_leaf_scan(h->st, op.lc, h->L, dptr<LeafTask>(h, op.off), op.ntasks, op.mixed);
+                break;
             case OP_GEMM64:
                 e = launch_gemm_update<double>(h->st, dptr<UpdTask<double>>(h, op.off), op.ntasks, op.s, op.maxM);
                 break;
@@ -258,9 +274,9 @@ int run_ops(fracsolve_ctx *h, const std::vector<Op> &ops)
         h->kernels++;
         if (h->timing >= 2) {
             HIPCHK(h, hipEventRecord(h->evpool[evi + 1], h->st));
-            int kind = op.kind == OP_LEAF ? 0 : op.kind == OP_GEMM64 ? 1 : op.kind == OP_GEMM32 ? 2
-                     : op.kind == OP_FFT64 ? 3 : 4;
-            h->recs.push_back({kind, op.kind == OP_LEAF ? h->L : op.s, op.ntasks, op.bytes, evi});
+            const bool lf = op.kind == OP_LEAF || op.kind == OP_LEAF_SCAN;
+            int kind = lf ? 0 : op.kind == OP_GEMM64 ? 1 : op.kind == OP_GEMM32 ? 2 : op.kind == OP_FFT64 ? 3 : 4;
+            h->recs.push_back({kind, lf ? h->L : op.s, op.ntasks, op.bytes, evi});
         }
     }
     return FRACSOLVE_OK;
@@ -272,6 +288,72 @@ template <typename T>
 double upd_bytes(const UpdTask<T> &t, double elem)
 {
     return ((double)t.s + 2.0 * (double)t.ny) * (double)t.M * elem;
+}
+
+// Launch-sequence signature: equal signatures replay the same recorded graph
+// (kernel arguments point into the descriptor buffer, whose contents are
+// re-uploaded before every replay).
+uint64_t ops_key(const std::vector<Op> &ops, const void *d_desc)
+{
+    uint64_t hsh = 1469598103934665603ULL ^ (uint64_t)(uintptr_t)d_desc;
+    auto mix = [&](uint64_t v) {
+        hsh ^= v;
+        hsh *= 1099511628211ULL;
+    };
+    for (const Op &op : ops) {
+        mix((uint64_t)op.kind);
+        mix((uint64_t)op.off);
+        mix((uint64_t)op.ntasks);
+        mix((uint64_t)op.s);
+        mix((uint64_t)op.maxM);
+        mix((uint64_t)(op.lc.nt * 100 + op.lc.pt));
+        mix((uint64_t)op.mixed);
+    }
+    mix((uint64_t)ops.size());
+    return hsh;
+}
+
+// Run a launch sequence through a cached graph on the internal stream,
+// ordered after and before the caller's stream by events.
+int run_ops_graph(fracsolve_ctx *h, const std::vector<Op> &ops)
+{
+    uint64_t key = ops_key(ops, h->d_desc);
+    hipGraphExec_t exec = nullptr;
+    for (auto &g : h->graphs)
+        if (g.key == key) exec = g.exec;
+    HIPCHK(h, hipEventRecord(h->ev_in, h->st));
+    HIPCHK(h, hipStreamWaitEvent(h->gst, h->ev_in, 0));
+    if (!exec) {
+        hipStream_t user = h->st;
+        h->st = h->gst;
+        hipGraph_t graph = nullptr;
+        hipError_t e = hipStreamBeginCapture(h->gst, hipStreamCaptureModeThreadLocal);
+        int rc = (e == hipSuccess) ? run_ops(h, ops) : FRACSOLVE_E_DEVICE;
+        hipError_t e2 = hipStreamEndCapture(h->gst, &graph);
+        h->st = user;
+        if (rc) return rc;
+        if (e != hipSuccess || e2 != hipSuccess)
+            return fail(h, FRACSOLVE_E_DEVICE, "graph capture failed: %s",
+                        hipGetErrorString(e != hipSuccess ? e : e2));
+        e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        hipGraphDestroy(graph);
+        if (e != hipSuccess) return fail(h, FRACSOLVE_E_DEVICE, "graph instantiate failed: %s", hipGetErrorString(e));
+        if (h->graphs.size() >= 16) {
+            hipGraphExecDestroy(h->graphs.front().exec);
+            h->graphs.erase(h->graphs.begin());
+        }
+        h->graphs.push_back({key, exec});
+    }
+    HIPCHK(h, hipGraphLaunch(exec, h->gst));
+    HIPCHK(h, hipEventRecord(h->ev_out, h->gst));
+    HIPCHK(h, hipStreamWaitEvent(h->st, h->ev_out, 0));
+    return FRACSOLVE_OK;
+}
+
+int run_ops_any(fracsolve_ctx *h, const std::vector<Op> &ops)
+{
+    if (h->use_graph && h->timing < 2) return run_ops_graph(h, ops);
+    return run_ops(h, ops);
 }
 
 // Field views of one recursive solve.
@@ -306,7 +388,7 @@ void build_solve(fracsolve_ctx *h, const std::vector<int> &sel, const std::vecto
             t.M = in.M;
             t.lo = lo;
             t.nrows = (int)std::min<int64_t>(L, in.N - lo);
-            lt.push_back({in.lc.nt * 100 + in.lc.pt, t});
+            lt.push_back({(in.scan ? 1000000 : 0) + in.lc.nt * 100 + in.lc.pt, t});
         }
         std::sort(lt.begin(), lt.end(), [](const auto &x, const auto &y) { return x.first < y.first; });
         for (size_t b = 0; b < lt.size();) {
@@ -315,9 +397,10 @@ void build_solve(fracsolve_ctx *h, const std::vector<int> &sel, const std::vecto
             std::vector<LeafTask> v;
             for (size_t j = b; j < e; ++j) v.push_back(lt[j].second);
             size_t off = db.add(v.data(), v.size() * sizeof(LeafTask));
-            LeafCfg lc{lt[b].first / 100, lt[b].first % 100, 0};
+            const int key = lt[b].first % 1000000;
+            LeafCfg lc{key / 100, key % 100, 0};
             lc.S = ilog2i(2 * lc.nt);
-            Op op{OP_LEAF, off, (int)v.size(), 0, 0, lc, mixed};
+            Op op{lt[b].first >= 1000000 ? OP_LEAF_SCAN : OP_LEAF, off, (int)v.size(), 0, 0, lc, mixed};
             for (auto &t : v) op.bytes += (double)t.nrows * (double)t.M * (mixed ? 24.0 : 16.0);
             ops.push_back(op);
             b = e;
@@ -327,21 +410,26 @@ void build_solve(fracsolve_ctx *h, const std::vector<int> &sel, const std::vecto
         int64_t kk = k + 1;
         int64_t s = (int64_t)L * (kk & -kk);
         int64_t mid = kk * L, lo = mid - s;
+        // Dense levels carry the largest weights and stay float64 in every
+        // mode; FFT levels use float32 products in the mixed modes (their
+        // near-corner band is added in float64 through xc/yc).
+        const bool fft = s > h->crossover;
+        const bool f32 = mixed && fft;
         std::vector<UpdTask<double>> t64;
         std::vector<UpdTask<float>> t32;
         int64_t maxM = 0;
-        std::vector<int> users;
         for (size_t q = 0; q < sel.size(); ++q) {
             const Inst &in = h->inst[sel[q]];
             if (mid >= in.N) continue;
-            int lev = ilog2i(s);
-            bool fft = s > h->crossover;
-            if (!mixed) {
+            const int lev = ilog2i(s);
+            if (!f32) {
                 UpdTask<double> t{};
                 t.x = fld[q].u;
                 t.y = fld[q].u;
                 t.w = in.a;
                 t.spec = fft ? in.spec64 + in.spec_off[lev] : nullptr;
+                t.xc = fld[q].u;
+                t.yc = fld[q].u;
                 t.M = in.M;
                 t.xlo = lo;
                 t.ylo = mid;
@@ -354,7 +442,9 @@ void build_solve(fracsolve_ctx *h, const std::vector<int> &sel, const std::vecto
                 t.x = fld[q].x32;
                 t.y = fld[q].hist32;
                 t.w = in.a;
-                t.spec = fft ? in.spec32 + in.spec_off[lev] : nullptr;
+                t.spec = in.spec32 + in.spec_off[lev];
+                t.xc = fld[q].u;
+                t.yc = fld[q].u;
                 t.M = in.M;
                 t.xlo = lo;
                 t.ylo = mid;
@@ -365,9 +455,8 @@ void build_solve(fracsolve_ctx *h, const std::vector<int> &sel, const std::vecto
             }
             maxM = std::max(maxM, in.M);
         }
-        bool fft = s > h->crossover;
-        bool multipass = 2 * s > fft_max_single_pass(mixed);
-        if (!mixed && !t64.empty()) {
+        const bool multipass = 2 * s > fft_max_single_pass(f32);
+        if (!t64.empty()) {
             if (fft && multipass) {
                 for (auto &t : t64) {
                     Op op{OP_FFT64, db.add(&t, sizeof t), 1, (int)s, t.M, {}, false};
@@ -381,8 +470,8 @@ void build_solve(fracsolve_ctx *h, const std::vector<int> &sel, const std::vecto
                 ops.push_back(op);
             }
         }
-        if (mixed && !t32.empty()) {
-            if (fft && multipass) {
+        if (!t32.empty()) {
+            if (multipass) {
                 for (auto &t : t32) {
                     Op op{OP_FFT32, db.add(&t, sizeof t), 1, (int)s, t.M, {}, true};
                     op.bytes = upd_bytes(t, 4);
@@ -390,7 +479,7 @@ void build_solve(fracsolve_ctx *h, const std::vector<int> &sel, const std::vecto
                 }
             } else {
                 size_t off = db.add(t32.data(), t32.size() * sizeof(t32[0]));
-                Op op{fft ? OP_FFT32 : OP_GEMM32, off, (int)t32.size(), (int)s, maxM, {}, true};
+                Op op{OP_FFT32, off, (int)t32.size(), (int)s, maxM, {}, true};
                 for (auto &t : t32) op.bytes += upd_bytes(t, 4);
                 ops.push_back(op);
             }
@@ -421,6 +510,8 @@ void build_apply_levels(fracsolve_ctx *h, const Inst &in, const double *x, doubl
             t.s = (int)s;
             t.ny = (int)std::min<int64_t>(s, in.N - (lo + s));
             t.alpha = 1.0;
+            t.xc = x;
+            t.yc = y;
             tv.push_back(t);
         }
         if (tv.empty()) continue;
@@ -465,7 +556,7 @@ int dc_solve(fracsolve_ctx *h, const std::vector<int> &sel, const std::vector<Fi
     build_solve(h, sel, fld, prec, db, ops);
     int rc = desc_upload(h, db);
     if (rc) return rc;
-    return run_ops(h, ops);
+    return run_ops_any(h, ops);
 }
 
 // y = A x in float64 (deriv: y = (dA/dgamma) x, i.e. weights a' and no K).
@@ -480,7 +571,7 @@ int apply_op(fracsolve_ctx *h, int i, const double *x, double *y, bool deriv)
     build_apply_levels(h, in, x, y, deriv, db, ops);
     int rc = desc_upload(h, db);
     if (rc) return rc;
-    return run_ops(h, ops);
+    return run_ops_any(h, ops);
 }
 
 // sum of a device reduction written as per-block partials
@@ -527,6 +618,13 @@ int validate_problem(const fracsolve_problem &p, int k)
 
 void free_all(fracsolve_ctx *h)
 {
+    for (auto &g : h->graphs) hipGraphExecDestroy(g.exec);
+    h->graphs.clear();
+    if (h->gst) hipStreamDestroy(h->gst);
+    if (h->ev_in) hipEventDestroy(h->ev_in);
+    if (h->ev_out) hipEventDestroy(h->ev_out);
+    h->gst = nullptr;
+    h->ev_in = h->ev_out = nullptr;
     for (double *p : h->allocs) hipFree(p);
     h->allocs.clear();
     if (h->h_desc) hipHostFree(h->h_desc);
@@ -551,8 +649,9 @@ int setup_instance(fracsolve_ctx *h, Inst &in)
     double garg = (in.regime == 0) ? 2.0 - p.gamma : 3.0 - p.gamma;
     in.coef = std::pow(in.tau, -p.gamma) / std::tgamma(garg);
     in.dcoef = in.coef * (-std::log(in.tau) + digamma_host(garg));
-    in.lc = leaf_config(in.M);
-    if (in.lc.pt == 16 && h->L > 8)
+    in.scan = (h->opts.leaf_solver == 0);
+    in.lc = in.scan ? scan_config(in.M) : leaf_config(in.M);
+    if (h->L > 8 && ((in.scan && in.lc.pt > 4) || (!in.scan && in.lc.pt == 16)))
         return fail(h, FRACSOLVE_E_ARG, "leaf size %d is not available for M = %lld (use 4 or 8)", h->L,
                     (long long)in.M);
 
@@ -569,8 +668,13 @@ int setup_instance(fracsolve_ctx *h, Inst &in)
                              in.psi, in.da, in.drho, in.dpsi));
 
     // factor table of a_0 I + K
-    if ((rc = dalloc(h, &in.fac, leaf_table_doubles(in.lc)))) return rc;
-    HIPCHK(h, launch_leaf_factor(h->st, in.lc, in.M, in.coef, in.e, in.fac));
+    if (in.scan) {
+        if ((rc = dalloc(h, &in.fac, scan_table_doubles(in.lc)))) return rc;
+        HIPCHK(h, launch_scan_factor(h->st, in.lc, in.M, in.coef, in.e, in.fac));
+    } else {
+        if ((rc = dalloc(h, &in.fac, leaf_table_doubles(in.lc)))) return rc;
+        HIPCHK(h, launch_leaf_factor(h->st, in.lc, in.M, in.coef, in.e, in.fac));
+    }
 
     // spectra of a and a' for every level s in [L, Np/2] (all levels, so that
     // the crossover can be changed and the apply can use the FFT route)
@@ -686,6 +790,8 @@ int fracsolve_create(const fracsolve_problem *probs, int32_t count, const fracso
         return fail(nullptr, FRACSOLVE_E_ARG, "unknown precision %d", (int)o.precision);
     if (o.refine_steps < 0 || o.refine_steps > 8)
         return fail(nullptr, FRACSOLVE_E_ARG, "refine_steps must lie in [0, 8], got %d", (int)o.refine_steps);
+    if (o.leaf_solver < 0 || o.leaf_solver > 1)
+        return fail(nullptr, FRACSOLVE_E_ARG, "leaf_solver must be 0 or 1, got %d", (int)o.leaf_solver);
     if (o.leaf != 0 && o.leaf != 4 && o.leaf != 8 && o.leaf != 16)
         return fail(nullptr, FRACSOLVE_E_ARG, "leaf must be 0, 4, 8 or 16, got %d", (int)o.leaf);
     int ndev = 0;
@@ -708,6 +814,17 @@ int fracsolve_create(const fracsolve_problem *probs, int32_t count, const fracso
     h->nmax = std::max<int64_t>(npmax, 16384);
     int rc = FRACSOLVE_OK;
     if (hipEventCreateWithFlags(&h->desc_ready, hipEventDisableTiming) != hipSuccess) rc = FRACSOLVE_E_DEVICE;
+    {
+        const char *g = getenv("FRACSOLVE_GRAPH");
+        h->use_graph = g && g[0] == '1';
+    }
+    if (!rc && h->use_graph) {
+        // internal stream at the default priority
+        if (hipStreamCreateWithFlags(&h->gst, hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&h->ev_in, hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&h->ev_out, hipEventDisableTiming) != hipSuccess)
+            rc = fail(h, FRACSOLVE_E_DEVICE, "stream/event creation failed");
+    }
     if (!rc) rc = dalloc(h, &h->tw64, h->nmax);
     if (!rc) rc = dalloc(h, &h->tw32, h->nmax);
     if (!rc) rc = dalloc(h, &h->partial, kRedBlocks);
@@ -911,6 +1028,7 @@ void fracsolve_destroy(fracsolve_t h)
 {
     if (!h) return;
     hipStreamSynchronize(h->st);
+    if (h->gst) hipStreamSynchronize(h->gst);
     for (hipEvent_t e : h->evpool) hipEventDestroy(e);
     h->evpool.clear();
     free_all(h);

@@ -138,6 +138,32 @@ __device__ __forceinline__ void add_pair(T *__restrict__ row, int64_t col, int64
     if (col + 1 < M) row[col + 1] += scale * v.y;
 }
 
+// Near-corner terms of a level product, kept out of the FFT: the entries of
+// T_s at distance d = s + p - q < D0 (only rows p < D0 - 1 have any) carry the
+// largest weights (|a_1| is of the size of a_0), and leaving them in the
+// spectrum would put an error of order eps * |a_1| * |X| * log n on every
+// output.  They are added here exactly:
+//   Y[p] += alpha * sum_{d = p+1}^{D0-1} w_d X[s + p - d].
+// The band is read from the float64 view xc and added to the float64 view
+// yc (in float32 mode the products themselves go to a float32 accumulator,
+// but the band's weights are too large to round to float32).
+template <typename T>
+__device__ __forceinline__ void corner_add(const UpdTask<T> &tk, int p, int64_t col, int64_t M)
+{
+    const int D0 = corner_width(tk.s);
+    double sx = 0.0, sy = 0.0;
+    const double *__restrict__ xb = tk.xc + tk.xlo * M;
+    for (int d = p + 1; d < D0; ++d) {
+        const double *__restrict__ row = xb + (int64_t)(tk.s + p - d) * M;
+        const double wd = tk.w[d];
+        if (col < M) sx += wd * row[col];
+        if (col + 1 < M) sy += wd * row[col + 1];
+    }
+    double *__restrict__ yr = tk.yc + (tk.ylo + p) * M;
+    if (col < M) yr[col] += tk.alpha * sx;
+    if (col + 1 < M) yr[col + 1] += tk.alpha * sy;
+}
+
 // Source/destination of the first and last digit.
 //  UPDATE mode: X rows from global memory (zero upper half), Y rows out.
 //  INNER mode (multi-pass pass 2): complex scratch Z, layout
@@ -218,7 +244,10 @@ __global__ __launch_bounds__(256) void k_fft2(const UpdTask<T> *__restrict__ tas
 #pragma unroll
             for (int q1 = N1 / 2; q1 < N1; ++q1) {
                 const int p = (q1 - N1 / 2) * N2 + q2;
-                if (p < tk.ny) add_pair(yb + (int64_t)p * M, col, M, v[q1], scale);
+                if (p < tk.ny) {
+                    add_pair(yb + (int64_t)p * M, col, M, v[q1], scale);
+                    if (p < corner_width(tk.s) - 1) corner_add(tk, p, col, M);
+                }
             }
         } else if (cgrp + c < Mc) {
             cplx<T> *__restrict__ zb = zs + ((int64_t)k1g * Mc + cgrp + c) * n;
@@ -331,7 +360,10 @@ __global__ __launch_bounds__(256) void k_fft3(const UpdTask<T> *__restrict__ tas
 #pragma unroll
             for (int q1 = N1 / 2; q1 < N1; ++q1) {
                 const int p = (q1 - N1 / 2) * N2 * N3 + r;
-                if (p < tk.ny) add_pair(yb + (int64_t)p * M, col, M, v[q1], scale);
+                if (p < tk.ny) {
+                    add_pair(yb + (int64_t)p * M, col, M, v[q1], scale);
+                    if (p < corner_width(tk.s) - 1) corner_add(tk, p, col, M);
+                }
             }
         } else if (cgrp + c < Mc) {
             cplx<T> *__restrict__ zb = zs + ((int64_t)k1g * Mc + cgrp + c) * n;
@@ -418,7 +450,10 @@ __global__ __launch_bounds__(256) void k_mp_pass3(const UpdTask<T> *__restrict__
 #pragma unroll
         for (int q1 = N1 / 2; q1 < N1; ++q1) {
             const int64_t p = (int64_t)(q1 - N1 / 2) * nin + q2;
-            if (p < tk.ny) add_pair(yb + p * M, col, M, v[q1], scale);
+            if (p < tk.ny) {
+                add_pair(yb + p * M, col, M, v[q1], scale);
+                if (p < corner_width(tk.s) - 1) corner_add(tk, (int)p, col, M);
+            }
         }
     }
 }
@@ -441,10 +476,10 @@ __global__ void k_stockham_pass(const cplx<double> *__restrict__ x, cplx<double>
     }
 }
 
-__global__ void k_real_to_cplx(const double *__restrict__ w, int64_t n, cplx<double> *__restrict__ out)
+__global__ void k_real_to_cplx(const double *__restrict__ w, int64_t n, int64_t d0, cplx<double> *__restrict__ out)
 {
     for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x)
-        out[j] = {w[j], 0.0};
+        out[j] = {j < d0 ? 0.0 : w[j], 0.0};
 }
 
 __global__ void k_spec_store(const cplx<double> *__restrict__ in, int64_t n, cplx<double> *__restrict__ s64,
@@ -457,7 +492,9 @@ __global__ void k_spec_store(const cplx<double> *__restrict__ in, int64_t n, cpl
     }
 }
 
-// spec = DFT_{2s}(w[0..2s)); scratch holds 2*2s complex entries.
+// spec = DFT_{2s}(w'), w'_j = w_j for j >= corner_width(s), 0 below (the
+// near-corner terms are added exactly by the FFT kernels' last stage);
+// scratch holds 2*2s complex entries.
 hipError_t launch_spectrum(hipStream_t st, const double *w, int s, cplx<double> *spec64, cplx<float> *spec32,
                            const cplx<double> *tw, int64_t nmax, cplx<double> *scratch)
 {
@@ -465,7 +502,7 @@ hipError_t launch_spectrum(hipStream_t st, const double *w, int s, cplx<double> 
     cplx<double> *b0 = scratch, *b1 = scratch + n;
     unsigned nb = (unsigned)((n + 255) / 256);
     if (nb > 4096) nb = 4096;
-    hipLaunchKernelGGL(k_real_to_cplx, dim3(nb), dim3(256), 0, st, w, n, b0);
+    hipLaunchKernelGGL(k_real_to_cplx, dim3(nb), dim3(256), 0, st, w, n, (int64_t)corner_width(s), b0);
     cplx<double> *src = b0, *dst = b1;
     for (int64_t Ns = 1; Ns < n; Ns *= 2) {
         hipLaunchKernelGGL(k_stockham_pass, dim3(nb), dim3(256), 0, st, src, dst, n, Ns, tw, nmax);

@@ -35,13 +35,13 @@ __device__ __forceinline__ double wdb(int64_t k, double p)
     return -(log(kd) * wb(k, p) + log1p(1.0 / kd) * pow(kd + 1.0, p));
 }
 
-// (m+1)^p - 2 m^p + (m-1)^p for m >= 16
+// (m+1)^p - 2 m^p + (m-1)^p for m >= 4
 __device__ double second_diff_series(int64_t m, double p)
 {
     double x = 1.0 / (double)m, x2 = x * x;
     double t = 0.5 * p * (p - 1.0) * x2;  // C(p,2) x^2
     double s = t;
-    for (int k = 1; k < 16; ++k) {
+    for (int k = 1; k < 24; ++k) {
         double j = 2.0 * k;
         t *= (p - j) * (p - j - 1.0) / ((j + 1.0) * (j + 2.0)) * x2;
         s += t;
@@ -50,7 +50,7 @@ __device__ double second_diff_series(int64_t m, double p)
     return 2.0 * pow((double)m, p) * s;
 }
 
-// (m+1)^q - 3 m^q + 3 (m-1)^q - (m-2)^q for m >= 32
+// (m+1)^q - 3 m^q + 3 (m-1)^q - (m-2)^q for m >= 8
 __device__ double third_diff_series(int64_t m, double q)
 {
     double x = 1.0 / (double)m;
@@ -58,7 +58,7 @@ __device__ double third_diff_series(int64_t m, double q)
     double s = 0.0;
     double pm = 1.0;  // (-1)^k
     double p2 = 1.0;  // (-2)^k
-    for (int k = 1; k < 40; ++k) {
+    for (int k = 1; k < 64; ++k) {
         u *= (q - (double)(k - 1)) / (double)k * x;
         pm = -pm;
         p2 *= -2.0;
@@ -84,11 +84,11 @@ __global__ void k_weights(int regime, double p, double coef, double dcoef, doubl
     double am, dam;
     if (regime == 0) {
         // b_m - b_{m-1} = (m+1)^p - 2 m^p + (m-1)^p for m >= 1
-        double diff = (m >= 16) ? second_diff_series(m, p) : (b0 - b1);
+        double diff = (m >= 4) ? second_diff_series(m, p) : (b0 - b1);
         am = coef * diff;
         dam = dcoef * diff + coef * (d0 - d1);
     } else {
-        double diff = (m >= 32) ? third_diff_series(m, p) : (b2 - 2.0 * b1 + b0);
+        double diff = (m >= 8) ? third_diff_series(m, p) : (b2 - 2.0 * b1 + b0);
         am = coef * diff;
         dam = dcoef * diff + coef * (d2 - 2.0 * d1 + d0);
     }
@@ -103,8 +103,9 @@ __global__ void k_weights(int regime, double p, double coef, double dcoef, doubl
         s = 0.0;
         ds = 0.0;
     } else {
-        // rho_n = c (b_{n-2} - b_{n-1}) = c (b_{m-1} - b_m), psi_n = c tau b_m
-        r = coef * (b1 - b0);
+        // rho_n = c (b_{n-2} - b_{n-1}) = c (b_{m-1} - b_m) = -c ((m+1)^q - 2 m^q + (m-1)^q),
+        // psi_n = c tau b_m
+        r = (m >= 4) ? -coef * second_diff_series(m, p) : coef * (b1 - b0);
         dr = dcoef * (b1 - b0) + coef * (d1 - d0);
         s = coef * tau * b0;
         ds = tau * (dcoef * b0 + coef * d0);

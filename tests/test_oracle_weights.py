@@ -60,6 +60,11 @@ def test_a_relative_against_decimal(orc, gamma):
             d = dec_b(m - 2, pd) - 2 * dec_b(m - 1, pd) + dec_b(m, pd)
         rel = abs((Decimal(repr(float(w["a"][m]))) - Decimal(repr(coef)) * d) / (Decimal(repr(coef)) * d))
         worst = max(worst, float(rel))
+        if gamma > 1 and m >= 1:
+            # rho_{m+1} = c (M_{m-1} - M_m)
+            dr = dec_b(m - 1, pd) - dec_b(m, pd)
+            relr = abs((Decimal(repr(float(w["rho"][m]))) - Decimal(repr(coef)) * dr) / (Decimal(repr(coef)) * dr))
+            worst = max(worst, float(relr))
     assert worst <= 64 * EPS, worst
 
 
