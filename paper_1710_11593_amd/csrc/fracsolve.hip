@@ -651,7 +651,7 @@ int setup_instance(fracsolve_ctx *h, Inst &in)
     in.dcoef = in.coef * (-std::log(in.tau) + digamma_host(garg));
     in.scan = (h->opts.leaf_solver == 0);
     in.lc = in.scan ? scan_config(in.M) : leaf_config(in.M);
-    if (h->L > 8 && ((in.scan && in.lc.pt > 4) || (!in.scan && in.lc.pt == 16)))
+    if (h->L > 8 && ((in.scan && in.lc.pt > 2) || (!in.scan && in.lc.pt == 16)))
         return fail(h, FRACSOLVE_E_ARG, "leaf size %d is not available for M = %lld (use 4 or 8)", h->L,
                     (long long)in.M);
 

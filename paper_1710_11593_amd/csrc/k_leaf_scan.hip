@@ -80,15 +80,11 @@ __global__ __launch_bounds__(NT) void k_scan_factor(int64_t M, double a0, double
 template <int NT, int PT, int L, bool MIXED>
 __global__ __launch_bounds__(NT) void k_leaf_scan(const LeafTask *__restrict__ tasks)
 {
+    static_assert(PT % 2 == 0, "rows per thread must be even");
     constexpr int S = slog2<NT>::value;
     constexpr int NW = NT / 64;
     constexpr int MP = NT * PT;
-    // sX: row transposes between the coalesced global layout (element
-    // t + NT j of a row per thread) and the thread's PT consecutive rows.
-    // padded: the PT rows of thread t sit at t*(PT+1), so that a thread's
-    // consecutive accesses do not all fall on the same LDS banks
-    constexpr int PS = PT + 1;
-    __shared__ double sX[2][NT * PS];
+    constexpr int UT = PT / 2;  // 16-byte units per thread
     __shared__ double sW[2][2][NW > 1 ? NW : 1];
 
     const LeafTask tk = tasks[blockIdx.x];
@@ -102,20 +98,30 @@ __global__ __launch_bounds__(NT) void k_leaf_scan(const LeafTask *__restrict__ t
     double *__restrict__ u = tk.u + tk.lo * M;
     const float *__restrict__ hist = MIXED ? tk.hist + tk.lo * M : nullptr;
     float *__restrict__ x32 = MIXED ? tk.x32 + tk.lo * M : nullptr;
+    // the thread's PT rows are whole 16-byte units inside the field
+    const bool vec = ((M & 1) == 0) && ((((uintptr_t)tk.u) & 15) == 0) && (c0 + PT <= M);
 
-    // right-hand sides of the leaf's rows, coalesced (issued before any use)
-    double g[L][PT];
+    // right-hand sides of the leaf's rows: the thread's PT consecutive
+    // entries of each row, as 16-byte loads (lanes 32 bytes apart)
+    double acc[L][PT];
 #pragma unroll
     for (int r = 0; r < L; ++r) {
+        const double *row = u + (int64_t)r * M + c0;
+        if (r < nrows && vec) {
 #pragma unroll
-        for (int j = 0; j < PT; ++j) {
-            const int col = t + NT * j;
-            double v = 0.0;
-            if (r < nrows && col < M) {
-                v = u[(int64_t)r * M + col];
-                if (MIXED) v += (double)hist[(int64_t)r * M + col];
+            for (int i = 0; i < UT; ++i) {
+                const double2 v = reinterpret_cast<const double2 *>(row)[i];
+                acc[r][2 * i] = v.x;
+                acc[r][2 * i + 1] = v.y;
             }
-            g[r][j] = v;
+        } else {
+#pragma unroll
+            for (int k = 0; k < PT; ++k) acc[r][k] = (r < nrows && c0 + k < M) ? row[k] : 0.0;
+        }
+        if (MIXED && r < nrows) {
+#pragma unroll
+            for (int k = 0; k < PT; ++k)
+                if (c0 + k < M) acc[r][k] += (double)hist[(int64_t)r * M + c0 + k];
         }
     }
 
@@ -147,30 +153,19 @@ __global__ __launch_bounds__(NT) void k_leaf_scan(const LeafTask *__restrict__ t
 #pragma unroll
     for (int m = 0; m < L; ++m) aw[m] = (m > 0) ? tk.a[m] : 0.0;
 
-    // transpose the right-hand sides into per-thread consecutive rows
-    double acc[L][PT];
-#pragma unroll
-    for (int r = 0; r < L; ++r) {
-#pragma unroll
-        for (int j = 0; j < PT; ++j) {
-            const int col = t + NT * j;
-            sX[r & 1][(col / PT) * PS + col % PT] = g[r][j];
-        }
-        __syncthreads();
-#pragma unroll
-        for (int k = 0; k < PT; ++k) acc[r][k] = sX[r & 1][t * PS + k];
-    }
-
     int par = 0;
-#pragma unroll
-    for (int r = 0; r < L; ++r) {
-        if (r < nrows) {
+    // Rolled step loop: acc[0] holds the current row's right-hand side and
+    // acc[j] the row j steps ahead; after a step every row moves down by one.
+    // The push below therefore always uses a_j for acc[j].
+#pragma unroll 1
+    for (int r = 0; r < nrows; ++r) {
+        {
             // fold the two recurrences over the thread's rows
             double Tf = 0.0, Tb = 0.0;
 #pragma unroll
-            for (int k = 0; k < PT; ++k) Tf = rho * Tf + al[k] * acc[r][k];
+            for (int k = 0; k < PT; ++k) Tf = rho * Tf + al[k] * acc[0][k];
 #pragma unroll
-            for (int k = PT - 1; k >= 0; --k) Tb = rho * (Tb + be[k] * acc[r][k]);
+            for (int k = PT - 1; k >= 0; --k) Tb = rho * (Tb + be[k] * acc[0][k]);
             // Row-local (16 lanes) inclusive scans by DPP shifts:
             //   prefix  R_t = sum_{t' <= t in row} m^(t-t') Tf(t')
             //   suffix  S_t = sum_{t' >= t in row} m^(t'-t) Tb(t')
@@ -197,22 +192,7 @@ __global__ __launch_bounds__(NT) void k_leaf_scan(const LeafTask *__restrict__ t
                     sW[par][0][wv] = W63;
                     sW[par][1][wv] = V0;
                 }
-            }
-            // one barrier per step: wave totals of this step and the solution
-            // row of the previous step become visible
-            __syncthreads();
-            if (r > 0) {
-#pragma unroll
-                for (int j = 0; j < PT; ++j) {
-                    const int col = t + NT * j;
-                    if (col < M) {
-                        const double v = sX[(r - 1) & 1][(col / PT) * PS + col % PT];
-                        u[(int64_t)(r - 1) * M + col] = v;
-                        if (MIXED) x32[(int64_t)(r - 1) * M + col] = (float)v;
-                    }
-                }
-            }
-            if (NW > 1) {
+                __syncthreads();
                 double tf[NW], tb[NW];
 #pragma unroll
                 for (int w = 0; w < NW; ++w) {
@@ -230,12 +210,10 @@ __global__ __launch_bounds__(NT) void k_leaf_scan(const LeafTask *__restrict__ t
             // exclusive carries: prefix up to the row before this thread's
             // rows, suffix from the row after them
             const int rw = lane >> 4;
-            // global prefix at the last lane of the previous 16-lane row
             const double Gf = (rw == 0) ? Cf
                             : (rw == 1) ? W15 + m16 * Cf
                             : (rw == 2) ? W31 + m32 * Cf
                                         : W47 + m48 * Cf;
-            // global suffix at the first lane of the next 16-lane row
             const double Gb = (rw == 3) ? Cb
                             : (rw == 2) ? V48 + m16 * Cb
                             : (rw == 1) ? V32 + m32 * Cb
@@ -247,52 +225,50 @@ __global__ __launch_bounds__(NT) void k_leaf_scan(const LeafTask *__restrict__ t
             double P = cf;
 #pragma unroll
             for (int k = 0; k < PT; ++k) {
-                P = rho * P + al[k] * acc[r][k];
+                P = rho * P + al[k] * acc[0][k];
                 x[k] = be[k] * P;
             }
             double Q = cb;
 #pragma unroll
             for (int k = PT - 1; k >= 0; --k) {
                 x[k] = K0 * (x[k] + al[k] * Q);
-                Q = rho * (Q + be[k] * acc[r][k]);
+                Q = rho * (Q + be[k] * acc[0][k]);
+            }
+            double *row = u + (int64_t)r * M + c0;
+            if (vec) {
+#pragma unroll
+                for (int i = 0; i < UT; ++i)
+                    reinterpret_cast<double2 *>(row)[i] = double2{x[2 * i], x[2 * i + 1]};
+            } else {
+#pragma unroll
+                for (int k = 0; k < PT; ++k)
+                    if (c0 + k < M) row[k] = x[k];
+            }
+            if (MIXED) {
+#pragma unroll
+                for (int k = 0; k < PT; ++k)
+                    if (c0 + k < M) x32[(int64_t)r * M + c0 + k] = (float)x[k];
             }
 #pragma unroll
-            for (int k = 0; k < PT; ++k) sX[r & 1][t * PS + k] = x[k];
+            for (int j = 1; j < L; ++j) {
 #pragma unroll
-            for (int f = r + 1; f < L; ++f) {
-#pragma unroll
-                for (int k = 0; k < PT; ++k) acc[f][k] -= aw[f - r] * x[k];
-            }
-        }
-    }
-    // last solved row
-    __syncthreads();
-    {
-        const int r = nrows - 1;
-#pragma unroll
-        for (int j = 0; j < PT; ++j) {
-            const int col = t + NT * j;
-            if (col < M) {
-                const double v = sX[r & 1][(col / PT) * PS + col % PT];
-                u[(int64_t)r * M + col] = v;
-                if (MIXED) x32[(int64_t)r * M + col] = (float)v;
+                for (int k = 0; k < PT; ++k) acc[j - 1][k] = acc[j][k] - aw[j] * x[k];
             }
         }
     }
 }
 
-// One wave per SIMD at most (<= 256 threads): the leaf's right-hand sides
-// and in-leaf accumulators (L x PT doubles per thread) then fit the unified
-// register file without scratch.
+// Up to 512 threads (two waves per SIMD) with 2, 4 or 8 rows per thread: the
+// leaf's right-hand sides and accumulators (L x PT doubles per thread) stay
+// in registers and each thread's rows are whole 16-byte units.
 LeafCfg scan_config(int64_t M)
 {
-    if (M <= 64) return {64, 1, 6};
     if (M <= 128) return {64, 2, 6};
     if (M <= 256) return {64, 4, 6};
     if (M <= 512) return {128, 4, 7};
     if (M <= 1024) return {256, 4, 8};
-    if (M <= 2048) return {256, 8, 8};
-    return {256, 16, 8};
+    if (M <= 2048) return {512, 4, 9};
+    return {512, 8, 9};
 }
 
 size_t scan_table_doubles(const LeafCfg &c) { return (size_t)SCAN_TAB_ALPHA + 2 * (size_t)c.nt * c.pt; }
@@ -304,13 +280,12 @@ hipError_t launch_scan_factor(hipStream_t st, const LeafCfg &c, int64_t M, doubl
         hipLaunchKernelGGL((k_scan_factor<NT_, PT_>), dim3(1), dim3(NT_), 0, st, M, a0, e, tab);       \
         return hipGetLastError();                                                                      \
     }
-    FS_SF(64, 1)
     FS_SF(64, 2)
     FS_SF(64, 4)
     FS_SF(128, 4)
     FS_SF(256, 4)
-    FS_SF(256, 8)
-    FS_SF(256, 16)
+    FS_SF(512, 4)
+    FS_SF(512, 8)
 #undef FS_SF
     return hipErrorInvalidValue;
 }
@@ -325,6 +300,15 @@ static hipError_t scan_go(hipStream_t st, bool mixed, const LeafTask *d_tasks, i
     return hipGetLastError();
 }
 
+template <int NT, int PT>
+static hipError_t scan_go16(hipStream_t st, bool mixed, const LeafTask *d_tasks, int ntasks)
+{
+    if constexpr (PT <= 2)
+        return scan_go<NT, PT, 16>(st, mixed, d_tasks, ntasks);
+    else
+        return hipErrorInvalidValue;
+}
+
 hipError_t launch_leaf_scan(hipStream_t st, const LeafCfg &c, int L, const LeafTask *d_tasks, int ntasks,
                             bool mixed)
 {
@@ -332,16 +316,15 @@ hipError_t launch_leaf_scan(hipStream_t st, const LeafCfg &c, int L, const LeafT
     if (c.nt == NT_ && c.pt == PT_) {                                                \
         if (L == 4) return scan_go<NT_, PT_, 4>(st, mixed, d_tasks, ntasks);         \
         if (L == 8) return scan_go<NT_, PT_, 8>(st, mixed, d_tasks, ntasks);         \
-        if (L == 16 && PT_ <= 4) return scan_go<NT_, PT_, 16>(st, mixed, d_tasks, ntasks); \
+        if (L == 16 && PT_ <= 2) return scan_go16<NT_, PT_>(st, mixed, d_tasks, ntasks);   \
         return hipErrorInvalidValue;                                                 \
     }
-    FS_SL(64, 1)
     FS_SL(64, 2)
     FS_SL(64, 4)
     FS_SL(128, 4)
     FS_SL(256, 4)
-    FS_SL(256, 8)
-    FS_SL(256, 16)
+    FS_SL(512, 4)
+    FS_SL(512, 8)
 #undef FS_SL
     return hipErrorInvalidValue;
 }
