@@ -7,6 +7,22 @@
 
 namespace fs {
 
+// Global-memory view of a pointer.  The kernels receive their buffers inside
+// task descriptors, where the compiler cannot see that they point to global
+// memory and would emit flat accesses; flat accesses count against the LDS
+// wait counter as well, so every LDS wait or barrier would also wait for
+// outstanding HBM traffic.  Kernels convert each descriptor pointer once.
+#if defined(__HIP_DEVICE_COMPILE__)
+#define FS_G __attribute__((address_space(1)))
+#else
+#define FS_G
+#endif
+template <typename T>
+__device__ __forceinline__ FS_G T *gptr(T *p)
+{
+    return (FS_G T *)p;
+}
+
 template <typename T>
 struct cplx {
     T x, y;
@@ -60,6 +76,19 @@ struct UpdTask {
     double alpha;
 };
 
+// XCD-aware block order.  Workgroups are dispatched round-robin over the 8
+// XCDs (each with its own L2), so consecutive block ids land on different
+// L2s.  This maps block b to logical block (b mod 8) * (G/8) + b/8, so that
+// logical neighbours (adjacent column groups, which share cache lines) run
+// on the same XCD at about the same time.  Blocks past the last multiple of
+// 8 keep their id.
+__device__ __forceinline__ unsigned xcd_remap(unsigned b, unsigned G)
+{
+    const unsigned full = G & ~7u;
+    if (b >= full) return b;
+    return (b & 7u) * (full >> 3) + (b >> 3);
+}
+
 // Width of the near-corner band of a level product that the FFT route adds
 // exactly instead of through the spectrum (see k_fft.hip).
 __host__ __device__ inline int corner_width(int s) { return s < 32 ? s : 32; }
@@ -75,9 +104,10 @@ hipError_t launch_rhs_scale(hipStream_t st, double *y, const double *u0, const d
 
 // Leaf configuration chosen from M.
 struct LeafCfg {
-    int nt;   // threads per workgroup
-    int pt;   // rows per thread
-    int S;    // PCR stages = log2(2 nt)
+    int nt;       // threads per workgroup
+    int pt;       // rows per thread
+    int S;        // PCR stages = log2(2 nt)
+    int vec = 0;  // scan leaf: M % pt == 0 and 16-byte aligned fields (whole-unit row access)
 };
 LeafCfg leaf_config(int64_t M);
 size_t leaf_table_doubles(const LeafCfg &c);
@@ -88,7 +118,7 @@ LeafCfg scan_config(int64_t M);
 size_t scan_table_doubles(const LeafCfg &c);
 hipError_t launch_scan_factor(hipStream_t st, const LeafCfg &c, int64_t M, double a0, double e, double *tab);
 hipError_t launch_leaf_scan(hipStream_t st, const LeafCfg &c, int L, const LeafTask *d_tasks, int ntasks,
-                            bool mixed);
+                            bool mixed, bool vec);
 
 hipError_t launch_twiddles(hipStream_t st, int64_t nmax, cplx<double> *w64, cplx<float> *w32);
 

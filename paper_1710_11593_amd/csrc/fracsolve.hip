@@ -251,7 +251,8 @@ int run_ops(fracsolve_ctx *h, const std::vector<Op> &ops)
                 e = launch_leaf(h->st, op.lc, h->L, dptr<LeafTask>(h, op.off), op.ntasks, op.mixed);
                 break;
             case OP_LEAF_SCAN:
-                e = launch_leaf_scan(h->st, op.lc, h->L, dptr<LeafTask>(h, op.off), op.ntasks, op.mixed);
+                e = launch_leaf_scan(h->st, op.lc, h->L, dptr<LeafTask>(h, op.off), op.ntasks, op.mixed,
+                                     op.lc.vec != 0);
                 break;
             case OP_GEMM64:
                 e = launch_gemm_update<double>(h->st, dptr<UpdTask<double>>(h, op.off), op.ntasks, op.s, op.maxM);
@@ -388,7 +389,9 @@ void build_solve(fracsolve_ctx *h, const std::vector<int> &sel, const std::vecto
             t.M = in.M;
             t.lo = lo;
             t.nrows = (int)std::min<int64_t>(L, in.N - lo);
-            lt.push_back({(in.scan ? 1000000 : 0) + in.lc.nt * 100 + in.lc.pt, t});
+            // whole 16-byte row units for the scan leaf
+            const bool vec = in.scan && (in.M % in.lc.pt) == 0 && ((uintptr_t)t.u & 15) == 0;
+            lt.push_back({(in.scan ? 1000000 : 0) + (vec ? 200000 : 0) + in.lc.nt * 100 + in.lc.pt, t});
         }
         std::sort(lt.begin(), lt.end(), [](const auto &x, const auto &y) { return x.first < y.first; });
         for (size_t b = 0; b < lt.size();) {
@@ -397,9 +400,10 @@ void build_solve(fracsolve_ctx *h, const std::vector<int> &sel, const std::vecto
             std::vector<LeafTask> v;
             for (size_t j = b; j < e; ++j) v.push_back(lt[j].second);
             size_t off = db.add(v.data(), v.size() * sizeof(LeafTask));
-            const int key = lt[b].first % 1000000;
+            const int key = lt[b].first % 200000;
             LeafCfg lc{key / 100, key % 100, 0};
             lc.S = ilog2i(2 * lc.nt);
+            lc.vec = (lt[b].first % 1000000) >= 200000;
             Op op{lt[b].first >= 1000000 ? OP_LEAF_SCAN : OP_LEAF, off, (int)v.size(), 0, 0, lc, mixed};
             for (auto &t : v) op.bytes += (double)t.nrows * (double)t.M * (mixed ? 24.0 : 16.0);
             ops.push_back(op);

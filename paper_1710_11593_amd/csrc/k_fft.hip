@@ -121,10 +121,12 @@ __device__ __forceinline__ cplx<T> twiddle(const cplx<T> *__restrict__ tw, int64
     return t;
 }
 
-// Loads of the two packed real columns; zero beyond M.
+// Loads of the two packed real columns (one vector access when the pair is
+// whole and aligned, i.e. M even and col even); zero beyond M.
 template <typename T>
-__device__ __forceinline__ cplx<T> load_pair(const T *__restrict__ row, int64_t col, int64_t M)
+__device__ __forceinline__ cplx<T> load_pair(FS_G const T *__restrict__ row, int64_t col, int64_t M)
 {
+    if (((M & 1) == 0) && col + 1 < M) return *reinterpret_cast<FS_G const cplx<T> *>(row + col);
     cplx<T> v;
     v.x = (col < M) ? row[col] : (T)0;
     v.y = (col + 1 < M) ? row[col + 1] : (T)0;
@@ -132,8 +134,16 @@ __device__ __forceinline__ cplx<T> load_pair(const T *__restrict__ row, int64_t 
 }
 
 template <typename T>
-__device__ __forceinline__ void add_pair(T *__restrict__ row, int64_t col, int64_t M, cplx<T> v, T scale)
+__device__ __forceinline__ void add_pair(FS_G T *__restrict__ row, int64_t col, int64_t M, cplx<T> v, T scale)
 {
+    if (((M & 1) == 0) && col + 1 < M) {
+        FS_G cplx<T> *p = reinterpret_cast<FS_G cplx<T> *>(row + col);
+        cplx<T> o = *p;
+        o.x += scale * v.x;
+        o.y += scale * v.y;
+        *p = o;
+        return;
+    }
     if (col < M) row[col] += scale * v.x;
     if (col + 1 < M) row[col + 1] += scale * v.y;
 }
@@ -152,14 +162,14 @@ __device__ __forceinline__ void corner_add(const UpdTask<T> &tk, int p, int64_t 
 {
     const int D0 = corner_width(tk.s);
     double sx = 0.0, sy = 0.0;
-    const double *__restrict__ xb = tk.xc + tk.xlo * M;
+    FS_G const double *__restrict__ xb = gptr(tk.xc) + tk.xlo * M;
     for (int d = p + 1; d < D0; ++d) {
-        const double *__restrict__ row = xb + (int64_t)(tk.s + p - d) * M;
-        const double wd = tk.w[d];
+        FS_G const double *__restrict__ row = xb + (int64_t)(tk.s + p - d) * M;
+        const double wd = gptr(tk.w)[d];
         if (col < M) sx += wd * row[col];
         if (col + 1 < M) sy += wd * row[col + 1];
     }
-    double *__restrict__ yr = tk.yc + (tk.ylo + p) * M;
+    FS_G double *__restrict__ yr = gptr(tk.yc) + (tk.ylo + p) * M;
     if (col < M) yr[col] += tk.alpha * sx;
     if (col + 1 < M) yr[col + 1] += tk.alpha * sy;
 }
@@ -183,7 +193,8 @@ __global__ __launch_bounds__(256) void k_fft2(const UpdTask<T> *__restrict__ tas
     const UpdTask<T> tk = tasks[MODE == MODE_UPDATE ? blockIdx.z : 0];
     const int64_t M = tk.M;
     const int t = threadIdx.x;
-    const int64_t cgrp = (int64_t)blockIdx.x * CC;  // first complex column of this workgroup
+    // first complex column of this workgroup (XCD-aware order in update mode)
+    const int64_t cgrp = (int64_t)(MODE == MODE_UPDATE ? xcd_remap(blockIdx.x, gridDim.x) : blockIdx.x) * CC;
     if (MODE == MODE_UPDATE && 2 * cgrp >= M) return;
     const int64_t tws = nmax / n;
     // spectrum index: spec[k1g + N1g * k]
@@ -196,7 +207,7 @@ __global__ __launch_bounds__(256) void k_fft2(const UpdTask<T> *__restrict__ tas
         cplx<T> v[N1];
         if (MODE == MODE_UPDATE) {
             const int64_t col = 2 * (cgrp + c);
-            const T *__restrict__ xb = tk.x + tk.xlo * M;
+            FS_G const T *__restrict__ xb = gptr(tk.x) + tk.xlo * M;
 #pragma unroll
             for (int q1 = 0; q1 < N1 / 2; ++q1) v[q1] = load_pair(xb + (int64_t)(q1 * N2 + q2) * M, col, M);
             dft_reg<N1, false, true>(v, tw, nmax);
@@ -221,7 +232,7 @@ __global__ __launch_bounds__(256) void k_fft2(const UpdTask<T> *__restrict__ tas
         for (int q2 = 0; q2 < N2; ++q2) v[q2] = sd[k1 * RS + q2 * CC + c];
         dft_reg<N2, false, false>(v, tw, nmax);
 #pragma unroll
-        for (int k2 = 0; k2 < N2; ++k2) v[k2] = cmul(v[k2], tk.spec[k1g + (int64_t)sstride * (k1 + N1 * k2)]);
+        for (int k2 = 0; k2 < N2; ++k2) v[k2] = cmul(v[k2], gptr(tk.spec)[k1g + (int64_t)sstride * (k1 + N1 * k2)]);
         dft_reg<N2, true, false>(v, tw, nmax);
 #pragma unroll
         for (int q2 = 0; q2 < N2; ++q2) sd[k1 * RS + q2 * CC + c] = v[q2];
@@ -240,7 +251,7 @@ __global__ __launch_bounds__(256) void k_fft2(const UpdTask<T> *__restrict__ tas
         if (MODE == MODE_UPDATE) {
             const int64_t col = 2 * (cgrp + c);
             const T scale = (T)(tk.alpha / (double)n);
-            T *__restrict__ yb = tk.y + tk.ylo * M;
+            FS_G T *__restrict__ yb = gptr(tk.y) + tk.ylo * M;
 #pragma unroll
             for (int q1 = N1 / 2; q1 < N1; ++q1) {
                 const int p = (q1 - N1 / 2) * N2 + q2;
@@ -271,7 +282,7 @@ __global__ __launch_bounds__(256) void k_fft3(const UpdTask<T> *__restrict__ tas
     const UpdTask<T> tk = tasks[MODE == MODE_UPDATE ? blockIdx.z : 0];
     const int64_t M = tk.M;
     const int t = threadIdx.x;
-    const int64_t cgrp = (int64_t)blockIdx.x * CC;
+    const int64_t cgrp = (int64_t)(MODE == MODE_UPDATE ? xcd_remap(blockIdx.x, gridDim.x) : blockIdx.x) * CC;
     if (MODE == MODE_UPDATE && 2 * cgrp >= M) return;
     const int64_t tws = nmax / n;
     const int k1g = (MODE == MODE_INNER) ? blockIdx.y : 0;
@@ -284,7 +295,7 @@ __global__ __launch_bounds__(256) void k_fft3(const UpdTask<T> *__restrict__ tas
         cplx<T> v[N1];
         if (MODE == MODE_UPDATE) {
             const int64_t col = 2 * (cgrp + c);
-            const T *__restrict__ xb = tk.x + tk.xlo * M;
+            FS_G const T *__restrict__ xb = gptr(tk.x) + tk.xlo * M;
 #pragma unroll
             for (int q1 = 0; q1 < N1 / 2; ++q1) v[q1] = load_pair(xb + (int64_t)(q1 * N2 * N3 + r) * M, col, M);
             dft_reg<N1, false, true>(v, tw, nmax);
@@ -323,7 +334,7 @@ __global__ __launch_bounds__(256) void k_fft3(const UpdTask<T> *__restrict__ tas
         dft_reg<N3, false, false>(v, tw, nmax);
 #pragma unroll
         for (int k3 = 0; k3 < N3; ++k3)
-            v[k3] = cmul(v[k3], tk.spec[k1g + (int64_t)sstride * (k1 + N1 * k2 + N1 * N2 * k3)]);
+            v[k3] = cmul(v[k3], gptr(tk.spec)[k1g + (int64_t)sstride * (k1 + N1 * k2 + N1 * N2 * k3)]);
         dft_reg<N3, true, false>(v, tw, nmax);
 #pragma unroll
         for (int q3 = 0; q3 < N3; ++q3) sd[at(k1, k2, q3, c)] = v[q3];
@@ -356,7 +367,7 @@ __global__ __launch_bounds__(256) void k_fft3(const UpdTask<T> *__restrict__ tas
         if (MODE == MODE_UPDATE) {
             const int64_t col = 2 * (cgrp + c);
             const T scale = (T)(tk.alpha / (double)n);
-            T *__restrict__ yb = tk.y + tk.ylo * M;
+            FS_G T *__restrict__ yb = gptr(tk.y) + tk.ylo * M;
 #pragma unroll
             for (int q1 = N1 / 2; q1 < N1; ++q1) {
                 const int p = (q1 - N1 / 2) * N2 * N3 + r;
@@ -394,7 +405,7 @@ __global__ __launch_bounds__(256) void k_mp_pass1(const UpdTask<T> *__restrict__
     const int q2 = blockIdx.y * 16 + ty;
     cplx<T> v[N1];
     const int64_t col = 2 * (c0 + cl);
-    const T *__restrict__ xb = tk.x + tk.xlo * M;
+    FS_G const T *__restrict__ xb = gptr(tk.x) + tk.xlo * M;
 #pragma unroll
     for (int q1 = 0; q1 < N1 / 2; ++q1)
         v[q1] = (cl < Mc) ? load_pair(xb + ((int64_t)q1 * nin + q2) * M, col, M) : cplx<T>{0, 0};
@@ -446,7 +457,7 @@ __global__ __launch_bounds__(256) void k_mp_pass3(const UpdTask<T> *__restrict__
     if (cl < Mc) {
         const int64_t col = 2 * (c0 + cl);
         const T scale = (T)(tk.alpha / (double)n);
-        T *__restrict__ yb = tk.y + tk.ylo * M;
+        FS_G T *__restrict__ yb = gptr(tk.y) + tk.ylo * M;
 #pragma unroll
         for (int q1 = N1 / 2; q1 < N1; ++q1) {
             const int64_t p = (int64_t)(q1 - N1 / 2) * nin + q2;

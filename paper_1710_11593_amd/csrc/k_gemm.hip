@@ -29,7 +29,7 @@ __global__ __launch_bounds__(256) void k_gemm_update(const UpdTask<T> *__restric
     if (pb >= tk.ny || cb >= M) return;  // whole workgroup exits together
 
     // sw[k] = w[pb + 1 + k] for k in [0, s + GEMM_ROWS - 1)
-    for (int k = threadIdx.x; k < s + GEMM_ROWS - 1; k += 256) sw[k] = tk.w[pb + 1 + k];
+    for (int k = threadIdx.x; k < s + GEMM_ROWS - 1; k += 256) sw[k] = gptr(tk.w)[pb + 1 + k];
     __syncthreads();
 
     const int lane = threadIdx.x & 63;
@@ -42,14 +42,14 @@ __global__ __launch_bounds__(256) void k_gemm_update(const UpdTask<T> *__restric
 #pragma unroll
     for (int r = 0; r < GEMM_PB; ++r) acc[r] = (T)0;
     const bool ok = col < M;
-    const T *__restrict__ xp = tk.x + tk.xlo * M + col;
+    FS_G const T *__restrict__ xp = gptr(tk.x) + tk.xlo * M + col;
     for (int q = 0; q < s; ++q) {
         T xq = ok ? xp[(int64_t)q * M] : (T)0;
 #pragma unroll
         for (int r = 0; r < GEMM_PB; ++r) acc[r] += (T)sw[off + r - q] * xq;
     }
     if (ok) {
-        T *__restrict__ yp = tk.y + tk.ylo * M + col;
+        FS_G T *__restrict__ yp = gptr(tk.y) + tk.ylo * M + col;
         const T alpha = (T)tk.alpha;
 #pragma unroll
         for (int r = 0; r < GEMM_PB; ++r)

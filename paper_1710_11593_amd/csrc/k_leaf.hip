@@ -148,11 +148,11 @@ __global__ __launch_bounds__(NT) void k_leaf(const LeafTask *__restrict__ tasks)
 
     const LeafTask tk = tasks[blockIdx.x];
     const int t = threadIdx.x;
-    const double *__restrict__ fac = tk.fac;
+    FS_G const double *__restrict__ fac = gptr(tk.fac);
     const int64_t M = tk.M;
     const int64_t c0 = (int64_t)t * PT;
     const int nrows = tk.nrows;
-    double *__restrict__ u = tk.u + tk.lo * M;
+    FS_G double *__restrict__ u = gptr(tk.u) + tk.lo * M;
 
     for (int i = t; i < 3 * S * R2; i += NT) sP[i] = fac[LY::pcr_base() + i];
 
@@ -168,7 +168,7 @@ __global__ __launch_bounds__(NT) void k_leaf(const LeafTask *__restrict__ tasks)
     const double invD0 = fac[LY::invd0(t)];
     double aw[L];
 #pragma unroll
-    for (int m = 0; m < L; ++m) aw[m] = (m > 0) ? tk.a[m] : 0.0;
+    for (int m = 0; m < L; ++m) aw[m] = (m > 0) ? gptr(tk.a)[m] : 0.0;
 
     double acc[L][PT];
 #pragma unroll
@@ -179,7 +179,7 @@ __global__ __launch_bounds__(NT) void k_leaf(const LeafTask *__restrict__ tasks)
             double v = 0.0;
             if (r < nrows && i < M) {
                 v = u[(int64_t)r * M + i];
-                if (MIXED) v += (double)tk.hist[(tk.lo + r) * M + i];
+                if (MIXED) v += (double)gptr(tk.hist)[(tk.lo + r) * M + i];
             }
             acc[r][k] = v;
         }
@@ -232,7 +232,7 @@ __global__ __launch_bounds__(NT) void k_leaf(const LeafTask *__restrict__ tasks)
                 int64_t i = c0 + k;
                 if (i < M) {
                     u[(int64_t)r * M + i] = x[k];
-                    if (MIXED) tk.x32[(tk.lo + r) * M + i] = (float)x[k];
+                    if (MIXED) gptr(tk.x32)[(tk.lo + r) * M + i] = (float)x[k];
                 }
             }
 #pragma unroll

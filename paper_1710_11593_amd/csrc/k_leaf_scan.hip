@@ -8,17 +8,25 @@
 //   K0 = 1 / (e (1/rho - rho) (1 - rho^(2 (M+1)))),
 // (A0^-1)_{ij} = K0 rho^|i-j| alpha_min(i,j) beta_max(i,j), so
 //   x_i = K0 (beta_i P_i + alpha_i Q_i),
-//   P_i = rho P_{i-1} + alpha_i r_i,      Q_i = rho (Q_{i+1} + beta_{i+1} r_{i+1}),
-// two first-order recurrences with a common multiplier rho <= 1.  Each thread
-// owns PT consecutive rows; the recurrences are folded per thread, combined
-// across the workgroup by an inclusive scan (multiplier rho^PT per thread:
-// shuffles inside a wave, one LDS exchange of wave totals between waves), and
-// unfolded again with the carries.  One barrier per time step; no table per
-// row beyond alpha and beta.  theta = log1p(d + sqrt(d (2 + d))), d =
-// a_0 / (2 e), keeps a_0 exact even when it is tiny next to 2 e, where
-// forming the diagonal a_0 + 2 e in float64 would round a_0 away.
+//   P_i = sum_{j <= i} rho^(i-j) alpha_j r_j,   Q_i = sum_{j > i} rho^(j-i) beta_j r_j,
+// two first-order recurrences with the common multiplier rho <= 1.
+// theta = log1p(d + sqrt(d (2 + d))), d = a_0 / (2 e), keeps a_0 exact even
+// when it is tiny next to 2 e, where forming the diagonal a_0 + 2 e in
+// float64 would round a_0 away.
 //
-// In-leaf history is pushed forward in registers as in the PCR leaf.
+// Work split.  Thread t owns the PT consecutive rows c0+1 .. c0+PT
+// (c0 = t PT).  Per time step it forms the local prefix l_k and suffix s_k
+// of its rows (carry-free), so that
+//   P_{c0+1+k} = l_k + rho^(k+1) P_{c0},
+//   Q_{c0+1+k} = rho s_{k+1} + rho^(PT-1-k) Q_{c0+PT},
+// and the two carries P_{c0}, Q_{c0+PT} are exclusive scans of the thread
+// totals with multiplier m = rho^PT.  The scans run in three levels: DPP
+// shifts inside rows of 16 lanes, one LDS exchange of the row totals (the
+// only barrier of the step), and a DPP scan of those totals over the first
+// lanes of every wave; each lane then fetches its row's carry with a lane
+// permute.  The whole leaf (L steps) is unrolled: the in-leaf history
+// sum_{j<n} a_{n-j} x_j is pushed into the later rows' right-hand sides in
+// registers right after x_j is known, touching only rows still in the leaf.
 #include "common.hpp"
 
 namespace fs {
@@ -32,15 +40,45 @@ struct slog2<1> {
     static constexpr int value = 0;
 };
 
-// DPP lane moves of a double (two 32-bit halves); lanes without a source
-// receive 0.  CTRL: 0x110+d = row_shr:d, 0x100+d = row_shl:d (inside rows
-// of 16 lanes).
-template <int CTRL>
+// Table layout (doubles):
+//   [0] K0, [1] rho,
+//   [8 + s]  m^(2^s), m = rho^PT, s < 16,
+//   [24 + k] rho^(k+1), k < 16,
+//   [SCAN_TAB_ALPHA + r] alpha of row r+1 (r < NT*PT, 0 beyond M), then beta.
+constexpr int SCAN_TAB_POW = 24;
+constexpr int SCAN_TAB_ALPHA = 40;
+
+template <int NT, int PT>
+__global__ __launch_bounds__(NT) void k_scan_factor(int64_t M, double a0, double e, double *__restrict__ tab)
+{
+    constexpr int MP = NT * PT;
+    const double dlt = a0 / (2.0 * e);
+    const double th = log1p(dlt + sqrt(dlt * (2.0 + dlt)));
+    const int t = threadIdx.x;
+    if (t == 0) {
+        double gam = -expm1(-2.0 * (double)(M + 1) * th);
+        tab[0] = 1.0 / (e * 2.0 * sinh(th) * gam);
+        tab[1] = exp(-th);
+        for (int s = 0; s < 16; ++s) tab[8 + s] = exp(-(double)PT * (double)(1 << s) * th);
+        for (int k = 0; k < 16; ++k) tab[SCAN_TAB_POW + k] = exp(-(double)(k + 1) * th);
+    }
+    for (int r = t; r < MP; r += NT) {
+        double i = (double)(r + 1);
+        bool real = r < M;
+        tab[SCAN_TAB_ALPHA + r] = real ? -expm1(-2.0 * i * th) : 0.0;
+        tab[SCAN_TAB_ALPHA + MP + r] = real ? -expm1(-2.0 * ((double)(M + 1) - i) * th) : 0.0;
+    }
+}
+
+// DPP lane move of a double (two 32-bit halves).  Lanes without a source,
+// or outside ROWMASK, receive 0.  CTRL: 0x110+d row_shr:d, 0x100+d
+// row_shl:d (inside rows of 16 lanes), 0x142 row_bcast:15.
+template <int CTRL, int ROWMASK = 0xF>
 __device__ __forceinline__ double dpp_move(double v)
 {
     int lo = __double2loint(v), hi = __double2hiint(v);
-    lo = __builtin_amdgcn_update_dpp(0, lo, CTRL, 0xF, 0xF, true);
-    hi = __builtin_amdgcn_update_dpp(0, hi, CTRL, 0xF, 0xF, true);
+    lo = __builtin_amdgcn_update_dpp(0, lo, CTRL, ROWMASK, 0xF, true);
+    hi = __builtin_amdgcn_update_dpp(0, hi, CTRL, ROWMASK, 0xF, true);
     return __hiloint2double(hi, lo);
 }
 
@@ -51,68 +89,90 @@ __device__ __forceinline__ double read_lane(double v, int lane)
     return __hiloint2double(hi, lo);
 }
 
-// Table layout (doubles): [0] K0, [1] rho, [8 + s] = rho^(PT 2^s) for
-// s < log2(NT) (<= 10), [32 + r] alpha of row r (r < NT*PT), then beta.
-constexpr int SCAN_TAB_ALPHA = 32;
-
-template <int NT, int PT>
-__global__ __launch_bounds__(NT) void k_scan_factor(int64_t M, double a0, double e, double *__restrict__ tab)
+// v from lane src (any lane of the wave)
+__device__ __forceinline__ double lane_fetch(double v, int src)
 {
-    constexpr int S = slog2<NT>::value;
-    constexpr int MP = NT * PT;
-    const double dlt = a0 / (2.0 * e);
-    const double th = log1p(dlt + sqrt(dlt * (2.0 + dlt)));
-    const int t = threadIdx.x;
-    if (t == 0) {
-        double gam = -expm1(-2.0 * (double)(M + 1) * th);
-        tab[0] = 1.0 / (e * 2.0 * sinh(th) * gam);
-        tab[1] = exp(-th);
-        for (int s = 0; s < (S > 7 ? S : 7); ++s) tab[8 + s] = exp(-(double)PT * (double)(1 << s) * th);
+    int lo = __builtin_amdgcn_ds_bpermute(src << 2, __double2loint(v));
+    int hi = __builtin_amdgcn_ds_bpermute(src << 2, __double2hiint(v));
+    return __hiloint2double(hi, lo);
+}
+
+// c^e for 0 <= e < 32 from the powers c^(2^s) in pw[0..4]
+__device__ __forceinline__ double pow_bits(const double *pw, int e)
+{
+    double r = 1.0;
+#pragma unroll
+    for (int s = 0; s < 5; ++s)
+        if (e & (1 << s)) r *= pw[s];
+    return r;
+}
+
+// Inclusive scans over the 16 lanes of each row with lane multiplier c:
+//   fwd: S_l = sum_{l' <= l} c^(l-l') v_l',  bwd: S_l = sum_{l' >= l} c^(l'-l) v_l'.
+// cp[s] = c^(2^s).  Only the first NL (power of two <= 16) lanes of a row
+// carry data when NL < 16.
+template <int NL>
+__device__ __forceinline__ void row_scans(double &f, double &b, const double *cp)
+{
+    f = fma(cp[0], dpp_move<0x111>(f), f);
+    b = fma(cp[0], dpp_move<0x101>(b), b);
+    if constexpr (NL > 2) {
+        f = fma(cp[1], dpp_move<0x112>(f), f);
+        b = fma(cp[1], dpp_move<0x102>(b), b);
     }
-    for (int r = t; r < MP; r += NT) {
-        double i = (double)(r + 1);
-        bool real = r < M;
-        tab[SCAN_TAB_ALPHA + r] = real ? -expm1(-2.0 * i * th) : 0.0;
-        tab[SCAN_TAB_ALPHA + MP + r] = real ? -expm1(-2.0 * ((double)(M + 1) - i) * th) : 0.0;
+    if constexpr (NL > 4) {
+        f = fma(cp[2], dpp_move<0x114>(f), f);
+        b = fma(cp[2], dpp_move<0x104>(b), b);
+    }
+    if constexpr (NL > 8) {
+        f = fma(cp[3], dpp_move<0x118>(f), f);
+        b = fma(cp[3], dpp_move<0x108>(b), b);
     }
 }
 
-template <int NT, int PT, int L, bool MIXED>
+template <int NT, int PT, int L, bool MIXED, bool VEC>
 __global__ __launch_bounds__(NT) void k_leaf_scan(const LeafTask *__restrict__ tasks)
 {
-    static_assert(PT % 2 == 0, "rows per thread must be even");
-    constexpr int S = slog2<NT>::value;
+    static_assert(PT % 2 == 0 && PT <= 16, "rows per thread must be even and at most 16");
     constexpr int NW = NT / 64;
+    constexpr int NR = NT / 16;  // rows of 16 lanes in the workgroup (<= 32)
+    static_assert(NR <= 32, "at most 512 threads");
     constexpr int MP = NT * PT;
-    constexpr int UT = PT / 2;  // 16-byte units per thread
-    __shared__ double sW[2][2][NW > 1 ? NW : 1];
+    constexpr int UT = PT / 2;
+    __shared__ double sR[2][2][NR];  // [parity][forward/backward][row]
 
     const LeafTask tk = tasks[blockIdx.x];
     const int t = threadIdx.x;
     const int lane = t & 63;
-    const int wv = t >> 6;
-    const double *__restrict__ tab = tk.fac;
+    const int rl = lane & 15;  // position inside the row
+    const int G = t >> 4;      // row index in the workgroup
+    FS_G const double *__restrict__ tab = gptr(tk.fac);
     const int64_t M = tk.M;
     const int c0 = t * PT;
     const int nrows = tk.nrows;
-    double *__restrict__ u = tk.u + tk.lo * M;
-    const float *__restrict__ hist = MIXED ? tk.hist + tk.lo * M : nullptr;
-    float *__restrict__ x32 = MIXED ? tk.x32 + tk.lo * M : nullptr;
-    // the thread's PT rows are whole 16-byte units inside the field
-    const bool vec = ((M & 1) == 0) && ((((uintptr_t)tk.u) & 15) == 0) && (c0 + PT <= M);
+    FS_G double *__restrict__ u = gptr(tk.u) + tk.lo * M;
+    FS_G const float *__restrict__ hist = MIXED ? gptr(tk.hist) + tk.lo * M : nullptr;
+    FS_G float *__restrict__ x32 = MIXED ? gptr(tk.x32) + tk.lo * M : nullptr;
+    // VEC: M is a multiple of PT and the field is 16-byte aligned, so a
+    // thread's rows are either all inside [0, M) or all outside.
+    const bool act = c0 < M;
 
-    // right-hand sides of the leaf's rows: the thread's PT consecutive
-    // entries of each row, as 16-byte loads (lanes 32 bytes apart)
+    // right-hand sides of the leaf's rows (row r of the leaf in acc[r])
     double acc[L][PT];
 #pragma unroll
     for (int r = 0; r < L; ++r) {
-        const double *row = u + (int64_t)r * M + c0;
-        if (r < nrows && vec) {
+        FS_G const double *row = u + (int64_t)r * M + c0;
+        if (VEC) {
+            if (r < nrows && act) {
 #pragma unroll
-            for (int i = 0; i < UT; ++i) {
-                const double2 v = reinterpret_cast<const double2 *>(row)[i];
-                acc[r][2 * i] = v.x;
-                acc[r][2 * i + 1] = v.y;
+                for (int i = 0; i < UT; ++i) {
+                    const double2 v = reinterpret_cast<FS_G const double2 *>(row)[i];
+                    acc[r][2 * i] = v.x;
+                    acc[r][2 * i + 1] = v.y;
+                }
+            } else {
+#pragma unroll
+                for (int k = 0; k < PT; ++k) acc[r][k] = 0.0;
             }
         } else {
 #pragma unroll
@@ -127,140 +187,107 @@ __global__ __launch_bounds__(NT) void k_leaf_scan(const LeafTask *__restrict__ t
 
     const double K0 = tab[0];
     const double rho = tab[1];
-    double mult[S > 7 ? S : 7];
+    double mp[4];  // m^(1,2,4,8): lane steps inside a row
 #pragma unroll
-    for (int s = 0; s < (S > 7 ? S : 7); ++s) mult[s] = tab[8 + s];
+    for (int s = 0; s < 4; ++s) mp[s] = tab[8 + s];
+    double cp[5];  // c^(2^s), c = m^16: row steps
+#pragma unroll
+    for (int s = 0; s < 5; ++s) cp[s] = tab[12 + s];
+    double rp[PT];  // rho^(k+1)
+#pragma unroll
+    for (int k = 0; k < PT; ++k) rp[k] = tab[SCAN_TAB_POW + k];
     double al[PT], be[PT];
 #pragma unroll
     for (int k = 0; k < PT; ++k) {
         al[k] = tab[SCAN_TAB_ALPHA + c0 + k];
         be[k] = tab[SCAN_TAB_ALPHA + MP + c0 + k];
     }
-    // per-lane powers m^(lane mod 16) and m^(15 - lane mod 16), m = rho^PT,
-    // and the row/wave strides m^16, m^32, m^48, m^64
-    double m_lo = 1.0, m_hi = 1.0;
-    {
-        const int el = lane & 15, eh = 15 - (lane & 15);
-#pragma unroll
-        for (int s = 0; s < 4; ++s) {
-            if (el & (1 << s)) m_lo *= mult[s];
-            if (eh & (1 << s)) m_hi *= mult[s];
-        }
-    }
-    const double m16 = mult[4], m32 = mult[5], m48 = mult[4] * mult[5];
-    const double m64 = (S > 6) ? mult[6 < S ? 6 : 0] : 0.0;
+    // lane multipliers: m^rl and m^(15-rl) (row carries into a thread);
+    // c^((lane&15)+1) for the row_bcast:15 step and c^(16-lane) for the
+    // backward step of the row scan (both used only on lanes < NR)
+    double mpw[5] = {mp[0], mp[1], mp[2], mp[3], 0.0};
+    const double m_lo = pow_bits(mpw, rl);
+    const double m_hi = pow_bits(mpw, 15 - rl);
+    const double c_b15 = pow_bits(cp, (lane & 15) + 1);
+    const double c_bk = pow_bits(cp, 16 - (lane & 15));
     double aw[L];
 #pragma unroll
-    for (int m = 0; m < L; ++m) aw[m] = (m > 0) ? tk.a[m] : 0.0;
+    for (int m = 0; m < L; ++m) aw[m] = (m > 0) ? gptr(tk.a)[m] : 0.0;
 
-    int par = 0;
-    // Rolled step loop: acc[0] holds the current row's right-hand side and
-    // acc[j] the row j steps ahead; after a step every row moves down by one.
-    // The push below therefore always uses a_j for acc[j].
-#pragma unroll 1
-    for (int r = 0; r < nrows; ++r) {
-        {
-            // fold the two recurrences over the thread's rows
-            double Tf = 0.0, Tb = 0.0;
 #pragma unroll
-            for (int k = 0; k < PT; ++k) Tf = rho * Tf + al[k] * acc[0][k];
+    for (int r = 0; r < L; ++r) {
+        if (r >= nrows) break;
+        const int par = r & 1;
+        // carry-free local prefix l and suffix s of the thread's rows
+        double lf[PT], sb[PT];
+        lf[0] = al[0] * acc[r][0];
 #pragma unroll
-            for (int k = PT - 1; k >= 0; --k) Tb = rho * (Tb + be[k] * acc[0][k]);
-            // Row-local (16 lanes) inclusive scans by DPP shifts:
-            //   prefix  R_t = sum_{t' <= t in row} m^(t-t') Tf(t')
-            //   suffix  S_t = sum_{t' >= t in row} m^(t'-t) Tb(t')
-            double Rf = Tf, Rb = Tb;
-            Rf += mult[0] * dpp_move<0x111>(Rf);
-            Rb += mult[0] * dpp_move<0x101>(Rb);
-            Rf += mult[1] * dpp_move<0x112>(Rf);
-            Rb += mult[1] * dpp_move<0x102>(Rb);
-            Rf += mult[2] * dpp_move<0x114>(Rf);
-            Rb += mult[2] * dpp_move<0x104>(Rb);
-            Rf += mult[3] * dpp_move<0x118>(Rf);
-            Rb += mult[3] * dpp_move<0x108>(Rb);
-            // row totals (uniform): forward at lanes 15, 31, 47, 63, backward at 0, 16, 32, 48
-            const double f0 = read_lane(Rf, 15), f1 = read_lane(Rf, 31), f2 = read_lane(Rf, 47),
-                         f3 = read_lane(Rf, 63);
-            const double b0 = read_lane(Rb, 0), b1 = read_lane(Rb, 16), b2 = read_lane(Rb, 32),
-                         b3 = read_lane(Rb, 48);
-            // wave-level prefix at the end of rows 0..3 and suffix at the start of rows 3..0
-            const double W15 = f0, W31 = f1 + m16 * W15, W47 = f2 + m16 * W31, W63 = f3 + m16 * W47;
-            const double V48 = b3, V32 = b2 + m16 * V48, V16 = b1 + m16 * V32, V0 = b0 + m16 * V16;
-            double Cf = 0.0, Cb = 0.0;  // prefix before this wave, suffix after it
-            if (NW > 1) {
-                if (lane == 0) {
-                    sW[par][0][wv] = W63;
-                    sW[par][1][wv] = V0;
-                }
-                __syncthreads();
-                double tf[NW], tb[NW];
+        for (int k = 1; k < PT; ++k) lf[k] = fma(rho, lf[k - 1], al[k] * acc[r][k]);
+        sb[PT - 1] = be[PT - 1] * acc[r][PT - 1];
 #pragma unroll
-                for (int w = 0; w < NW; ++w) {
-                    tf[w] = sW[par][0][w];
-                    tb[w] = sW[par][1][w];
-                }
+        for (int k = PT - 2; k >= 0; --k) sb[k] = fma(rho, sb[k + 1], be[k] * acc[r][k]);
+        // thread totals and their row scans (multiplier m per lane)
+        double Sf = lf[PT - 1], Sb = rho * sb[0];
+        row_scans<16>(Sf, Sb, mp);
+        if (rl == 15) sR[par][0][G] = Sf;
+        if (rl == 0) sR[par][1][G] = Sb;
+        __syncthreads();
+        // scan of the NR row totals (multiplier c = m^16 per row) on lanes < NR
+        double vf = (lane < NR) ? sR[par][0][lane] : 0.0;
+        double vb = (lane < NR) ? sR[par][1][lane] : 0.0;
+        row_scans<(NR < 16 ? NR : 16)>(vf, vb, cp);
+        if constexpr (NR > 16) {
+            // rows 0-15 -> 16-31: forward by row_bcast:15 into lanes 16..31,
+            // backward by the uniform suffix at lane 16 into lanes 0..15
+            vf = fma(c_b15, dpp_move<0x142, 0xA>(vf), vf);
+            const double s16 = read_lane(vb, 16);
+            vb = (lane < 16) ? fma(c_bk, s16, vb) : vb;
+        }
+        // carries: P at the row before the thread's rows, Q at its last row
+        double Cr = lane_fetch(vf, G > 0 ? G - 1 : 0);
+        double Dr = lane_fetch(vb, G < NR - 1 ? G + 1 : 0);
+        Cr = (G > 0) ? Cr : 0.0;
+        Dr = (G < NR - 1) ? Dr : 0.0;
+        const double cf = fma(m_lo, Cr, dpp_move<0x111>(Sf));
+        const double cb = fma(m_hi, Dr, dpp_move<0x101>(Sb));
+        // unfold
+        double x[PT];
 #pragma unroll
-                for (int w = 0; w < NW; ++w)
-                    if (w < wv) Cf = Cf * m64 + tf[w];
-#pragma unroll
-                for (int w = NW - 1; w >= 0; --w)
-                    if (w > wv) Cb = Cb * m64 + tb[w];
-                par ^= 1;
-            }
-            // exclusive carries: prefix up to the row before this thread's
-            // rows, suffix from the row after them
-            const int rw = lane >> 4;
-            const double Gf = (rw == 0) ? Cf
-                            : (rw == 1) ? W15 + m16 * Cf
-                            : (rw == 2) ? W31 + m32 * Cf
-                                        : W47 + m48 * Cf;
-            const double Gb = (rw == 3) ? Cb
-                            : (rw == 2) ? V48 + m16 * Cb
-                            : (rw == 1) ? V32 + m32 * Cb
-                                        : V16 + m48 * Cb;
-            const double cf = dpp_move<0x111>(Rf) + m_lo * Gf;
-            const double cb = dpp_move<0x101>(Rb) + m_hi * Gb;
-            // unfold with the carries: P forward, Q backward
-            double x[PT];
-            double P = cf;
-#pragma unroll
-            for (int k = 0; k < PT; ++k) {
-                P = rho * P + al[k] * acc[0][k];
-                x[k] = be[k] * P;
-            }
-            double Q = cb;
-#pragma unroll
-            for (int k = PT - 1; k >= 0; --k) {
-                x[k] = K0 * (x[k] + al[k] * Q);
-                Q = rho * (Q + be[k] * acc[0][k]);
-            }
-            double *row = u + (int64_t)r * M + c0;
-            if (vec) {
+        for (int k = 0; k < PT; ++k) {
+            const double P = fma(rp[k], cf, lf[k]);
+            const double Q = (k < PT - 1) ? fma(rho, sb[k + 1 < PT ? k + 1 : k], rp[PT - 2 - k >= 0 ? PT - 2 - k : 0] * cb)
+                                          : cb;
+            x[k] = K0 * fma(be[k], P, al[k] * Q);
+        }
+        FS_G double *row = u + (int64_t)r * M + c0;
+        if (VEC) {
+            if (act) {
 #pragma unroll
                 for (int i = 0; i < UT; ++i)
-                    reinterpret_cast<double2 *>(row)[i] = double2{x[2 * i], x[2 * i + 1]};
-            } else {
-#pragma unroll
-                for (int k = 0; k < PT; ++k)
-                    if (c0 + k < M) row[k] = x[k];
+                    reinterpret_cast<FS_G double2 *>(row)[i] = double2{x[2 * i], x[2 * i + 1]};
             }
-            if (MIXED) {
+        } else {
 #pragma unroll
-                for (int k = 0; k < PT; ++k)
-                    if (c0 + k < M) x32[(int64_t)r * M + c0 + k] = (float)x[k];
-            }
+            for (int k = 0; k < PT; ++k)
+                if (c0 + k < M) row[k] = x[k];
+        }
+        if (MIXED) {
 #pragma unroll
-            for (int j = 1; j < L; ++j) {
+            for (int k = 0; k < PT; ++k)
+                if (c0 + k < M) x32[(int64_t)r * M + c0 + k] = (float)x[k];
+        }
+        // push x_r into the right-hand sides of the later rows of the leaf
 #pragma unroll
-                for (int k = 0; k < PT; ++k) acc[j - 1][k] = acc[j][k] - aw[j] * x[k];
-            }
+        for (int j = r + 1; j < L; ++j) {
+#pragma unroll
+            for (int k = 0; k < PT; ++k) acc[j][k] = fma(-aw[j - r], x[k], acc[j][k]);
         }
     }
 }
 
 // Up to 512 threads (two waves per SIMD) with 2, 4 or 8 rows per thread: the
-// leaf's right-hand sides and accumulators (L x PT doubles per thread) stay
-// in registers and each thread's rows are whole 16-byte units.
+// leaf's right-hand sides (L x PT doubles per thread) stay in registers and
+// each thread's rows are whole 16-byte units.
 LeafCfg scan_config(int64_t M)
 {
     if (M <= 128) return {64, 2, 6};
@@ -291,33 +318,40 @@ hipError_t launch_scan_factor(hipStream_t st, const LeafCfg &c, int64_t M, doubl
 }
 
 template <int NT, int PT, int L>
-static hipError_t scan_go(hipStream_t st, bool mixed, const LeafTask *d_tasks, int ntasks)
+static hipError_t scan_go(hipStream_t st, bool mixed, bool vec, const LeafTask *d_tasks, int ntasks)
 {
-    if (mixed)
-        hipLaunchKernelGGL((k_leaf_scan<NT, PT, L, true>), dim3(ntasks), dim3(NT), 0, st, d_tasks);
-    else
-        hipLaunchKernelGGL((k_leaf_scan<NT, PT, L, false>), dim3(ntasks), dim3(NT), 0, st, d_tasks);
+    if (mixed) {
+        if (vec)
+            hipLaunchKernelGGL((k_leaf_scan<NT, PT, L, true, true>), dim3(ntasks), dim3(NT), 0, st, d_tasks);
+        else
+            hipLaunchKernelGGL((k_leaf_scan<NT, PT, L, true, false>), dim3(ntasks), dim3(NT), 0, st, d_tasks);
+    } else {
+        if (vec)
+            hipLaunchKernelGGL((k_leaf_scan<NT, PT, L, false, true>), dim3(ntasks), dim3(NT), 0, st, d_tasks);
+        else
+            hipLaunchKernelGGL((k_leaf_scan<NT, PT, L, false, false>), dim3(ntasks), dim3(NT), 0, st, d_tasks);
+    }
     return hipGetLastError();
 }
 
 template <int NT, int PT>
-static hipError_t scan_go16(hipStream_t st, bool mixed, const LeafTask *d_tasks, int ntasks)
+static hipError_t scan_go16(hipStream_t st, bool mixed, bool vec, const LeafTask *d_tasks, int ntasks)
 {
     if constexpr (PT <= 2)
-        return scan_go<NT, PT, 16>(st, mixed, d_tasks, ntasks);
+        return scan_go<NT, PT, 16>(st, mixed, vec, d_tasks, ntasks);
     else
         return hipErrorInvalidValue;
 }
 
 hipError_t launch_leaf_scan(hipStream_t st, const LeafCfg &c, int L, const LeafTask *d_tasks, int ntasks,
-                            bool mixed)
+                            bool mixed, bool vec)
 {
-#define FS_SL(NT_, PT_)                                                              \
-    if (c.nt == NT_ && c.pt == PT_) {                                                \
-        if (L == 4) return scan_go<NT_, PT_, 4>(st, mixed, d_tasks, ntasks);         \
-        if (L == 8) return scan_go<NT_, PT_, 8>(st, mixed, d_tasks, ntasks);         \
-        if (L == 16 && PT_ <= 2) return scan_go16<NT_, PT_>(st, mixed, d_tasks, ntasks);   \
-        return hipErrorInvalidValue;                                                 \
+#define FS_SL(NT_, PT_)                                                                        \
+    if (c.nt == NT_ && c.pt == PT_) {                                                          \
+        if (L == 4) return scan_go<NT_, PT_, 4>(st, mixed, vec, d_tasks, ntasks);              \
+        if (L == 8) return scan_go<NT_, PT_, 8>(st, mixed, vec, d_tasks, ntasks);              \
+        if (L == 16 && PT_ <= 2) return scan_go16<NT_, PT_>(st, mixed, vec, d_tasks, ntasks);  \
+        return hipErrorInvalidValue;                                                           \
     }
     FS_SL(64, 2)
     FS_SL(64, 4)
