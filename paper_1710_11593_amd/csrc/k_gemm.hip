@@ -5,64 +5,84 @@
 // sum that section 3 identifies as the O(M N^2) cost of time marching, for
 // the small blocks where the FFT route of section 3.1 does not pay.
 //
-// Workgroup tile: 64 columns (one per lane) x 4 waves x PB output rows.
-// Each thread keeps PB accumulators; X values stream from global memory
-// (coalesced over the 64 columns), the needed slice of w sits in LDS and is
-// read as wave-uniform (broadcast) values.
+// These products are small (s <= 64 by default: at most a few MB of
+// traffic) and sit on the critical path of the recursion, so the kernel is
+// organised for latency: every thread owns one column and DENSE_RB output
+// rows; all loads of its X column (a chunk of up to 64 rows) and of
+// its Y rows are issued together, the weight window sits in LDS (read as
+// wave-uniform broadcasts), and the output rows are spread over the grid so
+// that even s = 64 occupies every CU.
 #include "common.hpp"
 
 namespace fs {
 
-constexpr int GEMM_PB = 16;          // output rows per thread
-constexpr int GEMM_ROWS = 4 * GEMM_PB;
-constexpr int GEMM_MAXS = 1024;      // largest half-block size for this kernel
+constexpr int DENSE_RB = 4;      // output rows per thread
+constexpr int DENSE_MAXS = 1024; // largest half-block size for this kernel
 
-template <typename T>
-__global__ __launch_bounds__(256) void k_gemm_update(const UpdTask<T> *__restrict__ tasks)
+// QC: X rows per load batch (min(s, 64))
+template <typename T, int QC>
+__global__ __launch_bounds__(256) void k_dense_update(const UpdTask<T> *__restrict__ tasks)
 {
-    __shared__ double sw[GEMM_ROWS + GEMM_MAXS];
+    __shared__ double sw[DENSE_MAXS + DENSE_RB];
     const UpdTask<T> tk = tasks[blockIdx.z];
     const int s = tk.s;
     const int64_t M = tk.M;
-    const int pb = blockIdx.y * GEMM_ROWS;
-    const int64_t cb = (int64_t)blockIdx.x * 64;
-    if (pb >= tk.ny || cb >= M) return;  // whole workgroup exits together
-
-    // sw[k] = w[pb + 1 + k] for k in [0, s + GEMM_ROWS - 1)
-    for (int k = threadIdx.x; k < s + GEMM_ROWS - 1; k += 256) sw[k] = gptr(tk.w)[pb + 1 + k];
-    __syncthreads();
-
-    const int lane = threadIdx.x & 63;
-    const int wv = threadIdx.x >> 6;
-    const int64_t col = cb + lane;
-    const int p0 = pb + wv * GEMM_PB;  // first output row of this thread
-    // w[s + p - q] = sw[s + p - q - pb - 1]
-    const int off = s + (p0 - pb) - 1;
-    T acc[GEMM_PB];
-#pragma unroll
-    for (int r = 0; r < GEMM_PB; ++r) acc[r] = (T)0;
+    const int p0 = blockIdx.y * DENSE_RB;  // first output row of the workgroup
+    const int64_t col = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (p0 >= tk.ny || (int64_t)blockIdx.x * 256 >= M) return;  // whole workgroup exits together
     const bool ok = col < M;
+    const int np = (tk.ny - p0 < DENSE_RB) ? tk.ny - p0 : DENSE_RB;
+
     FS_G const T *__restrict__ xp = gptr(tk.x) + tk.xlo * M + col;
-    for (int q = 0; q < s; ++q) {
-        T xq = ok ? xp[(int64_t)q * M] : (T)0;
+    FS_G T *__restrict__ yp = gptr(tk.y) + (tk.ylo + p0) * M + col;
+    // Y rows of this thread, loaded up front with the first X chunk
+    T yv[DENSE_RB];
 #pragma unroll
-        for (int r = 0; r < GEMM_PB; ++r) acc[r] += (T)sw[off + r - q] * xq;
+    for (int r = 0; r < DENSE_RB; ++r) yv[r] = (ok && r < np) ? yp[(int64_t)r * M] : (T)0;
+    // weight window: sw[k] = w[p0 + 1 + k], k < s + DENSE_RB - 1
+    FS_G const double *__restrict__ w = gptr(tk.w);
+    for (int k = threadIdx.x; k < s + DENSE_RB - 1; k += 256) sw[k] = w[p0 + 1 + k];
+
+    T acc[DENSE_RB];
+#pragma unroll
+    for (int r = 0; r < DENSE_RB; ++r) acc[r] = (T)0;
+    // w[s + p - q] with p = p0 + r: sw[s - 1 + r - q]
+    for (int q0 = 0; q0 < s; q0 += QC) {
+        T xv[QC];
+#pragma unroll
+        for (int j = 0; j < QC; ++j) xv[j] = (ok && q0 + j < s) ? xp[(int64_t)(q0 + j) * M] : (T)0;
+        if (q0 == 0) __syncthreads();  // weight window ready
+#pragma unroll
+        for (int j = 0; j < QC; ++j) {
+            if (q0 + j < s) {
+#pragma unroll
+                for (int r = 0; r < DENSE_RB; ++r) acc[r] += (T)sw[s - 1 + r - q0 - j] * xv[j];
+            }
+        }
     }
     if (ok) {
-        FS_G T *__restrict__ yp = gptr(tk.y) + tk.ylo * M + col;
         const T alpha = (T)tk.alpha;
 #pragma unroll
-        for (int r = 0; r < GEMM_PB; ++r)
-            if (p0 + r < tk.ny) yp[(int64_t)(p0 + r) * M] += alpha * acc[r];
+        for (int r = 0; r < DENSE_RB; ++r)
+            if (r < np) yp[(int64_t)r * M] = yv[r] + alpha * acc[r];
     }
 }
 
 template <typename T>
 hipError_t launch_gemm_update(hipStream_t st, const UpdTask<T> *d_tasks, int ntasks, int s, int64_t maxM)
 {
-    if (s > GEMM_MAXS) return hipErrorInvalidValue;
-    dim3 grid((unsigned)((maxM + 63) / 64), (unsigned)((s + GEMM_ROWS - 1) / GEMM_ROWS), (unsigned)ntasks);
-    hipLaunchKernelGGL((k_gemm_update<T>), grid, dim3(256), 0, st, d_tasks);
+    if (s > DENSE_MAXS) return hipErrorInvalidValue;
+    dim3 grid((unsigned)((maxM + 255) / 256), (unsigned)((s + DENSE_RB - 1) / DENSE_RB), (unsigned)ntasks);
+    if (s <= 4)
+        hipLaunchKernelGGL((k_dense_update<T, 4>), grid, dim3(256), 0, st, d_tasks);
+    else if (s <= 8)
+        hipLaunchKernelGGL((k_dense_update<T, 8>), grid, dim3(256), 0, st, d_tasks);
+    else if (s <= 16)
+        hipLaunchKernelGGL((k_dense_update<T, 16>), grid, dim3(256), 0, st, d_tasks);
+    else if (s <= 32)
+        hipLaunchKernelGGL((k_dense_update<T, 32>), grid, dim3(256), 0, st, d_tasks);
+    else
+        hipLaunchKernelGGL((k_dense_update<T, 64>), grid, dim3(256), 0, st, d_tasks);
     return hipGetLastError();
 }
 

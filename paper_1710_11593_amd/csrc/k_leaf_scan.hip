@@ -134,7 +134,6 @@ template <int NT, int PT, int L, bool MIXED, bool VEC>
 __global__ __launch_bounds__(NT) void k_leaf_scan(const LeafTask *__restrict__ tasks)
 {
     static_assert(PT % 2 == 0 && PT <= 16, "rows per thread must be even and at most 16");
-    constexpr int NW = NT / 64;
     constexpr int NR = NT / 16;  // rows of 16 lanes in the workgroup (<= 32)
     static_assert(NR <= 32, "at most 512 threads");
     constexpr int MP = NT * PT;
@@ -157,6 +156,13 @@ __global__ __launch_bounds__(NT) void k_leaf_scan(const LeafTask *__restrict__ t
     // thread's rows are either all inside [0, M) or all outside.
     const bool act = c0 < M;
 
+    // per-row coefficients first (their latency overlaps the field loads)
+    double al[PT], be[PT];
+#pragma unroll
+    for (int k = 0; k < PT; ++k) {
+        al[k] = tab[SCAN_TAB_ALPHA + c0 + k];
+        be[k] = tab[SCAN_TAB_ALPHA + MP + c0 + k];
+    }
     // right-hand sides of the leaf's rows (row r of the leaf in acc[r])
     double acc[L][PT];
 #pragma unroll
@@ -185,6 +191,7 @@ __global__ __launch_bounds__(NT) void k_leaf_scan(const LeafTask *__restrict__ t
         }
     }
 
+    // uniform constants
     const double K0 = tab[0];
     const double rho = tab[1];
     double mp[4];  // m^(1,2,4,8): lane steps inside a row
@@ -196,12 +203,9 @@ __global__ __launch_bounds__(NT) void k_leaf_scan(const LeafTask *__restrict__ t
     double rp[PT];  // rho^(k+1)
 #pragma unroll
     for (int k = 0; k < PT; ++k) rp[k] = tab[SCAN_TAB_POW + k];
-    double al[PT], be[PT];
+    double aw[L];
 #pragma unroll
-    for (int k = 0; k < PT; ++k) {
-        al[k] = tab[SCAN_TAB_ALPHA + c0 + k];
-        be[k] = tab[SCAN_TAB_ALPHA + MP + c0 + k];
-    }
+    for (int m = 0; m < L; ++m) aw[m] = (m > 0) ? gptr(tk.a)[m] : 0.0;
     // lane multipliers: m^rl and m^(15-rl) (row carries into a thread);
     // c^((lane&15)+1) for the row_bcast:15 step and c^(16-lane) for the
     // backward step of the row scan (both used only on lanes < NR)
@@ -210,27 +214,60 @@ __global__ __launch_bounds__(NT) void k_leaf_scan(const LeafTask *__restrict__ t
     const double m_hi = pow_bits(mpw, 15 - rl);
     const double c_b15 = pow_bits(cp, (lane & 15) + 1);
     const double c_bk = pow_bits(cp, 16 - (lane & 15));
-    double aw[L];
+
+    double xp[PT];  // solution of the previous step, pushed and stored during this step
 #pragma unroll
-    for (int m = 0; m < L; ++m) aw[m] = (m > 0) ? gptr(tk.a)[m] : 0.0;
+    for (int k = 0; k < PT; ++k) xp[k] = 0.0;
 
 #pragma unroll
-    for (int r = 0; r < L; ++r) {
-        if (r >= nrows) break;
+    for (int r = 0; r <= L; ++r) {
+        const bool run = r < L && r < nrows;
         const int par = r & 1;
-        // carry-free local prefix l and suffix s of the thread's rows
         double lf[PT], sb[PT];
-        lf[0] = al[0] * acc[r][0];
+        double Sf = 0.0, Sb = 0.0;
+        if (run) {
+            // carry-free local prefix l and suffix s of the thread's rows
+            lf[0] = al[0] * acc[r][0];
 #pragma unroll
-        for (int k = 1; k < PT; ++k) lf[k] = fma(rho, lf[k - 1], al[k] * acc[r][k]);
-        sb[PT - 1] = be[PT - 1] * acc[r][PT - 1];
+            for (int k = 1; k < PT; ++k) lf[k] = fma(rho, lf[k - 1], al[k] * acc[r][k]);
+            sb[PT - 1] = be[PT - 1] * acc[r][PT - 1];
 #pragma unroll
-        for (int k = PT - 2; k >= 0; --k) sb[k] = fma(rho, sb[k + 1], be[k] * acc[r][k]);
-        // thread totals and their row scans (multiplier m per lane)
-        double Sf = lf[PT - 1], Sb = rho * sb[0];
-        row_scans<16>(Sf, Sb, mp);
-        if (rl == 15) sR[par][0][G] = Sf;
-        if (rl == 0) sR[par][1][G] = Sb;
+            for (int k = PT - 2; k >= 0; --k) sb[k] = fma(rho, sb[k + 1], be[k] * acc[r][k]);
+            // thread totals and their row scans (multiplier m per lane)
+            Sf = lf[PT - 1];
+            Sb = rho * sb[0];
+            row_scans<16>(Sf, Sb, mp);
+            if (rl == 15) sR[par][0][G] = Sf;
+            if (rl == 0) sR[par][1][G] = Sb;
+        }
+        // deferred work of the previous step: store its solution row and
+        // push it into the right-hand sides beyond the next row (the next
+        // row itself was updated right after the solve)
+        if (r > 0 && r - 1 < nrows) {
+            FS_G double *row = u + (int64_t)(r - 1) * M + c0;
+            if (VEC) {
+                if (act) {
+#pragma unroll
+                    for (int i = 0; i < UT; ++i)
+                        reinterpret_cast<FS_G double2 *>(row)[i] = double2{xp[2 * i], xp[2 * i + 1]};
+                }
+            } else {
+#pragma unroll
+                for (int k = 0; k < PT; ++k)
+                    if (c0 + k < M) row[k] = xp[k];
+            }
+            if (MIXED) {
+#pragma unroll
+                for (int k = 0; k < PT; ++k)
+                    if (c0 + k < M) x32[(int64_t)(r - 1) * M + c0 + k] = (float)xp[k];
+            }
+#pragma unroll
+            for (int j = r + 1; j < L; ++j) {
+#pragma unroll
+                for (int k = 0; k < PT; ++k) acc[j][k] = fma(-aw[j - r + 1], xp[k], acc[j][k]);
+            }
+        }
+        if (!run) break;
         __syncthreads();
         // scan of the NR row totals (multiplier c = m^16 per row) on lanes < NR
         double vf = (lane < NR) ? sR[par][0][lane] : 0.0;
@@ -251,36 +288,17 @@ __global__ __launch_bounds__(NT) void k_leaf_scan(const LeafTask *__restrict__ t
         const double cf = fma(m_lo, Cr, dpp_move<0x111>(Sf));
         const double cb = fma(m_hi, Dr, dpp_move<0x101>(Sb));
         // unfold
-        double x[PT];
 #pragma unroll
         for (int k = 0; k < PT; ++k) {
             const double P = fma(rp[k], cf, lf[k]);
             const double Q = (k < PT - 1) ? fma(rho, sb[k + 1 < PT ? k + 1 : k], rp[PT - 2 - k >= 0 ? PT - 2 - k : 0] * cb)
                                           : cb;
-            x[k] = K0 * fma(be[k], P, al[k] * Q);
+            xp[k] = K0 * fma(be[k], P, al[k] * Q);
         }
-        FS_G double *row = u + (int64_t)r * M + c0;
-        if (VEC) {
-            if (act) {
+        // the next row's right-hand side needs x_r now
+        if (r + 1 < L) {
 #pragma unroll
-                for (int i = 0; i < UT; ++i)
-                    reinterpret_cast<FS_G double2 *>(row)[i] = double2{x[2 * i], x[2 * i + 1]};
-            }
-        } else {
-#pragma unroll
-            for (int k = 0; k < PT; ++k)
-                if (c0 + k < M) row[k] = x[k];
-        }
-        if (MIXED) {
-#pragma unroll
-            for (int k = 0; k < PT; ++k)
-                if (c0 + k < M) x32[(int64_t)r * M + c0 + k] = (float)x[k];
-        }
-        // push x_r into the right-hand sides of the later rows of the leaf
-#pragma unroll
-        for (int j = r + 1; j < L; ++j) {
-#pragma unroll
-            for (int k = 0; k < PT; ++k) acc[j][k] = fma(-aw[j - r], x[k], acc[j][k]);
+            for (int k = 0; k < PT; ++k) acc[r + 1][k] = fma(-aw[1], xp[k], acc[r + 1][k]);
         }
     }
 }
