@@ -44,6 +44,39 @@ __device__ __forceinline__ cplx<T> cmulc(cplx<T> a, cplx<T> b)
     return {a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y};
 }
 
+// Column order of the solver's internal fields.  The scan leaf gives each
+// thread PT consecutive spatial columns; so that a wave's 16-byte accesses
+// to them are contiguous in memory, every full block of B = 64 PT columns is
+// stored transposed: memory offset o = 128 j + 2 i + e (j < PT/2, i < 64,
+// e < 2) holds spatial offset PT i + 2 j + e.  Columns from mfull on, and all
+// columns when pt <= 2, keep the natural order.  Only the leaf and the
+// tridiagonal part of the operator look at spatial neighbours; the level
+// products treat columns independently, so they run unchanged.
+struct ColPerm {
+    int pt;        // rows per leaf thread (0 or <= 2: natural order)
+    int64_t mfull; // columns covered by full blocks
+};
+
+__host__ __device__ inline int64_t perm_s2m(int64_t x, ColPerm p)
+{
+    if (p.pt <= 2 || x >= p.mfull) return x;
+    const int64_t B = 64 * (int64_t)p.pt;
+    const int64_t blk = x / B;
+    const int s = (int)(x - blk * B);
+    const int i = s / p.pt, j = (s % p.pt) >> 1, e = s & 1;
+    return blk * B + 128 * j + 2 * i + e;
+}
+
+__host__ __device__ inline int64_t perm_m2s(int64_t c, ColPerm p)
+{
+    if (p.pt <= 2 || c >= p.mfull) return c;
+    const int64_t B = 64 * (int64_t)p.pt;
+    const int64_t blk = c / B;
+    const int o = (int)(c - blk * B);
+    const int j = o >> 7, i = (o & 127) >> 1, e = o & 1;
+    return blk * B + (int64_t)p.pt * i + 2 * j + e;
+}
+
 // One leaf of the recursion: rows [lo, lo+nrows) of one instance, solved by
 // forward substitution in time with a tridiagonal solve per row.
 struct LeafTask {
@@ -55,7 +88,7 @@ struct LeafTask {
     int64_t M;
     int64_t lo;
     int32_t nrows;
-    int32_t pad;
+    int32_t perm;       // fields in the transposed column order of ColPerm (scan leaf)
 };
 
 // One off-diagonal Toeplitz-block product:
@@ -132,8 +165,13 @@ hipError_t launch_spectrum(hipStream_t st, const double *w, int s, cplx<double> 
 int fft_max_single_pass(bool fp32);
 
 hipError_t launch_diag_apply(hipStream_t st, const double *x, double *y, const double *a, double e, int64_t M,
-                             int64_t N, int L);
+                             int64_t N, int L, ColPerm perm);
 hipError_t launch_copy_reverse(hipStream_t st, const double *src, double *dst, int64_t M, int64_t N);
+// dst row n = src row (reverse ? N-1-n : n) with the columns moved from
+// natural to internal order (to_internal) or back.  src == dst is allowed
+// without reverse.
+hipError_t launch_permute(hipStream_t st, const double *src, double *dst, int64_t M, int64_t N, ColPerm perm,
+                          bool to_internal, bool reverse);
 hipError_t launch_axpy(hipStream_t st, double *y, const double *x, double alpha, int64_t n);
 hipError_t launch_sub(hipStream_t st, double *r, const double *b, const double *y, int64_t n);
 hipError_t launch_to_f32(hipStream_t st, const double *x, float *y, int64_t n);

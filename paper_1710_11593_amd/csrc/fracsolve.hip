@@ -34,6 +34,7 @@ struct Inst {
     int64_t M = 0, N = 0, Np = 0;
     LeafCfg lc{};
     bool scan = true;  // leaf solver: closed-form scan (true) or block Thomas + PCR
+    ColPerm perm{0, 0};  // internal column order of the solve's fields
     double *b = nullptr, *a = nullptr, *rho = nullptr, *psi = nullptr;
     double *da = nullptr, *drho = nullptr, *dpsi = nullptr;
     double *fac = nullptr;
@@ -389,6 +390,7 @@ void build_solve(fracsolve_ctx *h, const std::vector<int> &sel, const std::vecto
             t.M = in.M;
             t.lo = lo;
             t.nrows = (int)std::min<int64_t>(L, in.N - lo);
+            t.perm = (in.perm.pt > 2 && in.perm.mfull > 0) ? 1 : 0;
             // whole 16-byte row units for the scan leaf
             const bool vec = in.scan && (in.M % in.lc.pt) == 0 && ((uintptr_t)t.u & 15) == 0;
             lt.push_back({(in.scan ? 1000000 : 0) + (vec ? 200000 : 0) + in.lc.nt * 100 + in.lc.pt, t});
@@ -565,10 +567,11 @@ int dc_solve(fracsolve_ctx *h, const std::vector<int> &sel, const std::vector<Fi
 
 // y = A x in float64 (deriv: y = (dA/dgamma) x, i.e. weights a' and no K).
 // x and y are distinct [N][M] device arrays of instance i.
-int apply_op(fracsolve_ctx *h, int i, const double *x, double *y, bool deriv)
+// x and y are in the column order perm (natural order: {0, 0}).
+int apply_op(fracsolve_ctx *h, int i, const double *x, double *y, bool deriv, ColPerm perm)
 {
     Inst &in = h->inst[i];
-    HIPCHK(h, launch_diag_apply(h->st, x, y, deriv ? in.da : in.a, deriv ? 0.0 : in.e, in.M, in.N, h->L));
+    HIPCHK(h, launch_diag_apply(h->st, x, y, deriv ? in.da : in.a, deriv ? 0.0 : in.e, in.M, in.N, h->L, perm));
     h->kernels++;
     DescBuilder db{h, {}};
     std::vector<Op> ops;
@@ -655,6 +658,8 @@ int setup_instance(fracsolve_ctx *h, Inst &in)
     in.dcoef = in.coef * (-std::log(in.tau) + digamma_host(garg));
     in.scan = (h->opts.leaf_solver == 0);
     in.lc = in.scan ? scan_config(in.M) : leaf_config(in.M);
+    if (in.scan && in.lc.pt > 2 && in.M % in.lc.pt == 0)
+        in.perm = ColPerm{in.lc.pt, (in.M / (64 * (int64_t)in.lc.pt)) * 64 * (int64_t)in.lc.pt};
     if (h->L > 8 && ((in.scan && in.lc.pt > 2) || (!in.scan && in.lc.pt == 16)))
         return fail(h, FRACSOLVE_E_ARG, "leaf size %d is not available for M = %lld (use 4 or 8)", h->L,
                     (long long)in.M);
@@ -731,11 +736,28 @@ int solve_all(fracsolve_ctx *h, const double *const *f, const double *const *u0,
         const double *ph = (in.regime == 1) ? opt_ptr(phi, k) : nullptr;
         HIPCHK(h, launch_rhs(h->st, f[k], opt_ptr(u0, k), ph, in.rho, in.psi, u[k], in.M, in.N));
         h->kernels++;
+        // to the internal column order (in place)
+        if (in.perm.mfull > 0) {
+            HIPCHK(h, launch_permute(h->st, u[k], u[k], in.M, in.N, in.perm, true, false));
+            h->kernels++;
+        }
     }
+    // back to the natural column order (in place)
+    auto restore = [&]() -> int {
+        for (size_t k = 0; k < cnt; ++k) {
+            Inst &in = h->inst[k];
+            if (in.perm.mfull > 0) {
+                HIPCHK(h, launch_permute(h->st, u[k], u[k], in.M, in.N, in.perm, false, false));
+                h->kernels++;
+            }
+        }
+        return FRACSOLVE_OK;
+    };
     if (prec == FRACSOLVE_FP64) {
         std::vector<Field> fld(cnt);
         for (size_t k = 0; k < cnt; ++k) fld[k] = {u[k], nullptr, nullptr};
-        return dc_solve(h, sel, fld, FRACSOLVE_FP64);
+        if ((rc = dc_solve(h, sel, fld, FRACSOLVE_FP64))) return rc;
+        return restore();
     }
     // mixed: float32 products, float64 leaves; then refinement steps
     std::vector<Field> fld(cnt);
@@ -754,7 +776,7 @@ int solve_all(fracsolve_ctx *h, const double *const *f, const double *const *u0,
         // W = R - A U ; solve A D = W (mixed) ; U += D
         for (size_t k = 0; k < cnt; ++k) {
             Inst &in = h->inst[k];
-            if ((rc = apply_op(h, (int)k, u[k], in.V, false))) return rc;
+            if ((rc = apply_op(h, (int)k, u[k], in.V, false, in.perm))) return rc;
             HIPCHK(h, launch_sub(h->st, in.W, in.R, in.V, in.M * in.N));
             h->kernels++;
             fld[k] = {in.W, in.hist32, in.x32};
@@ -771,7 +793,7 @@ int solve_all(fracsolve_ctx *h, const double *const *f, const double *const *u0,
             h->kernels++;
         }
     }
-    return FRACSOLVE_OK;
+    return restore();
 }
 
 }  // namespace
@@ -952,7 +974,7 @@ int fracsolve_apply(fracsolve_t h, const double *const *u, double *const *y)
         if ((const void *)u[k] == (const void *)y[k]) return fail(h, FRACSOLVE_E_ARG, "u[%zu] and y[%zu] alias", k, k);
     hipEvent_t ev[2];
     if ((rc = timed_begin(h, ev))) return rc;
-    for (size_t k = 0; k < h->inst.size() && !rc; ++k) rc = apply_op(h, (int)k, u[k], y[k], false);
+    for (size_t k = 0; k < h->inst.size() && !rc; ++k) rc = apply_op(h, (int)k, u[k], y[k], false, ColPerm{0, 0});
     return timed_end(h, ev, rc);
 }
 
@@ -974,7 +996,8 @@ int fracsolve_adjoint(fracsolve_t h, const double *const *g, const double *const
         sel[k] = (int)k;
         if ((rc = ensure(h, &in.W, in.M * in.N))) break;
         // reversed time: lambda~^m = lambda^{N-1-m} solves the same lower-triangular system
-        if (launch_copy_reverse(h->st, g[k], in.W, in.M, in.N) != hipSuccess) {
+        // (and the internal column order of the solve)
+        if (launch_permute(h->st, g[k], in.W, in.M, in.N, in.perm, true, true) != hipSuccess) {
             rc = fail(h, FRACSOLVE_E_DEVICE, "launch failed");
             break;
         }
@@ -983,7 +1006,7 @@ int fracsolve_adjoint(fracsolve_t h, const double *const *g, const double *const
     if (!rc) rc = dc_solve(h, sel, fld, FRACSOLVE_FP64);
     for (size_t k = 0; k < cnt && !rc; ++k) {
         Inst &in = h->inst[k];
-        if (launch_copy_reverse(h->st, in.W, dL_df[k], in.M, in.N) != hipSuccess)
+        if (launch_permute(h->st, in.W, dL_df[k], in.M, in.N, in.perm, false, true) != hipSuccess)
             rc = fail(h, FRACSOLVE_E_DEVICE, "launch failed");
     }
     if (!rc && dL_dgamma) {
@@ -991,7 +1014,7 @@ int fracsolve_adjoint(fracsolve_t h, const double *const *g, const double *const
             Inst &in = h->inst[k];
             if ((rc = ensure(h, &in.V, in.M * in.N))) break;
             // V = (dA/dgamma) U
-            if ((rc = apply_op(h, (int)k, u[k], in.V, true))) break;
+            if ((rc = apply_op(h, (int)k, u[k], in.V, true, ColPerm{0, 0}))) break;
             double t1 = 0.0, t2 = 0.0;
             HIPCHK(h, launch_dot_partial(h->st, dL_df[k], in.V, in.M * in.N, h->partial, kRedBlocks));
             if ((rc = finish_sum(h, kRedBlocks, &t1))) break;

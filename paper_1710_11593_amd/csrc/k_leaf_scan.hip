@@ -26,7 +26,10 @@
 // lanes of every wave; each lane then fetches its row's carry with a lane
 // permute.  The whole leaf (L steps) is unrolled: the in-leaf history
 // sum_{j<n} a_{n-j} x_j is pushed into the later rows' right-hand sides in
-// registers right after x_j is known, touching only rows still in the leaf.
+// registers (the next row at once, the rest together with the store of x_j
+// during the following step), touching only rows still in the leaf.  The
+// fields are read and written in the internal column order of ColPerm, so
+// that each wave's row accesses are contiguous.
 #include "common.hpp"
 
 namespace fs {
@@ -155,6 +158,14 @@ __global__ __launch_bounds__(NT) void k_leaf_scan(const LeafTask *__restrict__ t
     // VEC: M is a multiple of PT and the field is 16-byte aligned, so a
     // thread's rows are either all inside [0, M) or all outside.
     const bool act = c0 < M;
+    // Memory column of the thread's element k.  In the internal column order
+    // (tk.perm) a full block of 64 PT columns belongs to one wave, and pair
+    // j of lane i sits at 128 j + 2 i, so each of the wave's 16-byte
+    // accesses covers 1 KB of contiguous memory.
+    constexpr int64_t B = 64 * PT;
+    const bool pf = tk.perm && (int64_t)((t >> 6) + 1) * B <= M;
+    const int64_t cw = (int64_t)(t >> 6) * B + 2 * lane;
+    auto col = [&](int k) -> int64_t { return pf ? cw + 128 * (k >> 1) + (k & 1) : (int64_t)c0 + k; };
 
     // per-row coefficients first (their latency overlaps the field loads)
     double al[PT], be[PT];
@@ -167,12 +178,12 @@ __global__ __launch_bounds__(NT) void k_leaf_scan(const LeafTask *__restrict__ t
     double acc[L][PT];
 #pragma unroll
     for (int r = 0; r < L; ++r) {
-        FS_G const double *row = u + (int64_t)r * M + c0;
+        FS_G const double *row = u + (int64_t)r * M;
         if (VEC) {
             if (r < nrows && act) {
 #pragma unroll
                 for (int i = 0; i < UT; ++i) {
-                    const double2 v = reinterpret_cast<FS_G const double2 *>(row)[i];
+                    const double2 v = *reinterpret_cast<FS_G const double2 *>(row + col(2 * i));
                     acc[r][2 * i] = v.x;
                     acc[r][2 * i + 1] = v.y;
                 }
@@ -182,12 +193,12 @@ __global__ __launch_bounds__(NT) void k_leaf_scan(const LeafTask *__restrict__ t
             }
         } else {
 #pragma unroll
-            for (int k = 0; k < PT; ++k) acc[r][k] = (r < nrows && c0 + k < M) ? row[k] : 0.0;
+            for (int k = 0; k < PT; ++k) acc[r][k] = (r < nrows && c0 + k < M) ? row[col(k)] : 0.0;
         }
         if (MIXED && r < nrows) {
 #pragma unroll
             for (int k = 0; k < PT; ++k)
-                if (c0 + k < M) acc[r][k] += (double)hist[(int64_t)r * M + c0 + k];
+                if (c0 + k < M) acc[r][k] += (double)hist[(int64_t)r * M + col(k)];
         }
     }
 
@@ -244,22 +255,22 @@ __global__ __launch_bounds__(NT) void k_leaf_scan(const LeafTask *__restrict__ t
         // push it into the right-hand sides beyond the next row (the next
         // row itself was updated right after the solve)
         if (r > 0 && r - 1 < nrows) {
-            FS_G double *row = u + (int64_t)(r - 1) * M + c0;
+            FS_G double *row = u + (int64_t)(r - 1) * M;
             if (VEC) {
                 if (act) {
 #pragma unroll
                     for (int i = 0; i < UT; ++i)
-                        reinterpret_cast<FS_G double2 *>(row)[i] = double2{xp[2 * i], xp[2 * i + 1]};
+                        *reinterpret_cast<FS_G double2 *>(row + col(2 * i)) = double2{xp[2 * i], xp[2 * i + 1]};
                 }
             } else {
 #pragma unroll
                 for (int k = 0; k < PT; ++k)
-                    if (c0 + k < M) row[k] = xp[k];
+                    if (c0 + k < M) row[col(k)] = xp[k];
             }
             if (MIXED) {
 #pragma unroll
                 for (int k = 0; k < PT; ++k)
-                    if (c0 + k < M) x32[(int64_t)(r - 1) * M + c0 + k] = (float)xp[k];
+                    if (c0 + k < M) x32[(int64_t)(r - 1) * M + col(k)] = (float)xp[k];
             }
 #pragma unroll
             for (int j = r + 1; j < L; ++j) {

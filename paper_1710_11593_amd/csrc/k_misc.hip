@@ -1,5 +1,7 @@
 // Streaming kernels of the solver: right-hand-side assembly, the diagonal
 // (within-leaf) part of the operator apply, time reversal, reductions.
+#include <algorithm>
+
 #include "common.hpp"
 
 namespace fs {
@@ -62,8 +64,10 @@ hipError_t launch_rhs_scale(hipStream_t st, double *y, const double *u0, const d
 // with K = e tridiag(-1,2,-1) (e = 0 drops K: used for the gamma-derivative
 // of the operator, whose K part does not depend on gamma).
 // The off-diagonal blocks between leaves are added by the level products.
+// Fields in internal column order (perm): the spatial neighbours of memory
+// column c are found through the order's maps.
 __global__ void k_diag_apply(const double *__restrict__ x, double *__restrict__ y, const double *__restrict__ a,
-                             double e, int64_t M, int64_t N, int L)
+                             double e, int64_t M, int64_t N, int L, ColPerm perm)
 {
     const double a0 = a[0];
     int64_t total = M * N;
@@ -71,8 +75,9 @@ __global__ void k_diag_apply(const double *__restrict__ x, double *__restrict__ 
          idx += (int64_t)gridDim.x * blockDim.x) {
         int64_t n = idx / M, i = idx - n * M;
         const double *xn = x + n * M;
-        double left = (i > 0) ? xn[i - 1] : 0.0;
-        double right = (i + 1 < M) ? xn[i + 1] : 0.0;
+        const int64_t xs = perm_m2s(i, perm);
+        double left = (xs > 0) ? xn[perm_s2m(xs - 1, perm)] : 0.0;
+        double right = (xs + 1 < M) ? xn[perm_s2m(xs + 1, perm)] : 0.0;
         double v = (a0 + 2.0 * e) * xn[i] - e * (left + right);
         int64_t lo = (n / L) * L;
         for (int64_t j = lo; j < n; ++j) v += a[n - j] * x[j * M + i];
@@ -81,10 +86,61 @@ __global__ void k_diag_apply(const double *__restrict__ x, double *__restrict__ 
 }
 
 hipError_t launch_diag_apply(hipStream_t st, const double *x, double *y, const double *a, double e, int64_t M,
-                             int64_t N, int L)
+                             int64_t N, int L, ColPerm perm)
 {
     int64_t total = M * N;
-    hipLaunchKernelGGL(k_diag_apply, dim3(nblocks_for(total, 256)), dim3(256), 0, st, x, y, a, e, M, N, L);
+    hipLaunchKernelGGL(k_diag_apply, dim3(nblocks_for(total, 256)), dim3(256), 0, st, x, y, a, e, M, N, L, perm);
+    return hipGetLastError();
+}
+
+// Column reordering between natural and internal order, one block of
+// B = 64 pt columns of one row per pass of a workgroup, staged in LDS so that
+// both the reads and the writes are contiguous (and src == dst is safe).
+// Columns past the full blocks are copied unchanged.
+__global__ __launch_bounds__(256) void k_permute(const double *src, double *dst, int64_t M, int64_t N,
+                                                 ColPerm perm, int to_internal, int reverse)
+{
+    __shared__ double sb[1024];
+    const int64_t B = 64 * (int64_t)perm.pt;
+    const int64_t nblk = perm.mfull / B;
+    const int64_t tail = M - perm.mfull;
+    const int64_t units = N * (nblk + (tail > 0 ? 1 : 0));
+    for (int64_t u = blockIdx.x; u < units; u += gridDim.x) {
+        const int64_t per = nblk + (tail > 0 ? 1 : 0);
+        const int64_t n = u / per, b = u - n * per;
+        const double *sr = src + (reverse ? (N - 1 - n) : n) * M;
+        double *dr = dst + n * M;
+        if (b == nblk) {
+            // natural-order tail (read completely before any write: in place is a no-op)
+            if (sr != dr)
+                for (int64_t c = perm.mfull + threadIdx.x; c < M; c += blockDim.x) dr[c] = sr[c];
+            continue;
+        }
+        const int64_t base = b * B;
+        for (int k = threadIdx.x; k < B; k += blockDim.x) sb[k] = sr[base + k];
+        __syncthreads();
+        for (int k = threadIdx.x; k < B; k += blockDim.x) {
+            const int64_t from = to_internal ? perm_m2s(base + k, perm) : perm_s2m(base + k, perm);
+            dr[base + k] = sb[from - base];
+        }
+        __syncthreads();
+    }
+}
+
+hipError_t launch_permute(hipStream_t st, const double *src, double *dst, int64_t M, int64_t N, ColPerm perm,
+                          bool to_internal, bool reverse)
+{
+    if (perm.pt <= 2 || perm.mfull == 0) {
+        if (reverse) return launch_copy_reverse(st, src, dst, M, N);
+        if (src != dst) return hipMemcpyAsync(dst, src, sizeof(double) * (size_t)(M * N), hipMemcpyDeviceToDevice, st);
+        return hipSuccess;
+    }
+    if (64 * (int64_t)perm.pt > 1024 || (reverse && src == dst)) return hipErrorInvalidValue;
+    const int64_t nblk = perm.mfull / (64 * (int64_t)perm.pt);
+    const int64_t units = N * (nblk + (M > perm.mfull ? 1 : 0));
+    const unsigned g = (unsigned)std::min<int64_t>(units, 65535LL * 8);
+    hipLaunchKernelGGL(k_permute, dim3(g), dim3(256), 0, st, src, dst, M, N, perm, to_internal ? 1 : 0,
+                       reverse ? 1 : 0);
     return hipGetLastError();
 }
 
