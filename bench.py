@@ -48,6 +48,25 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def recorded_traffic(kernel: str, M: int):
+    """HBM bytes per launch of `kernel` recorded in profiles/ (FETCH_SIZE and
+    WRITE_SIZE passes scaled by the copy calibration), or None when there is no
+    record for this M or the FFT source changed since it was taken."""
+    import hashlib
+    import re
+
+    path = os.path.join(ROOT, "profiles", "fft_level_traffic_M%d.md" % M)
+    src = os.path.join(ROOT, "paper_1710_11593_amd", "csrc", "k_fft.hip")
+    if not os.path.exists(path):
+        return None
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    for line in open(path):
+        m = re.match(r'traffic: kernel="(.*)" s=(\d+) bytes_per_launch=(\d+) k_fft_sha=(\w+)', line.strip())
+        if m and m.group(1) == kernel and m.group(4) == sha:
+            return float(m.group(3))
+    return None
+
+
 def build_instance(args):
     from paper_1710_11593_amd import workloads as wl
 
@@ -97,7 +116,21 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true")
     ap.add_argument("--out", default="")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain device copy of 512 MiB (3 times), the reference kernel for "
+                         "scaling HBM counters (FETCH_SIZE / WRITE_SIZE) taken with rocprofv3 --pmc")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+
+        n = (512 << 20) // 8
+        a = torch.ones(n, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8, "launches": 3}))
+        return
 
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (instances would shard "
@@ -184,12 +217,13 @@ def main():
         per_launch_ms = dom["ms"] / dom["launches"]
         per_launch_bytes = dom["bytes"] / dom["launches"]
         achieved = per_launch_bytes / (per_launch_ms * 1e-3) / 1e9
+        kname = ("fs::" + FFT64_NAMES[2 * dom["s"]]) if (prec == "fp64" and 2 * dom["s"] in FFT64_NAMES) \
+            else "fft_f32 s=%d" % dom["s"]
+        traffic = recorded_traffic(kname, M) if prec == "fp64" else None
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": FFT64_NAMES.get(2 * dom["s"], "fft level s=%d" % dom["s"]) if prec == "fp64"
-                else "fft_f32 s=%d" % dom["s"],
-                "level_s": dom["s"], "launches": dom["launches"], "avg_us": round(per_launch_ms * 1e3, 2),
-                "bytes_per_launch": per_launch_bytes}
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "kernel": kname, "level_s": dom["s"], "launches": dom["launches"],
+                "avg_us": round(per_launch_ms * 1e3, 2), "bytes_per_launch": per_launch_bytes}
     leaf = [g for g in ks if g["kind"] == "leaf"]
     leaf_ms = sum(g["ms"] for g in leaf)
 
