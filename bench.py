@@ -36,11 +36,12 @@ HBM_PEAK_GBS = 8000.0
 
 # single-pass FFT kernel instantiations (k_fft.hip): n -> template text
 FFT64_NAMES = {
-    8: "k_fft2<double, 4, 2, 8, 0>", 16: "k_fft2<double, 4, 4, 8, 0>", 32: "k_fft2<double, 8, 4, 8, 0>",
-    64: "k_fft2<double, 8, 8, 8, 0>", 128: "k_fft2<double, 16, 8, 8, 0>", 256: "k_fft2<double, 16, 16, 8, 0>",
-    512: "k_fft2<double, 32, 16, 8, 0>", 1024: "k_fft2<double, 32, 32, 8, 0>",
-    2048: "k_fft3<double, 16, 16, 8, 4, 0>", 4096: "k_fft3<double, 16, 16, 16, 2, 0>",
-    8192: "k_fft3<double, 32, 16, 16, 1, 0>",
+    8: "k_fft2u<double, 4, 2, 8, true>", 16: "k_fft2u<double, 4, 4, 8, true>",
+    32: "k_fft2u<double, 8, 4, 8, true>", 64: "k_fft2u<double, 8, 8, 8, true>",
+    128: "k_fft2u<double, 16, 8, 8, true>", 256: "k_fft2u<double, 16, 16, 8, true>",
+    512: "k_fft3u<double, 16, 8, 4, 8, 256, true>", 1024: "k_fft3u<double, 16, 8, 8, 8, 256, true>",
+    2048: "k_fft3u<double, 16, 16, 8, 4, 256, true>", 4096: "k_fft3u<double, 16, 16, 16, 2, 256, true>",
+    8192: "k_fft3u<double, 16, 16, 32, 1, 256, true>",
 }
 
 
@@ -99,6 +100,168 @@ def modal_factors(inst):
     return js, G, [series[j][1] for j in js], [series[j][2] for j in js]
 
 
+def device_inputs(inst, dev):
+    """f = G S (built on the device), u0, phi and the modal factors of inst."""
+    import numpy as np
+    import torch
+
+    from paper_1710_11593_amd import workloads as wl
+
+    js, G, c_u0, c_phi = modal_factors(inst)
+    x, _, _, _ = wl.grid(inst.M, inst.N)
+    S = np.stack([np.sin(j * math.pi * x) for j in js])
+    Sd = torch.from_numpy(S).to(dev)
+    f = (torch.from_numpy(G).to(dev) @ Sd).contiguous()
+    u0 = torch.from_numpy(np.asarray(c_u0) @ S).to(dev)
+    phi = torch.from_numpy(np.asarray(c_phi) @ S).to(dev)
+    return dict(f=f, u0=u0, phi=phi, js=js, G=G, c_u0=c_u0, c_phi=c_phi, Sd=Sd)
+
+
+def mode_error(inst, d, u, threads=16):
+    """Max-norm relative error of u against the oracle through single-mode
+    reduction (each source mode's discrete solution from the oracle's scalar
+    recurrence)."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    import numpy as np
+    import torch
+
+    import oracle
+    from paper_1710_11593_amd import workloads as wl
+
+    if "V" not in d:  # the oracle's modal time series, computed once per instance
+        _, _, h, _ = wl.grid(inst.M, inst.N)
+        js, G = d["js"], d["G"]
+        lam = [4.0 / h ** 2 * math.sin(j * math.pi * h / 2) ** 2 for j in js]
+        with ThreadPoolExecutor(max_workers=min(threads, len(js))) as ex:
+            vs = list(ex.map(lambda k: oracle.mode(inst.gamma, inst.T, inst.N, lam[k], G[:, k], d["c_u0"][k],
+                                                   d["c_phi"][k]), range(len(js))))
+        d["V"] = torch.from_numpy(np.stack(vs, axis=1)).to(u.device)
+    ref = d["V"] @ d["Sd"]
+    return float((u - ref).abs().max() / ref.abs().max())
+
+
+def timed(fn, reps):
+    import torch
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) * 1e3 / reps
+
+
+def run_forms(dev):
+    """The other forms of the metric, each against the plain float64 GPU solve
+    of the same instances: mixed precision (c3), batching (c4) and the adjoint
+    (c5).  Returns a dict for the JSON line."""
+    import numpy as np
+    import torch
+
+    from paper_1710_11593_amd import binding, workloads as wl
+
+    out = {}
+    # c3: diffusion-wave, float64 vs float32 products + one refinement step
+    inst = wl.c3(build=False)
+    d = device_inputs(inst, dev)
+    u = torch.empty_like(d["f"])
+    res = {}
+    for prec, ref in (("fp64", 0), ("fp32", 1)):
+        sv = binding.Solver([dict(gamma=inst.gamma, M=inst.M, N=inst.N)], precision=prec, refine_steps=ref)
+        run = lambda: sv.solve([d["f"]], [d["u0"]], [d["phi"]], out=[u])  # noqa: E731
+        run()
+        ms = timed(run, 2)
+        err = mode_error(inst, d, u)
+        res[prec] = {"ms": round(ms, 2), "unknowns_per_s": inst.M * inst.N / (ms * 1e-3), "error_vs_oracle": err,
+                     "refine_steps": ref}
+        sv.close()
+        log("forms: c3 %s %.1f ms, err %.3e" % (prec, ms, err))
+    out["c3_mixed_fp32"] = res["fp32"]
+    out["c3_fp64"] = res["fp64"]
+    out["mixed_speedup_vs_fp64"] = round(res["fp64"]["ms"] / res["fp32"]["ms"], 3)
+    del d, u
+    torch.cuda.empty_cache()
+
+    # c4: 256 uneven instances, one batched handle (float32 + refinement) vs
+    # the same instances one by one in float64
+    insts = wl.c4()
+    ds = [device_inputs(i, dev) for i in insts]
+    us = [torch.empty_like(x["f"]) for x in ds]
+    probs = [dict(gamma=i.gamma, M=i.M, N=i.N) for i in insts]
+    wave = [i.gamma > 1 for i in insts]
+    sb = binding.Solver(probs, precision="fp32", refine_steps=1)
+    run = lambda: sb.solve([x["f"] for x in ds], [x["u0"] for x in ds],  # noqa: E731
+                           [x["phi"] if w else None for x, w in zip(ds, wave)], out=us)
+    run()
+    ms_b = timed(run, 1)
+    sb.close()
+    sample = list(range(0, len(insts), 32))
+    err_b = max(mode_error(insts[k], ds[k], us[k]) for k in sample)
+    solvers = [binding.Solver([p]) for p in probs]
+
+    def one_by_one():
+        for k, sv in enumerate(solvers):
+            sv.solve([ds[k]["f"]], [ds[k]["u0"]], [ds[k]["phi"]] if wave[k] else None, out=[us[k]])
+
+    one_by_one()
+    ms_1 = timed(one_by_one, 1)
+    err_1 = max(mode_error(insts[k], ds[k], us[k]) for k in sample)
+    for sv in solvers:
+        sv.close()
+    mn = sum(i.M * i.N for i in insts)
+    out["c4_batched_fp32"] = {"ms": round(ms_b, 2), "unknowns_per_s": mn / (ms_b * 1e-3), "instances": len(insts),
+                              "max_error_vs_oracle_sampled": err_b, "sampled_instances": len(sample)}
+    out["c4_one_by_one_fp64"] = {"ms": round(ms_1, 2), "unknowns_per_s": mn / (ms_1 * 1e-3),
+                                 "max_error_vs_oracle_sampled": err_1}
+    out["batched_speedup_vs_fp64"] = round(ms_1 / ms_b, 3)
+    log("forms: c4 batched %.1f ms (err %.3e), one by one fp64 %.1f ms (err %.3e)" % (ms_b, err_b, ms_1, err_1))
+    del ds, us
+    torch.cuda.empty_cache()
+
+    # c5: forward solve + adjoint (dL/df, dL/dgamma) of L = ||u - u_obs||^2
+    base, obs = wl.c5(build=False)
+    db, do = device_inputs(base, dev), device_inputs(obs, dev)
+    sv = binding.Solver([dict(gamma=base.gamma, M=base.M, N=base.N)])
+    u_obs = sv.solve([do["f"]], [do["u0"]])[0]
+    u = torch.empty_like(db["f"])
+    fw = lambda: sv.solve([db["f"]], [db["u0"]], out=[u])  # noqa: E731
+    fw()
+    ms_f = timed(fw, 2)
+    g = 2.0 * (u - u_obs)
+    lam = torch.empty_like(g)
+    holder = {}
+
+    def bw():
+        holder["r"] = sv.adjoint([g], [u], [db["u0"]], out=[lam])
+
+    bw()
+    ms_a = timed(bw, 2)
+    dgamma = float(holder["r"][1][0])
+    sv.close()
+    # dL/df = lambda: the adjoint of a modal g is modal (modes of base and obs),
+    # each the time-reversed scalar recurrence
+    import oracle
+
+    _, _, h, _ = wl.grid(base.M, base.N)
+    js = sorted(set(db["js"]) | set(do["js"]))
+    x, _, _, _ = wl.grid(base.M, base.N)
+    S = np.stack([np.sin(j * math.pi * x) for j in js])
+    gmodal = (g @ torch.from_numpy(S.T).to(dev)).cpu().numpy() * (2.0 / (base.M + 1))
+    lamj = [4.0 / h ** 2 * math.sin(j * math.pi * h / 2) ** 2 for j in js]
+    from concurrent.futures import ThreadPoolExecutor
+
+    with ThreadPoolExecutor(max_workers=len(js)) as ex:
+        vs = list(ex.map(lambda k: oracle.mode(base.gamma, base.T, base.N, lamj[k], gmodal[::-1, k].copy(), 0.0,
+                                               0.0)[::-1], range(len(js))))
+    ref = torch.from_numpy(np.stack(vs, axis=1).copy()).to(dev) @ torch.from_numpy(S).to(dev)
+    err_l = float((lam - ref).abs().max() / ref.abs().max())
+    out["c5_adjoint"] = {"ms_forward": round(ms_f, 2), "ms_adjoint": round(ms_a, 2), "dL_dgamma": dgamma,
+                         "dL_df_error_vs_oracle": err_l}
+    log("forms: c5 forward %.1f ms, adjoint %.1f ms, dL/df err %.3e, dL/dgamma %.6e" % (ms_f, ms_a, err_l, dgamma))
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -115,6 +278,8 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=4096)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true")
+    ap.add_argument("--no-forms", action="store_true",
+                    help="skip the mixed-precision (c3), batched (c4) and adjoint (c5) comparisons")
     ap.add_argument("--out", default="")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of 512 MiB (3 times), the reference kernel for "
@@ -247,6 +412,13 @@ def main():
         log("bench: oracle sample %.2f s on %d threads -> %.4g unknowns/s (full-run estimate)" % (
             c1 - c0, th, cpu["value"]))
 
+    forms = None
+    if not args.no_forms and args.config == "c2" and not (args.M or args.N):
+        del f, u
+        solver.close()
+        torch.cuda.empty_cache()
+        forms = run_forms(dev)
+
     line = {
         "metric": METRIC,
         "value": value,
@@ -268,13 +440,15 @@ def main():
         "kernels_per_solve": st["kernels"],
         "roofline": roof,
         "cpu_baseline": cpu,
+        "forms": forms,
     }
     s = json.dumps(line)
     print(s, flush=True)
     if args.out:
         with open(args.out, "w") as fh_:
             fh_.write(s + "\n")
-    solver.close()
+    if forms is None:
+        solver.close()
 
 
 if __name__ == "__main__":

@@ -109,6 +109,24 @@ struct UpdTask {
     double alpha;
 };
 
+// Task descriptors reach a kernel either inline, for single-task launches
+// (the descriptor travels in the kernel arguments, which saves the kernel a
+// dependent memory round trip before its first data load), or through a
+// device array indexed by a block index.
+template <typename TASK>
+struct TaskRef {
+    const TASK *tasks;  // device array, used when one_valid == 0
+    TASK one;           // the only task, used when one_valid != 0
+    int32_t one_valid;
+};
+
+template <typename TASK>
+__device__ __forceinline__ TASK get_task(const TaskRef<TASK> &r, unsigned i)
+{
+    if (r.one_valid) return r.one;
+    return r.tasks[i];
+}
+
 // XCD-aware block order.  Workgroups are dispatched round-robin over the 8
 // XCDs (each with its own L2), so consecutive block ids land on different
 // L2s.  This maps block b to logical block (b mod 8) * (G/8) + b/8, so that
@@ -150,16 +168,18 @@ hipError_t launch_leaf(hipStream_t st, const LeafCfg &c, int L, const LeafTask *
 LeafCfg scan_config(int64_t M);
 size_t scan_table_doubles(const LeafCfg &c);
 hipError_t launch_scan_factor(hipStream_t st, const LeafCfg &c, int64_t M, double a0, double e, double *tab);
-hipError_t launch_leaf_scan(hipStream_t st, const LeafCfg &c, int L, const LeafTask *d_tasks, int ntasks,
+hipError_t launch_leaf_scan(hipStream_t st, const LeafCfg &c, int L, const TaskRef<LeafTask> &tr, int ntasks,
                             bool mixed, bool vec);
 
 hipError_t launch_twiddles(hipStream_t st, int64_t nmax, cplx<double> *w64, cplx<float> *w32);
 
 template <typename T>
-hipError_t launch_gemm_update(hipStream_t st, const UpdTask<T> *d_tasks, int ntasks, int s, int64_t maxM);
+hipError_t launch_gemm_update(hipStream_t st, const TaskRef<UpdTask<T>> &tr, int ntasks, int s, int64_t maxM);
+// even: every task has M even and 16-byte aligned rows (one vector access per
+// column pair)
 template <typename T>
 hipError_t launch_fft_update_ex(hipStream_t st, const UpdTask<T> *d_tasks, int ntasks, int s, int64_t maxM,
-                                const cplx<T> *tw, int64_t nmax, cplx<T> *zs, size_t zs_elems);
+                                const cplx<T> *tw, int64_t nmax, cplx<T> *zs, size_t zs_elems, bool even);
 hipError_t launch_spectrum(hipStream_t st, const double *w, int s, cplx<double> *spec64, cplx<float> *spec32,
                            const cplx<double> *tw, int64_t nmax, cplx<double> *scratch);
 int fft_max_single_pass(bool fp32);

@@ -116,6 +116,7 @@ struct fracsolve_ctx {
     std::vector<fracsolve_kernel_stat> kstats;
     // replay of recorded launch sequences (hipGraph) on an internal stream
     bool use_graph = false;
+    bool capturing = false;  // a launch sequence is being recorded into a graph
     hipStream_t gst = nullptr;
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
     struct GraphEntry {
@@ -220,7 +221,29 @@ struct Op {
     LeafCfg lc;
     bool mixed;
     double bytes = 0.0;  // algorithmic HBM bytes of the launch
+    bool even = false;   // FFT levels: every task has M even and aligned rows
 };
+
+// Column pairs of every row are whole, aligned vector elements.
+template <typename T>
+bool pairs_aligned(const UpdTask<T> &t)
+{
+    const uintptr_t a = 2 * sizeof(T);
+    return (t.M % 2) == 0 && ((uintptr_t)t.x % a) == 0 && ((uintptr_t)t.y % a) == 0;
+}
+
+// Single-task launches carry their descriptor inline, except while a graph is
+// being recorded (a replay must read the descriptors uploaded for it).
+template <typename TASK>
+TaskRef<TASK> task_ref(fracsolve_ctx *h, const Op &op)
+{
+    TaskRef<TASK> r{dptr<TASK>(h, op.off), TASK{}, 0};
+    if (op.ntasks == 1 && !h->capturing) {
+        memcpy(&r.one, (const char *)h->h_desc + op.off, sizeof(TASK));
+        r.one_valid = 1;
+    }
+    return r;
+}
 
 int get_event(fracsolve_ctx *h, size_t idx, hipEvent_t *ev)
 {
@@ -252,24 +275,24 @@ int run_ops(fracsolve_ctx *h, const std::vector<Op> &ops)
                 e = launch_leaf(h->st, op.lc, h->L, dptr<LeafTask>(h, op.off), op.ntasks, op.mixed);
                 break;
             case OP_LEAF_SCAN:
-                e = launch_leaf_scan(h->st, op.lc, h->L, dptr<LeafTask>(h, op.off), op.ntasks, op.mixed,
+                e = launch_leaf_scan(h->st, op.lc, h->L, task_ref<LeafTask>(h, op), op.ntasks, op.mixed,
                                      op.lc.vec != 0);
                 break;
             case OP_GEMM64:
-                e = launch_gemm_update<double>(h->st, dptr<UpdTask<double>>(h, op.off), op.ntasks, op.s, op.maxM);
+                e = launch_gemm_update<double>(h->st, task_ref<UpdTask<double>>(h, op), op.ntasks, op.s, op.maxM);
                 break;
             case OP_GEMM32:
-                e = launch_gemm_update<float>(h->st, dptr<UpdTask<float>>(h, op.off), op.ntasks, op.s, op.maxM);
+                e = launch_gemm_update<float>(h->st, task_ref<UpdTask<float>>(h, op), op.ntasks, op.s, op.maxM);
                 break;
             case OP_FFT64:
                 e = launch_fft_update_ex<double>(h->st, dptr<UpdTask<double>>(h, op.off), op.ntasks, op.s, op.maxM,
                                                  h->tw64, h->nmax, (cplx<double> *)h->zs,
-                                                 h->zs_bytes / sizeof(cplx<double>));
+                                                 h->zs_bytes / sizeof(cplx<double>), op.even);
                 break;
             case OP_FFT32:
                 e = launch_fft_update_ex<float>(h->st, dptr<UpdTask<float>>(h, op.off), op.ntasks, op.s, op.maxM,
                                                 h->tw32, h->nmax, (cplx<float> *)h->zs,
-                                                h->zs_bytes / sizeof(cplx<float>));
+                                                h->zs_bytes / sizeof(cplx<float>), op.even);
                 break;
         }
         if (e != hipSuccess) return fail(h, FRACSOLVE_E_DEVICE, "kernel launch failed: %s", hipGetErrorString(e));
@@ -310,6 +333,8 @@ uint64_t ops_key(const std::vector<Op> &ops, const void *d_desc)
         mix((uint64_t)op.maxM);
         mix((uint64_t)(op.lc.nt * 100 + op.lc.pt));
         mix((uint64_t)op.mixed);
+        mix((uint64_t)op.even);
+        mix((uint64_t)op.lc.vec);
     }
     mix((uint64_t)ops.size());
     return hsh;
@@ -330,7 +355,9 @@ int run_ops_graph(fracsolve_ctx *h, const std::vector<Op> &ops)
         h->st = h->gst;
         hipGraph_t graph = nullptr;
         hipError_t e = hipStreamBeginCapture(h->gst, hipStreamCaptureModeThreadLocal);
+        h->capturing = true;
         int rc = (e == hipSuccess) ? run_ops(h, ops) : FRACSOLVE_E_DEVICE;
+        h->capturing = false;
         hipError_t e2 = hipStreamEndCapture(h->gst, &graph);
         h->st = user;
         if (rc) return rc;
@@ -472,7 +499,11 @@ void build_solve(fracsolve_ctx *h, const std::vector<int> &sel, const std::vecto
             } else {
                 size_t off = db.add(t64.data(), t64.size() * sizeof(t64[0]));
                 Op op{fft ? OP_FFT64 : OP_GEMM64, off, (int)t64.size(), (int)s, maxM, {}, false};
-                for (auto &t : t64) op.bytes += upd_bytes(t, 8);
+                op.even = true;
+                for (auto &t : t64) {
+                    op.bytes += upd_bytes(t, 8);
+                    op.even = op.even && pairs_aligned(t);
+                }
                 ops.push_back(op);
             }
         }
@@ -486,7 +517,11 @@ void build_solve(fracsolve_ctx *h, const std::vector<int> &sel, const std::vecto
             } else {
                 size_t off = db.add(t32.data(), t32.size() * sizeof(t32[0]));
                 Op op{OP_FFT32, off, (int)t32.size(), (int)s, maxM, {}, true};
-                for (auto &t : t32) op.bytes += upd_bytes(t, 4);
+                op.even = true;
+                for (auto &t : t32) {
+                    op.bytes += upd_bytes(t, 4);
+                    op.even = op.even && pairs_aligned(t);
+                }
                 ops.push_back(op);
             }
         }
@@ -530,7 +565,11 @@ void build_apply_levels(fracsolve_ctx *h, const Inst &in, const double *x, doubl
         } else {
             size_t off = db.add(tv.data(), tv.size() * sizeof(tv[0]));
             Op op{fft ? OP_FFT64 : OP_GEMM64, off, (int)tv.size(), (int)s, in.M, {}, false};
-            for (auto &t : tv) op.bytes += upd_bytes(t, 8);
+            op.even = true;
+            for (auto &t : tv) {
+                op.bytes += upd_bytes(t, 8);
+                op.even = op.even && pairs_aligned(t);
+            }
             ops.push_back(op);
         }
     }

@@ -60,13 +60,35 @@ __host__ __device__ constexpr int bitrev(int i, int bits)
     return r;
 }
 
-// Radix-2 decimation-in-time DFT of length R held in registers; natural
-// order in and out.  Forward uses exp(-2 pi i jk/R), inverse its conjugate
-// (unnormalised).  tw is the exp(-2 pi i j/nmax) table.  HALFZERO: inputs
-// R/2..R-1 are zero and are not read.
-template <int R, bool INV, bool HALFZERO, typename T>
-__device__ __forceinline__ void dft_reg(cplx<T> (&v)[R], const cplx<T> *__restrict__ tw, int64_t nmax)
+// exp(-2 pi i m / 32), m < 32, from cos and sin of pi k / 16, k < 8 (folded
+// to constants when m is known at compile time).
+template <typename T>
+__device__ __forceinline__ cplx<T> root32(int m)
 {
+    constexpr double C[8] = {1.0,
+                             0.98078528040323044913,
+                             0.92387953251128675613,
+                             0.83146961230254523708,
+                             0.70710678118654752440,
+                             0.55557023301960222474,
+                             0.38268343236508977173,
+                             0.19509032201612826785};
+    const int q = m & 7, h = (m >> 3) & 3;
+    const double c0 = C[q], s0 = (q == 0) ? 0.0 : C[8 - q];
+    // rotate (c0, s0) by h quarter turns
+    const double c = (h == 0) ? c0 : (h == 1) ? -s0 : (h == 2) ? -c0 : s0;
+    const double s = (h == 0) ? s0 : (h == 1) ? c0 : (h == 2) ? -s0 : -c0;
+    return cplx<T>{(T)c, (T)(-s)};
+}
+
+// Radix-2 decimation-in-time DFT of length R <= 32 held in registers;
+// natural order in and out.  Forward uses exp(-2 pi i jk/R), inverse its
+// conjugate (unnormalised).  The twiddles are compile-time constants.
+// HALFZERO: inputs R/2..R-1 are zero and are not read.
+template <int R, bool INV, bool HALFZERO, typename T>
+__device__ __forceinline__ void dft_reg(cplx<T> (&v)[R])
+{
+    static_assert(R <= 32, "in-register DFTs up to 32 points");
     constexpr int B = lg2<R>::v;
     cplx<T> w[R];
     if (HALFZERO) {
@@ -90,7 +112,6 @@ __device__ __forceinline__ void dft_reg(cplx<T> (&v)[R], const cplx<T> *__restri
 #pragma unroll
     for (int len = 4; len <= R; len <<= 1) {
         const int half = len / 2;
-        const int64_t ts = nmax / len;
 #pragma unroll
         for (int st = 0; st < R; st += len) {
 #pragma unroll
@@ -101,7 +122,7 @@ __device__ __forceinline__ void dft_reg(cplx<T> (&v)[R], const cplx<T> *__restri
                     // multiply by -i (forward) or +i (inverse)
                     b = INV ? cplx<T>{-b.y, b.x} : cplx<T>{b.y, -b.x};
                 } else {
-                    cplx<T> t = tw[j * ts];
+                    const cplx<T> t = root32<T>(j * (32 / len));
                     b = INV ? cmulc(b, t) : cmul(b, t);
                 }
                 w[st + j] = cadd(a, b);
@@ -119,6 +140,66 @@ __device__ __forceinline__ cplx<T> twiddle(const cplx<T> *__restrict__ tw, int64
     cplx<T> t = tw[idx];
     if (inv) t.y = -t.y;
     return t;
+}
+
+// v[k] *= W^(k e) (conjugated for INV), k = 1..R-1, W = exp(-2 pi i / nmax)
+// from the table, with e = base * stride.  Only the powers W^(2^j e) are
+// read; W^(k e) is built as W^((k - lowbit k) e) W^(lowbit(k) e), at most
+// log2(R) - 1 products deep.
+template <int R, bool INV, typename T>
+__device__ __forceinline__ void apply_twiddles(cplx<T> (&v)[R], const cplx<T> *__restrict__ tw, int64_t e)
+{
+    constexpr int B = lg2<R>::v;
+    cplx<T> p[B];
+#pragma unroll
+    for (int j = 0; j < B; ++j) p[j] = twiddle(tw, e << j, INV);
+    cplx<T> w[R];
+    w[0] = cplx<T>{(T)1, (T)0};
+#pragma unroll
+    for (int k = 1; k < R; ++k) {
+        const int low = k & -k;
+        const int j = __builtin_ctz(k);
+        w[k] = (k == low) ? p[j] : cmul(w[k - low], p[j]);
+        v[k] = cmul(v[k], w[k]);
+    }
+}
+
+// The pointer unchanged, but opaque to the optimiser: loads through it
+// inside a loop are not hoisted out of the loop (the persistent kernels
+// would otherwise keep every loop-invariant spectrum and twiddle value of
+// all stages live in registers at once).
+template <typename P>
+__device__ __forceinline__ P opaque(P p)
+{
+    asm volatile("" : "+s"(p));
+    return p;
+}
+
+// Bases p[j] = W^(e 2^j), j < log2(R), for apply_twiddles_b.
+template <int R, typename T>
+__device__ __forceinline__ void twiddle_bases(cplx<T> (&p)[lg2<R>::v], const cplx<T> *__restrict__ tw, int64_t e)
+{
+#pragma unroll
+    for (int j = 0; j < lg2<R>::v; ++j) p[j] = tw[e << j];
+}
+
+// apply_twiddles with the bases already in registers (conjugated for INV).
+template <int R, bool INV, typename T>
+__device__ __forceinline__ void apply_twiddles_b(cplx<T> (&v)[R], const cplx<T> (&pb)[lg2<R>::v])
+{
+    constexpr int B = lg2<R>::v;
+    cplx<T> p[B];
+#pragma unroll
+    for (int j = 0; j < B; ++j) p[j] = INV ? cplx<T>{pb[j].x, -pb[j].y} : pb[j];
+    cplx<T> w[R];
+    w[0] = cplx<T>{(T)1, (T)0};
+#pragma unroll
+    for (int k = 1; k < R; ++k) {
+        const int low = k & -k;
+        const int j = __builtin_ctz(k);
+        w[k] = (k == low) ? p[j] : cmul(w[k - low], p[j]);
+        v[k] = cmul(v[k], w[k]);
+    }
 }
 
 // Loads of the two packed real columns (one vector access when the pair is
@@ -146,6 +227,17 @@ __device__ __forceinline__ void add_pair(FS_G T *__restrict__ row, int64_t col, 
     }
     if (col < M) row[col] += scale * v.x;
     if (col + 1 < M) row[col + 1] += scale * v.y;
+}
+
+template <typename T>
+__device__ __forceinline__ void store_pair(FS_G T *__restrict__ row, int64_t col, int64_t M, cplx<T> v)
+{
+    if (((M & 1) == 0) && col + 1 < M) {
+        *reinterpret_cast<FS_G cplx<T> *>(row + col) = v;
+        return;
+    }
+    if (col < M) row[col] = v.x;
+    if (col + 1 < M) row[col + 1] = v.y;
 }
 
 // Near-corner terms of a level product, kept out of the FFT: the entries of
@@ -210,13 +302,13 @@ __global__ __launch_bounds__(256) void k_fft2(const UpdTask<T> *__restrict__ tas
             FS_G const T *__restrict__ xb = gptr(tk.x) + tk.xlo * M;
 #pragma unroll
             for (int q1 = 0; q1 < N1 / 2; ++q1) v[q1] = load_pair(xb + (int64_t)(q1 * N2 + q2) * M, col, M);
-            dft_reg<N1, false, true>(v, tw, nmax);
+            dft_reg<N1, false, true>(v);
         } else {
             const bool cv = cgrp + c < Mc;
             const cplx<T> *__restrict__ zb = zs + ((int64_t)k1g * Mc + cgrp + c) * n;
 #pragma unroll
             for (int q1 = 0; q1 < N1; ++q1) v[q1] = cv ? zb[q1 * N2 + q2] : cplx<T>{0, 0};
-            dft_reg<N1, false, false>(v, tw, nmax);
+            dft_reg<N1, false, false>(v);
         }
 #pragma unroll
         for (int k1 = 1; k1 < N1; ++k1) v[k1] = cmul(v[k1], twiddle(tw, (int64_t)(q2 * k1) * tws, false));
@@ -230,10 +322,10 @@ __global__ __launch_bounds__(256) void k_fft2(const UpdTask<T> *__restrict__ tas
         cplx<T> v[N2];
 #pragma unroll
         for (int q2 = 0; q2 < N2; ++q2) v[q2] = sd[k1 * RS + q2 * CC + c];
-        dft_reg<N2, false, false>(v, tw, nmax);
+        dft_reg<N2, false, false>(v);
 #pragma unroll
         for (int k2 = 0; k2 < N2; ++k2) v[k2] = cmul(v[k2], gptr(tk.spec)[k1g + (int64_t)sstride * (k1 + N1 * k2)]);
-        dft_reg<N2, true, false>(v, tw, nmax);
+        dft_reg<N2, true, false>(v);
 #pragma unroll
         for (int q2 = 0; q2 < N2; ++q2) sd[k1 * RS + q2 * CC + c] = v[q2];
     }
@@ -247,7 +339,7 @@ __global__ __launch_bounds__(256) void k_fft2(const UpdTask<T> *__restrict__ tas
             cplx<T> e = sd[k1 * RS + q2 * CC + c];
             v[k1] = (k1 == 0) ? e : cmul(e, twiddle(tw, (int64_t)(q2 * k1) * tws, true));
         }
-        dft_reg<N1, true, false>(v, tw, nmax);
+        dft_reg<N1, true, false>(v);
         if (MODE == MODE_UPDATE) {
             const int64_t col = 2 * (cgrp + c);
             const T scale = (T)(tk.alpha / (double)n);
@@ -298,13 +390,13 @@ __global__ __launch_bounds__(256) void k_fft3(const UpdTask<T> *__restrict__ tas
             FS_G const T *__restrict__ xb = gptr(tk.x) + tk.xlo * M;
 #pragma unroll
             for (int q1 = 0; q1 < N1 / 2; ++q1) v[q1] = load_pair(xb + (int64_t)(q1 * N2 * N3 + r) * M, col, M);
-            dft_reg<N1, false, true>(v, tw, nmax);
+            dft_reg<N1, false, true>(v);
         } else {
             const bool cv = cgrp + c < Mc;
             const cplx<T> *__restrict__ zb = zs + ((int64_t)k1g * Mc + cgrp + c) * n;
 #pragma unroll
             for (int q1 = 0; q1 < N1; ++q1) v[q1] = cv ? zb[q1 * N2 * N3 + r] : cplx<T>{0, 0};
-            dft_reg<N1, false, false>(v, tw, nmax);
+            dft_reg<N1, false, false>(v);
         }
 #pragma unroll
         for (int k1 = 1; k1 < N1; ++k1) v[k1] = cmul(v[k1], twiddle(tw, (int64_t)(r * k1) * tws, false));
@@ -318,7 +410,7 @@ __global__ __launch_bounds__(256) void k_fft3(const UpdTask<T> *__restrict__ tas
         cplx<T> v[N2];
 #pragma unroll
         for (int q2 = 0; q2 < N2; ++q2) v[q2] = sd[at(k1, q2, q3, c)];
-        dft_reg<N2, false, false>(v, tw, nmax);
+        dft_reg<N2, false, false>(v);
 #pragma unroll
         for (int k2 = 1; k2 < N2; ++k2) v[k2] = cmul(v[k2], twiddle(tw, (int64_t)(q3 * k2 * N1) * tws, false));
 #pragma unroll
@@ -331,11 +423,11 @@ __global__ __launch_bounds__(256) void k_fft3(const UpdTask<T> *__restrict__ tas
         cplx<T> v[N3];
 #pragma unroll
         for (int q3 = 0; q3 < N3; ++q3) v[q3] = sd[at(k1, k2, q3, c)];
-        dft_reg<N3, false, false>(v, tw, nmax);
+        dft_reg<N3, false, false>(v);
 #pragma unroll
         for (int k3 = 0; k3 < N3; ++k3)
             v[k3] = cmul(v[k3], gptr(tk.spec)[k1g + (int64_t)sstride * (k1 + N1 * k2 + N1 * N2 * k3)]);
-        dft_reg<N3, true, false>(v, tw, nmax);
+        dft_reg<N3, true, false>(v);
 #pragma unroll
         for (int q3 = 0; q3 < N3; ++q3) sd[at(k1, k2, q3, c)] = v[q3];
     }
@@ -349,7 +441,7 @@ __global__ __launch_bounds__(256) void k_fft3(const UpdTask<T> *__restrict__ tas
             cplx<T> e = sd[at(k1, k2, q3, c)];
             v[k2] = (k2 == 0) ? e : cmul(e, twiddle(tw, (int64_t)(q3 * k2 * N1) * tws, true));
         }
-        dft_reg<N2, true, false>(v, tw, nmax);
+        dft_reg<N2, true, false>(v);
 #pragma unroll
         for (int q2 = 0; q2 < N2; ++q2) sd[at(k1, q2, q3, c)] = v[q2];
     }
@@ -363,7 +455,7 @@ __global__ __launch_bounds__(256) void k_fft3(const UpdTask<T> *__restrict__ tas
             cplx<T> e = sd[at(k1, q2, q3, c)];
             v[k1] = (k1 == 0) ? e : cmul(e, twiddle(tw, (int64_t)(r * k1) * tws, true));
         }
-        dft_reg<N1, true, false>(v, tw, nmax);
+        dft_reg<N1, true, false>(v);
         if (MODE == MODE_UPDATE) {
             const int64_t col = 2 * (cgrp + c);
             const T scale = (T)(tk.alpha / (double)n);
@@ -380,6 +472,374 @@ __global__ __launch_bounds__(256) void k_fft3(const UpdTask<T> *__restrict__ tas
             cplx<T> *__restrict__ zb = zs + ((int64_t)k1g * Mc + cgrp + c) * n;
 #pragma unroll
             for (int q1 = 0; q1 < N1; ++q1) zb[q1 * N2 * N3 + r] = v[q1];
+        }
+    }
+}
+
+// ------------------------------------------- persistent update kernels
+// Level products (UPDATE mode) by persistent workgroups: workgroup b takes
+// column groups g = slot, slot + G0, ... (slot: XCD-aware order of b, so
+// that neighbouring groups, which share cache lines, run on one XCD).  The X
+// rows of group g + G0 are loaded into registers while group g is
+// transformed, and the Y rows of group g one stage before they are needed.
+// Vector-memory loads complete in issue order, so the only loads inside the
+// stage loop are the spectrum (middle stage, nothing else in flight), then
+// Y, then the next X: the twiddles of every stage are built from per-thread
+// bases loaded once, before the loop.  Digits are at most 16 points at the
+// first and last stage (32 in the middle), which keeps these buffers in
+// registers.  One workgroup per CU fits when the transform needs most of the
+// LDS, so this overlap is what hides the HBM latency.
+//
+// Item (c, r) of stage A / the last stage: complex column c of the group,
+// r = q2 N3 + q3; its X rows are q1 R + r (q1 < N1/2, the rest is the zero
+// padding) and its Y rows p = (q1 - N1/2) R + r (q1 >= N1/2).
+// Pair access: with EVEN (M even, rows 16-byte aligned) every in-range
+// pair is one aligned vector access; otherwise the scalar path of
+// load_pair/store_pair.  Columns past M read as zero and are not written.
+template <bool EVEN, typename T>
+__device__ __forceinline__ cplx<T> ld_pair(FS_G const T *__restrict__ row, int64_t col, int64_t M)
+{
+    if (EVEN) {
+        cplx<T> v{0, 0};
+        if (col < M) v = *reinterpret_cast<FS_G const cplx<T> *>(row + col);
+        return v;
+    }
+    return load_pair(row, col, M);
+}
+
+template <bool EVEN, typename T>
+__device__ __forceinline__ void st_pair(FS_G T *__restrict__ row, int64_t col, int64_t M, cplx<T> v)
+{
+    if (EVEN) {
+        if (col < M) *reinterpret_cast<FS_G cplx<T> *>(row + col) = v;
+        return;
+    }
+    store_pair(row, col, M, v);
+}
+
+template <typename T, int N1, int R, int CC, int NT, bool EVEN>
+struct GroupRows {
+    static constexpr int NI = CC * R;
+    static constexpr int NA = (NI + NT - 1) / NT;
+    static constexpr int H = N1 / 2;
+    cplx<T> v[NA][H];
+
+    // X rows q1 R + r, q1 < N1/2
+    __device__ __forceinline__ void load_x(FS_G const T *__restrict__ xb, int64_t g, int64_t M)
+    {
+#pragma unroll
+        for (int a = 0; a < NA; ++a) {
+            const int it = threadIdx.x + NT * a;
+            const bool ok = (NI % NT == 0) || it < NI;
+            const int c = it % CC, r = it / CC;
+            const int64_t col = 2 * (g * CC + c);
+#pragma unroll
+            for (int q1 = 0; q1 < H; ++q1)
+                v[a][q1] = ok ? ld_pair<EVEN>(xb + (int64_t)(q1 * R + r) * M, col, M) : cplx<T>{0, 0};
+        }
+    }
+    // Y rows p = j R + r, j < N1/2, p < ny
+    __device__ __forceinline__ void load_y(FS_G const T *__restrict__ yb, int64_t g, int64_t M, int ny)
+    {
+#pragma unroll
+        for (int a = 0; a < NA; ++a) {
+            const int it = threadIdx.x + NT * a;
+            const bool ok = (NI % NT == 0) || it < NI;
+            const int c = it % CC, r = it / CC;
+            const int64_t col = 2 * (g * CC + c);
+#pragma unroll
+            for (int j = 0; j < H; ++j) {
+                const int p = j * R + r;
+                v[a][j] = (ok && p < ny) ? ld_pair<EVEN>(yb + (int64_t)p * M, col, M) : cplx<T>{0, 0};
+            }
+        }
+    }
+};
+
+// two digits: n = N1 N2 (see k_fft2 for the stages)
+template <typename T, int N1, int N2, int CC, bool EVEN>
+__global__ __launch_bounds__(256) void k_fft2u(const UpdTask<T> *__restrict__ tasks, const cplx<T> *__restrict__ tw0,
+                                               int64_t nmax)
+{
+    constexpr int n = N1 * N2;
+    constexpr int RS = N2 * CC + 1;
+    using GR = GroupRows<T, N1, N2, CC, 256, EVEN>;
+    constexpr int NA = GR::NA, H = GR::H;
+    __shared__ cplx<T> sd[N1 * RS];
+    const UpdTask<T> tk = tasks[blockIdx.z];
+    const int64_t M = tk.M;
+    const int t = threadIdx.x;
+    const int64_t G = ((M + 1) / 2 + CC - 1) / CC;
+    const int64_t tws = nmax / n;
+    FS_G const T *__restrict__ xb = gptr(tk.x) + tk.xlo * M;
+    FS_G T *__restrict__ yb = gptr(tk.y) + tk.ylo * M;
+    FS_G const cplx<T> *__restrict__ spec0 = gptr(tk.spec);
+    const int ny = tk.ny;
+    const T scale = (T)(tk.alpha / (double)n);
+
+    // twiddle bases of the first/last stage, the same for every group
+    cplx<T> pa[NA][lg2<N1>::v];
+#pragma unroll
+    for (int a = 0; a < NA; ++a) twiddle_bases<N1>(pa[a], tw0, (int64_t)(((t + 256 * a) / CC) % N2) * tws);
+
+    GR xc;  // X rows of the current group (loaded during the previous group)
+    int64_t g = xcd_remap(blockIdx.x, gridDim.x);
+    if (g < G) xc.load_x(xb, g, M);
+    for (; g < G; g += gridDim.x) {
+        const cplx<T> *__restrict__ tw = opaque(tw0);  // per-thread twiddle bases
+        FS_G const cplx<T> *__restrict__ spec = opaque(spec0);
+        // stage A: digit q1 -> k1 (forward, zero upper half), twiddle, to LDS
+#pragma unroll
+        for (int a = 0; a < NA; ++a) {
+            const int it = t + 256 * a;
+            if (it < CC * N2) {
+                const int c = it % CC, q2 = it / CC;
+                cplx<T> v[N1];
+#pragma unroll
+                for (int q1 = 0; q1 < H; ++q1) v[q1] = xc.v[a][q1];
+                dft_reg<N1, false, true>(v);
+                apply_twiddles_b<N1, false>(v, pa[a]);
+#pragma unroll
+                for (int k1 = 0; k1 < N1; ++k1) sd[k1 * RS + q2 * CC + c] = v[k1];
+            }
+        }
+        __syncthreads();
+        // stage B: digit q2 -> k2, spectrum, back
+#pragma unroll 1
+        for (int it = t; it < CC * N1; it += 256) {
+            const int c = it % CC, k1 = it / CC;
+            cplx<T> v[N2];
+#pragma unroll
+            for (int q2 = 0; q2 < N2; ++q2) v[q2] = sd[k1 * RS + q2 * CC + c];
+            cplx<T> hs[N2];
+#pragma unroll
+            for (int k2 = 0; k2 < N2; ++k2) hs[k2] = spec[k1 + N1 * k2];
+            dft_reg<N2, false, false>(v);
+#pragma unroll
+            for (int k2 = 0; k2 < N2; ++k2) v[k2] = cmul(v[k2], hs[k2]);
+            dft_reg<N2, true, false>(v);
+#pragma unroll
+            for (int q2 = 0; q2 < N2; ++q2) sd[k1 * RS + q2 * CC + c] = v[q2];
+        }
+        // this group's Y rows, then the next group's X rows (in this order:
+        // loads complete in order, so waiting for Y does not wait for X)
+        GR yc;
+        yc.load_y(yb, g, M, ny);
+        GR xn;
+        const int64_t gn = g + gridDim.x;
+        if (gn < G) xn.load_x(xb, gn, M);
+        __syncthreads();
+        // stage C: conjugate twiddle, digit k1 -> q1 (inverse), Y = Y + scale z
+#pragma unroll
+        for (int a = 0; a < NA; ++a) {
+            const int it = t + 256 * a;
+            if (it < CC * N2) {
+                const int c = it % CC, q2 = it / CC;
+                cplx<T> v[N1];
+#pragma unroll
+                for (int k1 = 0; k1 < N1; ++k1) v[k1] = sd[k1 * RS + q2 * CC + c];
+                apply_twiddles_b<N1, true>(v, pa[a]);
+                dft_reg<N1, true, false>(v);
+                const int64_t col = 2 * (g * CC + c);
+#pragma unroll
+                for (int q1 = H; q1 < N1; ++q1) {
+                    const int p = (q1 - H) * N2 + q2;
+                    if (p < ny) {
+                        const cplx<T> y0 = yc.v[a][q1 - H];
+                        st_pair<EVEN>(yb + (int64_t)p * M, col, M, cplx<T>{y0.x + scale * v[q1].x, y0.y + scale * v[q1].y});
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        xc = xn;
+    }
+}
+
+// three digits: n = N1 N2 N3 (see k_fft3 for the stages)
+template <typename T, int N1, int N2, int N3, int CC, int NT, bool EVEN>
+__global__ __launch_bounds__(NT) void k_fft3u(const UpdTask<T> *__restrict__ tasks, const cplx<T> *__restrict__ tw0,
+                                               int64_t nmax)
+{
+    constexpr int n = N1 * N2 * N3;
+    constexpr int RS = N3 * CC + 1;
+    using GR = GroupRows<T, N1, N2 * N3, CC, NT, EVEN>;
+    constexpr int NA = GR::NA, H = GR::H;
+    constexpr int NB = (CC * N1 * N3 + NT - 1) / NT;  // items per thread of stages B and D
+    __shared__ cplx<T> sd[N1 * N2 * RS];
+    const UpdTask<T> tk = tasks[blockIdx.z];
+    const int64_t M = tk.M;
+    const int t = threadIdx.x;
+    const int64_t G = ((M + 1) / 2 + CC - 1) / CC;
+    const int64_t tws = nmax / n;
+    FS_G const T *__restrict__ xb = gptr(tk.x) + tk.xlo * M;
+    FS_G T *__restrict__ yb = gptr(tk.y) + tk.ylo * M;
+    FS_G const cplx<T> *__restrict__ spec0 = gptr(tk.spec);
+    const int ny = tk.ny;
+    const T scale = (T)(tk.alpha / (double)n);
+    auto at = [&](int a, int b, int d, int c) { return (a * N2 + b) * RS + d * CC + c; };
+    // exponents of the stage twiddles: A/E use W_n^{r k1}, r = q2 N3 + q3;
+    // B/D use W_n^{q3 N1 k2}
+    auto ea = [&](int a) { return (int64_t)(((t + NT * a) / CC) % (N2 * N3)) * tws; };
+    auto eb = [&](int b) { return (int64_t)((((t + NT * b) / CC) % N3) * N1) * tws; };
+
+    GR xc;  // X rows of the current group (loaded during the previous group)
+    int64_t g = xcd_remap(blockIdx.x, gridDim.x);
+    if (g < G) xc.load_x(xb, g, M);
+    for (; g < G; g += gridDim.x) {
+        const cplx<T> *__restrict__ tw = opaque(tw0);  // per-thread twiddle bases
+        FS_G const cplx<T> *__restrict__ spec = opaque(spec0);
+        // A: q1 -> k1 (zero upper half), twiddle by W_n^{(q2 N3 + q3) k1}
+        {
+            cplx<T> pa[NA][lg2<N1>::v];
+#pragma unroll
+            for (int a = 0; a < NA; ++a) twiddle_bases<N1>(pa[a], tw, ea(a));
+#pragma unroll
+            for (int a = 0; a < NA; ++a) {
+                const int it = t + NT * a;
+                if (it < CC * N2 * N3) {
+                    const int c = it % CC, r = it / CC, q3 = r % N3, q2 = r / N3;
+                    cplx<T> v[N1];
+#pragma unroll
+                    for (int q1 = 0; q1 < H; ++q1) v[q1] = xc.v[a][q1];
+                    dft_reg<N1, false, true>(v);
+                    apply_twiddles_b<N1, false>(v, pa[a]);
+#pragma unroll
+                    for (int k1 = 0; k1 < N1; ++k1) sd[at(k1, q2, q3, c)] = v[k1];
+                }
+            }
+        }
+        __syncthreads();
+        // B: q2 -> k2, twiddle by W_n^{q3 k2 N1}
+        {
+            cplx<T> pb[NB][lg2<N2>::v];
+#pragma unroll
+            for (int b = 0; b < NB; ++b) twiddle_bases<N2>(pb[b], tw, eb(b));
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+                const int it = t + NT * b;
+                if (it < CC * N1 * N3) {
+                    const int c = it % CC, r = it / CC, q3 = r % N3, k1 = r / N3;
+                    cplx<T> v[N2];
+#pragma unroll
+                    for (int q2 = 0; q2 < N2; ++q2) v[q2] = sd[at(k1, q2, q3, c)];
+                    dft_reg<N2, false, false>(v);
+                    apply_twiddles_b<N2, false>(v, pb[b]);
+#pragma unroll
+                    for (int k2 = 0; k2 < N2; ++k2) sd[at(k1, k2, q3, c)] = v[k2];
+                }
+            }
+        }
+        __syncthreads();
+        // C: q3 -> k3, spectrum, k3 -> q3 (no other loads in flight)
+#pragma unroll 1
+        for (int it = t; it < CC * N1 * N2; it += NT) {
+            const int c = it % CC, r = it / CC, k2 = r % N2, k1 = r / N2;
+            cplx<T> v[N3];
+#pragma unroll
+            for (int q3 = 0; q3 < N3; ++q3) v[q3] = sd[at(k1, k2, q3, c)];
+            cplx<T> hs[N3];
+#pragma unroll
+            for (int k3 = 0; k3 < N3; ++k3) hs[k3] = spec[k1 + N1 * k2 + N1 * N2 * k3];
+            dft_reg<N3, false, false>(v);
+#pragma unroll
+            for (int k3 = 0; k3 < N3; ++k3) v[k3] = cmul(v[k3], hs[k3]);
+            dft_reg<N3, true, false>(v);
+#pragma unroll
+            for (int q3 = 0; q3 < N3; ++q3) sd[at(k1, k2, q3, c)] = v[q3];
+        }
+        __syncthreads();
+        // Loads complete in issue order: first the twiddle bases of D and E,
+        // then this group's Y rows, then the next group's X rows, so that each
+        // wait below covers only what it needs.
+        cplx<T> pa[NA][lg2<N1>::v];
+#pragma unroll
+        for (int a = 0; a < NA; ++a) twiddle_bases<N1>(pa[a], tw, ea(a));
+        {
+            cplx<T> pb[NB][lg2<N2>::v];
+#pragma unroll
+            for (int b = 0; b < NB; ++b) twiddle_bases<N2>(pb[b], tw, eb(b));
+            GR yc;
+            yc.load_y(yb, g, M, ny);
+            GR xn;
+            const int64_t gn = g + gridDim.x;
+            if (gn < G) xn.load_x(xb, gn, M);
+            // D: conjugate twiddle, k2 -> q2
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+                const int it = t + NT * b;
+                if (it < CC * N1 * N3) {
+                    const int c = it % CC, r = it / CC, q3 = r % N3, k1 = r / N3;
+                    cplx<T> v[N2];
+#pragma unroll
+                    for (int k2 = 0; k2 < N2; ++k2) v[k2] = sd[at(k1, k2, q3, c)];
+                    apply_twiddles_b<N2, true>(v, pb[b]);
+                    dft_reg<N2, true, false>(v);
+#pragma unroll
+                    for (int q2 = 0; q2 < N2; ++q2) sd[at(k1, q2, q3, c)] = v[q2];
+                }
+            }
+            __syncthreads();
+            // E: conjugate twiddle, k1 -> q1, Y = Y + scale z
+#pragma unroll
+            for (int a = 0; a < NA; ++a) {
+                const int it = t + NT * a;
+                if (it < CC * N2 * N3) {
+                    const int c = it % CC, r = it / CC, q3 = r % N3, q2 = r / N3;
+                    cplx<T> v[N1];
+#pragma unroll
+                    for (int k1 = 0; k1 < N1; ++k1) v[k1] = sd[at(k1, q2, q3, c)];
+                    apply_twiddles_b<N1, true>(v, pa[a]);
+                    dft_reg<N1, true, false>(v);
+                    const int64_t col = 2 * (g * CC + c);
+#pragma unroll
+                    for (int q1 = H; q1 < N1; ++q1) {
+                        const int p = (q1 - H) * N2 * N3 + r;
+                        if (p < ny) {
+                            const cplx<T> y0 = yc.v[a][q1 - H];
+                            st_pair<EVEN>(yb + (int64_t)p * M, col, M,
+                                       cplx<T>{y0.x + scale * v[q1].x, y0.y + scale * v[q1].y});
+                            }
+                    }
+                }
+            }
+            __syncthreads();
+            xc = xn;
+        }
+    }
+}
+
+// The near-corner band of a level product (see corner_add), for the
+// persistent update kernels: every output row p < D0 - 1 of one column per
+// thread.  With k = d - p - 1 the band reads only the last D0 - 1 rows of X:
+//   Y[p] += alpha sum_{k <= D0-2-p} w_{p+1+k} X[s-1-k].
+// It runs after the transform kernel on the same stream.
+template <typename T>
+__global__ __launch_bounds__(256) void k_corner(const UpdTask<T> *__restrict__ tasks)
+{
+    constexpr int KMAX = 31;  // corner_width(s) - 1 <= 31
+    const UpdTask<T> tk = tasks[blockIdx.z];
+    const int64_t M = tk.M;
+    const int64_t col = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (col >= M) return;
+    const int K = corner_width(tk.s) - 1;
+    const int np = K < tk.ny ? K : tk.ny;
+    FS_G const double *__restrict__ xb = gptr(tk.xc) + (tk.xlo + tk.s - 1) * M + col;
+    FS_G const double *__restrict__ w = gptr(tk.w);
+    FS_G double *__restrict__ yb = gptr(tk.yc) + tk.ylo * M + col;
+    double xr[KMAX], yv[KMAX];
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k) xr[k] = (k < K) ? xb[-(int64_t)k * M] : 0.0;
+#pragma unroll
+    for (int p = 0; p < KMAX; ++p) yv[p] = (p < np) ? yb[(int64_t)p * M] : 0.0;
+#pragma unroll
+    for (int p = 0; p < KMAX; ++p) {
+        if (p < np) {
+            double acc = 0.0;
+#pragma unroll
+            for (int k = 0; k + p < KMAX; ++k)
+                if (k <= K - 1 - p) acc += w[p + 1 + k] * xr[k];
+            yb[(int64_t)p * M] = yv[p] + tk.alpha * acc;
         }
     }
 }
@@ -409,7 +869,7 @@ __global__ __launch_bounds__(256) void k_mp_pass1(const UpdTask<T> *__restrict__
 #pragma unroll
     for (int q1 = 0; q1 < N1 / 2; ++q1)
         v[q1] = (cl < Mc) ? load_pair(xb + ((int64_t)q1 * nin + q2) * M, col, M) : cplx<T>{0, 0};
-    dft_reg<N1, false, true>(v, tw, nmax);
+    dft_reg<N1, false, true>(v);
 #pragma unroll
     for (int k1 = 0; k1 < N1; ++k1) {
         cplx<T> e = (k1 == 0) ? v[k1] : cmul(v[k1], twiddle(tw, (int64_t)q2 * k1 * tws, false));
@@ -453,7 +913,7 @@ __global__ __launch_bounds__(256) void k_mp_pass3(const UpdTask<T> *__restrict__
         cplx<T> e = sb[k1][tx][ty];
         v[k1] = (k1 == 0) ? e : cmul(e, twiddle(tw, (int64_t)q2 * k1 * tws, true));
     }
-    dft_reg<N1, true, false>(v, tw, nmax);
+    dft_reg<N1, true, false>(v);
     if (cl < Mc) {
         const int64_t col = 2 * (c0 + cl);
         const T scale = (T)(tk.alpha / (double)n);
@@ -527,13 +987,31 @@ hipError_t launch_spectrum(hipStream_t st, const double *w, int s, cplx<double> 
 
 // ------------------------------------------------------------ dispatch
 // Single-pass factorisations and complex columns per workgroup.
-template <typename T, int MODE>
+// Persistent workgroups per task for the update kernels: as many as fit on
+// the chip at the kernel's LDS use (160 KiB per CU, 256 CUs), shared by the
+// tasks of the launch, at most one per column group.
+static unsigned persistent_groups(size_t lds_bytes, int64_t groups, int ntasks)
+{
+    int64_t per_cu = (int64_t)((160 * 1024) / (lds_bytes ? lds_bytes : 1));
+    if (per_cu < 1) per_cu = 1;
+    if (per_cu > 8) per_cu = 8;
+    int64_t np = (256 * per_cu + ntasks - 1) / ntasks;
+    if (np > groups) np = groups;
+    if (np < 1) np = 1;
+    return (unsigned)np;
+}
+
+template <typename T, int MODE, bool EVEN = false>
 static hipError_t single_pass(hipStream_t st, const UpdTask<T> *d_tasks, int ntasks, int n, int64_t ncols_c,
                               const cplx<T> *tw, int64_t nmax, cplx<T> *zs, int64_t Mc, int N1g, int nk1)
 {
     auto grid = [&](int CC) {
         unsigned gx = (unsigned)((ncols_c + CC - 1) / CC);
         return (MODE == MODE_UPDATE) ? dim3(gx, 1, (unsigned)ntasks) : dim3(gx, (unsigned)nk1, 1);
+    };
+    auto pgrid = [&](int CC, size_t lds) {
+        const int64_t groups = (ncols_c + CC - 1) / CC;
+        return dim3(persistent_groups(lds, groups, ntasks), 1, (unsigned)ntasks);
     };
 #define FS_F2(N1_, N2_, CC_)                                                                                     \
     case N1_ * N2_:                                                                                              \
@@ -545,6 +1023,55 @@ static hipError_t single_pass(hipStream_t st, const UpdTask<T> *d_tasks, int nta
         hipLaunchKernelGGL((k_fft3<T, N1_, N2_, N3_, CC_, MODE>), grid(CC_), dim3(256), 0, st, d_tasks, tw, nmax, \
                            zs, Mc, N1g);                                                                          \
         return hipGetLastError();
+#define FS_U2(N1_, N2_, CC_)                                                                                   \
+    case N1_ * N2_:                                                                                            \
+        hipLaunchKernelGGL((k_fft2u<T, N1_, N2_, CC_, EVEN>), pgrid(CC_, sizeof(cplx<T>) * N1_ * (N2_ * CC_ + 1)),   \
+                           dim3(256), 0, st, d_tasks, tw, nmax);                                               \
+        return hipGetLastError();
+#define FS_U3(N1_, N2_, N3_, CC_, NT_)                                                                         \
+    case N1_ * N2_ * N3_:                                                                                      \
+        hipLaunchKernelGGL((k_fft3u<T, N1_, N2_, N3_, CC_, NT_, EVEN>),                                              \
+                           pgrid(CC_, sizeof(cplx<T>) * N1_ * N2_ * (N3_ * CC_ + 1)), dim3(NT_), 0, st, d_tasks, \
+                           tw, nmax);                                                                          \
+        return hipGetLastError();
+    if constexpr (MODE == MODE_UPDATE) {
+        if constexpr (sizeof(T) == 8) {
+            switch (n) {
+                FS_U2(4, 2, 8)
+                FS_U2(4, 4, 8)
+                FS_U2(8, 4, 8)
+                FS_U2(8, 8, 8)
+                FS_U2(16, 8, 8)
+                FS_U2(16, 16, 8)
+                FS_U3(16, 8, 4, 8, 256)
+                FS_U3(16, 8, 8, 8, 256)
+                FS_U3(16, 16, 8, 4, 256)
+                FS_U3(16, 16, 16, 2, 256)
+                FS_U3(16, 16, 32, 1, 256)
+                default:
+                    return hipErrorInvalidValue;
+            }
+        } else {
+            switch (n) {
+                FS_U2(4, 2, 8)
+                FS_U2(4, 4, 8)
+                FS_U2(8, 4, 8)
+                FS_U2(8, 8, 8)
+                FS_U2(16, 8, 8)
+                FS_U2(16, 16, 8)
+                FS_U3(16, 8, 4, 8, 256)
+                FS_U3(16, 8, 8, 8, 256)
+                FS_U3(16, 16, 8, 8, 256)
+                FS_U3(16, 16, 16, 4, 256)
+                FS_U3(16, 16, 32, 2, 256)
+                FS_U3(16, 32, 32, 1, 256)
+                default:
+                    return hipErrorInvalidValue;
+            }
+        }
+#undef FS_U2
+#undef FS_U3
+    } else {
     if constexpr (sizeof(T) == 8) {
         switch (n) {
             FS_F2(4, 2, 8)
@@ -578,6 +1105,7 @@ static hipError_t single_pass(hipStream_t st, const UpdTask<T> *d_tasks, int nta
             default:
                 return hipErrorInvalidValue;
         }
+    }
     }
 #undef FS_F2
 #undef FS_F3
@@ -636,18 +1164,27 @@ static hipError_t multipass(hipStream_t st, const UpdTask<T> *d_task, int n, int
 // exactly one task and need the scratch buffer zs (zs_elems complex entries).
 template <typename T>
 hipError_t launch_fft_update_ex(hipStream_t st, const UpdTask<T> *d_tasks, int ntasks, int s, int64_t maxM,
-                                const cplx<T> *tw, int64_t nmax, cplx<T> *zs, size_t zs_elems)
+                                const cplx<T> *tw, int64_t nmax, cplx<T> *zs, size_t zs_elems, bool even)
 {
     const int n = 2 * s;
-    if (n <= fft_max_single_pass(sizeof(T) == 4))
-        return single_pass<T, MODE_UPDATE>(st, d_tasks, ntasks, n, (maxM + 1) / 2, tw, nmax, nullptr, 0, 1, 1);
+    if (n <= fft_max_single_pass(sizeof(T) == 4)) {
+        hipError_t e = even ? single_pass<T, MODE_UPDATE, true>(st, d_tasks, ntasks, n, (maxM + 1) / 2, tw, nmax,
+                                                                nullptr, 0, 1, 1)
+                            : single_pass<T, MODE_UPDATE, false>(st, d_tasks, ntasks, n, (maxM + 1) / 2, tw, nmax,
+                                                                 nullptr, 0, 1, 1);
+        if (e != hipSuccess) return e;
+        if (corner_width(s) < 2) return hipSuccess;
+        hipLaunchKernelGGL((k_corner<T>), dim3((unsigned)((maxM + 255) / 256), 1, (unsigned)ntasks), dim3(256), 0,
+                           st, d_tasks);
+        return hipGetLastError();
+    }
     if (ntasks != 1) return hipErrorInvalidValue;
     return multipass<T>(st, d_tasks, n, maxM, tw, nmax, zs, zs_elems);
 }
 
 template hipError_t launch_fft_update_ex<double>(hipStream_t, const UpdTask<double> *, int, int, int64_t,
-                                                const cplx<double> *, int64_t, cplx<double> *, size_t);
+                                                const cplx<double> *, int64_t, cplx<double> *, size_t, bool);
 template hipError_t launch_fft_update_ex<float>(hipStream_t, const UpdTask<float> *, int, int, int64_t,
-                                               const cplx<float> *, int64_t, cplx<float> *, size_t);
+                                               const cplx<float> *, int64_t, cplx<float> *, size_t, bool);
 
 }  // namespace fs

@@ -21,10 +21,10 @@ constexpr int DENSE_MAXS = 1024; // largest half-block size for this kernel
 
 // QC: X rows per load batch (min(s, 64))
 template <typename T, int QC>
-__global__ __launch_bounds__(256) void k_dense_update(const UpdTask<T> *__restrict__ tasks)
+__global__ __launch_bounds__(256) void k_dense_update(TaskRef<UpdTask<T>> tr)
 {
     __shared__ double sw[DENSE_MAXS + DENSE_RB];
-    const UpdTask<T> tk = tasks[blockIdx.z];
+    const UpdTask<T> tk = get_task(tr, blockIdx.z);
     const int s = tk.s;
     const int64_t M = tk.M;
     const int p0 = blockIdx.y * DENSE_RB;  // first output row of the workgroup
@@ -69,7 +69,7 @@ __global__ __launch_bounds__(256) void k_dense_update(const UpdTask<T> *__restri
 }
 
 template <typename T>
-hipError_t launch_gemm_update(hipStream_t st, const UpdTask<T> *d_tasks, int ntasks, int s, int64_t maxM)
+hipError_t launch_gemm_update(hipStream_t st, const TaskRef<UpdTask<T>> &d_tasks, int ntasks, int s, int64_t maxM)
 {
     if (s > DENSE_MAXS) return hipErrorInvalidValue;
     dim3 grid((unsigned)((maxM + 255) / 256), (unsigned)((s + DENSE_RB - 1) / DENSE_RB), (unsigned)ntasks);
@@ -86,7 +86,7 @@ hipError_t launch_gemm_update(hipStream_t st, const UpdTask<T> *d_tasks, int nta
     return hipGetLastError();
 }
 
-template hipError_t launch_gemm_update<double>(hipStream_t, const UpdTask<double> *, int, int, int64_t);
-template hipError_t launch_gemm_update<float>(hipStream_t, const UpdTask<float> *, int, int, int64_t);
+template hipError_t launch_gemm_update<double>(hipStream_t, const TaskRef<UpdTask<double>> &, int, int, int64_t);
+template hipError_t launch_gemm_update<float>(hipStream_t, const TaskRef<UpdTask<float>> &, int, int, int64_t);
 
 }  // namespace fs

@@ -134,7 +134,7 @@ __device__ __forceinline__ void row_scans(double &f, double &b, const double *cp
 }
 
 template <int NT, int PT, int L, bool MIXED, bool VEC>
-__global__ __launch_bounds__(NT) void k_leaf_scan(const LeafTask *__restrict__ tasks)
+__global__ __launch_bounds__(NT) void k_leaf_scan(TaskRef<LeafTask> tr)
 {
     static_assert(PT % 2 == 0 && PT <= 16, "rows per thread must be even and at most 16");
     constexpr int NR = NT / 16;  // rows of 16 lanes in the workgroup (<= 32)
@@ -143,7 +143,7 @@ __global__ __launch_bounds__(NT) void k_leaf_scan(const LeafTask *__restrict__ t
     constexpr int UT = PT / 2;
     __shared__ double sR[2][2][NR];  // [parity][forward/backward][row]
 
-    const LeafTask tk = tasks[blockIdx.x];
+    const LeafTask tk = get_task(tr, blockIdx.x);
     const int t = threadIdx.x;
     const int lane = t & 63;
     const int rl = lane & 15;  // position inside the row
@@ -347,7 +347,7 @@ hipError_t launch_scan_factor(hipStream_t st, const LeafCfg &c, int64_t M, doubl
 }
 
 template <int NT, int PT, int L>
-static hipError_t scan_go(hipStream_t st, bool mixed, bool vec, const LeafTask *d_tasks, int ntasks)
+static hipError_t scan_go(hipStream_t st, bool mixed, bool vec, const TaskRef<LeafTask> &d_tasks, int ntasks)
 {
     if (mixed) {
         if (vec)
@@ -364,7 +364,7 @@ static hipError_t scan_go(hipStream_t st, bool mixed, bool vec, const LeafTask *
 }
 
 template <int NT, int PT>
-static hipError_t scan_go16(hipStream_t st, bool mixed, bool vec, const LeafTask *d_tasks, int ntasks)
+static hipError_t scan_go16(hipStream_t st, bool mixed, bool vec, const TaskRef<LeafTask> &d_tasks, int ntasks)
 {
     if constexpr (PT <= 2)
         return scan_go<NT, PT, 16>(st, mixed, vec, d_tasks, ntasks);
@@ -372,7 +372,7 @@ static hipError_t scan_go16(hipStream_t st, bool mixed, bool vec, const LeafTask
         return hipErrorInvalidValue;
 }
 
-hipError_t launch_leaf_scan(hipStream_t st, const LeafCfg &c, int L, const LeafTask *d_tasks, int ntasks,
+hipError_t launch_leaf_scan(hipStream_t st, const LeafCfg &c, int L, const TaskRef<LeafTask> &d_tasks, int ntasks,
                             bool mixed, bool vec)
 {
 #define FS_SL(NT_, PT_)                                                                        \
