@@ -182,7 +182,8 @@ int fracsolve_get_stats(fracsolve_t h, fracsolve_stats *out);
 
 /* Per-kernel-group timing of the last call (timing level 2).  One record per
  * (kind, s): kind 0 = leaf solves (s = leaf size), 1 = dense float64 level
- * products, 2 = dense float32, 3 = FFT float64, 4 = FFT float32 (s = level
+ * products, 2 = dense float32, 3 = FFT float64, 4 = FFT float32, 5 = the
+ * near-corner band added after single-pass FFT levels (s = level
  * half-size).  bytes = algorithmic HBM bytes of those launches (reads of X
  * and of the right-hand side, read+write of Y, solution writes).  Writes at
  * most cap records to out and their number to *count. */

@@ -41,7 +41,7 @@ class KernelStat(ctypes.Structure):
                 ("tasks", ctypes.c_int32), ("ms", ctypes.c_double), ("bytes", ctypes.c_double)]
 
 
-KIND_NAMES = {0: "leaf", 1: "dense_f64", 2: "dense_f32", 3: "fft_f64", 4: "fft_f32"}
+KIND_NAMES = {0: "leaf", 1: "dense_f64", 2: "dense_f32", 3: "fft_f64", 4: "fft_f32", 5: "fft_corner"}
 
 EXPORTS = ["fracsolve_create", "fracsolve_weights", "fracsolve_solve", "fracsolve_apply", "fracsolve_adjoint",
            "fracsolve_set_timing", "fracsolve_get_stats", "fracsolve_kernel_stats", "fracsolve_destroy",

@@ -177,9 +177,16 @@ template <typename T>
 hipError_t launch_gemm_update(hipStream_t st, const TaskRef<UpdTask<T>> &tr, int ntasks, int s, int64_t maxM);
 // even: every task has M even and 16-byte aligned rows (one vector access per
 // column pair)
+// corner: also launch the near-corner band kernel of single-pass levels
+// (launch_fft_corner) after the transform
 template <typename T>
 hipError_t launch_fft_update_ex(hipStream_t st, const UpdTask<T> *d_tasks, int ntasks, int s, int64_t maxM,
-                                const cplx<T> *tw, int64_t nmax, cplx<T> *zs, size_t zs_elems, bool even);
+                                const cplx<T> *tw, int64_t nmax, cplx<T> *zs, size_t zs_elems, bool even,
+                                bool corner = true);
+// near-corner band of a single-pass FFT level (no-op for multi-pass levels,
+// which add it inside their last pass)
+template <typename T>
+hipError_t launch_fft_corner(hipStream_t st, const UpdTask<T> *d_tasks, int ntasks, int s, int64_t maxM);
 hipError_t launch_spectrum(hipStream_t st, const double *w, int s, cplx<double> *spec64, cplx<float> *spec32,
                            const cplx<double> *tw, int64_t nmax, cplx<double> *scratch);
 int fft_max_single_pass(bool fp32);

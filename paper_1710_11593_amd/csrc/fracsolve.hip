@@ -287,12 +287,12 @@ int run_ops(fracsolve_ctx *h, const std::vector<Op> &ops)
             case OP_FFT64:
                 e = launch_fft_update_ex<double>(h->st, dptr<UpdTask<double>>(h, op.off), op.ntasks, op.s, op.maxM,
                                                  h->tw64, h->nmax, (cplx<double> *)h->zs,
-                                                 h->zs_bytes / sizeof(cplx<double>), op.even);
+                                                 h->zs_bytes / sizeof(cplx<double>), op.even, h->timing < 2);
                 break;
             case OP_FFT32:
                 e = launch_fft_update_ex<float>(h->st, dptr<UpdTask<float>>(h, op.off), op.ntasks, op.s, op.maxM,
                                                 h->tw32, h->nmax, (cplx<float> *)h->zs,
-                                                h->zs_bytes / sizeof(cplx<float>), op.even);
+                                                h->zs_bytes / sizeof(cplx<float>), op.even, h->timing < 2);
                 break;
         }
         if (e != hipSuccess) return fail(h, FRACSOLVE_E_DEVICE, "kernel launch failed: %s", hipGetErrorString(e));
@@ -302,6 +302,25 @@ int run_ops(fracsolve_ctx *h, const std::vector<Op> &ops)
             const bool lf = op.kind == OP_LEAF || op.kind == OP_LEAF_SCAN;
             int kind = lf ? 0 : op.kind == OP_GEMM64 ? 1 : op.kind == OP_GEMM32 ? 2 : op.kind == OP_FFT64 ? 3 : 4;
             h->recs.push_back({kind, lf ? h->L : op.s, op.ntasks, op.bytes, evi});
+            // the near-corner band of an FFT level as a group of its own:
+            // X rows s-31..s-1, Y rows 0..30 read and written
+            const bool fft = op.kind == OP_FFT64 || op.kind == OP_FFT32;
+            if (fft && 2 * op.s <= fft_max_single_pass(op.kind == OP_FFT32) && corner_width(op.s) >= 2) {
+                const size_t evj = 2 * h->recs.size();
+                hipEvent_t e1;
+                int rc = get_event(h, evj + 1, &e1);
+                if (rc) return rc;
+                HIPCHK(h, hipEventRecord(h->evpool[evj], h->st));
+                e = op.kind == OP_FFT64
+                        ? launch_fft_corner<double>(h->st, dptr<UpdTask<double>>(h, op.off), op.ntasks, op.s, op.maxM)
+                        : launch_fft_corner<float>(h->st, dptr<UpdTask<float>>(h, op.off), op.ntasks, op.s, op.maxM);
+                if (e != hipSuccess)
+                    return fail(h, FRACSOLVE_E_DEVICE, "kernel launch failed: %s", hipGetErrorString(e));
+                h->kernels++;
+                HIPCHK(h, hipEventRecord(h->evpool[evj + 1], h->st));
+                const double band = 3.0 * (double)(corner_width(op.s) - 1) * (double)op.maxM * 8.0 * op.ntasks;
+                h->recs.push_back({5, op.s, op.ntasks, band, evj});
+            }
         }
     }
     return FRACSOLVE_OK;

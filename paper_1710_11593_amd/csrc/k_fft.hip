@@ -810,10 +810,13 @@ __global__ __launch_bounds__(NT) void k_fft3u(const UpdTask<T> *__restrict__ tas
 }
 
 // The near-corner band of a level product (see corner_add), for the
-// persistent update kernels: every output row p < D0 - 1 of one column per
-// thread.  With k = d - p - 1 the band reads only the last D0 - 1 rows of X:
-//   Y[p] += alpha sum_{k <= D0-2-p} w_{p+1+k} X[s-1-k].
-// It runs after the transform kernel on the same stream.
+// persistent update kernels.  With k = d - p - 1 the band reads only the
+// last D0 - 1 rows of X:
+//   Y[p] += alpha sum_{k <= D0-2-p} w_{p+1+k} X[s-1-k],   p < D0 - 1.
+// One thread per (output row p = blockIdx.y, column): all its X loads are
+// issued together (the rows are shared through the cache by the threads of
+// the other p), so a launch costs about two memory round trips.  It runs
+// after the transform kernel on the same stream.
 template <typename T>
 __global__ __launch_bounds__(256) void k_corner(const UpdTask<T> *__restrict__ tasks)
 {
@@ -821,27 +824,22 @@ __global__ __launch_bounds__(256) void k_corner(const UpdTask<T> *__restrict__ t
     const UpdTask<T> tk = tasks[blockIdx.z];
     const int64_t M = tk.M;
     const int64_t col = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (col >= M) return;
     const int K = corner_width(tk.s) - 1;
-    const int np = K < tk.ny ? K : tk.ny;
+    const int p = blockIdx.y;
+    if (col >= M || p >= K || p >= tk.ny) return;
     FS_G const double *__restrict__ xb = gptr(tk.xc) + (tk.xlo + tk.s - 1) * M + col;
-    FS_G const double *__restrict__ w = gptr(tk.w);
-    FS_G double *__restrict__ yb = gptr(tk.yc) + tk.ylo * M + col;
-    double xr[KMAX], yv[KMAX];
+    FS_G const double *__restrict__ w = gptr(tk.w) + p + 1;
+    FS_G double *__restrict__ yr = gptr(tk.yc) + (tk.ylo + p) * M + col;
+    const int nk = K - p;  // k < nk
+    double xr[KMAX];
 #pragma unroll
-    for (int k = 0; k < KMAX; ++k) xr[k] = (k < K) ? xb[-(int64_t)k * M] : 0.0;
+    for (int k = 0; k < KMAX; ++k) xr[k] = (k < nk) ? xb[-(int64_t)k * M] : 0.0;
+    const double y0 = *yr;
+    double acc = 0.0;
 #pragma unroll
-    for (int p = 0; p < KMAX; ++p) yv[p] = (p < np) ? yb[(int64_t)p * M] : 0.0;
-#pragma unroll
-    for (int p = 0; p < KMAX; ++p) {
-        if (p < np) {
-            double acc = 0.0;
-#pragma unroll
-            for (int k = 0; k + p < KMAX; ++k)
-                if (k <= K - 1 - p) acc += w[p + 1 + k] * xr[k];
-            yb[(int64_t)p * M] = yv[p] + tk.alpha * acc;
-        }
-    }
+    for (int k = 0; k < KMAX; ++k)
+        if (k < nk) acc += w[k] * xr[k];
+    *yr = y0 + tk.alpha * acc;
 }
 
 // ------------------------------------------------ multi-pass outer digit
@@ -1163,8 +1161,19 @@ static hipError_t multipass(hipStream_t st, const UpdTask<T> *d_task, int n, int
 // Entry: tasks of one level (all with the same s).  Multi-pass levels take
 // exactly one task and need the scratch buffer zs (zs_elems complex entries).
 template <typename T>
+hipError_t launch_fft_corner(hipStream_t st, const UpdTask<T> *d_tasks, int ntasks, int s, int64_t maxM)
+{
+    if (2 * s > fft_max_single_pass(sizeof(T) == 4) || corner_width(s) < 2) return hipSuccess;
+    hipLaunchKernelGGL((k_corner<T>), dim3((unsigned)((maxM + 255) / 256), (unsigned)(corner_width(s) - 1),
+                                           (unsigned)ntasks),
+                       dim3(256), 0, st, d_tasks);
+    return hipGetLastError();
+}
+
+template <typename T>
 hipError_t launch_fft_update_ex(hipStream_t st, const UpdTask<T> *d_tasks, int ntasks, int s, int64_t maxM,
-                                const cplx<T> *tw, int64_t nmax, cplx<T> *zs, size_t zs_elems, bool even)
+                                const cplx<T> *tw, int64_t nmax, cplx<T> *zs, size_t zs_elems, bool even,
+                                bool corner)
 {
     const int n = 2 * s;
     if (n <= fft_max_single_pass(sizeof(T) == 4)) {
@@ -1172,19 +1181,19 @@ hipError_t launch_fft_update_ex(hipStream_t st, const UpdTask<T> *d_tasks, int n
                                                                 nullptr, 0, 1, 1)
                             : single_pass<T, MODE_UPDATE, false>(st, d_tasks, ntasks, n, (maxM + 1) / 2, tw, nmax,
                                                                  nullptr, 0, 1, 1);
-        if (e != hipSuccess) return e;
-        if (corner_width(s) < 2) return hipSuccess;
-        hipLaunchKernelGGL((k_corner<T>), dim3((unsigned)((maxM + 255) / 256), 1, (unsigned)ntasks), dim3(256), 0,
-                           st, d_tasks);
-        return hipGetLastError();
+        if (e != hipSuccess || !corner) return e;
+        return launch_fft_corner<T>(st, d_tasks, ntasks, s, maxM);
     }
     if (ntasks != 1) return hipErrorInvalidValue;
     return multipass<T>(st, d_tasks, n, maxM, tw, nmax, zs, zs_elems);
 }
 
 template hipError_t launch_fft_update_ex<double>(hipStream_t, const UpdTask<double> *, int, int, int64_t,
-                                                const cplx<double> *, int64_t, cplx<double> *, size_t, bool);
+                                                const cplx<double> *, int64_t, cplx<double> *, size_t, bool,
+                                                bool);
+template hipError_t launch_fft_corner<double>(hipStream_t, const UpdTask<double> *, int, int, int64_t);
+template hipError_t launch_fft_corner<float>(hipStream_t, const UpdTask<float> *, int, int, int64_t);
 template hipError_t launch_fft_update_ex<float>(hipStream_t, const UpdTask<float> *, int, int, int64_t,
-                                               const cplx<float> *, int64_t, cplx<float> *, size_t, bool);
+                                               const cplx<float> *, int64_t, cplx<float> *, size_t, bool, bool);
 
 }  // namespace fs

@@ -195,12 +195,27 @@ __global__ __launch_bounds__(NT) void k_leaf_scan(TaskRef<LeafTask> tr)
 #pragma unroll
             for (int k = 0; k < PT; ++k) acc[r][k] = (r < nrows && c0 + k < M) ? row[col(k)] : 0.0;
         }
-        if (MIXED && r < nrows) {
-#pragma unroll
-            for (int k = 0; k < PT; ++k)
-                if (c0 + k < M) acc[r][k] += (double)hist[(int64_t)r * M + col(k)];
-        }
     }
+    // float32 history rows (mixed mode): row r is loaded one step ahead, in
+    // step r - 1 (row 0 with the float64 rows), and added when step r starts
+    float hv[PT];
+    auto load_hist = [&](int r) {
+        FS_G const float *hrow = hist + (int64_t)r * M;
+        if (VEC) {
+            // col(2i) is even and M is even: 8-byte aligned pairs
+#pragma unroll
+            for (int i = 0; i < UT; ++i) {
+                float2 v = float2{0.f, 0.f};
+                if (r < nrows && act) v = *reinterpret_cast<FS_G const float2 *>(hrow + col(2 * i));
+                hv[2 * i] = v.x;
+                hv[2 * i + 1] = v.y;
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < PT; ++k) hv[k] = (r < nrows && c0 + k < M) ? hrow[col(k)] : 0.f;
+        }
+    };
+    if (MIXED) load_hist(0);
 
     // uniform constants
     const double K0 = tab[0];
@@ -236,6 +251,11 @@ __global__ __launch_bounds__(NT) void k_leaf_scan(TaskRef<LeafTask> tr)
         const int par = r & 1;
         double lf[PT], sb[PT];
         double Sf = 0.0, Sb = 0.0;
+        if (MIXED && run) {
+#pragma unroll
+            for (int k = 0; k < PT; ++k) acc[r][k] += (double)hv[k];
+            if (r + 1 < L) load_hist(r + 1);
+        }
         if (run) {
             // carry-free local prefix l and suffix s of the thread's rows
             lf[0] = al[0] * acc[r][0];
@@ -268,9 +288,19 @@ __global__ __launch_bounds__(NT) void k_leaf_scan(TaskRef<LeafTask> tr)
                     if (c0 + k < M) row[col(k)] = xp[k];
             }
             if (MIXED) {
+                FS_G float *xrow = x32 + (int64_t)(r - 1) * M;
+                if (VEC) {
+                    if (act) {
 #pragma unroll
-                for (int k = 0; k < PT; ++k)
-                    if (c0 + k < M) x32[(int64_t)(r - 1) * M + col(k)] = (float)xp[k];
+                        for (int i = 0; i < UT; ++i)
+                            *reinterpret_cast<FS_G float2 *>(xrow + col(2 * i)) =
+                                float2{(float)xp[2 * i], (float)xp[2 * i + 1]};
+                    }
+                } else {
+#pragma unroll
+                    for (int k = 0; k < PT; ++k)
+                        if (c0 + k < M) xrow[col(k)] = (float)xp[k];
+                }
             }
 #pragma unroll
             for (int j = r + 1; j < L; ++j) {
