@@ -88,8 +88,12 @@ struct LeafTask {
     int64_t M;
     int64_t lo;
     int32_t nrows;
-    int32_t perm;       // fields in the transposed column order of ColPerm (scan leaf)
+    // scan leaf flags: bit 0 (LEAF_PERM) fields in the transposed column order
+    // of ColPerm; bit 1 (LEAF_VEC) whole 16-byte row units (M a multiple of
+    // PT, aligned rows)
+    int32_t flags;
 };
+constexpr int32_t LEAF_PERM = 1, LEAF_VEC = 2;
 
 // One off-diagonal Toeplitz-block product:
 //   Y[ylo + p] += alpha * sum_{q<s} w[s + p - q] X[xlo + q],   p < ny <= s,
@@ -158,7 +162,8 @@ struct LeafCfg {
     int nt;       // threads per workgroup
     int pt;       // rows per thread
     int S;        // PCR stages = log2(2 nt)
-    int vec = 0;  // scan leaf: M % pt == 0 and 16-byte aligned fields (whole-unit row access)
+    int vec = 0;  // scan leaf row access: 0 per element, 1 whole 16-byte units (M % pt == 0,
+                  // aligned fields), 2 chosen per task (LeafTask::vec)
 };
 LeafCfg leaf_config(int64_t M);
 size_t leaf_table_doubles(const LeafCfg &c);
@@ -169,7 +174,7 @@ LeafCfg scan_config(int64_t M);
 size_t scan_table_doubles(const LeafCfg &c);
 hipError_t launch_scan_factor(hipStream_t st, const LeafCfg &c, int64_t M, double a0, double e, double *tab);
 hipError_t launch_leaf_scan(hipStream_t st, const LeafCfg &c, int L, const TaskRef<LeafTask> &tr, int ntasks,
-                            bool mixed, bool vec);
+                            bool mixed, int vec);
 
 hipError_t launch_twiddles(hipStream_t st, int64_t nmax, cplx<double> *w64, cplx<float> *w32);
 

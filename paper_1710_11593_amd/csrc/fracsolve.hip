@@ -126,6 +126,9 @@ struct fracsolve_ctx {
     std::vector<GraphEntry> graphs;
     int kernels = 0;
     std::vector<double *> allocs;
+    // batches: every instance uses the leaf configuration of the widest one,
+    // so that one launch per step covers all leaves (0: single instance)
+    int64_t batch_M = 0;
 };
 
 namespace {
@@ -275,8 +278,7 @@ int run_ops(fracsolve_ctx *h, const std::vector<Op> &ops)
                 e = launch_leaf(h->st, op.lc, h->L, dptr<LeafTask>(h, op.off), op.ntasks, op.mixed);
                 break;
             case OP_LEAF_SCAN:
-                e = launch_leaf_scan(h->st, op.lc, h->L, task_ref<LeafTask>(h, op), op.ntasks, op.mixed,
-                                     op.lc.vec != 0);
+                e = launch_leaf_scan(h->st, op.lc, h->L, task_ref<LeafTask>(h, op), op.ntasks, op.mixed, op.lc.vec);
                 break;
             case OP_GEMM64:
                 e = launch_gemm_update<double>(h->st, task_ref<UpdTask<double>>(h, op), op.ntasks, op.s, op.maxM);
@@ -436,22 +438,27 @@ void build_solve(fracsolve_ctx *h, const std::vector<int> &sel, const std::vecto
             t.M = in.M;
             t.lo = lo;
             t.nrows = (int)std::min<int64_t>(L, in.N - lo);
-            t.perm = (in.perm.pt > 2 && in.perm.mfull > 0) ? 1 : 0;
+            t.flags = (in.perm.pt > 2 && in.perm.mfull > 0) ? LEAF_PERM : 0;
             // whole 16-byte row units for the scan leaf
-            const bool vec = in.scan && (in.M % in.lc.pt) == 0 && ((uintptr_t)t.u & 15) == 0;
-            lt.push_back({(in.scan ? 1000000 : 0) + (vec ? 200000 : 0) + in.lc.nt * 100 + in.lc.pt, t});
+            if (in.scan && (in.M % in.lc.pt) == 0 && ((uintptr_t)t.u & 15) == 0) t.flags |= LEAF_VEC;
+            lt.push_back({(in.scan ? 1000000 : 0) + in.lc.nt * 100 + in.lc.pt, t});
         }
         std::sort(lt.begin(), lt.end(), [](const auto &x, const auto &y) { return x.first < y.first; });
         for (size_t b = 0; b < lt.size();) {
             size_t e = b;
             while (e < lt.size() && lt[e].first == lt[b].first) ++e;
             std::vector<LeafTask> v;
-            for (size_t j = b; j < e; ++j) v.push_back(lt[j].second);
+            int nvec = 0;
+            for (size_t j = b; j < e; ++j) {
+                v.push_back(lt[j].second);
+                nvec += (lt[j].second.flags & LEAF_VEC) ? 1 : 0;
+            }
             size_t off = db.add(v.data(), v.size() * sizeof(LeafTask));
-            const int key = lt[b].first % 200000;
+            const int key = lt[b].first % 1000000;
             LeafCfg lc{key / 100, key % 100, 0};
             lc.S = ilog2i(2 * lc.nt);
-            lc.vec = (lt[b].first % 1000000) >= 200000;
+            // one launch per configuration: vector rows for all, for none, or per task
+            lc.vec = nvec == (int)v.size() ? 1 : (nvec == 0 ? 0 : 2);
             Op op{lt[b].first >= 1000000 ? OP_LEAF_SCAN : OP_LEAF, off, (int)v.size(), 0, 0, lc, mixed};
             for (auto &t : v) op.bytes += (double)t.nrows * (double)t.M * (mixed ? 24.0 : 16.0);
             ops.push_back(op);
@@ -715,7 +722,7 @@ int setup_instance(fracsolve_ctx *h, Inst &in)
     in.coef = std::pow(in.tau, -p.gamma) / std::tgamma(garg);
     in.dcoef = in.coef * (-std::log(in.tau) + digamma_host(garg));
     in.scan = (h->opts.leaf_solver == 0);
-    in.lc = in.scan ? scan_config(in.M) : leaf_config(in.M);
+    in.lc = in.scan ? scan_config(h->batch_M > 0 ? h->batch_M : in.M) : leaf_config(in.M);
     if (in.scan && in.lc.pt > 2 && in.M % in.lc.pt == 0)
         in.perm = ColPerm{in.lc.pt, (in.M / (64 * (int64_t)in.lc.pt)) * 64 * (int64_t)in.lc.pt};
     if (h->L > 8 && ((in.scan && in.lc.pt > 2) || (!in.scan && in.lc.pt == 16)))
@@ -915,6 +922,8 @@ int fracsolve_create(const fracsolve_problem *probs, int32_t count, const fracso
     if (!rc && launch_twiddles(h->st, h->nmax, h->tw64, h->tw32) != hipSuccess)
         rc = fail(h, FRACSOLVE_E_DEVICE, "twiddle kernel launch failed");
     h->inst.resize(count);
+    if (count > 1)
+        for (int k = 0; k < count; ++k) h->batch_M = std::max<int64_t>(h->batch_M, probs[k].M);
     for (int k = 0; k < count && !rc; ++k) {
         h->inst[k].p = probs[k];
         rc = setup_instance(h, h->inst[k]);

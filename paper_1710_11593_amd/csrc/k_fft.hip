@@ -588,6 +588,10 @@ __global__ __launch_bounds__(256) void k_fft2u(const UpdTask<T> *__restrict__ ta
     for (; g < G; g += gridDim.x) {
         const cplx<T> *__restrict__ tw = opaque(tw0);  // per-thread twiddle bases
         FS_G const cplx<T> *__restrict__ spec = opaque(spec0);
+        // this group's Y rows, in flight during stages A and B (issued after
+        // this group's X, so waiting for X does not wait for them)
+        GR yc;
+        yc.load_y(yb, g, M, ny);
         // stage A: digit q1 -> k1 (forward, zero upper half), twiddle, to LDS
 #pragma unroll
         for (int a = 0; a < NA; ++a) {
@@ -621,10 +625,8 @@ __global__ __launch_bounds__(256) void k_fft2u(const UpdTask<T> *__restrict__ ta
 #pragma unroll
             for (int q2 = 0; q2 < N2; ++q2) sd[k1 * RS + q2 * CC + c] = v[q2];
         }
-        // this group's Y rows, then the next group's X rows (in this order:
-        // loads complete in order, so waiting for Y does not wait for X)
-        GR yc;
-        yc.load_y(yb, g, M, ny);
+        // the next group's X rows (after this group's Y: loads complete in
+        // order, so waiting for Y does not wait for them)
         GR xn;
         const int64_t gn = g + gridDim.x;
         if (gn < G) xn.load_x(xb, gn, M);
@@ -657,10 +659,14 @@ __global__ __launch_bounds__(256) void k_fft2u(const UpdTask<T> *__restrict__ ta
 }
 
 // three digits: n = N1 N2 N3 (see k_fft3 for the stages)
+// Y rows: loaded at the top of the group iteration (in flight during
+// stages A-D) when the registers allow it (n <= 4096 in float64), else in
+// stage D after stage C's spectrum reads.
 template <typename T, int N1, int N2, int N3, int CC, int NT, bool EVEN>
 __global__ __launch_bounds__(NT) void k_fft3u(const UpdTask<T> *__restrict__ tasks, const cplx<T> *__restrict__ tw0,
                                                int64_t nmax)
 {
+    constexpr bool EARLY_Y = N1 * N2 * N3 * sizeof(T) <= 4096 * 8;
     constexpr int n = N1 * N2 * N3;
     constexpr int RS = N3 * CC + 1;
     using GR = GroupRows<T, N1, N2 * N3, CC, NT, EVEN>;
@@ -689,6 +695,8 @@ __global__ __launch_bounds__(NT) void k_fft3u(const UpdTask<T> *__restrict__ tas
     for (; g < G; g += gridDim.x) {
         const cplx<T> *__restrict__ tw = opaque(tw0);  // per-thread twiddle bases
         FS_G const cplx<T> *__restrict__ spec = opaque(spec0);
+        GR yc;
+        if constexpr (EARLY_Y) yc.load_y(yb, g, M, ny);
         // A: q1 -> k1 (zero upper half), twiddle by W_n^{(q2 N3 + q3) k1}
         {
             cplx<T> pa[NA][lg2<N1>::v];
@@ -759,8 +767,7 @@ __global__ __launch_bounds__(NT) void k_fft3u(const UpdTask<T> *__restrict__ tas
             cplx<T> pb[NB][lg2<N2>::v];
 #pragma unroll
             for (int b = 0; b < NB; ++b) twiddle_bases<N2>(pb[b], tw, eb(b));
-            GR yc;
-            yc.load_y(yb, g, M, ny);
+            if constexpr (!EARLY_Y) yc.load_y(yb, g, M, ny);
             GR xn;
             const int64_t gn = g + gridDim.x;
             if (gn < G) xn.load_x(xb, gn, M);

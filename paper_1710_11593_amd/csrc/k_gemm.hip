@@ -19,7 +19,10 @@ namespace fs {
 constexpr int DENSE_RB = 4;      // output rows per thread
 constexpr int DENSE_MAXS = 1024; // largest half-block size for this kernel
 
-// QC: X rows per load batch (min(s, 64))
+// QC: X rows per load batch; s is a multiple of QC (both powers of two).
+// Loads are unconditional: a thread past the last column reads column M - 1
+// (a valid address) and stores nothing, so the loads carry no branches and
+// are all in flight together.
 template <typename T, int QC>
 __global__ __launch_bounds__(256) void k_dense_update(TaskRef<UpdTask<T>> tr)
 {
@@ -31,14 +34,15 @@ __global__ __launch_bounds__(256) void k_dense_update(TaskRef<UpdTask<T>> tr)
     const int64_t col = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (p0 >= tk.ny || (int64_t)blockIdx.x * 256 >= M) return;  // whole workgroup exits together
     const bool ok = col < M;
+    const int64_t cl = ok ? col : M - 1;
     const int np = (tk.ny - p0 < DENSE_RB) ? tk.ny - p0 : DENSE_RB;
 
-    FS_G const T *__restrict__ xp = gptr(tk.x) + tk.xlo * M + col;
-    FS_G T *__restrict__ yp = gptr(tk.y) + (tk.ylo + p0) * M + col;
-    // Y rows of this thread, loaded up front with the first X chunk
+    FS_G const T *__restrict__ xp = gptr(tk.x) + tk.xlo * M + cl;
+    FS_G T *__restrict__ yp = gptr(tk.y) + (tk.ylo + p0) * M + cl;
+    // Y rows of this thread (rows past ny read row ny - 1 and are not stored)
     T yv[DENSE_RB];
 #pragma unroll
-    for (int r = 0; r < DENSE_RB; ++r) yv[r] = (ok && r < np) ? yp[(int64_t)r * M] : (T)0;
+    for (int r = 0; r < DENSE_RB; ++r) yv[r] = yp[(int64_t)(r < np ? r : np - 1) * M];
     // weight window: sw[k] = w[p0 + 1 + k], k < s + DENSE_RB - 1
     FS_G const double *__restrict__ w = gptr(tk.w);
     for (int k = threadIdx.x; k < s + DENSE_RB - 1; k += 256) sw[k] = w[p0 + 1 + k];
@@ -49,15 +53,15 @@ __global__ __launch_bounds__(256) void k_dense_update(TaskRef<UpdTask<T>> tr)
     // w[s + p - q] with p = p0 + r: sw[s - 1 + r - q]
     for (int q0 = 0; q0 < s; q0 += QC) {
         T xv[QC];
+        FS_G const T *__restrict__ xq = xp + (int64_t)q0 * M;
 #pragma unroll
-        for (int j = 0; j < QC; ++j) xv[j] = (ok && q0 + j < s) ? xp[(int64_t)(q0 + j) * M] : (T)0;
+        for (int j = 0; j < QC; ++j) xv[j] = xq[(int64_t)j * M];
         if (q0 == 0) __syncthreads();  // weight window ready
+        const double *__restrict__ wq = sw + (s - 1 - q0);
 #pragma unroll
         for (int j = 0; j < QC; ++j) {
-            if (q0 + j < s) {
 #pragma unroll
-                for (int r = 0; r < DENSE_RB; ++r) acc[r] += (T)sw[s - 1 + r - q0 - j] * xv[j];
-            }
+            for (int r = 0; r < DENSE_RB; ++r) acc[r] += (T)wq[r - j] * xv[j];
         }
     }
     if (ok) {
@@ -71,7 +75,7 @@ __global__ __launch_bounds__(256) void k_dense_update(TaskRef<UpdTask<T>> tr)
 template <typename T>
 hipError_t launch_gemm_update(hipStream_t st, const TaskRef<UpdTask<T>> &d_tasks, int ntasks, int s, int64_t maxM)
 {
-    if (s > DENSE_MAXS) return hipErrorInvalidValue;
+    if (s > DENSE_MAXS || s < 1 || (s & (s - 1)) != 0) return hipErrorInvalidValue;
     dim3 grid((unsigned)((maxM + 255) / 256), (unsigned)((s + DENSE_RB - 1) / DENSE_RB), (unsigned)ntasks);
     if (s <= 4)
         hipLaunchKernelGGL((k_dense_update<T, 4>), grid, dim3(256), 0, st, d_tasks);

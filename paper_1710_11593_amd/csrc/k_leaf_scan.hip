@@ -133,7 +133,7 @@ __device__ __forceinline__ void row_scans(double &f, double &b, const double *cp
     }
 }
 
-template <int NT, int PT, int L, bool MIXED, bool VEC>
+template <int NT, int PT, int L, bool MIXED, int VEC>
 __global__ __launch_bounds__(NT) void k_leaf_scan(TaskRef<LeafTask> tr)
 {
     static_assert(PT % 2 == 0 && PT <= 16, "rows per thread must be even and at most 16");
@@ -155,15 +155,17 @@ __global__ __launch_bounds__(NT) void k_leaf_scan(TaskRef<LeafTask> tr)
     FS_G double *__restrict__ u = gptr(tk.u) + tk.lo * M;
     FS_G const float *__restrict__ hist = MIXED ? gptr(tk.hist) + tk.lo * M : nullptr;
     FS_G float *__restrict__ x32 = MIXED ? gptr(tk.x32) + tk.lo * M : nullptr;
-    // VEC: M is a multiple of PT and the field is 16-byte aligned, so a
-    // thread's rows are either all inside [0, M) or all outside.
+    // vec: M is a multiple of PT and the field is 16-byte aligned, so a
+    // thread's rows are either all inside [0, M) or all outside.  VEC = 2
+    // takes it from the task flags (batches mixing both kinds in one launch).
+    const bool vec = (VEC == 2) ? ((tk.flags & LEAF_VEC) != 0) : (VEC == 1);
     const bool act = c0 < M;
     // Memory column of the thread's element k.  In the internal column order
-    // (tk.perm) a full block of 64 PT columns belongs to one wave, and pair
+    // ((tk.flags & LEAF_PERM)) a full block of 64 PT columns belongs to one wave, and pair
     // j of lane i sits at 128 j + 2 i, so each of the wave's 16-byte
     // accesses covers 1 KB of contiguous memory.
     constexpr int64_t B = 64 * PT;
-    const bool pf = tk.perm && (int64_t)((t >> 6) + 1) * B <= M;
+    const bool pf = (tk.flags & LEAF_PERM) && (int64_t)((t >> 6) + 1) * B <= M;
     const int64_t cw = (int64_t)(t >> 6) * B + 2 * lane;
     auto col = [&](int k) -> int64_t { return pf ? cw + 128 * (k >> 1) + (k & 1) : (int64_t)c0 + k; };
 
@@ -179,7 +181,7 @@ __global__ __launch_bounds__(NT) void k_leaf_scan(TaskRef<LeafTask> tr)
 #pragma unroll
     for (int r = 0; r < L; ++r) {
         FS_G const double *row = u + (int64_t)r * M;
-        if (VEC) {
+        if (vec) {
             if (r < nrows && act) {
 #pragma unroll
                 for (int i = 0; i < UT; ++i) {
@@ -201,7 +203,7 @@ __global__ __launch_bounds__(NT) void k_leaf_scan(TaskRef<LeafTask> tr)
     float hv[PT];
     auto load_hist = [&](int r) {
         FS_G const float *hrow = hist + (int64_t)r * M;
-        if (VEC) {
+        if (vec) {
             // col(2i) is even and M is even: 8-byte aligned pairs
 #pragma unroll
             for (int i = 0; i < UT; ++i) {
@@ -276,7 +278,7 @@ __global__ __launch_bounds__(NT) void k_leaf_scan(TaskRef<LeafTask> tr)
         // row itself was updated right after the solve)
         if (r > 0 && r - 1 < nrows) {
             FS_G double *row = u + (int64_t)(r - 1) * M;
-            if (VEC) {
+            if (vec) {
                 if (act) {
 #pragma unroll
                     for (int i = 0; i < UT; ++i)
@@ -289,7 +291,7 @@ __global__ __launch_bounds__(NT) void k_leaf_scan(TaskRef<LeafTask> tr)
             }
             if (MIXED) {
                 FS_G float *xrow = x32 + (int64_t)(r - 1) * M;
-                if (VEC) {
+                if (vec) {
                     if (act) {
 #pragma unroll
                         for (int i = 0; i < UT; ++i)
@@ -376,25 +378,29 @@ hipError_t launch_scan_factor(hipStream_t st, const LeafCfg &c, int64_t M, doubl
     return hipErrorInvalidValue;
 }
 
-template <int NT, int PT, int L>
-static hipError_t scan_go(hipStream_t st, bool mixed, bool vec, const TaskRef<LeafTask> &d_tasks, int ntasks)
+template <int NT, int PT, int L, bool MIXED>
+static void scan_go_m(hipStream_t st, int vec, const TaskRef<LeafTask> &d_tasks, int ntasks)
 {
-    if (mixed) {
-        if (vec)
-            hipLaunchKernelGGL((k_leaf_scan<NT, PT, L, true, true>), dim3(ntasks), dim3(NT), 0, st, d_tasks);
-        else
-            hipLaunchKernelGGL((k_leaf_scan<NT, PT, L, true, false>), dim3(ntasks), dim3(NT), 0, st, d_tasks);
-    } else {
-        if (vec)
-            hipLaunchKernelGGL((k_leaf_scan<NT, PT, L, false, true>), dim3(ntasks), dim3(NT), 0, st, d_tasks);
-        else
-            hipLaunchKernelGGL((k_leaf_scan<NT, PT, L, false, false>), dim3(ntasks), dim3(NT), 0, st, d_tasks);
-    }
+    if (vec == 1)
+        hipLaunchKernelGGL((k_leaf_scan<NT, PT, L, MIXED, 1>), dim3(ntasks), dim3(NT), 0, st, d_tasks);
+    else if (vec == 2)
+        hipLaunchKernelGGL((k_leaf_scan<NT, PT, L, MIXED, 2>), dim3(ntasks), dim3(NT), 0, st, d_tasks);
+    else
+        hipLaunchKernelGGL((k_leaf_scan<NT, PT, L, MIXED, 0>), dim3(ntasks), dim3(NT), 0, st, d_tasks);
+}
+
+template <int NT, int PT, int L>
+static hipError_t scan_go(hipStream_t st, bool mixed, int vec, const TaskRef<LeafTask> &d_tasks, int ntasks)
+{
+    if (mixed)
+        scan_go_m<NT, PT, L, true>(st, vec, d_tasks, ntasks);
+    else
+        scan_go_m<NT, PT, L, false>(st, vec, d_tasks, ntasks);
     return hipGetLastError();
 }
 
 template <int NT, int PT>
-static hipError_t scan_go16(hipStream_t st, bool mixed, bool vec, const TaskRef<LeafTask> &d_tasks, int ntasks)
+static hipError_t scan_go16(hipStream_t st, bool mixed, int vec, const TaskRef<LeafTask> &d_tasks, int ntasks)
 {
     if constexpr (PT <= 2)
         return scan_go<NT, PT, 16>(st, mixed, vec, d_tasks, ntasks);
@@ -403,7 +409,7 @@ static hipError_t scan_go16(hipStream_t st, bool mixed, bool vec, const TaskRef<
 }
 
 hipError_t launch_leaf_scan(hipStream_t st, const LeafCfg &c, int L, const TaskRef<LeafTask> &d_tasks, int ntasks,
-                            bool mixed, bool vec)
+                            bool mixed, int vec)
 {
 #define FS_SL(NT_, PT_)                                                                        \
     if (c.nt == NT_ && c.pt == PT_) {                                                          \

@@ -242,6 +242,43 @@ def test_batched_parity(torch_cuda, orc):
     s.close()
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_batched_widths_multipass(torch_cuda, orc, precision):
+    """A batch of instances of four widths (every instance runs the leaf
+    kernel of the widest one, so each step is one leaf launch; rows are
+    accessed per element or in 16-byte units per task), with multi-pass FFT
+    levels (Np > 8192) in several instances.  Each instance is checked
+    against the single-mode oracle reference within the bar of its form, and
+    against its own single-instance solve (a different leaf configuration,
+    so a different rounding order)."""
+    from paper_1710_11593_amd import binding
+
+    specs = [(0.4, 100, 20000), (1.3, 401, 12000), (0.7, 1000, 9000), (1.6, 3000, 16384)]
+    insts = []
+    for k, (g, M, N) in enumerate(specs):
+        rng = np.random.default_rng(40 + k)
+        amps, pows = wl.random_modes(rng, 3)
+        insts.append(wl.Instance(g, M, N, modes=[(j, float(a), float(p)) for j, a, p in zip((2, 5, 9), amps, pows)],
+                                 manufactured=True))
+    data = [mode_reference(torch_cuda, orc, inst) for inst in insts]
+    refine = 1 if precision == "fp32" else 0
+    bar = 1e-5 if precision == "fp32" else 1e-9
+    probs = [dict(gamma=i.gamma, M=i.M, N=i.N) for i in insts]
+    s = binding.Solver(probs, precision=precision, refine_steps=refine)
+    us = s.solve([d[0] for d in data], [d[1] for d in data], [d[2] if i.gamma > 1 else None for d, i in zip(data, insts)])
+    torch_cuda.cuda.synchronize()
+    s.close()
+    for inst, d, u in zip(insts, data, us):
+        err = float((u - d[3]).abs().max() / d[3].abs().max())
+        assert err <= bar, (inst.gamma, inst.M, inst.N, err)
+        one = binding.Solver([dict(gamma=inst.gamma, M=inst.M, N=inst.N)], precision=precision, refine_steps=refine)
+        u1 = one.solve([d[0]], [d[1]], [d[2]] if inst.gamma > 1 else None)[0]
+        torch_cuda.cuda.synchronize()
+        one.close()
+        diff = float((u - u1).abs().max() / u1.abs().max())
+        assert diff <= bar, (inst.gamma, inst.M, inst.N, diff)
+
+
 def test_graph_replay_matches_eager(torch_cuda, orc, monkeypatch):
     """Recorded launch sequences (FRACSOLVE_GRAPH=1) replayed several times,
     with eager work and synchronisations in between, give the eager result."""
