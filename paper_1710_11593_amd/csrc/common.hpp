@@ -184,10 +184,14 @@ hipError_t launch_gemm_update(hipStream_t st, const TaskRef<UpdTask<T>> &tr, int
 // column pair)
 // corner: also launch the near-corner band kernel of single-pass levels
 // (launch_fft_corner) after the transform
+// gbase (single-pass levels, device): ntasks + 1 offsets of each task's
+// first column group in the launch's flat group numbering (groups of
+// fft_update_cc(2 s, fp32) complex columns)
 template <typename T>
-hipError_t launch_fft_update_ex(hipStream_t st, const UpdTask<T> *d_tasks, int ntasks, int s, int64_t maxM,
-                                const cplx<T> *tw, int64_t nmax, cplx<T> *zs, size_t zs_elems, bool even,
-                                bool corner = true);
+hipError_t launch_fft_update_ex(hipStream_t st, const UpdTask<T> *d_tasks, const int64_t *gbase, int ntasks, int s,
+                                int64_t maxM, const cplx<T> *tw, int64_t nmax, cplx<T> *zs, size_t zs_elems,
+                                bool even, bool corner = true);
+int fft_update_cc(int n, bool fp32);
 // near-corner band of a single-pass FFT level (no-op for multi-pass levels,
 // which add it inside their last pass)
 template <typename T>

@@ -225,7 +225,19 @@ struct Op {
     bool mixed;
     double bytes = 0.0;  // algorithmic HBM bytes of the launch
     bool even = false;   // FFT levels: every task has M even and aligned rows
+    size_t goff = 0;     // single-pass FFT levels: descriptor offset of the group offsets
 };
+
+// Flat column-group offsets of the tasks of a single-pass FFT level (see
+// launch_fft_update_ex), added to the descriptors; returns their offset.
+template <typename T>
+size_t add_group_offsets(DescBuilder &db, const std::vector<UpdTask<T>> &tv, int s)
+{
+    const int cc = fft_update_cc(2 * s, sizeof(T) == 4);
+    std::vector<int64_t> gb(tv.size() + 1, 0);
+    for (size_t k = 0; k < tv.size(); ++k) gb[k + 1] = gb[k] + ((tv[k].M + 1) / 2 + cc - 1) / cc;
+    return db.add(gb.data(), gb.size() * sizeof(int64_t));
+}
 
 // Column pairs of every row are whole, aligned vector elements.
 template <typename T>
@@ -287,12 +299,14 @@ int run_ops(fracsolve_ctx *h, const std::vector<Op> &ops)
                 e = launch_gemm_update<float>(h->st, task_ref<UpdTask<float>>(h, op), op.ntasks, op.s, op.maxM);
                 break;
             case OP_FFT64:
-                e = launch_fft_update_ex<double>(h->st, dptr<UpdTask<double>>(h, op.off), op.ntasks, op.s, op.maxM,
+                e = launch_fft_update_ex<double>(h->st, dptr<UpdTask<double>>(h, op.off), dptr<int64_t>(h, op.goff),
+                                                 op.ntasks, op.s, op.maxM,
                                                  h->tw64, h->nmax, (cplx<double> *)h->zs,
                                                  h->zs_bytes / sizeof(cplx<double>), op.even, h->timing < 2);
                 break;
             case OP_FFT32:
-                e = launch_fft_update_ex<float>(h->st, dptr<UpdTask<float>>(h, op.off), op.ntasks, op.s, op.maxM,
+                e = launch_fft_update_ex<float>(h->st, dptr<UpdTask<float>>(h, op.off), dptr<int64_t>(h, op.goff),
+                                                op.ntasks, op.s, op.maxM,
                                                 h->tw32, h->nmax, (cplx<float> *)h->zs,
                                                 h->zs_bytes / sizeof(cplx<float>), op.even, h->timing < 2);
                 break;
@@ -355,6 +369,7 @@ uint64_t ops_key(const std::vector<Op> &ops, const void *d_desc)
         mix((uint64_t)(op.lc.nt * 100 + op.lc.pt));
         mix((uint64_t)op.mixed);
         mix((uint64_t)op.even);
+        mix((uint64_t)op.goff);
         mix((uint64_t)op.lc.vec);
     }
     mix((uint64_t)ops.size());
@@ -525,6 +540,7 @@ void build_solve(fracsolve_ctx *h, const std::vector<int> &sel, const std::vecto
             } else {
                 size_t off = db.add(t64.data(), t64.size() * sizeof(t64[0]));
                 Op op{fft ? OP_FFT64 : OP_GEMM64, off, (int)t64.size(), (int)s, maxM, {}, false};
+                if (fft) op.goff = add_group_offsets(db, t64, (int)s);
                 op.even = true;
                 for (auto &t : t64) {
                     op.bytes += upd_bytes(t, 8);
@@ -543,6 +559,7 @@ void build_solve(fracsolve_ctx *h, const std::vector<int> &sel, const std::vecto
             } else {
                 size_t off = db.add(t32.data(), t32.size() * sizeof(t32[0]));
                 Op op{OP_FFT32, off, (int)t32.size(), (int)s, maxM, {}, true};
+                op.goff = add_group_offsets(db, t32, (int)s);
                 op.even = true;
                 for (auto &t : t32) {
                     op.bytes += upd_bytes(t, 4);
@@ -591,6 +608,7 @@ void build_apply_levels(fracsolve_ctx *h, const Inst &in, const double *x, doubl
         } else {
             size_t off = db.add(tv.data(), tv.size() * sizeof(tv[0]));
             Op op{fft ? OP_FFT64 : OP_GEMM64, off, (int)tv.size(), (int)s, in.M, {}, false};
+            if (fft) op.goff = add_group_offsets(db, tv, (int)s);
             op.even = true;
             for (auto &t : tv) {
                 op.bytes += upd_bytes(t, 8);

@@ -556,26 +556,81 @@ struct GroupRows {
     }
 };
 
+// The column groups of all tasks of a launch, numbered task after task:
+// task t holds flat indices gbase[t] .. gbase[t+1]-1 (gbase has ntasks + 1
+// entries, built on the host from each task's width and the kernel's
+// columns per group).  The persistent workgroups walk this flat index
+// (workgroup b takes slot(b), slot(b) + P, ...), so tasks of different widths
+// share the workgroups in proportion to their groups.
+template <typename T>
+struct GroupCursor {
+    const UpdTask<T> *tasks;
+    const int64_t *gbase;
+    int ntasks;
+    int t;  // task holding the current flat index
+    // false once f is past the last group; f never decreases.  Each wave
+    // looks at 64 task boundaries per step (one load and a ballot).
+    __device__ bool seek(int64_t f)
+    {
+        if (f >= gbase[ntasks]) return false;
+        const int lane = threadIdx.x & 63;
+        for (;;) {
+            const int i = t + lane;
+            const bool le = (i <= ntasks) && gbase[i] <= f;
+            const int k = __popcll(__ballot(le));  // gbase is sorted: lanes 0..k-1
+            if (k < 64) {
+                t += k - 1;
+                return true;
+            }
+            t += 63;
+        }
+    }
+};
+
+// What one column group needs of its task.
+template <typename T>
+struct GroupView {
+    FS_G const T *xb;  // X row 0
+    FS_G T *yb;        // Y row 0
+    FS_G const cplx<T> *spec;
+    int64_t M;
+    int64_t g;  // group within the task
+    int ny;
+    T scale;
+};
+
+template <typename T>
+__device__ __forceinline__ GroupView<T> group_view(const GroupCursor<T> &c, int64_t f, int n)
+{
+    const UpdTask<T> &tk = c.tasks[c.t];
+    GroupView<T> v;
+    v.M = tk.M;
+    v.xb = gptr(tk.x) + tk.xlo * v.M;
+    v.yb = gptr(tk.y) + tk.ylo * v.M;
+    v.spec = gptr(tk.spec);
+    v.g = f - c.gbase[c.t];
+    v.ny = tk.ny;
+    v.scale = (T)(tk.alpha / (double)n);
+    return v;
+}
+
 // two digits: n = N1 N2 (see k_fft2 for the stages)
 template <typename T, int N1, int N2, int CC, bool EVEN>
-__global__ __launch_bounds__(256) void k_fft2u(const UpdTask<T> *__restrict__ tasks, const cplx<T> *__restrict__ tw0,
-                                               int64_t nmax)
+__global__ __launch_bounds__(256) void k_fft2u(const UpdTask<T> *__restrict__ tasks, const int64_t *__restrict__ gbase,
+                                               int ntasks, const cplx<T> *__restrict__ tw0, int64_t nmax)
 {
     constexpr int n = N1 * N2;
     constexpr int RS = N2 * CC + 1;
     using GR = GroupRows<T, N1, N2, CC, 256, EVEN>;
     constexpr int NA = GR::NA, H = GR::H;
     __shared__ cplx<T> sd[N1 * RS];
-    const UpdTask<T> tk = tasks[blockIdx.z];
-    const int64_t M = tk.M;
     const int t = threadIdx.x;
-    const int64_t G = ((M + 1) / 2 + CC - 1) / CC;
     const int64_t tws = nmax / n;
-    FS_G const T *__restrict__ xb = gptr(tk.x) + tk.xlo * M;
-    FS_G T *__restrict__ yb = gptr(tk.y) + tk.ylo * M;
-    FS_G const cplx<T> *__restrict__ spec0 = gptr(tk.spec);
-    const int ny = tk.ny;
-    const T scale = (T)(tk.alpha / (double)n);
+    const int64_t P = gridDim.x;
+    int64_t f = xcd_remap(blockIdx.x, gridDim.x);
+    GroupCursor<T> cur{tasks, gbase, ntasks, 0};
+    if (!cur.seek(f)) return;  // the whole workgroup: no group for it
+    GroupView<T> v = group_view(cur, f, n);
 
     // twiddle bases of the first/last stage, the same for every group
     cplx<T> pa[NA][lg2<N1>::v];
@@ -583,28 +638,27 @@ __global__ __launch_bounds__(256) void k_fft2u(const UpdTask<T> *__restrict__ ta
     for (int a = 0; a < NA; ++a) twiddle_bases<N1>(pa[a], tw0, (int64_t)(((t + 256 * a) / CC) % N2) * tws);
 
     GR xc;  // X rows of the current group (loaded during the previous group)
-    int64_t g = xcd_remap(blockIdx.x, gridDim.x);
-    if (g < G) xc.load_x(xb, g, M);
-    for (; g < G; g += gridDim.x) {
+    xc.load_x(v.xb, v.g, v.M);
+    for (;;) {
         const cplx<T> *__restrict__ tw = opaque(tw0);  // per-thread twiddle bases
-        FS_G const cplx<T> *__restrict__ spec = opaque(spec0);
+        FS_G const cplx<T> *__restrict__ spec = v.spec;  // per group: not hoisted
         // this group's Y rows, in flight during stages A and B (issued after
         // this group's X, so waiting for X does not wait for them)
         GR yc;
-        yc.load_y(yb, g, M, ny);
+        yc.load_y(v.yb, v.g, v.M, v.ny);
         // stage A: digit q1 -> k1 (forward, zero upper half), twiddle, to LDS
 #pragma unroll
         for (int a = 0; a < NA; ++a) {
             const int it = t + 256 * a;
             if (it < CC * N2) {
                 const int c = it % CC, q2 = it / CC;
-                cplx<T> v[N1];
+                cplx<T> w[N1];
 #pragma unroll
-                for (int q1 = 0; q1 < H; ++q1) v[q1] = xc.v[a][q1];
-                dft_reg<N1, false, true>(v);
-                apply_twiddles_b<N1, false>(v, pa[a]);
+                for (int q1 = 0; q1 < H; ++q1) w[q1] = xc.v[a][q1];
+                dft_reg<N1, false, true>(w);
+                apply_twiddles_b<N1, false>(w, pa[a]);
 #pragma unroll
-                for (int k1 = 0; k1 < N1; ++k1) sd[k1 * RS + q2 * CC + c] = v[k1];
+                for (int k1 = 0; k1 < N1; ++k1) sd[k1 * RS + q2 * CC + c] = w[k1];
             }
         }
         __syncthreads();
@@ -612,24 +666,30 @@ __global__ __launch_bounds__(256) void k_fft2u(const UpdTask<T> *__restrict__ ta
 #pragma unroll 1
         for (int it = t; it < CC * N1; it += 256) {
             const int c = it % CC, k1 = it / CC;
-            cplx<T> v[N2];
+            cplx<T> w[N2];
 #pragma unroll
-            for (int q2 = 0; q2 < N2; ++q2) v[q2] = sd[k1 * RS + q2 * CC + c];
+            for (int q2 = 0; q2 < N2; ++q2) w[q2] = sd[k1 * RS + q2 * CC + c];
             cplx<T> hs[N2];
 #pragma unroll
             for (int k2 = 0; k2 < N2; ++k2) hs[k2] = spec[k1 + N1 * k2];
-            dft_reg<N2, false, false>(v);
+            dft_reg<N2, false, false>(w);
 #pragma unroll
-            for (int k2 = 0; k2 < N2; ++k2) v[k2] = cmul(v[k2], hs[k2]);
-            dft_reg<N2, true, false>(v);
+            for (int k2 = 0; k2 < N2; ++k2) w[k2] = cmul(w[k2], hs[k2]);
+            dft_reg<N2, true, false>(w);
 #pragma unroll
-            for (int q2 = 0; q2 < N2; ++q2) sd[k1 * RS + q2 * CC + c] = v[q2];
+            for (int q2 = 0; q2 < N2; ++q2) sd[k1 * RS + q2 * CC + c] = w[q2];
         }
         // the next group's X rows (after this group's Y: loads complete in
         // order, so waiting for Y does not wait for them)
         GR xn;
-        const int64_t gn = g + gridDim.x;
-        if (gn < G) xn.load_x(xb, gn, M);
+        const int64_t fn = f + P;
+        GroupCursor<T> nxt = cur;
+        const bool more = nxt.seek(fn);
+        GroupView<T> vn = v;
+        if (more) {
+            vn = group_view(nxt, fn, n);
+            xn.load_x(vn.xb, vn.g, vn.M);
+        }
         __syncthreads();
         // stage C: conjugate twiddle, digit k1 -> q1 (inverse), Y = Y + scale z
 #pragma unroll
@@ -637,23 +697,28 @@ __global__ __launch_bounds__(256) void k_fft2u(const UpdTask<T> *__restrict__ ta
             const int it = t + 256 * a;
             if (it < CC * N2) {
                 const int c = it % CC, q2 = it / CC;
-                cplx<T> v[N1];
+                cplx<T> w[N1];
 #pragma unroll
-                for (int k1 = 0; k1 < N1; ++k1) v[k1] = sd[k1 * RS + q2 * CC + c];
-                apply_twiddles_b<N1, true>(v, pa[a]);
-                dft_reg<N1, true, false>(v);
-                const int64_t col = 2 * (g * CC + c);
+                for (int k1 = 0; k1 < N1; ++k1) w[k1] = sd[k1 * RS + q2 * CC + c];
+                apply_twiddles_b<N1, true>(w, pa[a]);
+                dft_reg<N1, true, false>(w);
+                const int64_t col = 2 * (v.g * CC + c);
 #pragma unroll
                 for (int q1 = H; q1 < N1; ++q1) {
                     const int p = (q1 - H) * N2 + q2;
-                    if (p < ny) {
+                    if (p < v.ny) {
                         const cplx<T> y0 = yc.v[a][q1 - H];
-                        st_pair<EVEN>(yb + (int64_t)p * M, col, M, cplx<T>{y0.x + scale * v[q1].x, y0.y + scale * v[q1].y});
+                        st_pair<EVEN>(v.yb + (int64_t)p * v.M, col, v.M,
+                                      cplx<T>{y0.x + v.scale * w[q1].x, y0.y + v.scale * w[q1].y});
                     }
                 }
             }
         }
         __syncthreads();
+        if (!more) break;
+        cur = nxt;
+        f = fn;
+        v = vn;
         xc = xn;
     }
 }
@@ -663,8 +728,8 @@ __global__ __launch_bounds__(256) void k_fft2u(const UpdTask<T> *__restrict__ ta
 // stages A-D) when the registers allow it (n <= 4096 in float64), else in
 // stage D after stage C's spectrum reads.
 template <typename T, int N1, int N2, int N3, int CC, int NT, bool EVEN>
-__global__ __launch_bounds__(NT) void k_fft3u(const UpdTask<T> *__restrict__ tasks, const cplx<T> *__restrict__ tw0,
-                                               int64_t nmax)
+__global__ __launch_bounds__(NT) void k_fft3u(const UpdTask<T> *__restrict__ tasks, const int64_t *__restrict__ gbase,
+                                               int ntasks, const cplx<T> *__restrict__ tw0, int64_t nmax)
 {
     constexpr bool EARLY_Y = N1 * N2 * N3 * sizeof(T) <= 4096 * 8;
     constexpr int n = N1 * N2 * N3;
@@ -673,16 +738,13 @@ __global__ __launch_bounds__(NT) void k_fft3u(const UpdTask<T> *__restrict__ tas
     constexpr int NA = GR::NA, H = GR::H;
     constexpr int NB = (CC * N1 * N3 + NT - 1) / NT;  // items per thread of stages B and D
     __shared__ cplx<T> sd[N1 * N2 * RS];
-    const UpdTask<T> tk = tasks[blockIdx.z];
-    const int64_t M = tk.M;
     const int t = threadIdx.x;
-    const int64_t G = ((M + 1) / 2 + CC - 1) / CC;
     const int64_t tws = nmax / n;
-    FS_G const T *__restrict__ xb = gptr(tk.x) + tk.xlo * M;
-    FS_G T *__restrict__ yb = gptr(tk.y) + tk.ylo * M;
-    FS_G const cplx<T> *__restrict__ spec0 = gptr(tk.spec);
-    const int ny = tk.ny;
-    const T scale = (T)(tk.alpha / (double)n);
+    const int64_t P = gridDim.x;
+    int64_t f = xcd_remap(blockIdx.x, gridDim.x);
+    GroupCursor<T> cur{tasks, gbase, ntasks, 0};
+    if (!cur.seek(f)) return;  // the whole workgroup: no group for it
+    GroupView<T> gv = group_view(cur, f, n);
     auto at = [&](int a, int b, int d, int c) { return (a * N2 + b) * RS + d * CC + c; };
     // exponents of the stage twiddles: A/E use W_n^{r k1}, r = q2 N3 + q3;
     // B/D use W_n^{q3 N1 k2}
@@ -690,13 +752,12 @@ __global__ __launch_bounds__(NT) void k_fft3u(const UpdTask<T> *__restrict__ tas
     auto eb = [&](int b) { return (int64_t)((((t + NT * b) / CC) % N3) * N1) * tws; };
 
     GR xc;  // X rows of the current group (loaded during the previous group)
-    int64_t g = xcd_remap(blockIdx.x, gridDim.x);
-    if (g < G) xc.load_x(xb, g, M);
-    for (; g < G; g += gridDim.x) {
+    xc.load_x(gv.xb, gv.g, gv.M);
+    for (;;) {
         const cplx<T> *__restrict__ tw = opaque(tw0);  // per-thread twiddle bases
-        FS_G const cplx<T> *__restrict__ spec = opaque(spec0);
+        FS_G const cplx<T> *__restrict__ spec = gv.spec;  // per group: not hoisted
         GR yc;
-        if constexpr (EARLY_Y) yc.load_y(yb, g, M, ny);
+        if constexpr (EARLY_Y) yc.load_y(gv.yb, gv.g, gv.M, gv.ny);
         // A: q1 -> k1 (zero upper half), twiddle by W_n^{(q2 N3 + q3) k1}
         {
             cplx<T> pa[NA][lg2<N1>::v];
@@ -757,6 +818,11 @@ __global__ __launch_bounds__(NT) void k_fft3u(const UpdTask<T> *__restrict__ tas
             for (int q3 = 0; q3 < N3; ++q3) sd[at(k1, k2, q3, c)] = v[q3];
         }
         __syncthreads();
+        // the next group (possibly of the next task)
+        const int64_t fn = f + P;
+        GroupCursor<T> nxt = cur;
+        GroupView<T> vn = gv;
+        bool more = false;
         // Loads complete in issue order: first the twiddle bases of D and E,
         // then this group's Y rows, then the next group's X rows, so that each
         // wait below covers only what it needs.
@@ -767,10 +833,13 @@ __global__ __launch_bounds__(NT) void k_fft3u(const UpdTask<T> *__restrict__ tas
             cplx<T> pb[NB][lg2<N2>::v];
 #pragma unroll
             for (int b = 0; b < NB; ++b) twiddle_bases<N2>(pb[b], tw, eb(b));
-            if constexpr (!EARLY_Y) yc.load_y(yb, g, M, ny);
+            if constexpr (!EARLY_Y) yc.load_y(gv.yb, gv.g, gv.M, gv.ny);
             GR xn;
-            const int64_t gn = g + gridDim.x;
-            if (gn < G) xn.load_x(xb, gn, M);
+            more = nxt.seek(fn);
+            if (more) {
+                vn = group_view(nxt, fn, n);
+                xn.load_x(vn.xb, vn.g, vn.M);
+            }
             // D: conjugate twiddle, k2 -> q2
 #pragma unroll
             for (int b = 0; b < NB; ++b) {
@@ -798,21 +867,25 @@ __global__ __launch_bounds__(NT) void k_fft3u(const UpdTask<T> *__restrict__ tas
                     for (int k1 = 0; k1 < N1; ++k1) v[k1] = sd[at(k1, q2, q3, c)];
                     apply_twiddles_b<N1, true>(v, pa[a]);
                     dft_reg<N1, true, false>(v);
-                    const int64_t col = 2 * (g * CC + c);
+                    const int64_t col = 2 * (gv.g * CC + c);
 #pragma unroll
                     for (int q1 = H; q1 < N1; ++q1) {
                         const int p = (q1 - H) * N2 * N3 + r;
-                        if (p < ny) {
+                        if (p < gv.ny) {
                             const cplx<T> y0 = yc.v[a][q1 - H];
-                            st_pair<EVEN>(yb + (int64_t)p * M, col, M,
-                                       cplx<T>{y0.x + scale * v[q1].x, y0.y + scale * v[q1].y});
-                            }
+                            st_pair<EVEN>(gv.yb + (int64_t)p * gv.M, col, gv.M,
+                                          cplx<T>{y0.x + gv.scale * v[q1].x, y0.y + gv.scale * v[q1].y});
+                        }
                     }
                 }
             }
             __syncthreads();
             xc = xn;
         }
+        if (!more) break;
+        cur = nxt;
+        f = fn;
+        gv = vn;
     }
 }
 
@@ -992,23 +1065,24 @@ hipError_t launch_spectrum(hipStream_t st, const double *w, int s, cplx<double> 
 
 // ------------------------------------------------------------ dispatch
 // Single-pass factorisations and complex columns per workgroup.
-// Persistent workgroups per task for the update kernels: as many as fit on
-// the chip at the kernel's LDS use (160 KiB per CU, 256 CUs), shared by the
-// tasks of the launch, at most one per column group.
+// Workgroups of a persistent launch: as many as fill the chip at the
+// kernel's LDS use (160 KiB per CU, 256 CUs, at most 8 per CU), and no more
+// than the launch has column groups (at most ntasks x groups of the widest).
 static unsigned persistent_groups(size_t lds_bytes, int64_t groups, int ntasks)
 {
     int64_t per_cu = (int64_t)((160 * 1024) / (lds_bytes ? lds_bytes : 1));
     if (per_cu < 1) per_cu = 1;
     if (per_cu > 8) per_cu = 8;
-    int64_t np = (256 * per_cu + ntasks - 1) / ntasks;
-    if (np > groups) np = groups;
+    int64_t np = 256 * per_cu;
+    if (np > groups * ntasks) np = groups * ntasks;
     if (np < 1) np = 1;
     return (unsigned)np;
 }
 
 template <typename T, int MODE, bool EVEN = false>
 static hipError_t single_pass(hipStream_t st, const UpdTask<T> *d_tasks, int ntasks, int n, int64_t ncols_c,
-                              const cplx<T> *tw, int64_t nmax, cplx<T> *zs, int64_t Mc, int N1g, int nk1)
+                              const cplx<T> *tw, int64_t nmax, cplx<T> *zs, int64_t Mc, int N1g, int nk1,
+                              const int64_t *gbase = nullptr)
 {
     auto grid = [&](int CC) {
         unsigned gx = (unsigned)((ncols_c + CC - 1) / CC);
@@ -1016,7 +1090,7 @@ static hipError_t single_pass(hipStream_t st, const UpdTask<T> *d_tasks, int nta
     };
     auto pgrid = [&](int CC, size_t lds) {
         const int64_t groups = (ncols_c + CC - 1) / CC;
-        return dim3(persistent_groups(lds, groups, ntasks), 1, (unsigned)ntasks);
+        return dim3(persistent_groups(lds, groups, ntasks), 1, 1);
     };
 #define FS_F2(N1_, N2_, CC_)                                                                                     \
     case N1_ * N2_:                                                                                              \
@@ -1030,14 +1104,16 @@ static hipError_t single_pass(hipStream_t st, const UpdTask<T> *d_tasks, int nta
         return hipGetLastError();
 #define FS_U2(N1_, N2_, CC_)                                                                                   \
     case N1_ * N2_:                                                                                            \
+        if (CC_ != fft_update_cc(n, sizeof(T) == 4)) return hipErrorInvalidValue;                             \
         hipLaunchKernelGGL((k_fft2u<T, N1_, N2_, CC_, EVEN>), pgrid(CC_, sizeof(cplx<T>) * N1_ * (N2_ * CC_ + 1)),   \
-                           dim3(256), 0, st, d_tasks, tw, nmax);                                               \
+                           dim3(256), 0, st, d_tasks, gbase, ntasks, tw, nmax);                                       \
         return hipGetLastError();
 #define FS_U3(N1_, N2_, N3_, CC_, NT_)                                                                         \
     case N1_ * N2_ * N3_:                                                                                      \
+        if (CC_ != fft_update_cc(n, sizeof(T) == 4)) return hipErrorInvalidValue;                             \
         hipLaunchKernelGGL((k_fft3u<T, N1_, N2_, N3_, CC_, NT_, EVEN>),                                              \
                            pgrid(CC_, sizeof(cplx<T>) * N1_ * N2_ * (N3_ * CC_ + 1)), dim3(NT_), 0, st, d_tasks, \
-                           tw, nmax);                                                                          \
+                           gbase, ntasks, tw, nmax);                                                           \
         return hipGetLastError();
     if constexpr (MODE == MODE_UPDATE) {
         if constexpr (sizeof(T) == 8) {
@@ -1177,17 +1253,27 @@ hipError_t launch_fft_corner(hipStream_t st, const UpdTask<T> *d_tasks, int ntas
     return hipGetLastError();
 }
 
+// Complex columns per column group of the single-pass update kernels (the
+// CC of the dispatch tables of single_pass, MODE_UPDATE).
+int fft_update_cc(int n, bool fp32)
+{
+    if (n <= 1024) return 8;
+    if (!fp32) return n == 2048 ? 4 : (n == 4096 ? 2 : 1);
+    return n == 2048 ? 8 : (n == 4096 ? 4 : (n == 8192 ? 2 : 1));
+}
+
 template <typename T>
-hipError_t launch_fft_update_ex(hipStream_t st, const UpdTask<T> *d_tasks, int ntasks, int s, int64_t maxM,
-                                const cplx<T> *tw, int64_t nmax, cplx<T> *zs, size_t zs_elems, bool even,
-                                bool corner)
+hipError_t launch_fft_update_ex(hipStream_t st, const UpdTask<T> *d_tasks, const int64_t *gbase, int ntasks, int s,
+                                int64_t maxM, const cplx<T> *tw, int64_t nmax, cplx<T> *zs, size_t zs_elems,
+                                bool even, bool corner)
 {
     const int n = 2 * s;
     if (n <= fft_max_single_pass(sizeof(T) == 4)) {
+        if (!gbase) return hipErrorInvalidValue;
         hipError_t e = even ? single_pass<T, MODE_UPDATE, true>(st, d_tasks, ntasks, n, (maxM + 1) / 2, tw, nmax,
-                                                                nullptr, 0, 1, 1)
+                                                                nullptr, 0, 1, 1, gbase)
                             : single_pass<T, MODE_UPDATE, false>(st, d_tasks, ntasks, n, (maxM + 1) / 2, tw, nmax,
-                                                                 nullptr, 0, 1, 1);
+                                                                 nullptr, 0, 1, 1, gbase);
         if (e != hipSuccess || !corner) return e;
         return launch_fft_corner<T>(st, d_tasks, ntasks, s, maxM);
     }
@@ -1195,12 +1281,13 @@ hipError_t launch_fft_update_ex(hipStream_t st, const UpdTask<T> *d_tasks, int n
     return multipass<T>(st, d_tasks, n, maxM, tw, nmax, zs, zs_elems);
 }
 
-template hipError_t launch_fft_update_ex<double>(hipStream_t, const UpdTask<double> *, int, int, int64_t,
-                                                const cplx<double> *, int64_t, cplx<double> *, size_t, bool,
-                                                bool);
+template hipError_t launch_fft_update_ex<double>(hipStream_t, const UpdTask<double> *, const int64_t *, int, int,
+                                                int64_t, const cplx<double> *, int64_t, cplx<double> *, size_t,
+                                                bool, bool);
 template hipError_t launch_fft_corner<double>(hipStream_t, const UpdTask<double> *, int, int, int64_t);
 template hipError_t launch_fft_corner<float>(hipStream_t, const UpdTask<float> *, int, int, int64_t);
-template hipError_t launch_fft_update_ex<float>(hipStream_t, const UpdTask<float> *, int, int, int64_t,
-                                               const cplx<float> *, int64_t, cplx<float> *, size_t, bool, bool);
+template hipError_t launch_fft_update_ex<float>(hipStream_t, const UpdTask<float> *, const int64_t *, int, int,
+                                               int64_t, const cplx<float> *, int64_t, cplx<float> *, size_t, bool,
+                                               bool);
 
 }  // namespace fs
