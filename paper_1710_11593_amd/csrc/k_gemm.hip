@@ -7,7 +7,7 @@
 //
 // These products are small (s <= 64 by default: at most a few MB of
 // traffic) and sit on the critical path of the recursion, so the kernel is
-// organised for latency: every thread owns one column and DENSE_RB output
+// organised for latency: every thread owns one column and RB output
 // rows; all loads of its X column (a chunk of up to 64 rows) and of
 // its Y rows are issued together, the weight window sits in LDS (read as
 // wave-uniform broadcasts), and the output rows are spread over the grid so
@@ -16,16 +16,19 @@
 
 namespace fs {
 
-constexpr int DENSE_RB = 4;      // output rows per thread
-constexpr int DENSE_MAXS = 1024; // largest half-block size for this kernel
+constexpr int DENSE_MAXS = 1024;  // largest half-block size for this kernel
 
-// QC: X rows per load batch; s is a multiple of QC (both powers of two).
+// RB: output rows per thread (4; 8 or 16 for launches with many tasks,
+// where re-reading the X rows once per row block costs more than the
+// parallelism gained); QC: X rows per load batch; s is a multiple of QC
+// (both powers of two).
 // Loads are unconditional: a thread past the last column reads column M - 1
 // (a valid address) and stores nothing, so the loads carry no branches and
 // are all in flight together.
-template <typename T, int QC>
+template <typename T, int QC, int RB>
 __global__ __launch_bounds__(256) void k_dense_update(TaskRef<UpdTask<T>> tr)
 {
+    constexpr int DENSE_RB = RB;
     __shared__ double sw[DENSE_MAXS + DENSE_RB];
     const UpdTask<T> tk = get_task(tr, blockIdx.z);
     const int s = tk.s;
@@ -72,21 +75,35 @@ __global__ __launch_bounds__(256) void k_dense_update(TaskRef<UpdTask<T>> tr)
     }
 }
 
+template <typename T, int RB>
+static void dense_go(hipStream_t st, const TaskRef<UpdTask<T>> &d_tasks, int ntasks, int s, int64_t maxM)
+{
+    dim3 grid((unsigned)((maxM + 255) / 256), (unsigned)((s + RB - 1) / RB), (unsigned)ntasks);
+    if (s <= 4)
+        hipLaunchKernelGGL((k_dense_update<T, 4, RB>), grid, dim3(256), 0, st, d_tasks);
+    else if (s <= 8)
+        hipLaunchKernelGGL((k_dense_update<T, 8, RB>), grid, dim3(256), 0, st, d_tasks);
+    else if (s <= 16)
+        hipLaunchKernelGGL((k_dense_update<T, 16, RB>), grid, dim3(256), 0, st, d_tasks);
+    else if (s <= 32 || RB > 4)
+        hipLaunchKernelGGL((k_dense_update<T, 32, RB>), grid, dim3(256), 0, st, d_tasks);
+    else
+        hipLaunchKernelGGL((k_dense_update<T, 64, RB>), grid, dim3(256), 0, st, d_tasks);
+}
+
 template <typename T>
 hipError_t launch_gemm_update(hipStream_t st, const TaskRef<UpdTask<T>> &d_tasks, int ntasks, int s, int64_t maxM)
 {
     if (s > DENSE_MAXS || s < 1 || (s & (s - 1)) != 0) return hipErrorInvalidValue;
-    dim3 grid((unsigned)((maxM + 255) / 256), (unsigned)((s + DENSE_RB - 1) / DENSE_RB), (unsigned)ntasks);
-    if (s <= 4)
-        hipLaunchKernelGGL((k_dense_update<T, 4>), grid, dim3(256), 0, st, d_tasks);
-    else if (s <= 8)
-        hipLaunchKernelGGL((k_dense_update<T, 8>), grid, dim3(256), 0, st, d_tasks);
-    else if (s <= 16)
-        hipLaunchKernelGGL((k_dense_update<T, 16>), grid, dim3(256), 0, st, d_tasks);
-    else if (s <= 32)
-        hipLaunchKernelGGL((k_dense_update<T, 32>), grid, dim3(256), 0, st, d_tasks);
+    // workgroups at 4 rows per thread; past a few per CU the X re-reads
+    // dominate and more rows per thread pay
+    const int64_t wg4 = (int64_t)ntasks * ((maxM + 255) / 256) * ((s + 3) / 4);
+    if (wg4 > 2048 && s >= 16)
+        dense_go<T, 16>(st, d_tasks, ntasks, s, maxM);
+    else if (wg4 > 2048 && s >= 8)
+        dense_go<T, 8>(st, d_tasks, ntasks, s, maxM);
     else
-        hipLaunchKernelGGL((k_dense_update<T, 64>), grid, dim3(256), 0, st, d_tasks);
+        dense_go<T, 4>(st, d_tasks, ntasks, s, maxM);
     return hipGetLastError();
 }
 

@@ -221,6 +221,17 @@ __global__ __launch_bounds__(NT) void k_leaf_scan(TaskRef<LeafTask> tr)
 
     // uniform constants
     const double K0 = tab[0];
+    // K0 alpha and K0 beta for the final product of each row (one multiply
+    // less per row and step) where the registers allow it (float64 mode)
+    constexpr bool KFOLD = !MIXED && (VEC != 0 || PT < 8);
+    double kal[KFOLD ? PT : 1], kbe[KFOLD ? PT : 1];
+    if constexpr (KFOLD) {
+#pragma unroll
+        for (int k = 0; k < PT; ++k) {
+            kal[k] = K0 * al[k];
+            kbe[k] = K0 * be[k];
+        }
+    }
     const double rho = tab[1];
     double mp[4];  // m^(1,2,4,8): lane steps inside a row
 #pragma unroll
@@ -336,7 +347,10 @@ __global__ __launch_bounds__(NT) void k_leaf_scan(TaskRef<LeafTask> tr)
             const double P = fma(rp[k], cf, lf[k]);
             const double Q = (k < PT - 1) ? fma(rho, sb[k + 1 < PT ? k + 1 : k], rp[PT - 2 - k >= 0 ? PT - 2 - k : 0] * cb)
                                           : cb;
-            xp[k] = K0 * fma(be[k], P, al[k] * Q);
+            if constexpr (KFOLD)
+                xp[k] = fma(kbe[k], P, kal[k] * Q);
+            else
+                xp[k] = K0 * fma(be[k], P, al[k] * Q);
         }
         // the next row's right-hand side needs x_r now
         if (r + 1 < L) {
