@@ -142,28 +142,6 @@ __device__ __forceinline__ cplx<T> twiddle(const cplx<T> *__restrict__ tw, int64
     return t;
 }
 
-// v[k] *= W^(k e) (conjugated for INV), k = 1..R-1, W = exp(-2 pi i / nmax)
-// from the table, with e = base * stride.  Only the powers W^(2^j e) are
-// read; W^(k e) is built as W^((k - lowbit k) e) W^(lowbit(k) e), at most
-// log2(R) - 1 products deep.
-template <int R, bool INV, typename T>
-__device__ __forceinline__ void apply_twiddles(cplx<T> (&v)[R], const cplx<T> *__restrict__ tw, int64_t e)
-{
-    constexpr int B = lg2<R>::v;
-    cplx<T> p[B];
-#pragma unroll
-    for (int j = 0; j < B; ++j) p[j] = twiddle(tw, e << j, INV);
-    cplx<T> w[R];
-    w[0] = cplx<T>{(T)1, (T)0};
-#pragma unroll
-    for (int k = 1; k < R; ++k) {
-        const int low = k & -k;
-        const int j = __builtin_ctz(k);
-        w[k] = (k == low) ? p[j] : cmul(w[k - low], p[j]);
-        v[k] = cmul(v[k], w[k]);
-    }
-}
-
 // The pointer unchanged, but opaque to the optimiser: loads through it
 // inside a loop are not hoisted out of the loop (the persistent kernels
 // would otherwise keep every loop-invariant spectrum and twiddle value of
@@ -183,7 +161,9 @@ __device__ __forceinline__ void twiddle_bases(cplx<T> (&p)[lg2<R>::v], const cpl
     for (int j = 0; j < lg2<R>::v; ++j) p[j] = tw[e << j];
 }
 
-// apply_twiddles with the bases already in registers (conjugated for INV).
+// v[k] *= W^(k e) (conjugated for INV), k = 1..R-1, W = exp(-2 pi i / nmax),
+// from the bases p[j] = W^(e 2^j) in registers: W^(k e) is built as
+// W^((k - lowbit k) e) W^(lowbit(k) e), at most log2(R) - 1 products deep.
 template <int R, bool INV, typename T>
 __device__ __forceinline__ void apply_twiddles_b(cplx<T> (&v)[R], const cplx<T> (&pb)[lg2<R>::v])
 {
@@ -266,52 +246,42 @@ __device__ __forceinline__ void corner_add(const UpdTask<T> &tk, int p, int64_t 
     if (col + 1 < M) yr[col + 1] += tk.alpha * sy;
 }
 
-// Source/destination of the first and last digit.
-//  UPDATE mode: X rows from global memory (zero upper half), Y rows out.
-//  INNER mode (multi-pass pass 2): complex scratch Z, layout
-//    Z[(k1g * Mc + c) * n + q]   (q contiguous), full input, full output.
+// Multi-pass pass 2 (the single-pass machinery over the inner n points):
+// complex scratch Z with layout Z[(k1g * Mc + c) * n + q] (q contiguous),
+// full input and full output, spectrum entries spec[k1g + N1g * k].
+// Twiddles as in the persistent kernels: per-thread bases W^(e 2^j) loaded
+// once per stage, compile-time roots inside the digit DFTs.
 enum { MODE_UPDATE = 0, MODE_INNER = 1 };
 
 // ---------------------------------------------------- two-digit kernel
 // n = N1 N2, q = q1 N2 + q2, k = k1 + N1 k2.
 // LDS layout of element (k1 or q1, q2 or k2, c): k1*(N2*CC+1) + q2*CC + c.
-template <typename T, int N1, int N2, int CC, int MODE>
-__global__ __launch_bounds__(256) void k_fft2(const UpdTask<T> *__restrict__ tasks, const cplx<T> *__restrict__ tw,
-                                              int64_t nmax, cplx<T> *__restrict__ zs, int64_t Mc, int N1g)
+template <typename T, int N1, int N2, int CC>
+__global__ __launch_bounds__(256) void k_fft2_inner(const UpdTask<T> *__restrict__ tasks,
+                                                    const cplx<T> *__restrict__ tw, int64_t nmax,
+                                                    cplx<T> *__restrict__ zs, int64_t Mc, int N1g)
 {
     constexpr int n = N1 * N2;
     constexpr int RS = N2 * CC + 1;
     __shared__ cplx<T> sd[N1 * RS];
-    const UpdTask<T> tk = tasks[MODE == MODE_UPDATE ? blockIdx.z : 0];
-    const int64_t M = tk.M;
+    FS_G const cplx<T> *__restrict__ spec = gptr(tasks[0].spec);
     const int t = threadIdx.x;
-    // first complex column of this workgroup (XCD-aware order in update mode)
-    const int64_t cgrp = (int64_t)(MODE == MODE_UPDATE ? xcd_remap(blockIdx.x, gridDim.x) : blockIdx.x) * CC;
-    if (MODE == MODE_UPDATE && 2 * cgrp >= M) return;
+    const int64_t cgrp = (int64_t)blockIdx.x * CC;  // first complex column of this workgroup
     const int64_t tws = nmax / n;
-    // spectrum index: spec[k1g + N1g * k]
-    const int k1g = (MODE == MODE_INNER) ? blockIdx.y : 0;
-    const int sstride = (MODE == MODE_INNER) ? N1g : 1;
+    const int k1g = blockIdx.y;
 
-    // stage A: digit q1 -> k1 (forward), twiddle, to LDS
+    // stage A: digit q1 -> k1 (forward), twiddle W_n^{q2 k1}, to LDS
     for (int it = t; it < CC * N2; it += 256) {
         const int c = it % CC, q2 = it / CC;
         cplx<T> v[N1];
-        if (MODE == MODE_UPDATE) {
-            const int64_t col = 2 * (cgrp + c);
-            FS_G const T *__restrict__ xb = gptr(tk.x) + tk.xlo * M;
+        const bool cv = cgrp + c < Mc;
+        const cplx<T> *__restrict__ zb = zs + ((int64_t)k1g * Mc + cgrp + c) * n;
 #pragma unroll
-            for (int q1 = 0; q1 < N1 / 2; ++q1) v[q1] = load_pair(xb + (int64_t)(q1 * N2 + q2) * M, col, M);
-            dft_reg<N1, false, true>(v);
-        } else {
-            const bool cv = cgrp + c < Mc;
-            const cplx<T> *__restrict__ zb = zs + ((int64_t)k1g * Mc + cgrp + c) * n;
-#pragma unroll
-            for (int q1 = 0; q1 < N1; ++q1) v[q1] = cv ? zb[q1 * N2 + q2] : cplx<T>{0, 0};
-            dft_reg<N1, false, false>(v);
-        }
-#pragma unroll
-        for (int k1 = 1; k1 < N1; ++k1) v[k1] = cmul(v[k1], twiddle(tw, (int64_t)(q2 * k1) * tws, false));
+        for (int q1 = 0; q1 < N1; ++q1) v[q1] = cv ? zb[q1 * N2 + q2] : cplx<T>{0, 0};
+        cplx<T> pa[lg2<N1>::v];
+        twiddle_bases<N1>(pa, tw, (int64_t)q2 * tws);
+        dft_reg<N1, false, false>(v);
+        apply_twiddles_b<N1, false>(v, pa);
 #pragma unroll
         for (int k1 = 0; k1 < N1; ++k1) sd[k1 * RS + q2 * CC + c] = v[k1];
     }
@@ -324,7 +294,7 @@ __global__ __launch_bounds__(256) void k_fft2(const UpdTask<T> *__restrict__ tas
         for (int q2 = 0; q2 < N2; ++q2) v[q2] = sd[k1 * RS + q2 * CC + c];
         dft_reg<N2, false, false>(v);
 #pragma unroll
-        for (int k2 = 0; k2 < N2; ++k2) v[k2] = cmul(v[k2], gptr(tk.spec)[k1g + (int64_t)sstride * (k1 + N1 * k2)]);
+        for (int k2 = 0; k2 < N2; ++k2) v[k2] = cmul(v[k2], spec[k1g + (int64_t)N1g * (k1 + N1 * k2)]);
         dft_reg<N2, true, false>(v);
 #pragma unroll
         for (int q2 = 0; q2 < N2; ++q2) sd[k1 * RS + q2 * CC + c] = v[q2];
@@ -335,24 +305,12 @@ __global__ __launch_bounds__(256) void k_fft2(const UpdTask<T> *__restrict__ tas
         const int c = it % CC, q2 = it / CC;
         cplx<T> v[N1];
 #pragma unroll
-        for (int k1 = 0; k1 < N1; ++k1) {
-            cplx<T> e = sd[k1 * RS + q2 * CC + c];
-            v[k1] = (k1 == 0) ? e : cmul(e, twiddle(tw, (int64_t)(q2 * k1) * tws, true));
-        }
+        for (int k1 = 0; k1 < N1; ++k1) v[k1] = sd[k1 * RS + q2 * CC + c];
+        cplx<T> pa[lg2<N1>::v];
+        twiddle_bases<N1>(pa, tw, (int64_t)q2 * tws);
+        apply_twiddles_b<N1, true>(v, pa);
         dft_reg<N1, true, false>(v);
-        if (MODE == MODE_UPDATE) {
-            const int64_t col = 2 * (cgrp + c);
-            const T scale = (T)(tk.alpha / (double)n);
-            FS_G T *__restrict__ yb = gptr(tk.y) + tk.ylo * M;
-#pragma unroll
-            for (int q1 = N1 / 2; q1 < N1; ++q1) {
-                const int p = (q1 - N1 / 2) * N2 + q2;
-                if (p < tk.ny) {
-                    add_pair(yb + (int64_t)p * M, col, M, v[q1], scale);
-                    if (p < corner_width(tk.s) - 1) corner_add(tk, p, col, M);
-                }
-            }
-        } else if (cgrp + c < Mc) {
+        if (cgrp + c < Mc) {
             cplx<T> *__restrict__ zb = zs + ((int64_t)k1g * Mc + cgrp + c) * n;
 #pragma unroll
             for (int q1 = 0; q1 < N1; ++q1) zb[q1 * N2 + q2] = v[q1];
@@ -364,42 +322,33 @@ __global__ __launch_bounds__(256) void k_fft2(const UpdTask<T> *__restrict__ tas
 // n = N1 N2 N3, q = q1 N2 N3 + q2 N3 + q3, k = k1 + N1 k2 + N1 N2 k3.
 // LDS layout of element (a = k1|q1, b = q2|k2, d = q3|k3, c):
 //   (a*N2 + b)*(N3*CC + 1) + d*CC + c.
-template <typename T, int N1, int N2, int N3, int CC, int MODE>
-__global__ __launch_bounds__(256) void k_fft3(const UpdTask<T> *__restrict__ tasks, const cplx<T> *__restrict__ tw,
-                                              int64_t nmax, cplx<T> *__restrict__ zs, int64_t Mc, int N1g)
+template <typename T, int N1, int N2, int N3, int CC>
+__global__ __launch_bounds__(256) void k_fft3_inner(const UpdTask<T> *__restrict__ tasks,
+                                                    const cplx<T> *__restrict__ tw, int64_t nmax,
+                                                    cplx<T> *__restrict__ zs, int64_t Mc, int N1g)
 {
     constexpr int n = N1 * N2 * N3;
     constexpr int RS = N3 * CC + 1;
     __shared__ cplx<T> sd[N1 * N2 * RS];
-    const UpdTask<T> tk = tasks[MODE == MODE_UPDATE ? blockIdx.z : 0];
-    const int64_t M = tk.M;
+    FS_G const cplx<T> *__restrict__ spec = gptr(tasks[0].spec);
     const int t = threadIdx.x;
-    const int64_t cgrp = (int64_t)(MODE == MODE_UPDATE ? xcd_remap(blockIdx.x, gridDim.x) : blockIdx.x) * CC;
-    if (MODE == MODE_UPDATE && 2 * cgrp >= M) return;
+    const int64_t cgrp = (int64_t)blockIdx.x * CC;
     const int64_t tws = nmax / n;
-    const int k1g = (MODE == MODE_INNER) ? blockIdx.y : 0;
-    const int sstride = (MODE == MODE_INNER) ? N1g : 1;
+    const int k1g = blockIdx.y;
     auto at = [&](int a, int b, int d, int c) { return (a * N2 + b) * RS + d * CC + c; };
 
     // A: q1 -> k1, twiddle by W_n^{(q2 N3 + q3) k1}
     for (int it = t; it < CC * N2 * N3; it += 256) {
         const int c = it % CC, r = it / CC, q3 = r % N3, q2 = r / N3;
         cplx<T> v[N1];
-        if (MODE == MODE_UPDATE) {
-            const int64_t col = 2 * (cgrp + c);
-            FS_G const T *__restrict__ xb = gptr(tk.x) + tk.xlo * M;
+        const bool cv = cgrp + c < Mc;
+        const cplx<T> *__restrict__ zb = zs + ((int64_t)k1g * Mc + cgrp + c) * n;
 #pragma unroll
-            for (int q1 = 0; q1 < N1 / 2; ++q1) v[q1] = load_pair(xb + (int64_t)(q1 * N2 * N3 + r) * M, col, M);
-            dft_reg<N1, false, true>(v);
-        } else {
-            const bool cv = cgrp + c < Mc;
-            const cplx<T> *__restrict__ zb = zs + ((int64_t)k1g * Mc + cgrp + c) * n;
-#pragma unroll
-            for (int q1 = 0; q1 < N1; ++q1) v[q1] = cv ? zb[q1 * N2 * N3 + r] : cplx<T>{0, 0};
-            dft_reg<N1, false, false>(v);
-        }
-#pragma unroll
-        for (int k1 = 1; k1 < N1; ++k1) v[k1] = cmul(v[k1], twiddle(tw, (int64_t)(r * k1) * tws, false));
+        for (int q1 = 0; q1 < N1; ++q1) v[q1] = cv ? zb[q1 * N2 * N3 + r] : cplx<T>{0, 0};
+        cplx<T> pa[lg2<N1>::v];
+        twiddle_bases<N1>(pa, tw, (int64_t)r * tws);
+        dft_reg<N1, false, false>(v);
+        apply_twiddles_b<N1, false>(v, pa);
 #pragma unroll
         for (int k1 = 0; k1 < N1; ++k1) sd[at(k1, q2, q3, c)] = v[k1];
     }
@@ -410,9 +359,10 @@ __global__ __launch_bounds__(256) void k_fft3(const UpdTask<T> *__restrict__ tas
         cplx<T> v[N2];
 #pragma unroll
         for (int q2 = 0; q2 < N2; ++q2) v[q2] = sd[at(k1, q2, q3, c)];
+        cplx<T> pb[lg2<N2>::v];
+        twiddle_bases<N2>(pb, tw, (int64_t)(q3 * N1) * tws);
         dft_reg<N2, false, false>(v);
-#pragma unroll
-        for (int k2 = 1; k2 < N2; ++k2) v[k2] = cmul(v[k2], twiddle(tw, (int64_t)(q3 * k2 * N1) * tws, false));
+        apply_twiddles_b<N2, false>(v, pb);
 #pragma unroll
         for (int k2 = 0; k2 < N2; ++k2) sd[at(k1, k2, q3, c)] = v[k2];
     }
@@ -423,10 +373,12 @@ __global__ __launch_bounds__(256) void k_fft3(const UpdTask<T> *__restrict__ tas
         cplx<T> v[N3];
 #pragma unroll
         for (int q3 = 0; q3 < N3; ++q3) v[q3] = sd[at(k1, k2, q3, c)];
+        cplx<T> hs[N3];
+#pragma unroll
+        for (int k3 = 0; k3 < N3; ++k3) hs[k3] = spec[k1g + (int64_t)N1g * (k1 + N1 * k2 + N1 * N2 * k3)];
         dft_reg<N3, false, false>(v);
 #pragma unroll
-        for (int k3 = 0; k3 < N3; ++k3)
-            v[k3] = cmul(v[k3], gptr(tk.spec)[k1g + (int64_t)sstride * (k1 + N1 * k2 + N1 * N2 * k3)]);
+        for (int k3 = 0; k3 < N3; ++k3) v[k3] = cmul(v[k3], hs[k3]);
         dft_reg<N3, true, false>(v);
 #pragma unroll
         for (int q3 = 0; q3 < N3; ++q3) sd[at(k1, k2, q3, c)] = v[q3];
@@ -437,10 +389,10 @@ __global__ __launch_bounds__(256) void k_fft3(const UpdTask<T> *__restrict__ tas
         const int c = it % CC, r = it / CC, q3 = r % N3, k1 = r / N3;
         cplx<T> v[N2];
 #pragma unroll
-        for (int k2 = 0; k2 < N2; ++k2) {
-            cplx<T> e = sd[at(k1, k2, q3, c)];
-            v[k2] = (k2 == 0) ? e : cmul(e, twiddle(tw, (int64_t)(q3 * k2 * N1) * tws, true));
-        }
+        for (int k2 = 0; k2 < N2; ++k2) v[k2] = sd[at(k1, k2, q3, c)];
+        cplx<T> pb[lg2<N2>::v];
+        twiddle_bases<N2>(pb, tw, (int64_t)(q3 * N1) * tws);
+        apply_twiddles_b<N2, true>(v, pb);
         dft_reg<N2, true, false>(v);
 #pragma unroll
         for (int q2 = 0; q2 < N2; ++q2) sd[at(k1, q2, q3, c)] = v[q2];
@@ -448,27 +400,15 @@ __global__ __launch_bounds__(256) void k_fft3(const UpdTask<T> *__restrict__ tas
     __syncthreads();
     // E: conjugate twiddle, k1 -> q1, out
     for (int it = t; it < CC * N2 * N3; it += 256) {
-        const int c = it % CC, r = it / CC, q3 = r % N3, q2 = r / N3;
+        const int c = it % CC, r = it / CC;
         cplx<T> v[N1];
 #pragma unroll
-        for (int k1 = 0; k1 < N1; ++k1) {
-            cplx<T> e = sd[at(k1, q2, q3, c)];
-            v[k1] = (k1 == 0) ? e : cmul(e, twiddle(tw, (int64_t)(r * k1) * tws, true));
-        }
+        for (int k1 = 0; k1 < N1; ++k1) v[k1] = sd[at(k1, r / N3, r % N3, c)];
+        cplx<T> pa[lg2<N1>::v];
+        twiddle_bases<N1>(pa, tw, (int64_t)r * tws);
+        apply_twiddles_b<N1, true>(v, pa);
         dft_reg<N1, true, false>(v);
-        if (MODE == MODE_UPDATE) {
-            const int64_t col = 2 * (cgrp + c);
-            const T scale = (T)(tk.alpha / (double)n);
-            FS_G T *__restrict__ yb = gptr(tk.y) + tk.ylo * M;
-#pragma unroll
-            for (int q1 = N1 / 2; q1 < N1; ++q1) {
-                const int p = (q1 - N1 / 2) * N2 * N3 + r;
-                if (p < tk.ny) {
-                    add_pair(yb + (int64_t)p * M, col, M, v[q1], scale);
-                    if (p < corner_width(tk.s) - 1) corner_add(tk, p, col, M);
-                }
-            }
-        } else if (cgrp + c < Mc) {
+        if (cgrp + c < Mc) {
             cplx<T> *__restrict__ zb = zs + ((int64_t)k1g * Mc + cgrp + c) * n;
 #pragma unroll
             for (int q1 = 0; q1 < N1; ++q1) zb[q1 * N2 * N3 + r] = v[q1];
@@ -1094,12 +1034,12 @@ static hipError_t single_pass(hipStream_t st, const UpdTask<T> *d_tasks, int nta
     };
 #define FS_F2(N1_, N2_, CC_)                                                                                     \
     case N1_ * N2_:                                                                                              \
-        hipLaunchKernelGGL((k_fft2<T, N1_, N2_, CC_, MODE>), grid(CC_), dim3(256), 0, st, d_tasks, tw, nmax, zs, \
+        hipLaunchKernelGGL((k_fft2_inner<T, N1_, N2_, CC_>), grid(CC_), dim3(256), 0, st, d_tasks, tw, nmax, zs,  \
                            Mc, N1g);                                                                             \
         return hipGetLastError();
 #define FS_F3(N1_, N2_, N3_, CC_)                                                                                 \
     case N1_ * N2_ * N3_:                                                                                         \
-        hipLaunchKernelGGL((k_fft3<T, N1_, N2_, N3_, CC_, MODE>), grid(CC_), dim3(256), 0, st, d_tasks, tw, nmax, \
+        hipLaunchKernelGGL((k_fft3_inner<T, N1_, N2_, N3_, CC_>), grid(CC_), dim3(256), 0, st, d_tasks, tw, nmax, \
                            zs, Mc, N1g);                                                                          \
         return hipGetLastError();
 #define FS_U2(N1_, N2_, CC_)                                                                                   \
