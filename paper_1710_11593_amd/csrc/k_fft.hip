@@ -134,14 +134,6 @@ __device__ __forceinline__ void dft_reg(cplx<T> (&v)[R])
     for (int i = 0; i < R; ++i) v[i] = w[i];
 }
 
-template <typename T>
-__device__ __forceinline__ cplx<T> twiddle(const cplx<T> *__restrict__ tw, int64_t idx, bool inv)
-{
-    cplx<T> t = tw[idx];
-    if (inv) t.y = -t.y;
-    return t;
-}
-
 // The pointer unchanged, but opaque to the optimiser: loads through it
 // inside a loop are not hoisted out of the loop (the persistent kernels
 // would otherwise keep every loop-invariant spectrum and twiddle value of
@@ -887,12 +879,12 @@ __global__ __launch_bounds__(256) void k_mp_pass1(const UpdTask<T> *__restrict__
 #pragma unroll
     for (int q1 = 0; q1 < N1 / 2; ++q1)
         v[q1] = (cl < Mc) ? load_pair(xb + ((int64_t)q1 * nin + q2) * M, col, M) : cplx<T>{0, 0};
+    cplx<T> pa[lg2<N1>::v];
+    twiddle_bases<N1>(pa, tw, (int64_t)q2 * tws);
     dft_reg<N1, false, true>(v);
+    apply_twiddles_b<N1, false>(v, pa);
 #pragma unroll
-    for (int k1 = 0; k1 < N1; ++k1) {
-        cplx<T> e = (k1 == 0) ? v[k1] : cmul(v[k1], twiddle(tw, (int64_t)q2 * k1 * tws, false));
-        sb[k1][tx][ty] = e;
-    }
+    for (int k1 = 0; k1 < N1; ++k1) sb[k1][tx][ty] = v[k1];
     __syncthreads();
     // write: thread (ty -> column, tx -> q2)
     const int64_t cw = (int64_t)blockIdx.x * 16 + ty;
@@ -927,10 +919,10 @@ __global__ __launch_bounds__(256) void k_mp_pass3(const UpdTask<T> *__restrict__
     const int q2 = blockIdx.y * 16 + ty;
     cplx<T> v[N1];
 #pragma unroll
-    for (int k1 = 0; k1 < N1; ++k1) {
-        cplx<T> e = sb[k1][tx][ty];
-        v[k1] = (k1 == 0) ? e : cmul(e, twiddle(tw, (int64_t)q2 * k1 * tws, true));
-    }
+    for (int k1 = 0; k1 < N1; ++k1) v[k1] = sb[k1][tx][ty];
+    cplx<T> pa[lg2<N1>::v];
+    twiddle_bases<N1>(pa, tw, (int64_t)q2 * tws);
+    apply_twiddles_b<N1, true>(v, pa);
     dft_reg<N1, true, false>(v);
     if (cl < Mc) {
         const int64_t col = 2 * (c0 + cl);
