@@ -740,7 +740,7 @@ int setup_instance(fracsolve_ctx *h, Inst &in)
     in.coef = std::pow(in.tau, -p.gamma) / std::tgamma(garg);
     in.dcoef = in.coef * (-std::log(in.tau) + digamma_host(garg));
     in.scan = (h->opts.leaf_solver == 0);
-    in.lc = in.scan ? scan_config(h->batch_M > 0 ? h->batch_M : in.M) : leaf_config(in.M);
+    in.lc = in.scan ? scan_config(h->batch_M > 0 ? h->batch_M : in.M, h->batch_M > 0) : leaf_config(in.M);
     if (in.scan && in.lc.pt > 2 && in.M % in.lc.pt == 0)
         in.perm = ColPerm{in.lc.pt, (in.M / (64 * (int64_t)in.lc.pt)) * 64 * (int64_t)in.lc.pt};
     if (h->L > 8 && ((in.scan && in.lc.pt > 2) || (!in.scan && in.lc.pt == 16)))

@@ -362,14 +362,17 @@ __global__ __launch_bounds__(NT) void k_leaf_scan(TaskRef<LeafTask> tr)
 
 // Up to 512 threads (two waves per SIMD) with 2, 4 or 8 rows per thread: the
 // leaf's right-hand sides (L x PT doubles per thread) stay in registers and
-// each thread's rows are whole 16-byte units.
-LeafCfg scan_config(int64_t M)
+// each thread's rows are whole 16-byte units.  For 1024 < M <= 2048 a single
+// instance runs faster on 256 threads x 8 rows (one wave per SIMD, a
+// shallower scan), but in a batch two such workgroups can share a CU, and
+// 512 x 4 (which fills the CU's registers at two waves per SIMD) is faster.
+LeafCfg scan_config(int64_t M, bool batched)
 {
     if (M <= 128) return {64, 2, 6};
     if (M <= 256) return {64, 4, 6};
     if (M <= 512) return {128, 4, 7};
     if (M <= 1024) return {256, 4, 8};
-    if (M <= 2048) return {512, 4, 9};
+    if (M <= 2048) return batched ? LeafCfg{512, 4, 9} : LeafCfg{256, 8, 8};
     return {512, 8, 9};
 }
 
@@ -388,6 +391,7 @@ hipError_t launch_scan_factor(hipStream_t st, const LeafCfg &c, int64_t M, doubl
     FS_SF(256, 4)
     FS_SF(512, 4)
     FS_SF(512, 8)
+    FS_SF(256, 8)
 #undef FS_SF
     return hipErrorInvalidValue;
 }
@@ -438,6 +442,7 @@ hipError_t launch_leaf_scan(hipStream_t st, const LeafCfg &c, int L, const TaskR
     FS_SL(256, 4)
     FS_SL(512, 4)
     FS_SL(512, 8)
+    FS_SL(256, 8)
 #undef FS_SL
     return hipErrorInvalidValue;
 }

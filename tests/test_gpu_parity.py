@@ -242,6 +242,23 @@ def test_batched_parity(torch_cuda, orc):
     s.close()
 
 
+def test_batched_parity_narrow(torch_cuda, orc):
+    """A batch whose widest instance has M <= 2048 (the batch leaf
+    configuration differs from the single-instance one there)."""
+    from paper_1710_11593_amd import binding
+
+    cases = [(0.3, 1500, 300), (1.4, 77, 500), (0.6, 600, 200), (1.8, 2048, 130)]
+    data = [rand_case(g, M, N, seed=10 + i) for i, (g, M, N) in enumerate(cases)]
+    s = binding.Solver([dict(gamma=g, M=M, N=N) for g, M, N in cases])
+    us = s.solve([dev(torch_cuda, d[0]) for d in data], [dev(torch_cuda, d[1]) for d in data],
+                 [dev(torch_cuda, d[2]) if d[2] is not None else None for d in data])
+    torch_cuda.cuda.synchronize()
+    for (g, M, N), d, u in zip(cases, data, us):
+        ref = orc.solve(g, 1.0, 0.0, 1.0, M, N, d[0], u0=d[1], phi=d[2])
+        assert_parity64(u.cpu().numpy(), ref, g, M, N, d[0], d[1], d[2])
+    s.close()
+
+
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_batched_widths_multipass(torch_cuda, orc, precision):
     """A batch of instances of four widths (every instance runs the leaf
