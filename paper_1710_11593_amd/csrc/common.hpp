@@ -178,8 +178,11 @@ hipError_t launch_leaf_scan(hipStream_t st, const LeafCfg &c, int L, const TaskR
 
 hipError_t launch_twiddles(hipStream_t st, int64_t nmax, cplx<double> *w64, cplx<float> *w32);
 
+// lead_rows: rows at the start of Y that the next launch (a leaf) reads
+// first; with one task their tiles run on the leaf's XCD (0 = no placement)
 template <typename T>
-hipError_t launch_gemm_update(hipStream_t st, const TaskRef<UpdTask<T>> &tr, int ntasks, int s, int64_t maxM);
+hipError_t launch_gemm_update(hipStream_t st, const TaskRef<UpdTask<T>> &tr, int ntasks, int s, int64_t maxM,
+                              int lead_rows = 0);
 // even: every task has M even and 16-byte aligned rows (one vector access per
 // column pair)
 // corner: also launch the near-corner band kernel of single-pass levels

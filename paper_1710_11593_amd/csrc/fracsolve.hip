@@ -226,6 +226,7 @@ struct Op {
     double bytes = 0.0;  // algorithmic HBM bytes of the launch
     bool even = false;   // FFT levels: every task has M even and aligned rows
     size_t goff = 0;     // single-pass FFT levels: descriptor offset of the group offsets
+    int lead = 0;        // dense levels of a solve: rows the next leaf reads first
 };
 
 // Flat column-group offsets of the tasks of a single-pass FFT level (see
@@ -293,7 +294,8 @@ int run_ops(fracsolve_ctx *h, const std::vector<Op> &ops)
                 e = launch_leaf_scan(h->st, op.lc, h->L, task_ref<LeafTask>(h, op), op.ntasks, op.mixed, op.lc.vec);
                 break;
             case OP_GEMM64:
-                e = launch_gemm_update<double>(h->st, task_ref<UpdTask<double>>(h, op), op.ntasks, op.s, op.maxM);
+                e = launch_gemm_update<double>(h->st, task_ref<UpdTask<double>>(h, op), op.ntasks, op.s, op.maxM,
+                                               op.lead);
                 break;
             case OP_GEMM32:
                 e = launch_gemm_update<float>(h->st, task_ref<UpdTask<float>>(h, op), op.ntasks, op.s, op.maxM);
@@ -370,6 +372,7 @@ uint64_t ops_key(const std::vector<Op> &ops, const void *d_desc)
         mix((uint64_t)op.mixed);
         mix((uint64_t)op.even);
         mix((uint64_t)op.goff);
+        mix((uint64_t)op.lead);
         mix((uint64_t)op.lc.vec);
     }
     mix((uint64_t)ops.size());
@@ -540,7 +543,10 @@ void build_solve(fracsolve_ctx *h, const std::vector<int> &sel, const std::vecto
             } else {
                 size_t off = db.add(t64.data(), t64.size() * sizeof(t64[0]));
                 Op op{fft ? OP_FFT64 : OP_GEMM64, off, (int)t64.size(), (int)s, maxM, {}, false};
-                if (fft) op.goff = add_group_offsets(db, t64, (int)s);
+                if (fft)
+                    op.goff = add_group_offsets(db, t64, (int)s);
+                else
+                    op.lead = L;
                 op.even = true;
                 for (auto &t : t64) {
                     op.bytes += upd_bytes(t, 8);

@@ -12,6 +12,8 @@
 // its Y rows are issued together, the weight window sits in LDS (read as
 // wave-uniform broadcasts), and the output rows are spread over the grid so
 // that even s = 64 occupies every CU.
+#include <algorithm>
+
 #include "common.hpp"
 
 namespace fs {
@@ -25,17 +27,39 @@ constexpr int DENSE_MAXS = 1024;  // largest half-block size for this kernel
 // Loads are unconditional: a thread past the last column reads column M - 1
 // (a valid address) and stores nothing, so the loads carry no branches and
 // are all in flight together.
+// Placement (lead > 0, single task): workgroups are dispatched to the XCDs
+// round robin (workgroup b on XCD b mod 8), and a single-workgroup leaf
+// launch runs on XCD 0.  The tiles of the first `lead` row blocks (the rows
+// the next leaf reads) are put on XCD 0, so that they reach the leaf through
+// that XCD's L2; the other tiles go to XCDs 1..7.  1-D grid, tile order
+// row-block major.
 template <typename T, int QC, int RB>
-__global__ __launch_bounds__(256) void k_dense_update(TaskRef<UpdTask<T>> tr)
+__global__ __launch_bounds__(256) void k_dense_update(TaskRef<UpdTask<T>> tr, int lead, int gxp, int gyp)
 {
     constexpr int DENSE_RB = RB;
     __shared__ double sw[DENSE_MAXS + DENSE_RB];
+    int bx = blockIdx.x, by = blockIdx.y;
+    if (lead > 0) {
+        const int xcd = blockIdx.x % 8, slot = blockIdx.x / 8;
+        const int ne = gxp * lead, nl = gxp * (gyp - lead);
+        int tile;
+        if (xcd == 0) {
+            if (slot >= ne) return;  // whole workgroup
+            tile = slot;
+        } else {
+            const int j = slot * 7 + (xcd - 1);
+            if (j >= nl) return;
+            tile = ne + j;
+        }
+        bx = tile % gxp;
+        by = tile / gxp;
+    }
     const UpdTask<T> tk = get_task(tr, blockIdx.z);
     const int s = tk.s;
     const int64_t M = tk.M;
-    const int p0 = blockIdx.y * DENSE_RB;  // first output row of the workgroup
-    const int64_t col = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (p0 >= tk.ny || (int64_t)blockIdx.x * 256 >= M) return;  // whole workgroup exits together
+    const int p0 = by * DENSE_RB;  // first output row of the workgroup
+    const int64_t col = (int64_t)bx * 256 + threadIdx.x;
+    if (p0 >= tk.ny || (int64_t)bx * 256 >= M) return;  // whole workgroup exits together
     const bool ok = col < M;
     const int64_t cl = ok ? col : M - 1;
     const int np = (tk.ny - p0 < DENSE_RB) ? tk.ny - p0 : DENSE_RB;
@@ -76,38 +100,47 @@ __global__ __launch_bounds__(256) void k_dense_update(TaskRef<UpdTask<T>> tr)
 }
 
 template <typename T, int RB>
-static void dense_go(hipStream_t st, const TaskRef<UpdTask<T>> &d_tasks, int ntasks, int s, int64_t maxM)
+static void dense_go(hipStream_t st, const TaskRef<UpdTask<T>> &d_tasks, int ntasks, int s, int64_t maxM, int lead_rows)
 {
     dim3 grid((unsigned)((maxM + 255) / 256), (unsigned)((s + RB - 1) / RB), (unsigned)ntasks);
+    const int gxp = (int)grid.x, gyp = (int)grid.y;
+    // single task: the row blocks the next leaf reads on XCD 0 (see the kernel)
+    int lead = 0;
+    if (ntasks == 1 && lead_rows > 0) {
+        lead = std::min(gyp, (lead_rows + RB - 1) / RB);
+        const int ne = gxp * lead, nl = gxp * (gyp - lead);
+        grid = dim3((unsigned)(8 * std::max(ne, (nl + 6) / 7)), 1, 1);
+    }
     if (s <= 4)
-        hipLaunchKernelGGL((k_dense_update<T, 4, RB>), grid, dim3(256), 0, st, d_tasks);
+        hipLaunchKernelGGL((k_dense_update<T, 4, RB>), grid, dim3(256), 0, st, d_tasks, lead, gxp, gyp);
     else if (s <= 8)
-        hipLaunchKernelGGL((k_dense_update<T, 8, RB>), grid, dim3(256), 0, st, d_tasks);
+        hipLaunchKernelGGL((k_dense_update<T, 8, RB>), grid, dim3(256), 0, st, d_tasks, lead, gxp, gyp);
     else if (s <= 16)
-        hipLaunchKernelGGL((k_dense_update<T, 16, RB>), grid, dim3(256), 0, st, d_tasks);
+        hipLaunchKernelGGL((k_dense_update<T, 16, RB>), grid, dim3(256), 0, st, d_tasks, lead, gxp, gyp);
     else if (s <= 32 || RB > 4)
-        hipLaunchKernelGGL((k_dense_update<T, 32, RB>), grid, dim3(256), 0, st, d_tasks);
+        hipLaunchKernelGGL((k_dense_update<T, 32, RB>), grid, dim3(256), 0, st, d_tasks, lead, gxp, gyp);
     else
-        hipLaunchKernelGGL((k_dense_update<T, 64, RB>), grid, dim3(256), 0, st, d_tasks);
+        hipLaunchKernelGGL((k_dense_update<T, 64, RB>), grid, dim3(256), 0, st, d_tasks, lead, gxp, gyp);
 }
 
 template <typename T>
-hipError_t launch_gemm_update(hipStream_t st, const TaskRef<UpdTask<T>> &d_tasks, int ntasks, int s, int64_t maxM)
+hipError_t launch_gemm_update(hipStream_t st, const TaskRef<UpdTask<T>> &d_tasks, int ntasks, int s, int64_t maxM,
+                              int lead_rows)
 {
     if (s > DENSE_MAXS || s < 1 || (s & (s - 1)) != 0) return hipErrorInvalidValue;
     // workgroups at 4 rows per thread; past a few per CU the X re-reads
     // dominate and more rows per thread pay
     const int64_t wg4 = (int64_t)ntasks * ((maxM + 255) / 256) * ((s + 3) / 4);
     if (wg4 > 2048 && s >= 16)
-        dense_go<T, 16>(st, d_tasks, ntasks, s, maxM);
+        dense_go<T, 16>(st, d_tasks, ntasks, s, maxM, lead_rows);
     else if (wg4 > 2048 && s >= 8)
-        dense_go<T, 8>(st, d_tasks, ntasks, s, maxM);
+        dense_go<T, 8>(st, d_tasks, ntasks, s, maxM, lead_rows);
     else
-        dense_go<T, 4>(st, d_tasks, ntasks, s, maxM);
+        dense_go<T, 4>(st, d_tasks, ntasks, s, maxM, lead_rows);
     return hipGetLastError();
 }
 
-template hipError_t launch_gemm_update<double>(hipStream_t, const TaskRef<UpdTask<double>> &, int, int, int64_t);
-template hipError_t launch_gemm_update<float>(hipStream_t, const TaskRef<UpdTask<float>> &, int, int, int64_t);
+template hipError_t launch_gemm_update<double>(hipStream_t, const TaskRef<UpdTask<double>> &, int, int, int64_t, int);
+template hipError_t launch_gemm_update<float>(hipStream_t, const TaskRef<UpdTask<float>> &, int, int, int64_t, int);
 
 }  // namespace fs
