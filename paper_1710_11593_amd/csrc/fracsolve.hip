@@ -461,7 +461,9 @@ void build_solve(fracsolve_ctx *h, const std::vector<int> &sel, const std::vecto
             if (in.scan && (in.M % in.lc.pt) == 0 && ((uintptr_t)t.u & 15) == 0) t.flags |= LEAF_VEC;
             lt.push_back({(in.scan ? 1000000 : 0) + in.lc.nt * 100 + in.lc.pt, t});
         }
-        std::sort(lt.begin(), lt.end(), [](const auto &x, const auto &y) { return x.first < y.first; });
+        // stable: with one leaf configuration, leaf task t is level task t
+        // (the dense levels place task t's tiles on leaf t's XCD)
+        std::stable_sort(lt.begin(), lt.end(), [](const auto &x, const auto &y) { return x.first < y.first; });
         for (size_t b = 0; b < lt.size();) {
             size_t e = b;
             while (e < lt.size() && lt[e].first == lt[b].first) ++e;

@@ -27,19 +27,26 @@ constexpr int DENSE_MAXS = 1024;  // largest half-block size for this kernel
 // Loads are unconditional: a thread past the last column reads column M - 1
 // (a valid address) and stores nothing, so the loads carry no branches and
 // are all in flight together.
-// Placement (lead > 0, single task): workgroups are dispatched to the XCDs
-// round robin (workgroup b on XCD b mod 8), and a single-workgroup leaf
-// launch runs on XCD 0.  The tiles of the first `lead` row blocks (the rows
-// the next leaf reads) are put on XCD 0, so that they reach the leaf through
-// that XCD's L2; the other tiles go to XCDs 1..7.  1-D grid, tile order
-// row-block major.
+// Placement.  Workgroups are dispatched to the XCDs round robin (workgroup b
+// on XCD b mod 8), so the leaf of task t in a leaf launch runs on XCD t mod 8.
+//  lead > 0 (single task): the tiles of the first `lead` row blocks (the rows
+//    the next leaf reads) are put on XCD 0, so that they reach the leaf
+//    through that XCD's L2; the other tiles go to XCDs 1..7.  1-D grid, tile
+//    order row-block major.
+//  lead < 0 (several tasks): every tile of task t runs on XCD t mod 8, next to
+//    its leaf: grid (8 gxp, gyp, ceil(ntasks / 8)), task = 8 z + x mod 8.
+//  lead = 0: grid (gxp, gyp, ntasks).
 template <typename T, int QC, int RB>
-__global__ __launch_bounds__(256) void k_dense_update(TaskRef<UpdTask<T>> tr, int lead, int gxp, int gyp)
+__global__ __launch_bounds__(256) void k_dense_update(TaskRef<UpdTask<T>> tr, int lead, int gxp, int gyp, int ntasks)
 {
     constexpr int DENSE_RB = RB;
     __shared__ double sw[DENSE_MAXS + DENSE_RB];
-    int bx = blockIdx.x, by = blockIdx.y;
-    if (lead > 0) {
+    int bx = blockIdx.x, by = blockIdx.y, task = blockIdx.z;
+    if (lead < 0) {
+        task = 8 * blockIdx.z + blockIdx.x % 8;
+        bx = blockIdx.x / 8;
+        if (task >= ntasks) return;  // whole workgroup
+    } else if (lead > 0) {
         const int xcd = blockIdx.x % 8, slot = blockIdx.x / 8;
         const int ne = gxp * lead, nl = gxp * (gyp - lead);
         int tile;
@@ -54,7 +61,7 @@ __global__ __launch_bounds__(256) void k_dense_update(TaskRef<UpdTask<T>> tr, in
         bx = tile % gxp;
         by = tile / gxp;
     }
-    const UpdTask<T> tk = get_task(tr, blockIdx.z);
+    const UpdTask<T> tk = get_task(tr, task);
     const int s = tk.s;
     const int64_t M = tk.M;
     const int p0 = by * DENSE_RB;  // first output row of the workgroup
@@ -110,17 +117,20 @@ static void dense_go(hipStream_t st, const TaskRef<UpdTask<T>> &d_tasks, int nta
         lead = std::min(gyp, (lead_rows + RB - 1) / RB);
         const int ne = gxp * lead, nl = gxp * (gyp - lead);
         grid = dim3((unsigned)(8 * std::max(ne, (nl + 6) / 7)), 1, 1);
+    } else if (ntasks > 1 && lead_rows > 0) {
+        lead = -1;
+        grid = dim3((unsigned)(8 * gxp), (unsigned)gyp, (unsigned)((ntasks + 7) / 8));
     }
     if (s <= 4)
-        hipLaunchKernelGGL((k_dense_update<T, 4, RB>), grid, dim3(256), 0, st, d_tasks, lead, gxp, gyp);
+        hipLaunchKernelGGL((k_dense_update<T, 4, RB>), grid, dim3(256), 0, st, d_tasks, lead, gxp, gyp, ntasks);
     else if (s <= 8)
-        hipLaunchKernelGGL((k_dense_update<T, 8, RB>), grid, dim3(256), 0, st, d_tasks, lead, gxp, gyp);
+        hipLaunchKernelGGL((k_dense_update<T, 8, RB>), grid, dim3(256), 0, st, d_tasks, lead, gxp, gyp, ntasks);
     else if (s <= 16)
-        hipLaunchKernelGGL((k_dense_update<T, 16, RB>), grid, dim3(256), 0, st, d_tasks, lead, gxp, gyp);
+        hipLaunchKernelGGL((k_dense_update<T, 16, RB>), grid, dim3(256), 0, st, d_tasks, lead, gxp, gyp, ntasks);
     else if (s <= 32 || RB > 4)
-        hipLaunchKernelGGL((k_dense_update<T, 32, RB>), grid, dim3(256), 0, st, d_tasks, lead, gxp, gyp);
+        hipLaunchKernelGGL((k_dense_update<T, 32, RB>), grid, dim3(256), 0, st, d_tasks, lead, gxp, gyp, ntasks);
     else
-        hipLaunchKernelGGL((k_dense_update<T, 64, RB>), grid, dim3(256), 0, st, d_tasks, lead, gxp, gyp);
+        hipLaunchKernelGGL((k_dense_update<T, 64, RB>), grid, dim3(256), 0, st, d_tasks, lead, gxp, gyp, ntasks);
 }
 
 template <typename T>
