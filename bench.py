@@ -271,6 +271,71 @@ def run_forms(dev):
     return out
 
 
+def run_batched(args, dev):
+    """--config c4: the 256 uneven instances as one batched handle; value =
+    sum of M N over the batch per second; error sampled on 8 instances."""
+    import torch
+
+    from paper_1710_11593_amd import binding, workloads as wl
+
+    insts = wl.c4()
+    ds = [device_inputs(i, dev) for i in insts]
+    us = [torch.empty_like(x["f"]) for x in ds]
+    wave = [i.gamma > 1 for i in insts]
+    prec = args.precision
+    ref = args.refine if prec != "fp64" else 0
+    sv = binding.Solver([dict(gamma=i.gamma, M=i.M, N=i.N) for i in insts], precision=prec, refine_steps=ref)
+
+    def step():
+        sv.solve([x["f"] for x in ds], [x["u0"] for x in ds], [x["phi"] if w else None for x, w in zip(ds, wave)],
+                 out=us)
+
+    for _ in range(args.warmup):
+        step()
+    ms = timed(step, args.steps)
+    mn = sum(i.M * i.N for i in insts)
+    err = None
+    if not args.no_check:
+        err = max(mode_error(insts[k], ds[k], us[k]) for k in range(0, len(insts), 32))
+    log("bench: c4 batched %s: %.3f ms per solve of 256 instances, error (sampled) %s" % (prec, ms, err))
+    sv.set_timing_level(2)
+    step()
+    torch.cuda.synchronize()
+    ks = sv.kernel_stats()
+    sv.set_timing_level(0)
+    groups = sorted(ks, key=lambda r: -r["ms"])
+    for g in groups[:12]:
+        log("  %-10s s=%-6d launches=%-6d tasks=%-7d %9.3f ms" % (g["kind"], g["s"], g["launches"], g["tasks"], g["ms"]))
+    fft_kind = "fft_f64" if prec == "fp64" else "fft_f32"
+    single = [g for g in ks if g["kind"] == fft_kind and 2 * g["s"] <= (8192 if prec == "fp64" else 16384)]
+    roof = None
+    if single:
+        dom = max(single, key=lambda r: r["s"])
+        per_ms = dom["ms"] / dom["launches"]
+        ach = dom["bytes"] / dom["launches"] / (per_ms * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "%s s=%d (batched)" % (fft_kind, dom["s"]),
+                "level_s": dom["s"], "launches": dom["launches"], "avg_us": round(per_ms * 1e3, 2),
+                "bytes_per_launch": dom["bytes"] / dom["launches"]}
+    line = {
+        "metric": METRIC, "value": mn / (ms * 1e-3), "unit": "unknowns/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if prec == "fp64" else "f32+f64", "data": "synthetic",
+        "config": {"workload": "c4: 256 uneven instances (M 64..2048, N 2^10..2^15, both regimes), one batched "
+                               "handle", "instances": len(insts), "sum_MN": mn, "precision": prec,
+                   "refine_steps": ref},
+        "error_vs_oracle": err, "roofline": roof, "cpu_baseline": None,
+        "kernel_groups": [{"kind": g["kind"], "s": g["s"], "launches": g["launches"], "ms": round(g["ms"], 3)}
+                          for g in groups[:10]],
+    }
+    s = json.dumps(line)
+    print(s, flush=True)
+    if args.out:
+        with open(args.out, "w") as fh_:
+            fh_.write(s + "\n")
+    sv.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -320,6 +385,8 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
+    if args.config == "c4":
+        return run_batched(args, dev)
     inst, desc = build_instance(args)
     M, N, gamma = inst.M, inst.N, inst.gamma
     log("bench: %s, precision %s" % (desc, args.precision))
