@@ -7,8 +7,9 @@
 // into one complex column (x = X[:,2c] + i X[:,2c+1]); the kernel is real, so
 // real and imaginary parts of z belong to the two columns.
 //
-// Single pass (n <= 8192 in float64): one workgroup owns CC complex columns
-// and the whole length-n transform in LDS.  n = n1 n2 (n3) is split
+// Single pass (n <= 8192 in float64, 16384 in float32): persistent
+// workgroups (k_fft2u, k_fft3u), each holding CC complex columns and the
+// whole length-n transform in LDS at a time.  n = n1 n2 (n3) is split
 // Cooley-Tukey style, q = q1 n2 n3 + q2 n3 + q3, k = k1 + n1 k2 + n1 n2 k3;
 // each digit transform runs in registers and LDS only transposes between
 // digits.  The first stage reads X straight from HBM and skips the zero half
@@ -546,7 +547,7 @@ __device__ __forceinline__ GroupView<T> group_view(const GroupCursor<T> &c, int6
     return v;
 }
 
-// two digits: n = N1 N2 (see k_fft2 for the stages)
+// two digits: n = N1 N2 (stage layout as in k_fft2_inner)
 template <typename T, int N1, int N2, int CC, bool EVEN>
 __global__ __launch_bounds__(256) void k_fft2u(const UpdTask<T> *__restrict__ tasks, const int64_t *__restrict__ gbase,
                                                int ntasks, const cplx<T> *__restrict__ tw0, int64_t nmax)
@@ -655,7 +656,7 @@ __global__ __launch_bounds__(256) void k_fft2u(const UpdTask<T> *__restrict__ ta
     }
 }
 
-// three digits: n = N1 N2 N3 (see k_fft3 for the stages)
+// three digits: n = N1 N2 N3 (stage layout as in k_fft3_inner)
 // Y rows: loaded at the top of the group iteration (in flight during
 // stages A-D) when the registers allow it (n <= 4096 in float64), else in
 // stage D after stage C's spectrum reads.
