@@ -65,14 +65,16 @@ enum {
 };
 
 /* Arithmetic of the off-diagonal Toeplitz-block products.  Weights, the
- * tridiagonal solves of the diagonal blocks and the refinement residual are
- * float64 in every mode. */
+ * tridiagonal solves of the diagonal blocks, the dense (small) level
+ * products, the near-corner band of the FFT levels and the refinement
+ * residual are float64 in every mode. */
 enum {
     FRACSOLVE_FP64 = 0,   /* all products in float64                          */
-    FRACSOLVE_FP32 = 1,   /* products in float32, history accumulated in f32  */
-    FRACSOLVE_BF16X3 = 2  /* dense products as three bf16 MFMA products with
-                             fp32 accumulation (hi*hi + hi*lo + lo*hi); FFT
-                             products in float32                              */
+    FRACSOLVE_FP32 = 1,   /* FFT level products in float32, their history
+                             accumulated in float32                           */
+    FRACSOLVE_BF16X3 = 2  /* accepted, and runs as FRACSOLVE_FP32: the
+                             products a split bf16 form would serve are bound
+                             by memory or latency, not by arithmetic          */
 };
 
 typedef struct {

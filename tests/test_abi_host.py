@@ -1,0 +1,138 @@
+"""Host-side checks of the C ABI and of the measurement plumbing (no GPU).
+
+* every function include/fracsolve.h declares is exported by the built
+  library and listed by the binding;
+* argument errors are reported before any device work (E_ARG, with a
+  message), so they are testable on a host without a GPU;
+* the kernel names bench.py uses for the roofline match the dispatch tables
+  of the FFT kernels, and the recorded-traffic lines of profiles/ parse.
+"""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "fracsolve.h")
+KFFT = os.path.join(ROOT, "paper_1710_11593_amd", "csrc", "k_fft.hip")
+
+E_ARG, E_DEVICE = -1, -3
+
+
+def header_functions():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^[A-Za-z_][\w \*]*?\b(fracsolve_\w+)\s*\(", text, re.M)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1710_11593_amd import binding
+    from paper_1710_11593_amd import build as hipbuild
+
+    if not os.path.exists(binding.LIBPATH):
+        hipbuild.build(force=False)
+    return binding.lib()
+
+
+def test_header_declares_the_binding_exports():
+    from paper_1710_11593_amd import binding
+
+    assert header_functions() == sorted(binding.EXPORTS)
+
+
+def test_library_exports_every_declared_function(lib):
+    for name in header_functions():
+        assert hasattr(lib, name), name
+
+
+def create(lib, probs, opts=None):
+    from paper_1710_11593_amd import binding
+
+    arr = (binding.Problem * max(len(probs), 1))()
+    for k, p in enumerate(probs):
+        arr[k] = binding.Problem(*p)
+    o = binding.Options(*(opts or (0, 0, 0, 0, 0, None)))
+    h = ctypes.c_void_p()
+    rc = lib.fracsolve_create(arr, len(probs), ctypes.byref(o), ctypes.byref(h))
+    return rc, h, lib.fracsolve_last_error(None).decode()
+
+
+GOOD = (0.5, 1.0, 0.0, 1.0, 64, 256)
+
+
+@pytest.mark.parametrize("prob, pattern", [
+    ((1.0, 1.0, 0.0, 1.0, 64, 256), "gamma"),
+    ((2.0, 1.0, 0.0, 1.0, 64, 256), "gamma"),
+    ((0.0, 1.0, 0.0, 1.0, 64, 256), "gamma"),
+    ((0.5, 0.0, 0.0, 1.0, 64, 256), "T"),
+    ((0.5, 1.0, 1.0, 1.0, 64, 256), "x1"),
+    ((0.5, 1.0, 0.0, 1.0, 0, 256), "M"),
+    ((0.5, 1.0, 0.0, 1.0, 4097, 256), "M"),
+    ((0.5, 1.0, 0.0, 1.0, 64, 0), "N"),
+])
+def test_invalid_problem_is_rejected_before_device_work(lib, prob, pattern):
+    rc, h, msg = create(lib, [GOOD, prob])
+    assert rc == E_ARG and not h.value
+    assert pattern in msg, msg
+
+
+@pytest.mark.parametrize("opts, pattern", [
+    ((3, 0, 0, 0, 0, None), "precision"),
+    ((1, 9, 0, 0, 0, None), "refine_steps"),
+    ((0, 0, 5, 0, 0, None), "leaf"),
+    ((0, 0, 0, 0, 2, None), "leaf_solver"),
+])
+def test_invalid_options_are_rejected(lib, opts, pattern):
+    rc, h, msg = create(lib, [GOOD], opts)
+    assert rc == E_ARG and not h.value
+    assert pattern in msg, msg
+
+
+def test_empty_batch_and_null_handle(lib):
+    rc, h, msg = create(lib, [])
+    assert rc == E_ARG and "count" in msg
+    lib.fracsolve_destroy(None)  # NULL-safe
+    assert lib.fracsolve_solve(None, None, None, None, None) == E_ARG
+
+
+def test_valid_problem_without_gpu_reports_no_device(lib):
+    torch = pytest.importorskip("torch")
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    rc, h, msg = create(lib, [GOOD])
+    assert rc == E_DEVICE and not h.value, (rc, msg)
+
+
+def dispatch_names():
+    """n -> kernel text of the float64 update dispatch (FS_U2 / FS_U3 rows)."""
+    text = open(KFFT).read()
+    body = text[text.index("if constexpr (sizeof(T) == 8) {", text.index("if constexpr (MODE == MODE_UPDATE)")):]
+    body = body[:body.index("} else {")]
+    out = {}
+    for m in re.finditer(r"FS_U2\((\d+), (\d+), (\d+)\)", body):
+        n1, n2, cc = map(int, m.groups())
+        out[n1 * n2] = "k_fft2u<double, %d, %d, %d, true>" % (n1, n2, cc)
+    for m in re.finditer(r"FS_U3\((\d+), (\d+), (\d+), (\d+), (\d+)\)", body):
+        n1, n2, n3, cc, nt = map(int, m.groups())
+        out[n1 * n2 * n3] = "k_fft3u<double, %d, %d, %d, %d, %d, true>" % (n1, n2, n3, cc, nt)
+    return out
+
+
+def test_bench_kernel_names_match_the_dispatch():
+    import bench
+
+    assert bench.FFT64_NAMES == dispatch_names()
+
+
+def test_recorded_traffic_lines_parse():
+    path = os.path.join(ROOT, "profiles", "fft_level_traffic_M4096.md")
+    lines = [l for l in open(path) if l.startswith("traffic:")]
+    assert lines
+    names = set(dispatch_names().values())
+    for l in lines:
+        m = re.match(r'traffic: kernel="fs::(.*)" s=(\d+) bytes_per_launch=(\d+) k_fft_sha=(\w{16})$', l.strip())
+        assert m, l
+        assert m.group(1) in names
+        s, b = int(m.group(2)), int(m.group(3))
+        assert 0.5 * 24 * s * 4096 <= b <= 2.0 * 24 * s * 4096  # within 2x of the algorithmic bytes
