@@ -227,6 +227,17 @@ def test_mixed_precision_refined(torch_cuda, orc, precision, gamma, M, N):
     assert e1 <= e0
 
 
+@pytest.mark.parametrize("gamma", [0.02, 0.98, 1.02, 1.98])
+def test_gamma_near_the_regime_ends(torch_cuda, orc, gamma):
+    """Orders close to 0, 1 and 2 (weights that nearly vanish or nearly
+    cancel), several levels and a ragged tail, against the oracle."""
+    M, N = 100, 600
+    f, u0, phi = rand_case(gamma, M, N, seed=7)
+    u = gpu_solve(torch_cuda, gamma, M, N, f, u0, phi)
+    ref = orc.solve(gamma, 1.0, 0.0, 1.0, M, N, f, u0=u0, phi=phi)
+    assert_parity64(u, ref, gamma, M, N, f, u0, phi)
+
+
 def test_batched_parity(torch_cuda, orc):
     from paper_1710_11593_amd import binding
 
