@@ -22,7 +22,10 @@
  *     b_{-1} = b_{-2} = 0,
  *     a_m = c (b_{m-2} - 2 b_{m-1} + b_m),  rho_n = c (b_{n-2} - b_{n-1}),
  *     psi_n = c tau b_{n-1},  F^n = f(x_i, t_{n-1/2});
- *     the spatial term is taken at t_n, as in e16/e17.
+ *     the spatial term is taken at t_n, as in e16/e17.  That timing is a
+ *     reading (the paper prints no diffusion-wave scheme with a second-order
+ *     space operator): parity unpinned beyond the observed convergence rate;
+ *     the time weights themselves are pinned by Table 7.
  *
  *   Both regimes give, for n = 1..N, with K = h^-2 tridiag(-1,2,-1):
  *     (a_0 I + K) U^n + sum_{j=1}^{n-1} a_{n-j} U^j = F^n - rho_n u^0 + psi_n phi
