@@ -15,6 +15,10 @@ Parity status of each function (what pins it, in tests/test_oracle_*.py):
   apply     -- dense brute force
   adjoint   -- dot test, central differences in f and in gamma
   mode      -- closed form on linear-in-time data, dense brute force
+  gmres     -- finite termination at the dense solve, least-squares estimates
+               equal to recomputed residuals, the one-step minimal-residual
+               closed form, exact convergence in N steps with the
+               block-diagonal preconditioner, agreement with solve
 """
 from __future__ import annotations
 
@@ -61,6 +65,9 @@ def _load():
     lib.oracle_adjoint.argtypes = [d, d, d, d, i64, i64, _dp, _dp, _dp, _dp, _dp, _dp, i32]
     lib.oracle_mode.restype = i32
     lib.oracle_mode.argtypes = [d, d, i64, d, _dp, d, d, _dp]
+    lib.oracle_gmres.restype = i32
+    lib.oracle_gmres.argtypes = [d, d, d, d, i64, i64, _dp, _dp, _dp, _dp, i32, i32, d, i32, i32,
+                                 ctypes.POINTER(i32), _dp, _dp, i32]
     _lib = lib
     return lib
 
@@ -149,6 +156,30 @@ def mode(gamma, T, N, lam, g, v0=0.0, phihat=0.0):
     v = np.zeros(N)
     _check(lib.oracle_mode(gamma, T, N, lam, _ptr(g), v0, phihat, _ptr(v)), "mode")
     return v
+
+
+def gmres(gamma, T, x0, x1, M, N, f, u0=None, phi=None, restart=30, maxit=1000, rtol=1e-10, precond=0,
+          guess=None, nthreads=0):
+    """Restarted GMRES(m) on the same system (the paper's iterative method).
+
+    Returns (u [N][M], info) with info = {"iters", "cycles", "converged",
+    "relres" (recomputed), "hist" (least-squares residuals / ||b||, length
+    iters + 1)}.
+    """
+    lib = _load()
+    f = _f64(f, (N, M))
+    u0 = _f64(u0, (M,))
+    phi = _f64(phi, (M,))
+    u = np.zeros((N, M)) if guess is None else np.array(_f64(guess, (N, M)))
+    out = (ctypes.c_int * 3)()
+    rel = ctypes.c_double(0.0)
+    hist = np.zeros(maxit + 1)
+    rc = lib.oracle_gmres(gamma, T, x0, x1, M, N, _ptr(f), _ptr(u0), _ptr(phi), _ptr(u), restart, maxit, rtol,
+                          precond, 0 if guess is None else 1, out, ctypes.byref(rel), _ptr(hist), nthreads)
+    _check(rc, "gmres")
+    it = int(out[0])
+    return u, {"iters": it, "cycles": int(out[1]), "converged": bool(out[2]), "relres": float(rel.value),
+               "hist": hist[: it + 1].copy()}
 
 
 def grid(x0, x1, M, T, N):

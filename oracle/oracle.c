@@ -31,6 +31,9 @@
  *     (a_0 I + K) U^n + sum_{j=1}^{n-1} a_{n-j} U^j = F^n - rho_n u^0 + psi_n phi
  *   and this file solves it by plain forward time stepping (the paper's
  *   "direct method" of section 3, O(M N^2) work), one Thomas solve per step.
+ *   It also solves it by restarted GMRES(m) (the paper's iterative method
+ *   for Scheme 4, section 3.1), with the operator products evaluated from
+ *   their definition.
  *
  * Layout: time-major [N][M] row-major, entry (n-1)*M + (i-1) is (x_i, t_n),
  * h = (x1-x0)/(M+1), x_i = x0 + i h, tau = T/N.
@@ -309,6 +312,25 @@ int oracle_solve(double gamma, double T, double x0, double x1, int64_t M, int64_
     return ORACLE_OK;
 }
 
+/* y = A u for the Toeplitz column a and e = 1/h^2 (the definition, row by
+ * row: the tridiagonal block on U^n plus the history sum). */
+static void apply_rows(int64_t M, int64_t N, const double *a, double e, const double *u, double *y)
+{
+    for (int64_t n = 1; n <= N; ++n) {
+        const double *un = u + (size_t)(n - 1) * (size_t)M;
+        double *yn = y + (size_t)(n - 1) * (size_t)M;
+        #pragma omp parallel for schedule(static)
+        for (int64_t i = 0; i < M; ++i) {
+            double left = (i > 0) ? un[i - 1] : 0.0;
+            double right = (i + 1 < M) ? un[i + 1] : 0.0;
+            double s = (a[0] + 2.0 * e) * un[i] - e * (left + right);
+            for (int64_t j = 1; j < n; ++j)
+                s += a[n - j] * u[(size_t)(j - 1) * (size_t)M + (size_t)i];
+            yn[i] = s;
+        }
+    }
+}
+
 /*
  * Operator apply y = A u of the whole block lower-triangular system:
  *   y^n = (a_0 I + K) U^n + sum_{j=1}^{n-1} a_{n-j} U^j.
@@ -324,19 +346,7 @@ int oracle_apply(double gamma, double T, double x0, double x1, int64_t M, int64_
     double *a = (double *)malloc(sizeof(double) * (size_t)N);
     if (!a) return ORACLE_ENOMEM;
     oracle_weights(gamma, T, N, NULL, a, NULL, NULL, NULL, NULL, NULL, NULL);
-    for (int64_t n = 1; n <= N; ++n) {
-        const double *un = u + (size_t)(n - 1) * (size_t)M;
-        double *yn = y + (size_t)(n - 1) * (size_t)M;
-        #pragma omp parallel for schedule(static)
-        for (int64_t i = 0; i < M; ++i) {
-            double left = (i > 0) ? un[i - 1] : 0.0;
-            double right = (i + 1 < M) ? un[i + 1] : 0.0;
-            double s = (a[0] + 2.0 * e) * un[i] - e * (left + right);
-            for (int64_t j = 1; j < n; ++j)
-                s += a[n - j] * u[(size_t)(j - 1) * (size_t)M + (size_t)i];
-            yn[i] = s;
-        }
-    }
+    apply_rows(M, N, a, e, u, y);
     free(a);
     return ORACLE_OK;
 }
@@ -434,4 +444,173 @@ int oracle_mode(double gamma, double T, int64_t N, double lam, const double *g,
     }
     free(a); free(rho); free(psi);
     return ORACLE_OK;
+}
+
+static double vdot(int64_t n, const double *x, const double *y)
+{
+    double s = 0.0;
+    for (int64_t i = 0; i < n; ++i) s += x[i] * y[i];
+    return s;
+}
+
+/*
+ * Restarted GMRES(m) for the same block system: the fast iterative method
+ * the paper uses for Scheme 4 (section 3.1): an Arnoldi process with
+ * modified Gram-Schmidt builds an orthonormal basis V of the Krylov space of
+ * the residual, and the update V y minimises || beta e_1 - H y ||_2 over the
+ * (j+1) x j Hessenberg matrix H; the method restarts after m steps.  The
+ * operator products here are the plain O(M N^2) definition, not the
+ * circulant-embedding FFT the paper uses to make them fast (the same
+ * products, evaluated slowly).
+ *
+ * Readings where the paper is silent:
+ *   - the least-squares problem is solved by Givens rotations applied as the
+ *     columns of H arrive, so |g_{j+1}| is the residual norm of the current
+ *     iterate after every step; the cycle stops early once it is at most
+ *     rtol ||b||, and the method stops when the residual recomputed from
+ *     its definition after a cycle is at most rtol ||b||;
+ *   - precond = 1 applies the block-diagonal matrix P = diag(a_0 I + K) on
+ *     the right (GMRES on A P^-1; the update is P^-1 V y).  The paper uses
+ *     no preconditioner (precond = 0).
+ *
+ *   f, u0, phi   as in oracle_solve; b = F - rho_n u0 + psi_n phi
+ *   u [N][M]     in: initial guess when use_guess != 0; out: the iterate
+ *   restart      m >= 1;  maxit: total Arnoldi steps >= 0
+ *   hist         NULL or maxit + 1 doubles: hist[0] = ||r_0|| / ||b||,
+ *                hist[k] = the least-squares residual after step k, / ||b||
+ *   out[0] = steps taken, out[1] = cycles, out[2] = 1 if converged;
+ *   *relres = ||b - A u|| / ||b|| recomputed at the end (0 when b = 0).
+ */
+int oracle_gmres(double gamma, double T, double x0, double x1, int64_t M, int64_t N,
+                 const double *f, const double *u0, const double *phi, double *u,
+                 int restart, int maxit, double rtol, int precond, int use_guess,
+                 int *out, double *relres, double *hist, int nthreads)
+{
+    if (regime_of(gamma) < 0 || !(T > 0.0) || !(x1 > x0) || M < 1 || N < 1 || !f || !u || !out || !relres)
+        return ORACLE_EARG;
+    if (restart < 1 || maxit < 0 || !(rtol >= 0.0) || precond < 0 || precond > 1) return ORACLE_EARG;
+    set_threads(nthreads);
+    const int64_t n = M * N;
+    const int m = restart;
+    double h = (x1 - x0) / (double)(M + 1);
+    double e = 1.0 / (h * h);
+    double *a = (double *)malloc(sizeof(double) * (size_t)N);
+    double *rho = (double *)malloc(sizeof(double) * (size_t)N);
+    double *psi = (double *)malloc(sizeof(double) * (size_t)N);
+    double *cp = (double *)malloc(sizeof(double) * (size_t)M);
+    double *inv = (double *)malloc(sizeof(double) * (size_t)M);
+    double *b = (double *)malloc(sizeof(double) * (size_t)n);
+    double *w = (double *)malloc(sizeof(double) * (size_t)n);
+    double *z = (double *)malloc(sizeof(double) * (size_t)n);
+    double *V = (double *)malloc(sizeof(double) * (size_t)n * (size_t)(m + 1));
+    double *H = (double *)calloc((size_t)(m + 1) * (size_t)m, sizeof(double));
+    double *cs = (double *)malloc(sizeof(double) * (size_t)m);
+    double *sn = (double *)malloc(sizeof(double) * (size_t)m);
+    double *g = (double *)malloc(sizeof(double) * (size_t)(m + 1));
+    double *y = (double *)malloc(sizeof(double) * (size_t)m);
+    int rc = ORACLE_OK;
+    if (!a || !rho || !psi || !cp || !inv || !b || !w || !z || !V || !H || !cs || !sn || !g || !y) {
+        rc = ORACLE_ENOMEM;
+        goto done;
+    }
+    oracle_weights(gamma, T, N, NULL, a, rho, psi, NULL, NULL, NULL, NULL);
+    thomas_factor(M, a[0] + 2.0 * e, -e, cp, inv);
+#define HH(i, j) H[(size_t)(i) * (size_t)m + (size_t)(j)]
+    for (int64_t r = 0; r < N; ++r)
+        for (int64_t i = 0; i < M; ++i) {
+            double s = f[r * M + i];
+            if (u0) s -= rho[r] * u0[i];
+            if (phi) s += psi[r] * phi[i];
+            b[r * M + i] = s;
+        }
+    if (!use_guess)
+        for (int64_t i = 0; i < n; ++i) u[i] = 0.0;
+    const double bnorm = sqrt(vdot(n, b, b));
+    out[0] = 0;
+    out[1] = 0;
+    out[2] = 0;
+    if (bnorm == 0.0) {
+        /* the solution of A u = 0 */
+        for (int64_t i = 0; i < n; ++i) u[i] = 0.0;
+        out[2] = 1;
+        *relres = 0.0;
+        if (hist) hist[0] = 0.0;
+        goto done;
+    }
+    /* r = b - A u */
+    apply_rows(M, N, a, e, u, w);
+    for (int64_t i = 0; i < n; ++i) w[i] = b[i] - w[i];
+    double beta = sqrt(vdot(n, w, w));
+    if (hist) hist[0] = beta / bnorm;
+    int it = 0;
+    while (beta > rtol * bnorm && it < maxit) {
+        out[1]++;
+        for (int64_t i = 0; i < n; ++i) V[i] = w[i] / beta;
+        for (int i = 0; i <= m; ++i) g[i] = 0.0;
+        g[0] = beta;
+        int k = 0;
+        for (int j = 0; j < m && it < maxit; ++j) {
+            double *vj = V + (size_t)j * (size_t)n;
+            /* w = A P^-1 v_j */
+            for (int64_t i = 0; i < n; ++i) z[i] = vj[i];
+            if (precond)
+                for (int64_t r = 0; r < N; ++r) thomas_solve(M, -e, cp, inv, z + r * M);
+            apply_rows(M, N, a, e, z, w);
+            /* modified Gram-Schmidt against v_0 .. v_j */
+            for (int i = 0; i <= j; ++i) {
+                const double *vi = V + (size_t)i * (size_t)n;
+                double hij = vdot(n, w, vi);
+                HH(i, j) = hij;
+                for (int64_t q = 0; q < n; ++q) w[q] -= hij * vi[q];
+            }
+            double hn = sqrt(vdot(n, w, w));
+            HH(j + 1, j) = hn;
+            /* earlier rotations on column j, then the one that zeroes H[j+1][j] */
+            for (int i = 0; i < j; ++i) {
+                double t0 = cs[i] * HH(i, j) + sn[i] * HH(i + 1, j);
+                double t1 = -sn[i] * HH(i, j) + cs[i] * HH(i + 1, j);
+                HH(i, j) = t0;
+                HH(i + 1, j) = t1;
+            }
+            double rr = hypot(HH(j, j), hn);
+            cs[j] = HH(j, j) / rr;
+            sn[j] = hn / rr;
+            HH(j, j) = rr;
+            HH(j + 1, j) = 0.0;
+            g[j + 1] = -sn[j] * g[j];
+            g[j] = cs[j] * g[j];
+            ++it;
+            k = j + 1;
+            if (hist) hist[it] = fabs(g[j + 1]) / bnorm;
+            if (hn == 0.0 || fabs(g[j + 1]) <= rtol * bnorm) break;
+            double *vn = V + (size_t)(j + 1) * (size_t)n;
+            for (int64_t q = 0; q < n; ++q) vn[q] = w[q] / hn;
+        }
+        /* y = R^-1 g (back substitution), u += P^-1 V y */
+        for (int i = k - 1; i >= 0; --i) {
+            double s = g[i];
+            for (int q = i + 1; q < k; ++q) s -= HH(i, q) * y[q];
+            y[i] = s / HH(i, i);
+        }
+        for (int64_t q = 0; q < n; ++q) z[q] = 0.0;
+        for (int i = 0; i < k; ++i) {
+            const double *vi = V + (size_t)i * (size_t)n;
+            for (int64_t q = 0; q < n; ++q) z[q] += y[i] * vi[q];
+        }
+        if (precond)
+            for (int64_t r = 0; r < N; ++r) thomas_solve(M, -e, cp, inv, z + r * M);
+        for (int64_t q = 0; q < n; ++q) u[q] += z[q];
+        /* residual from its definition */
+        apply_rows(M, N, a, e, u, w);
+        for (int64_t i = 0; i < n; ++i) w[i] = b[i] - w[i];
+        beta = sqrt(vdot(n, w, w));
+    }
+#undef HH
+    out[0] = it;
+    out[2] = beta <= rtol * bnorm;
+    *relres = beta / bnorm;
+done:
+    free(a); free(rho); free(psi); free(cp); free(inv); free(b); free(w); free(z);
+    free(V); free(H); free(cs); free(sn); free(g); free(y);
+    return rc;
 }
