@@ -160,6 +160,56 @@ int fracsolve_adjoint(fracsolve_t h, const double *const *g, const double *const
                       double *const *dL_df, double *dL_dgamma);
 
 /*
+ * Restarted GMRES(m) on the same system: the iterative method the paper uses
+ * for Scheme 4 (section 3.1), a second solver next to fracsolve_solve.  Each
+ * step applies the operator of fracsolve_apply (tridiagonal block plus the
+ * Toeplitz history, the latter as circulant-embedded FFT products above the
+ * crossover and dense products below it), orthogonalises against the basis
+ * and updates the Givens-rotated Hessenberg matrix; after m steps (or
+ * earlier, once the least-squares residual is at most rtol ||b||_2) the
+ * iterate is updated and the residual recomputed from its definition.  The
+ * method stops when that residual is at most rtol ||b||_2 or max_iters steps
+ * were taken.  b = F - rho_n u0 + psi_n phi is the right-hand side of
+ * fracsolve_solve; the arithmetic is float64 whatever the handle's precision.
+ */
+typedef struct {
+    int32_t restart;    /* m, Krylov steps per cycle, 1..512                   */
+    int32_t max_iters;  /* total Krylov steps over all cycles, >= 0            */
+    double rtol;        /* relative residual target, finite and >= 0           */
+    int32_t precond;    /* 0: none (the paper's method); 1: right block-
+                           diagonal preconditioner diag(a_0 I + K), i.e. the
+                           tridiagonal solve of every time step on its own     */
+    int32_t use_guess;  /* 0: start from zero; 1: start from the contents of u */
+} fracsolve_gmres_options;
+
+typedef struct {
+    int32_t iterations; /* Krylov steps taken                                  */
+    int32_t cycles;     /* cycles started (restarts + 1; 0 if none was needed) */
+    int32_t converged;  /* 1 if the recomputed residual reached rtol           */
+    int32_t reserved;
+    double relres;      /* ||b - A u||_2 / ||b||_2 recomputed at the end       */
+    double relres_est;  /* the last least-squares estimate of it               */
+} fracsolve_gmres_info;
+
+/*
+ * Solve every instance (one after another) by GMRES(m): u[k] <- iterate for
+ * source f[k] and initial data u0[k], phi[k] (as in fracsolve_solve; NULL
+ * entries mean zero).  u[k] may equal f[k].  opts NULL = {30, 1000, 1e-10, 0,
+ * 0}.  info (NULL or `count` records, host) receives the outcome per
+ * instance; hist (NULL or hist_cap doubles, host) receives instance 0's
+ * residual history divided by ||b||_2: hist[0] for the start, hist[j] for the
+ * least-squares residual after step j.  The call synchronises the stream
+ * (the Hessenberg matrix lives on the host) and holds (m + 1) M N doubles of
+ * basis per instance in the handle after the first call.
+ * Errors: E_ARG (bad option or field; nothing enqueued), E_NOMEM, E_DEVICE,
+ * E_NUMERIC (non-finite basis norm).
+ */
+int fracsolve_gmres(fracsolve_t h, const double *const *f, const double *const *u0,
+                    const double *const *phi, double *const *u,
+                    const fracsolve_gmres_options *opts, fracsolve_gmres_info *info,
+                    double *hist, int32_t hist_cap);
+
+/*
  * Timing and plan details of the last call, for reporting.  Fields are -1
  * when not measured.  Filled only if timing was enabled with
  * fracsolve_set_timing(h, 1) before the call (it adds events and a

@@ -41,10 +41,20 @@ class KernelStat(ctypes.Structure):
                 ("tasks", ctypes.c_int32), ("ms", ctypes.c_double), ("bytes", ctypes.c_double)]
 
 
+class GmresOptions(ctypes.Structure):
+    _fields_ = [("restart", ctypes.c_int32), ("max_iters", ctypes.c_int32), ("rtol", ctypes.c_double),
+                ("precond", ctypes.c_int32), ("use_guess", ctypes.c_int32)]
+
+
+class GmresInfo(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int32), ("cycles", ctypes.c_int32), ("converged", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("relres", ctypes.c_double), ("relres_est", ctypes.c_double)]
+
+
 KIND_NAMES = {0: "leaf", 1: "dense_f64", 2: "dense_f32", 3: "fft_f64", 4: "fft_f32", 5: "fft_corner"}
 
 EXPORTS = ["fracsolve_create", "fracsolve_weights", "fracsolve_solve", "fracsolve_apply", "fracsolve_adjoint",
-           "fracsolve_set_timing", "fracsolve_get_stats", "fracsolve_kernel_stats", "fracsolve_destroy",
+           "fracsolve_gmres", "fracsolve_set_timing", "fracsolve_get_stats", "fracsolve_kernel_stats", "fracsolve_destroy",
            "fracsolve_last_error"]
 
 _lib = None
@@ -77,6 +87,9 @@ def lib():
     L.fracsolve_apply.argtypes = [ctypes.c_void_p, vpp, vpp]
     L.fracsolve_adjoint.restype = ctypes.c_int
     L.fracsolve_adjoint.argtypes = [ctypes.c_void_p, vpp, vpp, vpp, vpp, vpp, dp]
+    L.fracsolve_gmres.restype = ctypes.c_int
+    L.fracsolve_gmres.argtypes = [ctypes.c_void_p, vpp, vpp, vpp, vpp, ctypes.POINTER(GmresOptions),
+                                  ctypes.POINTER(GmresInfo), dp, ctypes.c_int32]
     L.fracsolve_set_timing.restype = ctypes.c_int
     L.fracsolve_set_timing.argtypes = [ctypes.c_void_p, ctypes.c_int32]
     L.fracsolve_get_stats.restype = ctypes.c_int
@@ -194,6 +207,34 @@ class Solver:
             ctypes.cast(dg, ctypes.POINTER(ctypes.c_double)) if want_gamma else None)
         self._check(rc)
         return out, (list(dg) if want_gamma else None)
+
+    def gmres(self, f, u0=None, phi=None, out=None, restart=30, max_iters=1000, rtol=1e-10, precond=0,
+              use_guess=False, hist_cap=0):
+        """Restarted GMRES(m) on every instance (fracsolve_gmres).
+
+        Returns (list of iterates, list of info dicts, residual history of
+        instance 0 as a numpy array of length min(hist_cap, iterations + 1)).
+        """
+        import numpy as np
+        import torch
+
+        f = list(f)
+        if out is None:
+            out = [torch.empty_like(x) for x in f]
+        opts = GmresOptions(int(restart), int(max_iters), float(rtol), int(precond), 1 if use_guess else 0)
+        info = (GmresInfo * len(f))()
+        hist = np.zeros(max(int(hist_cap), 1))
+        dp = ctypes.POINTER(ctypes.c_double)
+        rc = self._lib.fracsolve_gmres(
+            self.h, _ptrs(f, name="f"), _ptrs(u0, required=False, name="u0") if u0 is not None else None,
+            _ptrs(phi, required=False, name="phi") if phi is not None else None, _ptrs(out, name="u"),
+            ctypes.byref(opts), info, hist.ctypes.data_as(dp) if hist_cap > 0 else None, int(hist_cap))
+        self._check(rc)
+        infos = [{k: getattr(info[i], k) for k, _ in GmresInfo._fields_ if k != "reserved"} for i in range(len(f))]
+        for d in infos:
+            d["converged"] = bool(d["converged"])
+        nh = min(int(hist_cap), infos[0]["iterations"] + 1) if hist_cap > 0 else 0
+        return out, infos, hist[:nh].copy()
 
     def set_timing(self, on=True):
         self._check(self._lib.fracsolve_set_timing(self.h, 1 if on else 0))

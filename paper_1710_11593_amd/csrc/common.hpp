@@ -217,6 +217,17 @@ hipError_t launch_to_f32(hipStream_t st, const double *x, float *y, int64_t n);
 hipError_t launch_zero(hipStream_t st, void *p, size_t bytes);
 hipError_t launch_dot_partial(hipStream_t st, const double *x, const double *y, int64_t n, double *partial,
                               int nblocks);
+// Krylov-basis products of GMRES: out[v] = <V_v, w> for v < nv (device
+// out, partial holds nv * nb doubles); y = beta y + sum_v c_v V_v with the
+// coefficients c[0..nv) on the host (passed by value, LINCOMB_MAX per launch).
+constexpr int LINCOMB_MAX = 32;
+struct LinCoef {
+    double c[LINCOMB_MAX];
+};
+hipError_t launch_multidot(hipStream_t st, const double *V, int64_t ldv, int nv, const double *w, int64_t n,
+                           double *partial, int nb, double *out);
+hipError_t launch_lincomb(hipStream_t st, double *y, double beta, const double *V, int64_t ldv, int nv,
+                          const double *c, int64_t n);
 hipError_t launch_gamma_rhs_terms(hipStream_t st, const double *lam, const double *u0, const double *phi,
                                   const double *drho, const double *dpsi, int64_t M, int64_t N, double *partial,
                                   int nblocks);

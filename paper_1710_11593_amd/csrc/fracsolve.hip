@@ -48,6 +48,8 @@ struct Inst {
     double *V = nullptr;      // operator apply output
     float *hist32 = nullptr;  // float32 history accumulator
     float *x32 = nullptr;     // float32 shadow of solved rows
+    double *kry = nullptr;    // GMRES: Krylov basis, kry_cap vectors of M N
+    int kry_cap = 0;
 };
 
 double digamma_host(double x)
@@ -129,6 +131,11 @@ struct fracsolve_ctx {
     // batches: every instance uses the leaf configuration of the widest one,
     // so that one launch per step covers all leaves (0: single instance)
     int64_t batch_M = 0;
+    // GMRES: zero history weights (block-diagonal solves through the leaf
+    // kernels), multi-dot partials and results
+    double *zeros = nullptr;
+    double *gpart = nullptr, *gdots = nullptr;
+    int gcap = 0;
 };
 
 namespace {
@@ -887,6 +894,200 @@ int solve_all(fracsolve_ctx *h, const double *const *f, const double *const *u0,
     return restore();
 }
 
+// ---- restarted GMRES(m) on the same system (section 3.1) ----
+
+void dfree(fracsolve_ctx *h, double *p)
+{
+    if (!p) return;
+    hipFree(p);
+    h->allocs.erase(std::remove(h->allocs.begin(), h->allocs.end(), p), h->allocs.end());
+}
+
+// z <- diag(a_0 I + K)^-1 z, every time row on its own: the leaf kernels with
+// zero history weights, all blocks of rows in one launch.
+int block_diag_solve(fracsolve_ctx *h, const Inst &in, double *z)
+{
+    const int L = h->L;
+    std::vector<LeafTask> v;
+    for (int64_t lo = 0; lo < in.N; lo += L) {
+        LeafTask t{};
+        t.u = z;
+        t.a = h->zeros;
+        t.fac = in.fac;
+        t.M = in.M;
+        t.lo = lo;
+        t.nrows = (int)std::min<int64_t>(L, in.N - lo);
+        t.flags = (in.scan && (in.M % in.lc.pt) == 0 && ((uintptr_t)z & 15) == 0) ? LEAF_VEC : 0;
+        v.push_back(t);
+    }
+    DescBuilder db{h, {}};
+    const size_t off = db.add(v.data(), v.size() * sizeof(LeafTask));
+    LeafCfg lc = in.lc;
+    lc.S = ilog2i(2 * lc.nt);
+    lc.vec = (v[0].flags & LEAF_VEC) ? 1 : 0;
+    Op op{in.scan ? OP_LEAF_SCAN : OP_LEAF, off, (int)v.size(), 0, 0, lc, false};
+    op.bytes = 16.0 * (double)in.M * (double)in.N;
+    int rc = desc_upload(h, db);
+    if (rc) return rc;
+    return run_ops_any(h, std::vector<Op>{op});
+}
+
+int dev_norm2(fracsolve_ctx *h, const double *x, int64_t n, double *out)
+{
+    HIPCHK(h, launch_dot_partial(h->st, x, x, n, h->partial, kRedBlocks));
+    h->kernels++;
+    double s = 0.0;
+    int rc = finish_sum(h, kRedBlocks, &s);
+    *out = std::sqrt(s);
+    return rc;
+}
+
+constexpr int kDotBlocks = 512;
+
+// out[i] = <V_i, w>, i < nv, on the host
+int basis_dots(fracsolve_ctx *h, const double *V, int64_t n, int nv, const double *w, double *out)
+{
+    const int nb = (int)std::min<int64_t>(kDotBlocks, std::max<int64_t>(1, (n + 1023) / 1024));
+    HIPCHK(h, launch_multidot(h->st, V, n, nv, w, n, h->gpart, nb, h->gdots));
+    h->kernels += 2;
+    HIPCHK(h, hipMemcpyAsync(out, h->gdots, sizeof(double) * (size_t)nv, hipMemcpyDeviceToHost, h->st));
+    HIPCHK(h, hipStreamSynchronize(h->st));
+    return FRACSOLVE_OK;
+}
+
+int lincomb(fracsolve_ctx *h, double *y, double beta, const double *V, int64_t n, int nv, const double *c)
+{
+    HIPCHK(h, launch_lincomb(h->st, y, beta, V, n, nv, c, n));
+    h->kernels += (nv + LINCOMB_MAX - 1) / LINCOMB_MAX;
+    return FRACSOLVE_OK;
+}
+
+struct GmresResult {
+    int iters = 0, cycles = 0, converged = 0;
+    double relres = 0.0, est = 0.0;
+};
+
+// One instance.  Arnoldi with classical Gram-Schmidt applied twice (two
+// multi-dot / multi-update passes per step instead of the j sequential dot
+// products of modified Gram-Schmidt), Givens rotations on the Hessenberg
+// column as it arrives, restart after m steps; the control flow (early stop
+// on the least-squares residual, recomputed residual after every cycle)
+// matches the oracle's.
+int gmres_one(fracsolve_ctx *h, int k, const double *f, const double *u0, const double *phi, double *u,
+              const fracsolve_gmres_options &o, GmresResult &res, double *hist, int hist_cap)
+{
+    Inst &in = h->inst[k];
+    const int64_t n = in.M * in.N;
+    const int m = o.restart;
+    int rc;
+    if ((rc = ensure(h, &in.R, n)) || (rc = ensure(h, &in.W, n)) || (rc = ensure(h, &in.V, n))) return rc;
+    if (in.kry_cap < m + 1) {
+        dfree(h, in.kry);
+        in.kry = nullptr;
+        in.kry_cap = 0;
+        if ((rc = dalloc(h, &in.kry, (size_t)(m + 1) * (size_t)n))) return rc;
+        in.kry_cap = m + 1;
+    }
+    double *b = in.R, *w = in.W, *z = in.V, *B = in.kry;
+    const double *ph = (in.regime == 1) ? phi : nullptr;
+    HIPCHK(h, launch_rhs(h->st, f, u0, ph, in.rho, in.psi, b, in.M, in.N));
+    h->kernels++;
+    double bnorm = 0.0;
+    if ((rc = dev_norm2(h, b, n, &bnorm))) return rc;
+    if (!o.use_guess || bnorm == 0.0) {
+        HIPCHK(h, launch_zero(h->st, u, sizeof(double) * (size_t)n));
+        h->kernels++;
+    }
+    auto put_hist = [&](int i, double v) {
+        if (hist && i < hist_cap) hist[i] = v;
+    };
+    if (bnorm == 0.0) {
+        res.converged = 1;
+        put_hist(0, 0.0);
+        return FRACSOLVE_OK;
+    }
+    // w = b - A u
+    auto residual = [&](double *beta) -> int {
+        int r = apply_op(h, k, u, w, false, ColPerm{0, 0});
+        if (r) return r;
+        HIPCHK(h, launch_sub(h->st, w, b, w, n));
+        h->kernels++;
+        return dev_norm2(h, w, n, beta);
+    };
+    double beta = 0.0;
+    if ((rc = residual(&beta))) return rc;
+    put_hist(0, beta / bnorm);
+    res.est = beta / bnorm;
+    std::vector<double> H((size_t)(m + 1) * m, 0.0), cs(m), sn(m), g(m + 1), y(m), c1(m + 1), c2(m + 1);
+    auto HH = [&](int i, int j) -> double & { return H[(size_t)i * m + j]; };
+    int it = 0;
+    while (beta > o.rtol * bnorm && it < o.max_iters) {
+        res.cycles++;
+        const double sc0 = 1.0 / beta;
+        if ((rc = lincomb(h, B, 0.0, w, n, 1, &sc0))) return rc;
+        std::fill(g.begin(), g.end(), 0.0);
+        g[0] = beta;
+        int kk = 0;
+        for (int j = 0; j < m && it < o.max_iters; ++j) {
+            const double *vj = B + (int64_t)j * n;
+            const double *x = vj;
+            if (o.precond) {
+                HIPCHK(h, hipMemcpyAsync(z, vj, sizeof(double) * (size_t)n, hipMemcpyDeviceToDevice, h->st));
+                if ((rc = block_diag_solve(h, in, z))) return rc;
+                x = z;
+            }
+            if ((rc = apply_op(h, k, x, w, false, ColPerm{0, 0}))) return rc;
+            // w -= V h twice (classical Gram-Schmidt with reorthogonalisation)
+            if ((rc = basis_dots(h, B, n, j + 1, w, c1.data()))) return rc;
+            for (int i = 0; i <= j; ++i) c2[i] = -c1[i];
+            if ((rc = lincomb(h, w, 1.0, B, n, j + 1, c2.data()))) return rc;
+            for (int i = 0; i <= j; ++i) HH(i, j) = c1[i];
+            if ((rc = basis_dots(h, B, n, j + 1, w, c1.data()))) return rc;
+            for (int i = 0; i <= j; ++i) c2[i] = -c1[i];
+            if ((rc = lincomb(h, w, 1.0, B, n, j + 1, c2.data()))) return rc;
+            for (int i = 0; i <= j; ++i) HH(i, j) += c1[i];
+            double hn = 0.0;
+            if ((rc = dev_norm2(h, w, n, &hn))) return rc;
+            if (!std::isfinite(hn)) return fail(h, FRACSOLVE_E_NUMERIC, "GMRES: non-finite basis norm at step %d", it);
+            // previous rotations on column j, then the one that removes hn
+            for (int i = 0; i < j; ++i) {
+                const double t0 = cs[i] * HH(i, j) + sn[i] * HH(i + 1, j);
+                const double t1 = -sn[i] * HH(i, j) + cs[i] * HH(i + 1, j);
+                HH(i, j) = t0;
+                HH(i + 1, j) = t1;
+            }
+            const double rr = std::hypot(HH(j, j), hn);
+            cs[j] = HH(j, j) / rr;
+            sn[j] = hn / rr;
+            HH(j, j) = rr;
+            g[j + 1] = -sn[j] * g[j];
+            g[j] = cs[j] * g[j];
+            ++it;
+            kk = j + 1;
+            res.est = std::fabs(g[j + 1]) / bnorm;
+            put_hist(it, res.est);
+            if (hn == 0.0 || std::fabs(g[j + 1]) <= o.rtol * bnorm) break;
+            const double sc = 1.0 / hn;
+            if ((rc = lincomb(h, B + (int64_t)(j + 1) * n, 0.0, w, n, 1, &sc))) return rc;
+        }
+        // u += P^-1 V y with R y = g
+        for (int i = kk - 1; i >= 0; --i) {
+            double s = g[i];
+            for (int q = i + 1; q < kk; ++q) s -= HH(i, q) * y[q];
+            y[i] = s / HH(i, i);
+        }
+        if ((rc = lincomb(h, z, 0.0, B, n, kk, y.data()))) return rc;
+        if (o.precond && (rc = block_diag_solve(h, in, z))) return rc;
+        HIPCHK(h, launch_axpy(h->st, u, z, 1.0, n));
+        h->kernels++;
+        if ((rc = residual(&beta))) return rc;
+    }
+    res.iters = it;
+    res.converged = beta <= o.rtol * bnorm;
+    res.relres = beta / bnorm;
+    return FRACSOLVE_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1117,6 +1318,51 @@ int fracsolve_adjoint(fracsolve_t h, const double *const *g, const double *const
             if ((rc = finish_sum(h, kRedBlocks, &t2))) break;
             dL_dgamma[k] = t2 - t1;
         }
+    }
+    return timed_end(h, ev, rc);
+}
+
+int fracsolve_gmres(fracsolve_t h, const double *const *f, const double *const *u0, const double *const *phi,
+                    double *const *u, const fracsolve_gmres_options *opts, fracsolve_gmres_info *info,
+                    double *hist, int32_t hist_cap)
+{
+    if (!h) return fail(nullptr, FRACSOLVE_E_ARG, "handle is NULL");
+    int rc;
+    if ((rc = check_fields(h, (const void *const *)f, "f", true))) return rc;
+    if ((rc = check_fields(h, (const void *const *)u, "u", true))) return rc;
+    fracsolve_gmres_options o{30, 1000, 1e-10, 0, 0};
+    if (opts) o = *opts;
+    if (o.restart < 1 || o.restart > 512)
+        return fail(h, FRACSOLVE_E_ARG, "restart must lie in [1, 512], got %d", (int)o.restart);
+    if (o.max_iters < 0) return fail(h, FRACSOLVE_E_ARG, "max_iters must be >= 0, got %d", (int)o.max_iters);
+    if (!(o.rtol >= 0.0) || !std::isfinite(o.rtol))
+        return fail(h, FRACSOLVE_E_ARG, "rtol must be finite and >= 0, got %g", o.rtol);
+    if (o.precond < 0 || o.precond > 1) return fail(h, FRACSOLVE_E_ARG, "precond must be 0 or 1, got %d", (int)o.precond);
+    if (o.use_guess < 0 || o.use_guess > 1)
+        return fail(h, FRACSOLVE_E_ARG, "use_guess must be 0 or 1, got %d", (int)o.use_guess);
+    if (hist_cap < 0 || (hist_cap > 0 && !hist)) return fail(h, FRACSOLVE_E_ARG, "hist is NULL with hist_cap %d", (int)hist_cap);
+    hipEvent_t ev[2];
+    if ((rc = timed_begin(h, ev))) return rc;
+    if (!h->zeros) {
+        if ((rc = dalloc(h, &h->zeros, 64))) return timed_end(h, ev, rc);
+        if (launch_zero(h->st, h->zeros, 64 * sizeof(double)) != hipSuccess)
+            return timed_end(h, ev, fail(h, FRACSOLVE_E_DEVICE, "launch failed"));
+    }
+    if (h->gcap < o.restart + 1) {
+        dfree(h, h->gpart);
+        dfree(h, h->gdots);
+        h->gpart = h->gdots = nullptr;
+        h->gcap = 0;
+        if ((rc = dalloc(h, &h->gpart, (size_t)(o.restart + 1) * kDotBlocks)) ||
+            (rc = dalloc(h, &h->gdots, (size_t)(o.restart + 1))))
+            return timed_end(h, ev, rc);
+        h->gcap = o.restart + 1;
+    }
+    for (size_t k = 0; k < h->inst.size() && !rc; ++k) {
+        GmresResult r;
+        rc = gmres_one(h, (int)k, f[k], opt_ptr(u0, k), opt_ptr(phi, k), u[k], o, r, k == 0 ? hist : nullptr,
+                       k == 0 ? hist_cap : 0);
+        if (!rc && info) info[k] = fracsolve_gmres_info{r.iters, r.cycles, r.converged, 0, r.relres, r.est};
     }
     return timed_end(h, ev, rc);
 }

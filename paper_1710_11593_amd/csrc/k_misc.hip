@@ -295,4 +295,99 @@ hipError_t launch_absmax_partial(hipStream_t st, const double *x, int64_t n, dou
     return hipGetLastError();
 }
 
+
+// ---- Krylov-basis kernels of the restarted GMRES(m) (section 3.1) ----
+// The basis V is stored as nv vectors of length n, vector k at V + k ldv.
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    return v;
+}
+
+// partial[v nb + b] = block b's share of <V_v, w>, for the VB vectors
+// v = VB blockIdx.y + k < nv (w is read once for all of them).
+template <int VB>
+__global__ __launch_bounds__(256) void k_multidot(const double *__restrict__ V, int64_t ldv, int nv,
+                                                  const double *__restrict__ w, int64_t n,
+                                                  double *__restrict__ partial)
+{
+    __shared__ double red[VB][4];
+    const int v0 = blockIdx.y * VB;
+    const int nb = gridDim.x;
+    double s[VB];
+#pragma unroll
+    for (int k = 0; k < VB; ++k) s[k] = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)nb * 256) {
+        const double wi = w[i];
+#pragma unroll
+        for (int k = 0; k < VB; ++k)
+            if (v0 + k < nv) s[k] = fma(V[(int64_t)(v0 + k) * ldv + i], wi, s[k]);
+    }
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+    for (int k = 0; k < VB; ++k) {
+        const double r = wave_sum(s[k]);
+        if (lane == 0) red[k][wv] = r;
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < VB && v0 + (int)threadIdx.x < nv) {
+        const int k = threadIdx.x;
+        partial[(int64_t)(v0 + k) * nb + blockIdx.x] = (red[k][0] + red[k][1]) + (red[k][2] + red[k][3]);
+    }
+}
+
+// out[v] = sum_b partial[v nb + b] (one workgroup per vector)
+__global__ __launch_bounds__(256) void k_sum_rows(const double *__restrict__ partial, int nb,
+                                                  double *__restrict__ out)
+{
+    __shared__ double red[4];
+    const int v = blockIdx.x;
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nb; b += 256) s += partial[(int64_t)v * nb + b];
+    s = wave_sum(s);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) out[v] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+hipError_t launch_multidot(hipStream_t st, const double *V, int64_t ldv, int nv, const double *w, int64_t n,
+                           double *partial, int nb, double *out)
+{
+    if (nv <= 0) return hipSuccess;
+    constexpr int VB = 8;
+    hipLaunchKernelGGL(k_multidot<VB>, dim3((unsigned)nb, (unsigned)((nv + VB - 1) / VB)), dim3(256), 0, st, V, ldv,
+                       nv, w, n, partial);
+    hipLaunchKernelGGL(k_sum_rows, dim3((unsigned)nv), dim3(256), 0, st, partial, nb, out);
+    return hipGetLastError();
+}
+
+// y = beta y + sum_{v < nv} c_v V_v  (beta = 0: y is not read)
+__global__ __launch_bounds__(256) void k_lincomb(double *__restrict__ y, double beta, const double *__restrict__ V,
+                                                 int64_t ldv, int nv, LinCoef c, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        double acc = (beta == 0.0) ? 0.0 : beta * y[i];
+        for (int k = 0; k < nv; ++k) acc = fma(c.c[k], V[(int64_t)k * ldv + i], acc);
+        y[i] = acc;
+    }
+}
+
+hipError_t launch_lincomb(hipStream_t st, double *y, double beta, const double *V, int64_t ldv, int nv,
+                          const double *c, int64_t n)
+{
+    // LINCOMB_MAX vectors per launch; later chunks accumulate into y
+    int k0 = 0;
+    do {
+        const int cnt = std::min(nv - k0, LINCOMB_MAX);
+        LinCoef cc{};
+        for (int k = 0; k < cnt; ++k) cc.c[k] = c[k0 + k];
+        hipLaunchKernelGGL(k_lincomb, dim3(nblocks_for(n, 256)), dim3(256), 0, st, y, k0 == 0 ? beta : 1.0,
+                           V + (int64_t)k0 * ldv, ldv, cnt, cc, n);
+        k0 += cnt;
+    } while (k0 < nv);
+    return hipGetLastError();
+}
+
 }  // namespace fs
