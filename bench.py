@@ -16,6 +16,10 @@ stream during one extra solve; achieved = its algorithmic bytes (24 B per
 X-row entry: read X, read and write Y) / its time, against the 8 TB/s HBM
 peak.  critical_path: the sequential chain of leaf solves (one workgroup
 each), which sets most of the solve time.
+forms (unless --no-forms): mixed precision (c3), batching (c4), the adjoint
+(c5) and the paper's own iterative method, restarted GMRES(m), on its
+Example 4 meshes next to the recursive solve (--config gmres runs only that;
+with --N 2^k only the mesh h = tau = 2^-k).
 cpu_baseline: the oracle (plain time stepping) on the same workload for the
 first --cpu-steps steps at full width; its wall time is scaled by
 (N / steps)^2 (the history work is quadratic in the step count) to the full
@@ -268,7 +272,69 @@ def run_forms(dev):
     out["c5_adjoint"] = {"ms_forward": round(ms_f, 2), "ms_adjoint": round(ms_a, 2), "dL_dgamma": dgamma,
                          "dL_df_error_vs_oracle": err_l}
     log("forms: c5 forward %.1f ms, adjoint %.1f ms, dL/df err %.3e, dL/dgamma %.6e" % (ms_f, ms_a, err_l, dgamma))
+    out["gmres_example4"] = run_gmres(dev)
     return out
+
+
+# The paper's timing table for Scheme 4 (gamma = 0.1, h = tau = 2^-k): CPU
+# seconds of its fast (GMRES) method on a Matlab PC; context only.
+PAPER_FAST_S = {8: 2.27, 9: 15.6, 10: 263.0}
+
+
+def run_gmres(dev, meshes=(8, 9, 10), rtol=1e-8):
+    """The paper's iterative method, restarted GMRES(m) (section 3.1), on its
+    Example 4 data (u = t^3 sin(pi x), gamma = 0.1, h = tau = 2^-k), next to
+    the recursive solve of the same system.  Unpreconditioned (the paper's
+    method, m = 100) and with the block-diagonal preconditioner (m = 30).
+    rtol = 1e-8: at h = 2^-10 the operator's condition number is about 2e6,
+    so the relative residual computed in float64 bottoms out near 1e-10 and a
+    target there spends most steps restarting on rounding.  Errors against
+    the oracle's scalar recurrence of the single sine mode the data carry."""
+    import numpy as np
+    import torch
+
+    import oracle
+    from paper_1710_11593_amd import binding
+
+    gamma = 0.1
+    res = {}
+    for k in meshes:
+        M, N = 2 ** k - 1, 2 ** k
+        h = 1.0 / (M + 1)
+        x = np.arange(1, M + 1) * h
+        t = np.arange(1, N + 1) / N
+        G = 6 * t ** (3 - gamma) / math.gamma(4 - gamma) + math.pi ** 2 * t ** 3
+        s = np.sin(math.pi * x)
+        f = torch.from_numpy(np.outer(G, s)).to(dev)
+        lam1 = 4.0 / h ** 2 * math.sin(math.pi * h / 2) ** 2
+        ref = torch.from_numpy(np.outer(oracle.mode(gamma, 1.0, N, lam1, G), s)).to(dev)
+        sv = binding.Solver([dict(gamma=gamma, M=M, N=N)])
+        u = torch.empty_like(f)
+        dc = lambda: sv.solve([f], out=[u])  # noqa: E731
+        dc()
+        ms_dc = timed(dc, 3)
+        err_dc = float((u - ref).abs().max() / ref.abs().max())
+        row = {"M": M, "N": N, "dc_ms": round(ms_dc, 3), "dc_error_vs_oracle": err_dc,
+               "paper_fast_method_cpu_s": PAPER_FAST_S.get(k)}
+        for pc, m in ((0, 100), (1, 30)):
+            holder = {}
+
+            def run():
+                holder["i"] = sv.gmres([f], out=[u], restart=m, max_iters=20000, rtol=rtol, precond=pc)[1][0]
+
+            run()
+            ms = timed(run, 1)
+            info = holder["i"]
+            err = float((u - ref).abs().max() / ref.abs().max())
+            key = "gmres" if pc == 0 else "gmres_block_precond"
+            row[key] = {"ms": round(ms, 3), "restart": m, "rtol": rtol, "iterations": info["iterations"],
+                        "cycles": info["cycles"],
+                        "relres": info["relres"], "converged": info["converged"], "error_vs_oracle": err}
+            log("forms: gmres h=tau=2^-%d precond %d: %.2f ms, %d steps in %d cycles, err %.2e (recursive solve "
+                "%.2f ms)" % (k, pc, ms, info["iterations"], info["cycles"], err, ms_dc))
+        sv.close()
+        res["h=tau=2^-%d" % k] = row
+    return res
 
 
 def run_batched(args, dev):
@@ -387,6 +453,11 @@ def main():
     dev = torch.device("cuda:0")
     if args.config == "c4":
         return run_batched(args, dev)
+    if args.config == "gmres":
+        # the paper's iterative method on its Example 4 meshes (a form, not the headline)
+        meshes = (int(round(math.log2(args.N))),) if args.N else (8, 9, 10)
+        print(json.dumps({"gmres_example4": run_gmres(dev, meshes)}))
+        return
     inst, desc = build_instance(args)
     M, N, gamma = inst.M, inst.N, inst.gamma
     log("bench: %s, precision %s" % (desc, args.precision))
