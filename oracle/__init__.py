@@ -15,6 +15,8 @@ Parity status of each function (what pins it, in tests/test_oracle_*.py):
   apply     -- dense brute force
   adjoint   -- dot test, central differences in f and in gamma
   mode      -- closed form on linear-in-time data, dense brute force
+  solve_adv -- Table 5 and Table 7 of the paper, closed forms on data
+               linear in x and t, dense brute force
   gmres     -- finite termination at the dense solve, least-squares estimates
                equal to recomputed residuals, the one-step minimal-residual
                closed form, exact convergence in N steps with the
@@ -65,6 +67,8 @@ def _load():
     lib.oracle_adjoint.argtypes = [d, d, d, d, i64, i64, _dp, _dp, _dp, _dp, _dp, _dp, i32]
     lib.oracle_mode.restype = i32
     lib.oracle_mode.argtypes = [d, d, i64, d, _dp, d, d, _dp]
+    lib.oracle_solve_adv.restype = i32
+    lib.oracle_solve_adv.argtypes = [d, d, d, d, i64, i64, _dp, _dp, _dp, _dp, i32]
     lib.oracle_gmres.restype = i32
     lib.oracle_gmres.argtypes = [d, d, d, d, i64, i64, _dp, _dp, _dp, _dp, i32, i32, d, i32, i32,
                                  ctypes.POINTER(i32), _dp, _dp, i32]
@@ -156,6 +160,20 @@ def mode(gamma, T, N, lam, g, v0=0.0, phihat=0.0):
     v = np.zeros(N)
     _check(lib.oracle_mode(gamma, T, N, lam, _ptr(g), v0, phihat, _ptr(v)), "mode")
     return v
+
+
+def solve_adv(gamma, T, x0, x1, M, N, f, u0=None, phi=None, nthreads=0):
+    """Advection equations D^gamma u + u_x = f, inflow u(x0, t) = 0: Scheme 2
+    (gamma < 1; f sampled at x_i - h/2, t_n) or Scheme 3 (gamma > 1; f at
+    x_i, t_{n-1/2}).  Returns U [N][M]."""
+    lib = _load()
+    f = _f64(f, (N, M))
+    u0 = _f64(u0, (M,))
+    phi = _f64(phi, (M,))
+    u = np.zeros((N, M))
+    _check(lib.oracle_solve_adv(gamma, T, x0, x1, M, N, _ptr(f), _ptr(u0), _ptr(phi), _ptr(u), nthreads),
+           "solve_adv")
+    return u
 
 
 def gmres(gamma, T, x0, x1, M, N, f, u0=None, phi=None, restart=30, maxit=1000, rtol=1e-10, precond=0,

@@ -35,6 +35,9 @@
  *   for Scheme 4, section 3.1), with the operator products evaluated from
  *   their definition.
  *
+ *   Advection equations D_t^gamma u + u_x = f (Schemes 2 and 3, eq. e11-e17)
+ *   are stepped by oracle_solve_adv (see there).
+ *
  * Layout: time-major [N][M] row-major, entry (n-1)*M + (i-1) is (x_i, t_n),
  * h = (x1-x0)/(M+1), x_i = x0 + i h, tau = T/N.
  */
@@ -443,6 +446,75 @@ int oracle_mode(double gamma, double T, int64_t N, double lam, const double *g,
         v[n - 1] = s / d;
     }
     free(a); free(rho); free(psi);
+    return ORACLE_OK;
+}
+
+/*
+ * Advection equations D_t^gamma u + u_x = f on (x0, x1) (a = 1), inflow value
+ * u(x0, t) = 0, by time stepping; the unknowns are x_i = x0 + i h, i = 1..M,
+ * h = (x1 - x0)/(M + 1), and U_0 = 0.
+ *   0<gamma<1, Scheme 2 (eq. e12, e13): the L1 formula of Scheme 4 (weights
+ *     a_m, rho_n of the diffusion case) averaged over x_i and x_{i-1}, and
+ *     the difference (U_i - U_{i-1})/h, at the midpoint x_{i-1/2}:
+ *       (1/2)[a_0 (U_i^n + U_{i-1}^n) + sum_{j<n} a_{n-j} (U_i^j + U_{i-1}^j)
+ *             + rho_n (u0_i + u0_{i-1})] + (U_i^n - U_{i-1}^n)/h = f(x_{i-1/2}, t_n);
+ *     the u0 term is read as for Scheme 4 (telescoping, rho_n = -mu b_{n-1}).
+ *   1<gamma<2, Scheme 3 (eq. e15-e17): the diffusion-wave weights with the
+ *     backward difference at x_i:
+ *       a_0 U_i^n + sum_{j<n} a_{n-j} U_i^j + (U_i^n - U_{i-1}^n)/h
+ *         = f(x_i, t_{n-1/2}) - rho_n u0_i + psi_n phi_i.
+ *   Each step is a forward sweep in i.  f[n-1][i-1] holds the source where
+ *   the scheme samples it (x_i - h/2 for Scheme 2, x_i for Scheme 3); u0[i-1]
+ *   is u0(x_i) (u0(x0) = 0 by the inflow condition).
+ */
+int oracle_solve_adv(double gamma, double T, double x0, double x1, int64_t M, int64_t N,
+                     const double *f, const double *u0, const double *phi, double *u, int nthreads)
+{
+    int reg = regime_of(gamma);
+    if (reg < 0 || !(T > 0.0) || !(x1 > x0) || M < 1 || N < 1 || !f || !u) return ORACLE_EARG;
+    set_threads(nthreads);
+    const double h = (x1 - x0) / (double)(M + 1);
+    double *a = (double *)malloc(sizeof(double) * (size_t)N);
+    double *rho = (double *)malloc(sizeof(double) * (size_t)N);
+    double *psi = (double *)malloc(sizeof(double) * (size_t)N);
+    double *r = (double *)malloc(sizeof(double) * (size_t)M);
+    if (!a || !rho || !psi || !r) {
+        free(a); free(rho); free(psi); free(r);
+        return ORACLE_ENOMEM;
+    }
+    oracle_weights(gamma, T, N, NULL, a, rho, psi, NULL, NULL, NULL, NULL);
+    for (int64_t n = 1; n <= N; ++n) {
+        const double *fn = f + (size_t)(n - 1) * (size_t)M;
+        double *un = u + (size_t)(n - 1) * (size_t)M;
+        #pragma omp parallel for schedule(static)
+        for (int64_t i = 0; i < M; ++i) {
+            double s;
+            if (reg == 0) {
+                double w0 = u0 ? u0[i] + (i > 0 ? u0[i - 1] : 0.0) : 0.0;
+                s = 2.0 * fn[i] - rho[n - 1] * w0;
+                for (int64_t j = 1; j < n; ++j) {
+                    const double *uj = u + (size_t)(j - 1) * (size_t)M;
+                    s -= a[n - j] * (uj[i] + (i > 0 ? uj[i - 1] : 0.0));
+                }
+            } else {
+                s = fn[i];
+                if (u0) s -= rho[n - 1] * u0[i];
+                if (phi) s += psi[n - 1] * phi[i];
+                for (int64_t j = 1; j < n; ++j) s -= a[n - j] * u[(size_t)(j - 1) * (size_t)M + (size_t)i];
+            }
+            r[i] = s;
+        }
+        /* forward sweep in i */
+        double prev = 0.0;
+        for (int64_t i = 0; i < M; ++i) {
+            if (reg == 0)
+                un[i] = (r[i] - (a[0] - 2.0 / h) * prev) / (a[0] + 2.0 / h);
+            else
+                un[i] = (r[i] + prev / h) / (a[0] + 1.0 / h);
+            prev = un[i];
+        }
+    }
+    free(a); free(rho); free(psi); free(r);
     return ORACLE_OK;
 }
 

@@ -1,0 +1,132 @@
+"""Pins for the oracle's advection time stepping (Scheme 2, eq. e12/e13, for
+0<gamma<1; Scheme 3, eq. e15-e17, for 1<gamma<2; inflow value u(x0,t) = 0).
+
+* Table 5 (Scheme 2, Example 2) and Table 7 (Scheme 3, Example 3) of the
+  paper, to the printed digits;
+* closed forms: both schemes are exact on u = (1 + t)(x - x0) (the L1
+  formulas are exact on data linear in t, the differences on data linear in
+  x);
+* a dense solve of the whole block system assembled from the schemes'
+  component equations.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def read_table(name):
+    rows = []
+    for line in open(os.path.join(GOLDEN, name)):
+        line = line.strip()
+        if not line or line.startswith("#"):
+            continue
+        parts = line.split()
+        misprint = parts[3].split("=")[1] if len(parts) > 3 else None
+        rows.append((float(parts[0]), int(parts[1]), parts[2], misprint))
+    return rows
+
+
+def within_printed(err, printed):
+    target = float(printed)
+    e = math.floor(math.log10(target))
+    return abs(err - target) <= 1.0001 * 10 ** (e - 4)
+
+
+@pytest.mark.parametrize("row", read_table("table5.txt"), ids=lambda r: "g%.1f-k%d" % (r[0], r[1]))
+def test_table5_scheme2(orc, row):
+    gamma, k, printed, _ = row
+    Mp, N = 2 ** k, 2 ** 10
+    h = 1.0 / Mp
+    x = h * np.arange(1, Mp)
+    t = np.arange(1, N + 1) / N
+    xm = x - h / 2
+    f = (np.outer(t ** (1 - gamma) / math.gamma(2 - gamma), np.sin(np.pi * xm))
+         + np.outer(np.pi * t, np.cos(np.pi * xm)))
+    U = orc.solve_adv(gamma, 1.0, 0.0, 1.0, Mp - 1, N, f)
+    err = math.sqrt(h * np.sum((U[-1] - np.sin(np.pi * x)) ** 2))
+    # printed exponents are one higher than the discrete errors (golden file)
+    assert within_printed(10.0 * err, printed), (err, printed)
+
+
+@pytest.mark.parametrize("row", read_table("table7.txt"), ids=lambda r: "g%.1f-k%d" % (r[0], r[1]))
+def test_table7_scheme3(orc, row):
+    gamma, k, printed, misprint = row
+    Mp = N = 2 ** k
+    h = 1.0 / Mp
+    x = h * np.arange(1, Mp)
+    th = (np.arange(1, N + 1) - 0.5) / N
+    f = (np.outer(6 * th ** (3 - gamma) / math.gamma(4 - gamma), x - x * x)
+         + np.outer(th ** 3, 1 - 2 * x))
+    U = orc.solve_adv(gamma, 1.0, 0.0, 1.0, Mp - 1, N, f)
+    err = math.sqrt(h * np.sum((U[-1] - x * (1 - x)) ** 2))
+    assert within_printed(err, misprint or printed), (err, printed, misprint)
+
+
+@pytest.mark.parametrize("gamma", [0.2, 0.7, 1.3, 1.8])
+@pytest.mark.parametrize("M,N", [(1, 5), (7, 9), (30, 40)])
+def test_exact_on_linear_data(orc, gamma, M, N):
+    x0, x1, T = 0.5, 2.0, 1.5
+    h = (x1 - x0) / (M + 1)
+    x = x0 + h * np.arange(1, M + 1)
+    tau = T / N
+    t = tau * np.arange(1, N + 1)
+    if gamma < 1:
+        xs, ts = x - h / 2, t
+        f = np.outer(ts ** (1 - gamma) / math.gamma(2 - gamma), xs - x0) + np.outer(1 + ts, np.ones(M))
+        phi = None
+    else:
+        # the L1 formula of Scheme 3 gives 0 on (1 + t) (and its phi term);
+        # the difference is taken at t_n, so the data that make (1 + t)(x - x0)
+        # the discrete solution are 1 + t_n
+        f = np.outer(1 + t, np.ones(M))
+        phi = x - x0
+    U = orc.solve_adv(gamma, T, x0, x1, M, N, f, u0=x - x0, phi=phi)
+    exact = np.outer(1 + t, x - x0)
+    assert np.max(np.abs(U - exact)) <= 1e-12 * np.max(np.abs(exact))
+
+
+def dense_adv(gamma, M, N, T=1.0):
+    """Block system of Scheme 2 / 3 from the component equations (tiny sizes)."""
+    tau, h = T / N, 1.0 / (M + 1)
+    if gamma < 1:
+        p, coef = 1 - gamma, tau ** (-gamma) / math.gamma(2 - gamma)
+    else:
+        p, coef = 2 - gamma, tau ** (-gamma) / math.gamma(3 - gamma)
+
+    def b(k):
+        return 0.0 if k < 0 else (k + 1) ** p - k ** p
+
+    if gamma < 1:
+        a = [coef * (b(m) - b(m - 1)) for m in range(N)]
+        rho = [-coef * b(n - 1) for n in range(1, N + 1)]
+        psi = [0.0] * N
+        B = 0.5 * (np.eye(M) + np.eye(M, k=-1))  # average of x_i and x_{i-1}
+    else:
+        a = [coef * (b(m - 2) - 2 * b(m - 1) + b(m)) for m in range(N)]
+        rho = [coef * (b(n - 2) - b(n - 1)) for n in range(1, N + 1)]
+        psi = [coef * tau * b(n - 1) for n in range(1, N + 1)]
+        B = np.eye(M)
+    D = (np.eye(M) - np.eye(M, k=-1)) / h
+    A = np.zeros((M * N, M * N))
+    for n in range(N):
+        for j in range(n + 1):
+            A[n * M:(n + 1) * M, j * M:(j + 1) * M] = a[n - j] * B + (D if j == n else 0.0)
+    return A, B, np.array(rho), np.array(psi)
+
+
+@pytest.mark.parametrize("gamma", [0.4, 1.6])
+@pytest.mark.parametrize("M,N", [(1, 7), (5, 6), (12, 10)])
+def test_dense_bruteforce(orc, gamma, M, N):
+    rng = np.random.default_rng(M * N)
+    F = rng.standard_normal((N, M))
+    u0 = rng.standard_normal(M)
+    phi = rng.standard_normal(M)
+    A, B, rho, psi = dense_adv(gamma, M, N)
+    R = F - np.outer(rho, B @ u0) + (np.outer(psi, phi) if gamma > 1 else 0.0)
+    ref = np.linalg.solve(A, R.ravel()).reshape(N, M)
+    U = orc.solve_adv(gamma, 1.0, 0.0, 1.0, M, N, F, u0=u0, phi=phi)
+    assert np.max(np.abs(U - ref)) <= 1e-11 * np.max(np.abs(ref))
