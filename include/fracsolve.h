@@ -86,6 +86,22 @@ typedef struct {
                        exact, because the system is causal)                   */
 } fracsolve_problem;
 
+/* Equation of every instance of a handle. */
+enum {
+    FRACSOLVE_DIFFUSION = 0,  /* D_t^gamma u = u_xx + f (the system above)      */
+    FRACSOLVE_ADVECTION = 1   /* D_t^gamma u + u_x = f with inflow value
+                                 u(x0, t) = 0 (section 3, eq. e11-e17): Scheme 2
+                                 for 0<gamma<1 (L1 formula averaged over x_i and
+                                 x_{i-1}, difference (U_i - U_{i-1})/h, both at
+                                 the midpoint x_i - h/2, where f is sampled, at
+                                 t_n); Scheme 3 for 1<gamma<2 (the diffusion-
+                                 wave weights, the same difference at x_i, f at
+                                 (x_i, t_{n-1/2})).  The diagonal block is lower
+                                 bidiagonal; the history keeps the scalar
+                                 Toeplitz form (for Scheme 2 in W = B U,
+                                 (B U)_i = U_i + U_{i-1}).  Float64 solves only. */
+};
+
 typedef struct {
     int32_t precision;    /* FRACSOLVE_FP64 / FP32 / BF16X3                    */
     int32_t refine_steps; /* iterative-refinement steps against the float64
@@ -99,6 +115,11 @@ typedef struct {
                              0 = closed-form inverse by parallel scan (default),
                              1 = block Thomas + parallel cyclic reduction      */
     void *stream;         /* hipStream_t for all work; NULL = null stream      */
+    int32_t equation;     /* FRACSOLVE_DIFFUSION (0) or FRACSOLVE_ADVECTION;
+                             ADVECTION needs precision FP64 and leaf_solver 0,
+                             and supports fracsolve_solve and
+                             fracsolve_weights only (the other entry points
+                             return E_ARG)                                     */
 } fracsolve_options;
 
 /*

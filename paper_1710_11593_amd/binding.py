@@ -18,6 +18,7 @@ LIBPATH = os.path.join(HERE, "csrc", "libfracsolve.so")
 FRACSOLVE_OK = 0
 STATUS = {0: "OK", -1: "E_ARG", -2: "E_NOMEM", -3: "E_DEVICE", -4: "E_NUMERIC", -5: "E_STATE"}
 PRECISION = {"fp64": 0, "fp32": 1, "bf16x3": 2}
+EQUATION = {"diffusion": 0, "advection": 1}
 
 
 class Problem(ctypes.Structure):
@@ -27,7 +28,8 @@ class Problem(ctypes.Structure):
 
 class Options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("refine_steps", ctypes.c_int32), ("leaf", ctypes.c_int32),
-                ("crossover", ctypes.c_int32), ("leaf_solver", ctypes.c_int32), ("stream", ctypes.c_void_p)]
+                ("crossover", ctypes.c_int32), ("leaf_solver", ctypes.c_int32), ("stream", ctypes.c_void_p),
+                ("equation", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -126,7 +128,7 @@ class Solver:
     """One handle over `len(problems)` instances (see fracsolve_create)."""
 
     def __init__(self, problems: Sequence[dict], precision="fp64", refine_steps=0, leaf=0, crossover=0,
-                 leaf_solver=0, stream=None):
+                 leaf_solver=0, stream=None, equation="diffusion"):
         L = lib()
         self._lib = L
         self.problems = [dict(p) for p in problems]
@@ -140,7 +142,8 @@ class Solver:
             stream = torch.cuda.current_stream().cuda_stream
         self.stream = stream
         opts = Options(PRECISION[precision] if isinstance(precision, str) else int(precision), int(refine_steps),
-                       int(leaf), int(crossover), int(leaf_solver), ctypes.c_void_p(stream))
+                       int(leaf), int(crossover), int(leaf_solver), ctypes.c_void_p(stream),
+                       EQUATION[equation] if isinstance(equation, str) else int(equation))
         h = ctypes.c_void_p()
         rc = L.fracsolve_create(arr, len(problems), ctypes.byref(opts), ctypes.byref(h))
         if rc != FRACSOLVE_OK:

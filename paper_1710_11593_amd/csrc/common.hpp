@@ -95,6 +95,18 @@ struct LeafTask {
 };
 constexpr int32_t LEAF_PERM = 1, LEAF_VEC = 2;
 
+// Leaf of the advection equations (bidiagonal diagonal block, k_leaf_scan.hip)
+struct AdvTask {
+    double *x;          // field the level products use: right-hand sides in, X out
+    double *u;          // solution U [N][M] (Scheme 2: X = B U is not U) or null
+    const double *a;    // Toeplitz column a_0..a_{L-1}
+    const double *fac;  // factor table (g, kappa and its powers)
+    int64_t M;
+    int64_t lo;
+    int32_t nrows;
+    int32_t pad;
+};
+
 // One off-diagonal Toeplitz-block product:
 //   Y[ylo + p] += alpha * sum_{q<s} w[s + p - q] X[xlo + q],   p < ny <= s,
 // for all M columns.  The rows of X and Y are rows of [*][M] arrays.
@@ -152,6 +164,8 @@ __host__ __device__ inline int corner_width(int s) { return s < 32 ? s : 32; }
 hipError_t launch_weights(hipStream_t st, int regime, double p, double coef, double dcoef, double tau,
                           int64_t N, double *b, double *a, double *rho, double *psi, double *da,
                           double *drho, double *dpsi);
+hipError_t launch_rhs_adv2(hipStream_t st, const double *f, const double *u0, const double *rho, double *y,
+                           int64_t M, int64_t N);
 hipError_t launch_rhs(hipStream_t st, const double *f, const double *u0, const double *phi,
                       const double *rho, const double *psi, double *u, int64_t M, int64_t N);
 hipError_t launch_rhs_scale(hipStream_t st, double *y, const double *u0, const double *phi,
@@ -173,6 +187,10 @@ hipError_t launch_leaf(hipStream_t st, const LeafCfg &c, int L, const LeafTask *
 LeafCfg scan_config(int64_t M, bool batched = false);
 size_t scan_table_doubles(const LeafCfg &c);
 hipError_t launch_scan_factor(hipStream_t st, const LeafCfg &c, int64_t M, double a0, double e, double *tab);
+hipError_t launch_adv_factor(hipStream_t st, const LeafCfg &c, double a0, double h, bool scheme2, double *tab);
+size_t adv_table_doubles();
+hipError_t launch_leaf_adv(hipStream_t st, const LeafCfg &c, int L, const TaskRef<AdvTask> &d_tasks, int ntasks,
+                           bool wsum);
 hipError_t launch_leaf_scan(hipStream_t st, const LeafCfg &c, int L, const TaskRef<LeafTask> &tr, int ntasks,
                             bool mixed, int vec);
 

@@ -34,6 +34,7 @@ struct Inst {
     int64_t M = 0, N = 0, Np = 0;
     LeafCfg lc{};
     bool scan = true;  // leaf solver: closed-form scan (true) or block Thomas + PCR
+    int adv = 0;       // advection equations: 2 = Scheme 2 (gamma < 1), 3 = Scheme 3; 0 = diffusion
     ColPerm perm{0, 0};  // internal column order of the solve's fields
     double *b = nullptr, *a = nullptr, *rho = nullptr, *psi = nullptr;
     double *da = nullptr, *drho = nullptr, *dpsi = nullptr;
@@ -221,7 +222,7 @@ const T *dptr(fracsolve_ctx *h, size_t off)
 }
 
 // ---- one call = a list of launch records built on the host, then replayed.
-enum OpKind { OP_LEAF, OP_LEAF_SCAN, OP_GEMM64, OP_GEMM32, OP_FFT64, OP_FFT32 };
+enum OpKind { OP_LEAF, OP_LEAF_SCAN, OP_GEMM64, OP_GEMM32, OP_FFT64, OP_FFT32, OP_LEAF_ADV };
 struct Op {
     OpKind kind;
     size_t off;   // descriptor offset
@@ -234,6 +235,7 @@ struct Op {
     bool even = false;   // FFT levels: every task has M even and aligned rows
     size_t goff = 0;     // single-pass FFT levels: descriptor offset of the group offsets
     int lead = 0;        // dense levels of a solve: rows the next leaf reads first
+    bool wsum = false;   // advection leaves: Scheme 2 (X = B U, U to its own field)
 };
 
 // Flat column-group offsets of the tasks of a single-pass FFT level (see
@@ -300,6 +302,9 @@ int run_ops(fracsolve_ctx *h, const std::vector<Op> &ops)
             case OP_LEAF_SCAN:
                 e = launch_leaf_scan(h->st, op.lc, h->L, task_ref<LeafTask>(h, op), op.ntasks, op.mixed, op.lc.vec);
                 break;
+            case OP_LEAF_ADV:
+                e = launch_leaf_adv(h->st, op.lc, h->L, task_ref<AdvTask>(h, op), op.ntasks, op.wsum);
+                break;
             case OP_GEMM64:
                 e = launch_gemm_update<double>(h->st, task_ref<UpdTask<double>>(h, op), op.ntasks, op.s, op.maxM,
                                                op.lead);
@@ -324,7 +329,7 @@ int run_ops(fracsolve_ctx *h, const std::vector<Op> &ops)
         h->kernels++;
         if (h->timing >= 2) {
             HIPCHK(h, hipEventRecord(h->evpool[evi + 1], h->st));
-            const bool lf = op.kind == OP_LEAF || op.kind == OP_LEAF_SCAN;
+            const bool lf = op.kind == OP_LEAF || op.kind == OP_LEAF_SCAN || op.kind == OP_LEAF_ADV;
             int kind = lf ? 0 : op.kind == OP_GEMM64 ? 1 : op.kind == OP_GEMM32 ? 2 : op.kind == OP_FFT64 ? 3 : 4;
             h->recs.push_back({kind, lf ? h->L : op.s, op.ntasks, op.bytes, evi});
             // the near-corner band of an FFT level as a group of its own:
@@ -381,6 +386,7 @@ uint64_t ops_key(const std::vector<Op> &ops, const void *d_desc)
         mix((uint64_t)op.goff);
         mix((uint64_t)op.lead);
         mix((uint64_t)op.lc.vec);
+        mix((uint64_t)op.wsum);
     }
     mix((uint64_t)ops.size());
     return hsh;
@@ -436,6 +442,7 @@ struct Field {
     double *u;        // right-hand side in / solution out [N][M]
     float *hist32;    // mixed: history accumulator (zeroed by caller)
     float *x32;       // mixed: float32 shadow of solved rows
+    double *out = nullptr;  // advection, Scheme 2: solution U (u then holds W = B U)
 };
 
 // Build the launch list of the recursive solve of every instance in `sel`
@@ -450,10 +457,23 @@ void build_solve(fracsolve_ctx *h, const std::vector<int> &sel, const std::vecto
     for (int64_t k = 0; k < K; ++k) {
         // leaves, one launch per leaf configuration
         std::vector<std::pair<int, LeafTask>> lt;
+        std::vector<std::pair<int, AdvTask>> at;
         for (size_t q = 0; q < sel.size(); ++q) {
             const Inst &in = h->inst[sel[q]];
             int64_t lo = k * L;
             if (lo >= in.N) continue;
+            if (in.adv) {
+                AdvTask t{};
+                t.x = fld[q].u;
+                t.u = (in.adv == 2) ? fld[q].out : nullptr;
+                t.a = in.a;
+                t.fac = in.fac;
+                t.M = in.M;
+                t.lo = lo;
+                t.nrows = (int)std::min<int64_t>(L, in.N - lo);
+                at.push_back({(in.adv == 2 ? 100000 : 0) + in.lc.nt * 100 + in.lc.pt, t});
+                continue;
+            }
             LeafTask t{};
             t.u = fld[q].u;
             t.a = in.a;
@@ -467,6 +487,21 @@ void build_solve(fracsolve_ctx *h, const std::vector<int> &sel, const std::vecto
             // whole 16-byte row units for the scan leaf
             if (in.scan && (in.M % in.lc.pt) == 0 && ((uintptr_t)t.u & 15) == 0) t.flags |= LEAF_VEC;
             lt.push_back({(in.scan ? 1000000 : 0) + in.lc.nt * 100 + in.lc.pt, t});
+        }
+        std::stable_sort(at.begin(), at.end(), [](const auto &x, const auto &y) { return x.first < y.first; });
+        for (size_t b = 0; b < at.size();) {
+            size_t e = b;
+            while (e < at.size() && at[e].first == at[b].first) ++e;
+            std::vector<AdvTask> v;
+            for (size_t j = b; j < e; ++j) v.push_back(at[j].second);
+            size_t off = db.add(v.data(), v.size() * sizeof(AdvTask));
+            const int key = at[b].first % 100000;
+            LeafCfg lc{key / 100, key % 100, 0};
+            Op op{OP_LEAF_ADV, off, (int)v.size(), 0, 0, lc, false};
+            op.wsum = at[b].first >= 100000;
+            for (auto &t : v) op.bytes += (double)t.nrows * (double)t.M * (op.wsum ? 24.0 : 16.0);
+            ops.push_back(op);
+            b = e;
         }
         // stable: with one leaf configuration, leaf task t is level task t
         // (the dense levels place task t's tiles on leaf t's XCD)
@@ -754,9 +789,10 @@ int setup_instance(fracsolve_ctx *h, Inst &in)
     double garg = (in.regime == 0) ? 2.0 - p.gamma : 3.0 - p.gamma;
     in.coef = std::pow(in.tau, -p.gamma) / std::tgamma(garg);
     in.dcoef = in.coef * (-std::log(in.tau) + digamma_host(garg));
-    in.scan = (h->opts.leaf_solver == 0);
+    in.adv = (h->opts.equation == FRACSOLVE_ADVECTION) ? (in.regime == 0 ? 2 : 3) : 0;
+    in.scan = (h->opts.leaf_solver == 0) || in.adv;
     in.lc = in.scan ? scan_config(h->batch_M > 0 ? h->batch_M : in.M, h->batch_M > 0) : leaf_config(in.M);
-    if (in.scan && in.lc.pt > 2 && in.M % in.lc.pt == 0)
+    if (!in.adv && in.scan && in.lc.pt > 2 && in.M % in.lc.pt == 0)
         in.perm = ColPerm{in.lc.pt, (in.M / (64 * (int64_t)in.lc.pt)) * 64 * (int64_t)in.lc.pt};
     if (h->L > 8 && ((in.scan && in.lc.pt > 2) || (!in.scan && in.lc.pt == 16)))
         return fail(h, FRACSOLVE_E_ARG, "leaf size %d is not available for M = %lld (use 4 or 8)", h->L,
@@ -774,8 +810,11 @@ int setup_instance(fracsolve_ctx *h, Inst &in)
     HIPCHK(h, launch_weights(h->st, in.regime, in.pexp, in.coef, in.dcoef, in.tau, in.Np, in.b, in.a, in.rho,
                              in.psi, in.da, in.drho, in.dpsi));
 
-    // factor table of a_0 I + K
-    if (in.scan) {
+    // factor table of a_0 I + K (advection: of the bidiagonal block)
+    if (in.adv) {
+        if ((rc = dalloc(h, &in.fac, adv_table_doubles()))) return rc;
+        HIPCHK(h, launch_adv_factor(h->st, in.lc, in.coef, in.h, in.adv == 2, in.fac));
+    } else if (in.scan) {
         if ((rc = dalloc(h, &in.fac, scan_table_doubles(in.lc)))) return rc;
         HIPCHK(h, launch_scan_factor(h->st, in.lc, in.M, in.coef, in.e, in.fac));
     } else {
@@ -829,8 +868,20 @@ int solve_all(fracsolve_ctx *h, const double *const *f, const double *const *u0,
     for (size_t k = 0; k < cnt; ++k) sel[k] = (int)k;
     int rc;
     // right-hand sides R = F - rho u0 + psi phi, written into u
+    std::vector<Field> fld(cnt);
     for (size_t k = 0; k < cnt; ++k) {
         Inst &in = h->inst[k];
+        fld[k] = {u[k], nullptr, nullptr};
+        if (in.adv == 2) {
+            // Scheme 2: the recursion runs on W = B U; twice the scheme's
+            // right-hand sides go to the workspace, U to u
+            int rc2 = ensure(h, &in.W, in.M * in.N);
+            if (rc2) return rc2;
+            HIPCHK(h, launch_rhs_adv2(h->st, f[k], opt_ptr(u0, k), in.rho, in.W, in.M, in.N));
+            h->kernels++;
+            fld[k] = {in.W, nullptr, nullptr, u[k]};
+            continue;
+        }
         const double *ph = (in.regime == 1) ? opt_ptr(phi, k) : nullptr;
         HIPCHK(h, launch_rhs(h->st, f[k], opt_ptr(u0, k), ph, in.rho, in.psi, u[k], in.M, in.N));
         h->kernels++;
@@ -852,13 +903,10 @@ int solve_all(fracsolve_ctx *h, const double *const *f, const double *const *u0,
         return FRACSOLVE_OK;
     };
     if (prec == FRACSOLVE_FP64) {
-        std::vector<Field> fld(cnt);
-        for (size_t k = 0; k < cnt; ++k) fld[k] = {u[k], nullptr, nullptr};
         if ((rc = dc_solve(h, sel, fld, FRACSOLVE_FP64))) return rc;
         return restore();
     }
     // mixed: float32 products, float64 leaves; then refinement steps
-    std::vector<Field> fld(cnt);
     for (size_t k = 0; k < cnt; ++k) {
         Inst &in = h->inst[k];
         int64_t n = in.M * in.N;
@@ -1112,6 +1160,16 @@ int fracsolve_create(const fracsolve_problem *probs, int32_t count, const fracso
         return fail(nullptr, FRACSOLVE_E_ARG, "leaf_solver must be 0 or 1, got %d", (int)o.leaf_solver);
     if (o.leaf != 0 && o.leaf != 4 && o.leaf != 8 && o.leaf != 16)
         return fail(nullptr, FRACSOLVE_E_ARG, "leaf must be 0, 4, 8 or 16, got %d", (int)o.leaf);
+    if (o.equation != FRACSOLVE_DIFFUSION && o.equation != FRACSOLVE_ADVECTION)
+        return fail(nullptr, FRACSOLVE_E_ARG, "equation must be 0 (diffusion) or 1 (advection), got %d",
+                    (int)o.equation);
+    if (o.equation == FRACSOLVE_ADVECTION) {
+        if (o.precision != FRACSOLVE_FP64)
+            return fail(nullptr, FRACSOLVE_E_ARG, "the advection equations are solved in float64 only (precision 0)");
+        if (o.leaf_solver != 0)
+            return fail(nullptr, FRACSOLVE_E_ARG, "the advection equations have their own leaf (leaf_solver 0)");
+        if (o.leaf == 16) return fail(nullptr, FRACSOLVE_E_ARG, "leaf must be 0, 4 or 8 for the advection equations");
+    }
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) {
         hipGetLastError();
@@ -1261,6 +1319,8 @@ int fracsolve_solve(fracsolve_t h, const double *const *f, const double *const *
 int fracsolve_apply(fracsolve_t h, const double *const *u, double *const *y)
 {
     if (!h) return fail(nullptr, FRACSOLVE_E_ARG, "handle is NULL");
+    if (h->opts.equation != FRACSOLVE_DIFFUSION)
+        return fail(h, FRACSOLVE_E_ARG, "not available for the advection equations");
     int rc;
     if ((rc = check_fields(h, (const void *const *)u, "u", true))) return rc;
     if ((rc = check_fields(h, (const void *const *)y, "y", true))) return rc;
@@ -1276,6 +1336,8 @@ int fracsolve_adjoint(fracsolve_t h, const double *const *g, const double *const
                       const double *const *phi, double *const *dL_df, double *dL_dgamma)
 {
     if (!h) return fail(nullptr, FRACSOLVE_E_ARG, "handle is NULL");
+    if (h->opts.equation != FRACSOLVE_DIFFUSION)
+        return fail(h, FRACSOLVE_E_ARG, "not available for the advection equations");
     int rc;
     if ((rc = check_fields(h, (const void *const *)g, "g", true))) return rc;
     if ((rc = check_fields(h, (const void *const *)dL_df, "dL_df", true))) return rc;
@@ -1327,6 +1389,8 @@ int fracsolve_gmres(fracsolve_t h, const double *const *f, const double *const *
                     double *hist, int32_t hist_cap)
 {
     if (!h) return fail(nullptr, FRACSOLVE_E_ARG, "handle is NULL");
+    if (h->opts.equation != FRACSOLVE_DIFFUSION)
+        return fail(h, FRACSOLVE_E_ARG, "not available for the advection equations");
     int rc;
     if ((rc = check_fields(h, (const void *const *)f, "f", true))) return rc;
     if ((rc = check_fields(h, (const void *const *)u, "u", true))) return rc;

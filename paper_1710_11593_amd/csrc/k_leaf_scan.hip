@@ -360,6 +360,188 @@ __global__ __launch_bounds__(NT) void k_leaf_scan(TaskRef<LeafTask> tr)
     }
 }
 
+// ---- leaf of the advection equations (Schemes 2 and 3) ----
+//
+// The diagonal block is lower bidiagonal, so each time step is one forward
+// recurrence in space,
+//   U_i = g r_i + kappa U_{i-1},   U_0 = 0 (inflow value),
+// Scheme 3: (a_0 + 1/h) U_i - U_{i-1}/h = r_i, g = 1/(a_0 + 1/h), kappa = g/h;
+// Scheme 2: (a_0 + 2/h) U_i + (a_0 - 2/h) U_{i-1} = r_i (twice the scheme,
+//   in the unknowns W = B U, W_i = U_i + U_{i-1}, which carry the history),
+//   g = 1/(a_0 + 2/h), kappa = (2/h - a_0) g.
+// It runs as the forward half of the scan leaf: carry-free local prefixes,
+// row scans by DPP, one LDS exchange of row totals, carries by lane fetch.
+// Table (doubles): [0] g, [1] kappa, [8 + s] m^(2^s) with m = kappa^PT,
+// [24 + k] kappa^(k+1).
+constexpr int ADV_TAB = 40;
+
+template <int PT>
+__global__ void k_adv_factor(double a0, double h, int scheme2, double *__restrict__ tab)
+{
+    if (threadIdx.x != 0) return;
+    // d = a_0 h / 2 (Scheme 2) or a_0 h (Scheme 3); kappa = (1 - d)/(1 + d)
+    // or 1/(1 + d), its powers from log|kappa| (log1p keeps d exact when small)
+    const double d = scheme2 ? 0.5 * a0 * h : a0 * h;
+    double g, lk, sgn = 1.0;
+    bool zero = false;
+    if (scheme2) {
+        g = 0.5 * h / (1.0 + d);
+        if (d < 1.0)
+            lk = log1p(-d) - log1p(d);
+        else if (d > 1.0) {
+            lk = log(d - 1.0) - log1p(d);
+            sgn = -1.0;
+        } else {
+            lk = 0.0;
+            zero = true;
+        }
+    } else {
+        g = h / (1.0 + d);
+        lk = -log1p(d);
+    }
+    auto kpow = [&](double n) -> double {  // kappa^n, n >= 1 integral
+        if (zero) return 0.0;
+        const double v = exp(n * lk);
+        return (sgn < 0.0 && fmod(n, 2.0) == 1.0) ? -v : v;
+    };
+    tab[0] = g;
+    tab[1] = kpow(1.0);
+    for (int s = 0; s < 16; ++s) tab[8 + s] = kpow((double)PT * (double)(1 << s));
+    for (int k = 0; k < 16; ++k) tab[24 + k] = kpow((double)(k + 1));
+}
+
+// inclusive forward scan over the 16 lanes of each row, lane multiplier c
+template <int NL>
+__device__ __forceinline__ void row_scan_fwd(double &f, const double *cp)
+{
+    f = fma(cp[0], dpp_move<0x111>(f), f);
+    if constexpr (NL > 2) f = fma(cp[1], dpp_move<0x112>(f), f);
+    if constexpr (NL > 4) f = fma(cp[2], dpp_move<0x114>(f), f);
+    if constexpr (NL > 8) f = fma(cp[3], dpp_move<0x118>(f), f);
+}
+
+// One workgroup per task.  Thread t owns columns c0 = t PT .. c0 + PT - 1 in
+// natural order.  WSUM (Scheme 2): x holds W (right-hand sides in, W = B U
+// out) and u receives U; otherwise x is U in place.  The in-leaf history
+// pushes -a_m X into the later rows.
+template <int NT, int PT, int L, bool WSUM>
+__global__ __launch_bounds__(NT) void k_leaf_adv(TaskRef<AdvTask> tr)
+{
+    constexpr int NR = NT / 16;
+    static_assert(NR <= 32, "at most 512 threads");
+    __shared__ double sR[2][NR];
+    const AdvTask tk = get_task(tr, blockIdx.x);
+    const int t = threadIdx.x, lane = t & 63, rl = lane & 15, G = t >> 4;
+    FS_G const double *__restrict__ tab = gptr(tk.fac);
+    const int64_t M = tk.M;
+    const int c0 = t * PT;
+    const int nrows = tk.nrows;
+    FS_G double *__restrict__ x = gptr(tk.x) + tk.lo * M;
+    FS_G double *__restrict__ u = WSUM ? gptr(tk.u) + tk.lo * M : nullptr;
+    double acc[L][PT];
+#pragma unroll
+    for (int r = 0; r < L; ++r) {
+#pragma unroll
+        for (int k = 0; k < PT; ++k) acc[r][k] = (r < nrows && c0 + k < M) ? x[(int64_t)r * M + c0 + k] : 0.0;
+    }
+    const double g = tab[0];
+    const double kap = tab[1];
+    double mp[4], cp[5], kp[PT];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) mp[s] = tab[8 + s];
+#pragma unroll
+    for (int s = 0; s < 5; ++s) cp[s] = tab[12 + s];
+#pragma unroll
+    for (int k = 0; k < PT; ++k) kp[k] = tab[24 + k];
+    double aw[L];
+#pragma unroll
+    for (int m = 0; m < L; ++m) aw[m] = (m > 0) ? gptr(tk.a)[m] : 0.0;
+    double mpw[5] = {mp[0], mp[1], mp[2], mp[3], 0.0};
+    const double m_lo = pow_bits(mpw, rl);
+    const double c_b15 = pow_bits(cp, (lane & 15) + 1);
+
+#pragma unroll
+    for (int r = 0; r < L; ++r) {
+        if (r >= nrows) break;
+        const int par = r & 1;
+        double lf[PT];
+        lf[0] = g * acc[r][0];
+#pragma unroll
+        for (int k = 1; k < PT; ++k) lf[k] = fma(kap, lf[k - 1], g * acc[r][k]);
+        double Sf = lf[PT - 1];
+        row_scan_fwd<16>(Sf, mp);
+        if (rl == 15) sR[par][G] = Sf;
+        __syncthreads();
+        double vf = (lane < NR) ? sR[par][lane] : 0.0;
+        row_scan_fwd<(NR < 16 ? NR : 16)>(vf, cp);
+        if constexpr (NR > 16) vf = fma(c_b15, dpp_move<0x142, 0xA>(vf), vf);
+        double Cr = lane_fetch(vf, G > 0 ? G - 1 : 0);
+        Cr = (G > 0) ? Cr : 0.0;
+        // U at the column before the thread's first one (0 at the inflow)
+        const double cf = fma(m_lo, Cr, dpp_move<0x111>(Sf));
+        double U[PT], X[PT];
+#pragma unroll
+        for (int k = 0; k < PT; ++k) U[k] = fma(kp[k], cf, lf[k]);
+#pragma unroll
+        for (int k = 0; k < PT; ++k) X[k] = WSUM ? U[k] + (k > 0 ? U[k - 1] : cf) : U[k];
+#pragma unroll
+        for (int k = 0; k < PT; ++k) {
+            if (c0 + k < M) {
+                x[(int64_t)r * M + c0 + k] = X[k];
+                if (WSUM) u[(int64_t)r * M + c0 + k] = U[k];
+            }
+        }
+#pragma unroll
+        for (int j = r + 1; j < L; ++j) {
+#pragma unroll
+            for (int k = 0; k < PT; ++k) acc[j][k] = fma(-aw[j - r], X[k], acc[j][k]);
+        }
+    }
+}
+
+hipError_t launch_adv_factor(hipStream_t st, const LeafCfg &c, double a0, double h, bool scheme2, double *tab)
+{
+    switch (c.pt) {
+        case 2: hipLaunchKernelGGL(k_adv_factor<2>, dim3(1), dim3(64), 0, st, a0, h, scheme2 ? 1 : 0, tab); break;
+        case 4: hipLaunchKernelGGL(k_adv_factor<4>, dim3(1), dim3(64), 0, st, a0, h, scheme2 ? 1 : 0, tab); break;
+        case 8: hipLaunchKernelGGL(k_adv_factor<8>, dim3(1), dim3(64), 0, st, a0, h, scheme2 ? 1 : 0, tab); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+size_t adv_table_doubles() { return ADV_TAB; }
+
+template <int NT, int PT, int L>
+static hipError_t adv_go(hipStream_t st, bool wsum, const TaskRef<AdvTask> &d_tasks, int ntasks)
+{
+    if (wsum)
+        hipLaunchKernelGGL((k_leaf_adv<NT, PT, L, true>), dim3(ntasks), dim3(NT), 0, st, d_tasks);
+    else
+        hipLaunchKernelGGL((k_leaf_adv<NT, PT, L, false>), dim3(ntasks), dim3(NT), 0, st, d_tasks);
+    return hipGetLastError();
+}
+
+hipError_t launch_leaf_adv(hipStream_t st, const LeafCfg &c, int L, const TaskRef<AdvTask> &d_tasks, int ntasks,
+                           bool wsum)
+{
+#define FS_AL(NT_, PT_)                                                             \
+    if (c.nt == NT_ && c.pt == PT_) {                                               \
+        if (L == 4) return adv_go<NT_, PT_, 4>(st, wsum, d_tasks, ntasks);          \
+        if (L == 8) return adv_go<NT_, PT_, 8>(st, wsum, d_tasks, ntasks);          \
+        return hipErrorInvalidValue;                                                \
+    }
+    FS_AL(64, 2)
+    FS_AL(64, 4)
+    FS_AL(128, 4)
+    FS_AL(256, 4)
+    FS_AL(512, 4)
+    FS_AL(512, 8)
+    FS_AL(256, 8)
+#undef FS_AL
+    return hipErrorInvalidValue;
+}
+
 // Up to 512 threads (two waves per SIMD) with 2, 4 or 8 rows per thread: the
 // leaf's right-hand sides (L x PT doubles per thread) stay in registers and
 // each thread's rows are whole 16-byte units.  For 1024 < M <= 2048 a single

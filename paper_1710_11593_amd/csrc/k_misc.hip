@@ -13,6 +13,29 @@ static inline unsigned nblocks_for(int64_t n, int bs)
     return (unsigned)nb;
 }
 
+// Scheme 2 of the advection equation, twice the scheme's right-hand side in
+// the unknowns W = B U: y[n][i] = 2 f[n][i] - rho_n (u0[i] + u0[i-1]), with
+// u0 at the inflow point taken as 0.
+__global__ void k_rhs_adv2(const double *__restrict__ f, const double *__restrict__ u0,
+                           const double *__restrict__ rho, double *__restrict__ y, int64_t M, int64_t total)
+{
+    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t n = idx / M, i = idx - n * M;
+        double v = 2.0 * f[idx];
+        if (u0) v -= rho[n] * (u0[i] + (i > 0 ? u0[i - 1] : 0.0));
+        y[idx] = v;
+    }
+}
+
+hipError_t launch_rhs_adv2(hipStream_t st, const double *f, const double *u0, const double *rho, double *y,
+                           int64_t M, int64_t N)
+{
+    const int64_t total = M * N;
+    hipLaunchKernelGGL(k_rhs_adv2, dim3(nblocks_for(total, 256)), dim3(256), 0, st, f, u0, rho, y, M, total);
+    return hipGetLastError();
+}
+
 // u[n][i] = f[n][i] - rho_n u0[i] + psi_n phi[i]   (right-hand side of step n+1)
 __global__ void k_rhs(const double *__restrict__ f, const double *__restrict__ u0, const double *__restrict__ phi,
                       const double *__restrict__ rho, const double *__restrict__ psi, double *__restrict__ u,

@@ -82,3 +82,36 @@ def solve(gamma, M, N, F, u0=None, phi=None, T=1.0, x0=0.0, x1=1.0):
             x[i] -= cp[i] * x[i + 1]
         U[n] = x
     return U
+
+
+def solve_adv(gamma, M, N, F, u0=None, phi=None, T=1.0, x0=0.0, x1=1.0):
+    """The advection time stepping of the oracle (Scheme 2 for gamma < 1,
+    Scheme 3 for gamma > 1; inflow value 0) in extended precision."""
+    a, rho, psi = weights(gamma, N, T)
+    h = (np.longdouble(x1) - np.longdouble(x0)) / np.longdouble(M + 1)
+    Fl = np.asarray(F, dtype=np.longdouble)
+    u0l = np.zeros(M, dtype=np.longdouble) if u0 is None else np.asarray(u0, dtype=np.longdouble)
+    phil = None if (phi is None or gamma < 1) else np.asarray(phi, dtype=np.longdouble)
+
+    def shift(v):  # v_{i-1}, with 0 at the inflow
+        return np.concatenate(([np.longdouble(0)], v[:-1]))
+
+    U = np.zeros((N, M), dtype=np.longdouble)
+    for n in range(N):
+        if gamma < 1:
+            r = 2 * Fl[n] - rho[n] * (u0l + shift(u0l))
+            for j in range(n):
+                r = r - a[n - j] * (U[j] + shift(U[j]))
+            lo, di = a[0] - 2 / h, a[0] + 2 / h
+        else:
+            r = Fl[n] - rho[n] * u0l
+            if phil is not None:
+                r = r + psi[n] * phil
+            for j in range(n):
+                r = r - a[n - j] * U[j]
+            lo, di = -1 / h, a[0] + 1 / h
+        pv = np.longdouble(0)
+        for i in range(M):
+            U[n, i] = (r[i] - lo * pv) / di
+            pv = U[n, i]
+    return U
