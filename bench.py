@@ -19,7 +19,8 @@ each), which sets most of the solve time.
 forms (unless --no-forms): mixed precision (c3), batching (c4), the adjoint
 (c5) and the paper's own iterative method, restarted GMRES(m), on its
 Example 4 meshes next to the recursive solve (--config gmres runs only that;
-with --N 2^k only the mesh h = tau = 2^-k).
+with --N 2^k only the mesh h = tau = 2^-k), and the advection equations
+(Schemes 2 and 3) on the paper's timing meshes (--config advection).
 cpu_baseline: the oracle (plain time stepping) on the same workload for the
 first --cpu-steps steps at full width; its wall time is scaled by
 (N / steps)^2 (the history work is quadratic in the step count) to the full
@@ -273,7 +274,69 @@ def run_forms(dev):
                          "dL_df_error_vs_oracle": err_l}
     log("forms: c5 forward %.1f ms, adjoint %.1f ms, dL/df err %.3e, dL/dgamma %.6e" % (ms_f, ms_a, err_l, dgamma))
     out["gmres_example4"] = run_gmres(dev)
+    out["advection"] = run_advection(dev)
     return out
+
+
+# The paper's timing tables for the advection schemes (h = tau = 2^-k): CPU
+# seconds of its fast method on a Matlab PC; context only.
+PAPER_ADV_FAST_S = {2: {7: 0.17, 8: 0.43, 9: 1.49, 10: 5.56, 11: 21.4, 12: 399.0},
+                    3: {6: 0.14, 7: 0.23, 8: 0.57, 9: 2.01, 10: 6.67, 11: 27.4, 12: 573.0}}
+
+
+def run_advection(dev, meshes=(6, 7, 8, 9, 10, 11, 12), oracle_upto=10):
+    """The advection equations on the paper's timing meshes h = tau = 2^-k:
+    Scheme 2 (gamma = 0.9, Example 2 data u = t sin(pi x)) and Scheme 3
+    (gamma = 1.5, Example 3 data u = t^3 x (1 - x)).  Time of the recursive
+    solve, L2 error at t = T against the exact solution (the paper's
+    measure), and the max-norm distance to the oracle's time stepping where
+    that finishes in seconds (k <= oracle_upto)."""
+    import numpy as np
+    import torch
+
+    import oracle
+    from paper_1710_11593_amd import binding
+
+    res = {}
+    for scheme, gamma in ((2, 0.9), (3, 1.5)):
+        rows = {}
+        for k in meshes:
+            if k not in PAPER_ADV_FAST_S[scheme]:
+                continue
+            Mp = N = 2 ** k
+            M, h = Mp - 1, 1.0 / Mp
+            x = h * np.arange(1, Mp)
+            if scheme == 2:
+                t = np.arange(1, N + 1) / N
+                xm = x - h / 2
+                f = (np.outer(t ** (1 - gamma) / math.gamma(2 - gamma), np.sin(np.pi * xm))
+                     + np.outer(np.pi * t, np.cos(np.pi * xm)))
+                exact = np.sin(np.pi * x)
+            else:
+                th = (np.arange(1, N + 1) - 0.5) / N
+                f = (np.outer(6 * th ** (3 - gamma) / math.gamma(4 - gamma), x - x * x)
+                     + np.outer(th ** 3, 1 - 2 * x))
+                exact = x * (1 - x)
+            fd = torch.from_numpy(f).to(dev)
+            sv = binding.Solver([dict(gamma=gamma, M=M, N=N)], equation="advection")
+            u = torch.empty_like(fd)
+            run = lambda: sv.solve([fd], out=[u])  # noqa: E731
+            run()
+            ms = timed(run, 3)
+            sv.close()
+            un = u.cpu().numpy()
+            row = {"M": M, "N": N, "ms": round(ms, 3), "unknowns_per_s": M * N / (ms * 1e-3),
+                   "l2_error_at_T": math.sqrt(h * np.sum((un[-1] - exact) ** 2)),
+                   "paper_fast_method_cpu_s": PAPER_ADV_FAST_S[scheme][k]}
+            if k <= oracle_upto:
+                ref = oracle.solve_adv(gamma, 1.0, 0.0, 1.0, M, N, f)
+                row["error_vs_oracle"] = float(np.max(np.abs(un - ref)) / np.max(np.abs(ref)))
+            rows["h=tau=2^-%d" % k] = row
+            log("forms: advection scheme %d gamma %.1f h=tau=2^-%d: %.3f ms, L2 err %.3e%s" % (
+                scheme, gamma, k, ms, row["l2_error_at_T"],
+                ", vs oracle %.2e" % row["error_vs_oracle"] if "error_vs_oracle" in row else ""))
+        res["scheme%d_gamma%.1f" % (scheme, gamma)] = rows
+    return res
 
 
 # The paper's timing table for Scheme 4 (gamma = 0.1, h = tau = 2^-k): CPU
@@ -453,6 +516,9 @@ def main():
     dev = torch.device("cuda:0")
     if args.config == "c4":
         return run_batched(args, dev)
+    if args.config == "advection":
+        print(json.dumps({"advection": run_advection(dev)}))
+        return
     if args.config == "gmres":
         # the paper's iterative method on its Example 4 meshes (a form, not the headline)
         meshes = (int(round(math.log2(args.N))),) if args.N else (8, 9, 10)
