@@ -17,6 +17,9 @@ Parity status of each function (what pins it, in tests/test_oracle_*.py):
   mode      -- closed form on linear-in-time data, dense brute force
   solve_adv -- Table 5 and Table 7 of the paper, closed forms on data
                linear in x and t, dense brute force
+  solve_cn, apply_cn, mode_cn
+            -- exactness on (1 + t) sine modes, dense brute force, single-mode
+               reduction, the convergence order 3 - gamma in tau
   gmres     -- finite termination at the dense solve, least-squares estimates
                equal to recomputed residuals, the one-step minimal-residual
                closed form, exact convergence in N steps with the
@@ -69,6 +72,12 @@ def _load():
     lib.oracle_mode.argtypes = [d, d, i64, d, _dp, d, d, _dp]
     lib.oracle_solve_adv.restype = i32
     lib.oracle_solve_adv.argtypes = [d, d, d, d, i64, i64, _dp, _dp, _dp, _dp, i32]
+    lib.oracle_solve_cn.restype = i32
+    lib.oracle_solve_cn.argtypes = [d, d, d, d, i64, i64, _dp, _dp, _dp, _dp, i32]
+    lib.oracle_apply_cn.restype = i32
+    lib.oracle_apply_cn.argtypes = [d, d, d, d, i64, i64, _dp, _dp, i32]
+    lib.oracle_mode_cn.restype = i32
+    lib.oracle_mode_cn.argtypes = [d, d, i64, d, _dp, d, d, _dp]
     lib.oracle_gmres.restype = i32
     lib.oracle_gmres.argtypes = [d, d, d, d, i64, i64, _dp, _dp, _dp, _dp, i32, i32, d, i32, i32,
                                  ctypes.POINTER(i32), _dp, _dp, i32]
@@ -174,6 +183,36 @@ def solve_adv(gamma, T, x0, x1, M, N, f, u0=None, phi=None, nthreads=0):
     _check(lib.oracle_solve_adv(gamma, T, x0, x1, M, N, _ptr(f), _ptr(u0), _ptr(phi), _ptr(u), nthreads),
            "solve_adv")
     return u
+
+
+def solve_cn(gamma, T, x0, x1, M, N, f, u0=None, phi=None, nthreads=0):
+    """Diffusion-wave (1 < gamma < 2) with the spatial term averaged over t_n
+    and t_{n-1}; f sampled at t_{n-1/2}.  Returns U [N][M]."""
+    lib = _load()
+    f = _f64(f, (N, M))
+    u0 = _f64(u0, (M,))
+    phi = _f64(phi, (M,))
+    u = np.zeros((N, M))
+    _check(lib.oracle_solve_cn(gamma, T, x0, x1, M, N, _ptr(f), _ptr(u0), _ptr(phi), _ptr(u), nthreads), "solve_cn")
+    return u
+
+
+def apply_cn(gamma, T, x0, x1, M, N, u, nthreads=0):
+    """y = A u for the system of solve_cn (without the u0/phi terms)."""
+    lib = _load()
+    u = _f64(u, (N, M))
+    y = np.zeros((N, M))
+    _check(lib.oracle_apply_cn(gamma, T, x0, x1, M, N, _ptr(u), _ptr(y), nthreads), "apply_cn")
+    return y
+
+
+def mode_cn(gamma, T, N, lam, g, v0=0.0, phihat=0.0):
+    """Scalar recurrence of one sine mode of solve_cn (length-N result)."""
+    lib = _load()
+    g = _f64(g, (N,))
+    v = np.zeros(N)
+    _check(lib.oracle_mode_cn(gamma, T, N, lam, _ptr(g), v0, phihat, _ptr(v)), "mode_cn")
+    return v
 
 
 def gmres(gamma, T, x0, x1, M, N, f, u0=None, phi=None, restart=30, maxit=1000, rtol=1e-10, precond=0,

@@ -36,7 +36,9 @@
  *   their definition.
  *
  *   Advection equations D_t^gamma u + u_x = f (Schemes 2 and 3, eq. e11-e17)
- *   are stepped by oracle_solve_adv (see there).
+ *   are stepped by oracle_solve_adv, and the diffusion-wave variant with the
+ *   spatial term averaged over t_n and t_{n-1} by oracle_solve_cn (see
+ *   there).
  *
  * Layout: time-major [N][M] row-major, entry (n-1)*M + (i-1) is (x_i, t_n),
  * h = (x1-x0)/(M+1), x_i = x0 + i h, tau = T/N.
@@ -443,6 +445,112 @@ int oracle_mode(double gamma, double T, int64_t N, double lam, const double *g,
     for (int64_t n = 1; n <= N; ++n) {
         double s = g[n - 1] - rho[n - 1] * v0 + psi[n - 1] * phihat;
         for (int64_t j = 1; j < n; ++j) s -= a[n - j] * v[j - 1];
+        v[n - 1] = s / d;
+    }
+    free(a); free(rho); free(psi);
+    return ORACLE_OK;
+}
+
+/*
+ * Diffusion-wave equation (1<gamma<2) with the spatial term averaged over
+ * t_n and t_{n-1} (Crank-Nicolson in the spatial term, the form of the
+ * Sun-Wu scheme cited with eq. e15): for n = 1..N, with U^0 = u0,
+ *   a_0 U^n + sum_{j=1}^{n-1} a_{n-j} U^j + (1/2) K (U^n + U^{n-1})
+ *     = f(x_i, t_{n-1/2}) - rho_n u0 + psi_n phi,
+ * the weights being those of oracle_weights.  Stepped with one Thomas solve
+ * of a_0 I + K/2 per step.
+ */
+int oracle_solve_cn(double gamma, double T, double x0, double x1, int64_t M, int64_t N,
+                    const double *f, const double *u0, const double *phi, double *u, int nthreads)
+{
+    if (regime_of(gamma) != 1 || !(T > 0.0) || !(x1 > x0) || M < 1 || N < 1 || !f || !u) return ORACLE_EARG;
+    set_threads(nthreads);
+    const double h = (x1 - x0) / (double)(M + 1);
+    const double e = 1.0 / (h * h);
+    double *a = (double *)malloc(sizeof(double) * (size_t)N);
+    double *rho = (double *)malloc(sizeof(double) * (size_t)N);
+    double *psi = (double *)malloc(sizeof(double) * (size_t)N);
+    double *cp = (double *)malloc(sizeof(double) * (size_t)M);
+    double *inv = (double *)malloc(sizeof(double) * (size_t)M);
+    double *zero = (double *)calloc((size_t)M, sizeof(double));
+    if (!a || !rho || !psi || !cp || !inv || !zero) {
+        free(a); free(rho); free(psi); free(cp); free(inv); free(zero);
+        return ORACLE_ENOMEM;
+    }
+    oracle_weights(gamma, T, N, NULL, a, rho, psi, NULL, NULL, NULL, NULL);
+    thomas_factor(M, a[0] + e, -0.5 * e, cp, inv);
+    for (int64_t n = 1; n <= N; ++n) {
+        double *r = u + (size_t)(n - 1) * (size_t)M;
+        const double *fn = f + (size_t)(n - 1) * (size_t)M;
+        const double *prev = (n == 1) ? (u0 ? u0 : zero) : u + (size_t)(n - 2) * (size_t)M;
+        #pragma omp parallel for schedule(static)
+        for (int64_t i = 0; i < M; ++i) {
+            double s = fn[i];
+            if (u0) s -= rho[n - 1] * u0[i];
+            if (phi) s += psi[n - 1] * phi[i];
+            for (int64_t j = 1; j < n; ++j) s -= a[n - j] * u[(size_t)(j - 1) * (size_t)M + (size_t)i];
+            /* (1/2) K U^{n-1} */
+            double left = (i > 0) ? prev[i - 1] : 0.0;
+            double right = (i + 1 < M) ? prev[i + 1] : 0.0;
+            s -= 0.5 * e * (2.0 * prev[i] - left - right);
+            r[i] = s;
+        }
+        thomas_solve(M, -0.5 * e, cp, inv, r);
+    }
+    free(a); free(rho); free(psi); free(cp); free(inv); free(zero);
+    return ORACLE_OK;
+}
+
+/* y = A u for the system of oracle_solve_cn (no u0 / phi terms):
+ *   y^n = a_0 U^n + sum_{j<n} a_{n-j} U^j + (1/2) K U^n + (1/2) K U^{n-1} [n >= 2]. */
+int oracle_apply_cn(double gamma, double T, double x0, double x1, int64_t M, int64_t N,
+                    const double *u, double *y, int nthreads)
+{
+    if (regime_of(gamma) != 1 || !(T > 0.0) || !(x1 > x0) || M < 1 || N < 1 || !u || !y) return ORACLE_EARG;
+    set_threads(nthreads);
+    const double h = (x1 - x0) / (double)(M + 1);
+    const double e = 1.0 / (h * h);
+    double *a = (double *)malloc(sizeof(double) * (size_t)N);
+    if (!a) return ORACLE_ENOMEM;
+    oracle_weights(gamma, T, N, NULL, a, NULL, NULL, NULL, NULL, NULL, NULL);
+    for (int64_t n = 1; n <= N; ++n) {
+        const double *un = u + (size_t)(n - 1) * (size_t)M;
+        const double *up = (n >= 2) ? u + (size_t)(n - 2) * (size_t)M : NULL;
+        double *yn = y + (size_t)(n - 1) * (size_t)M;
+        #pragma omp parallel for schedule(static)
+        for (int64_t i = 0; i < M; ++i) {
+            double left = (i > 0) ? un[i - 1] : 0.0;
+            double right = (i + 1 < M) ? un[i + 1] : 0.0;
+            double s = a[0] * un[i] + 0.5 * e * (2.0 * un[i] - left - right);
+            if (up) {
+                double pl = (i > 0) ? up[i - 1] : 0.0;
+                double pr = (i + 1 < M) ? up[i + 1] : 0.0;
+                s += 0.5 * e * (2.0 * up[i] - pl - pr);
+            }
+            for (int64_t j = 1; j < n; ++j) s += a[n - j] * u[(size_t)(j - 1) * (size_t)M + (size_t)i];
+            yn[i] = s;
+        }
+    }
+    free(a);
+    return ORACLE_OK;
+}
+
+/* One sine mode of oracle_solve_cn (eigenvalue lam of K, v^0 = v0):
+ *   (a_0 + lam/2) v^n = g^n - rho_n v0 + psi_n phihat - sum_{j<n} a_{n-j} v^j - (lam/2) v^{n-1}. */
+int oracle_mode_cn(double gamma, double T, int64_t N, double lam, const double *g, double v0, double phihat,
+                   double *v)
+{
+    if (regime_of(gamma) != 1 || !(T > 0.0) || N < 1 || !g || !v) return ORACLE_EARG;
+    double *a = (double *)malloc(sizeof(double) * (size_t)N);
+    double *rho = (double *)malloc(sizeof(double) * (size_t)N);
+    double *psi = (double *)malloc(sizeof(double) * (size_t)N);
+    if (!a || !rho || !psi) { free(a); free(rho); free(psi); return ORACLE_ENOMEM; }
+    oracle_weights(gamma, T, N, NULL, a, rho, psi, NULL, NULL, NULL, NULL);
+    const double d = a[0] + 0.5 * lam;
+    for (int64_t n = 1; n <= N; ++n) {
+        double s = g[n - 1] - rho[n - 1] * v0 + psi[n - 1] * phihat;
+        for (int64_t j = 1; j < n; ++j) s -= a[n - j] * v[j - 1];
+        s -= 0.5 * lam * (n == 1 ? v0 : v[n - 2]);
         v[n - 1] = s / d;
     }
     free(a); free(rho); free(psi);
