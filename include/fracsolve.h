@@ -89,7 +89,7 @@ typedef struct {
 /* Equation of every instance of a handle. */
 enum {
     FRACSOLVE_DIFFUSION = 0,  /* D_t^gamma u = u_xx + f (the system above)      */
-    FRACSOLVE_ADVECTION = 1   /* D_t^gamma u + u_x = f with inflow value
+    FRACSOLVE_ADVECTION = 1,  /* D_t^gamma u + u_x = f with inflow value
                                  u(x0, t) = 0 (section 3, eq. e11-e17): Scheme 2
                                  for 0<gamma<1 (L1 formula averaged over x_i and
                                  x_{i-1}, difference (U_i - U_{i-1})/h, both at
@@ -100,6 +100,14 @@ enum {
                                  bidiagonal; the history keeps the scalar
                                  Toeplitz form (for Scheme 2 in W = B U,
                                  (B U)_i = U_i + U_{i-1}).  Float64 solves only. */
+    FRACSOLVE_DIFFUSION_CN = 2  /* 1<gamma<2 only: the diffusion-wave equation
+                                 with the spatial term averaged over t_n and
+                                 t_{n-1} (Crank-Nicolson in the spatial term,
+                                 the form of the Sun-Wu scheme cited with eq.
+                                 e15): (a_0 I + K/2) U^n + (a_1 I + K/2) U^{n-1}
+                                 + sum_{j<n-1} a_{n-j} U^j = F^n - rho_n u0
+                                 + psi_n phi - [n = 1] (K/2) u0.  Float64;
+                                 solve, apply, adjoint and GMRES.           */
 };
 
 typedef struct {
@@ -115,11 +123,11 @@ typedef struct {
                              0 = closed-form inverse by parallel scan (default),
                              1 = block Thomas + parallel cyclic reduction      */
     void *stream;         /* hipStream_t for all work; NULL = null stream      */
-    int32_t equation;     /* FRACSOLVE_DIFFUSION (0) or FRACSOLVE_ADVECTION;
-                             ADVECTION needs precision FP64 and leaf_solver 0,
-                             and supports fracsolve_solve and
-                             fracsolve_weights only (the other entry points
-                             return E_ARG)                                     */
+    int32_t equation;     /* FRACSOLVE_DIFFUSION (0), FRACSOLVE_ADVECTION (1)
+                             or FRACSOLVE_DIFFUSION_CN (2); 1 and 2 need
+                             precision FP64 and leaf_solver 0.  ADVECTION
+                             supports fracsolve_solve and fracsolve_weights
+                             only (the other entry points return E_ARG)       */
 } fracsolve_options;
 
 /*

@@ -18,7 +18,7 @@ LIBPATH = os.path.join(HERE, "csrc", "libfracsolve.so")
 FRACSOLVE_OK = 0
 STATUS = {0: "OK", -1: "E_ARG", -2: "E_NOMEM", -3: "E_DEVICE", -4: "E_NUMERIC", -5: "E_STATE"}
 PRECISION = {"fp64": 0, "fp32": 1, "bf16x3": 2}
-EQUATION = {"diffusion": 0, "advection": 1}
+EQUATION = {"diffusion": 0, "advection": 1, "diffusion_cn": 2}
 
 
 class Problem(ctypes.Structure):

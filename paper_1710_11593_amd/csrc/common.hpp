@@ -164,6 +164,19 @@ __host__ __device__ inline int corner_width(int s) { return s < 32 ? s : 32; }
 hipError_t launch_weights(hipStream_t st, int regime, double p, double coef, double dcoef, double tau,
                           int64_t N, double *b, double *a, double *rho, double *psi, double *da,
                           double *drho, double *dpsi);
+// Lag-1 spatial term of the averaged variant: y_row += coef (2 x_i - x_{i-1}
+// - x_{i+1}) over the spatial order (fields in column order perm), one task
+// per row pair; and the same over nrows consecutive row pairs.
+struct Lag1Task {
+    const double *x;  // source row [M]
+    double *y;        // destination row [M]
+    int64_t M;
+    double coef;
+    ColPerm perm;
+};
+hipError_t launch_halfK_tasks(hipStream_t st, const Lag1Task *d_tasks, int ntasks, int64_t maxM);
+hipError_t launch_halfK_rows(hipStream_t st, const double *x, double *y, int64_t M, int64_t nrows, double coef,
+                             ColPerm perm);
 hipError_t launch_rhs_adv2(hipStream_t st, const double *f, const double *u0, const double *rho, double *y,
                            int64_t M, int64_t N);
 hipError_t launch_rhs(hipStream_t st, const double *f, const double *u0, const double *phi,
@@ -192,7 +205,7 @@ size_t adv_table_doubles();
 hipError_t launch_leaf_adv(hipStream_t st, const LeafCfg &c, int L, const TaskRef<AdvTask> &d_tasks, int ntasks,
                            bool wsum);
 hipError_t launch_leaf_scan(hipStream_t st, const LeafCfg &c, int L, const TaskRef<LeafTask> &tr, int ntasks,
-                            bool mixed, int vec);
+                            bool mixed, int vec, bool cn = false);
 
 hipError_t launch_twiddles(hipStream_t st, int64_t nmax, cplx<double> *w64, cplx<float> *w32);
 

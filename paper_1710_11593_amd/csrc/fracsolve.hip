@@ -35,6 +35,7 @@ struct Inst {
     LeafCfg lc{};
     bool scan = true;  // leaf solver: closed-form scan (true) or block Thomas + PCR
     int adv = 0;       // advection equations: 2 = Scheme 2 (gamma < 1), 3 = Scheme 3; 0 = diffusion
+    bool cn = false;   // diffusion-wave with the spatial term averaged over t_n and t_{n-1}
     ColPerm perm{0, 0};  // internal column order of the solve's fields
     double *b = nullptr, *a = nullptr, *rho = nullptr, *psi = nullptr;
     double *da = nullptr, *drho = nullptr, *dpsi = nullptr;
@@ -222,7 +223,7 @@ const T *dptr(fracsolve_ctx *h, size_t off)
 }
 
 // ---- one call = a list of launch records built on the host, then replayed.
-enum OpKind { OP_LEAF, OP_LEAF_SCAN, OP_GEMM64, OP_GEMM32, OP_FFT64, OP_FFT32, OP_LEAF_ADV };
+enum OpKind { OP_LEAF, OP_LEAF_SCAN, OP_GEMM64, OP_GEMM32, OP_FFT64, OP_FFT32, OP_LEAF_ADV, OP_LAG1 };
 struct Op {
     OpKind kind;
     size_t off;   // descriptor offset
@@ -236,6 +237,7 @@ struct Op {
     size_t goff = 0;     // single-pass FFT levels: descriptor offset of the group offsets
     int lead = 0;        // dense levels of a solve: rows the next leaf reads first
     bool wsum = false;   // advection leaves: Scheme 2 (X = B U, U to its own field)
+    bool cn = false;     // scan leaves: the lag-1 spatial term of the averaged variant
 };
 
 // Flat column-group offsets of the tasks of a single-pass FFT level (see
@@ -300,7 +302,11 @@ int run_ops(fracsolve_ctx *h, const std::vector<Op> &ops)
                 e = launch_leaf(h->st, op.lc, h->L, dptr<LeafTask>(h, op.off), op.ntasks, op.mixed);
                 break;
             case OP_LEAF_SCAN:
-                e = launch_leaf_scan(h->st, op.lc, h->L, task_ref<LeafTask>(h, op), op.ntasks, op.mixed, op.lc.vec);
+                e = launch_leaf_scan(h->st, op.lc, h->L, task_ref<LeafTask>(h, op), op.ntasks, op.mixed, op.lc.vec,
+                                     op.cn);
+                break;
+            case OP_LAG1:
+                e = launch_halfK_tasks(h->st, dptr<Lag1Task>(h, op.off), op.ntasks, op.maxM);
                 break;
             case OP_LEAF_ADV:
                 e = launch_leaf_adv(h->st, op.lc, h->L, task_ref<AdvTask>(h, op), op.ntasks, op.wsum);
@@ -330,7 +336,12 @@ int run_ops(fracsolve_ctx *h, const std::vector<Op> &ops)
         if (h->timing >= 2) {
             HIPCHK(h, hipEventRecord(h->evpool[evi + 1], h->st));
             const bool lf = op.kind == OP_LEAF || op.kind == OP_LEAF_SCAN || op.kind == OP_LEAF_ADV;
-            int kind = lf ? 0 : op.kind == OP_GEMM64 ? 1 : op.kind == OP_GEMM32 ? 2 : op.kind == OP_FFT64 ? 3 : 4;
+            int kind = lf                       ? 0
+                       : op.kind == OP_GEMM64   ? 1
+                       : op.kind == OP_GEMM32   ? 2
+                       : op.kind == OP_FFT64    ? 3
+                       : op.kind == OP_LAG1     ? 5
+                                                : 4;
             h->recs.push_back({kind, lf ? h->L : op.s, op.ntasks, op.bytes, evi});
             // the near-corner band of an FFT level as a group of its own:
             // X rows s-31..s-1, Y rows 0..30 read and written
@@ -387,6 +398,7 @@ uint64_t ops_key(const std::vector<Op> &ops, const void *d_desc)
         mix((uint64_t)op.lead);
         mix((uint64_t)op.lc.vec);
         mix((uint64_t)op.wsum);
+        mix((uint64_t)op.cn);
     }
     mix((uint64_t)ops.size());
     return hsh;
@@ -522,6 +534,7 @@ void build_solve(fracsolve_ctx *h, const std::vector<int> &sel, const std::vecto
             // one launch per configuration: vector rows for all, for none, or per task
             lc.vec = nvec == (int)v.size() ? 1 : (nvec == 0 ? 0 : 2);
             Op op{lt[b].first >= 1000000 ? OP_LEAF_SCAN : OP_LEAF, off, (int)v.size(), 0, 0, lc, mixed};
+            op.cn = (h->opts.equation == FRACSOLVE_DIFFUSION_CN);
             for (auto &t : v) op.bytes += (double)t.nrows * (double)t.M * (mixed ? 24.0 : 16.0);
             ops.push_back(op);
             b = e;
@@ -596,6 +609,24 @@ void build_solve(fracsolve_ctx *h, const std::vector<int> &sel, const std::vecto
                     op.bytes += upd_bytes(t, 8);
                     op.even = op.even && pairs_aligned(t);
                 }
+                ops.push_back(op);
+            }
+        }
+        if (h->opts.equation == FRACSOLVE_DIFFUSION_CN) {
+            // lag-1 block a_1 I + K/2: its K/2 part from the last row of the
+            // block to the first row of the next leaf
+            std::vector<Lag1Task> lg;
+            int64_t lm = 0;
+            for (size_t q = 0; q < sel.size(); ++q) {
+                const Inst &in = h->inst[sel[q]];
+                if (mid >= in.N) continue;
+                lg.push_back(Lag1Task{fld[q].u + (mid - 1) * in.M, fld[q].u + mid * in.M, in.M, -0.5 * in.e, in.perm});
+                lm = std::max(lm, in.M);
+            }
+            if (!lg.empty()) {
+                Op op{OP_LAG1, db.add(lg.data(), lg.size() * sizeof(Lag1Task)), (int)lg.size(), (int)s, lm, {}, false};
+                op.bytes = 0.0;
+                for (auto &g : lg) op.bytes += 3.0 * (double)g.M * 8.0;
                 ops.push_back(op);
             }
         }
@@ -704,14 +735,21 @@ int dc_solve(fracsolve_ctx *h, const std::vector<int> &sel, const std::vector<Fi
 int apply_op(fracsolve_ctx *h, int i, const double *x, double *y, bool deriv, ColPerm perm)
 {
     Inst &in = h->inst[i];
-    HIPCHK(h, launch_diag_apply(h->st, x, y, deriv ? in.da : in.a, deriv ? 0.0 : in.e, in.M, in.N, h->L, perm));
+    const double eb = in.cn ? 0.5 * in.e : in.e;  // K's coefficient in the diagonal block
+    HIPCHK(h, launch_diag_apply(h->st, x, y, deriv ? in.da : in.a, deriv ? 0.0 : eb, in.M, in.N, h->L, perm));
     h->kernels++;
     DescBuilder db{h, {}};
     std::vector<Op> ops;
     build_apply_levels(h, in, x, y, deriv, db, ops);
     int rc = desc_upload(h, db);
     if (rc) return rc;
-    return run_ops_any(h, ops);
+    if ((rc = run_ops_any(h, ops))) return rc;
+    if (in.cn && !deriv && in.N > 1) {
+        // (K/2) U^{n-1} in row n
+        HIPCHK(h, launch_halfK_rows(h->st, x, y + in.M, in.M, in.N - 1, 0.5 * in.e, perm));
+        h->kernels++;
+    }
+    return FRACSOLVE_OK;
 }
 
 // sum of a device reduction written as per-block partials
@@ -790,6 +828,7 @@ int setup_instance(fracsolve_ctx *h, Inst &in)
     in.coef = std::pow(in.tau, -p.gamma) / std::tgamma(garg);
     in.dcoef = in.coef * (-std::log(in.tau) + digamma_host(garg));
     in.adv = (h->opts.equation == FRACSOLVE_ADVECTION) ? (in.regime == 0 ? 2 : 3) : 0;
+    in.cn = (h->opts.equation == FRACSOLVE_DIFFUSION_CN);
     in.scan = (h->opts.leaf_solver == 0) || in.adv;
     in.lc = in.scan ? scan_config(h->batch_M > 0 ? h->batch_M : in.M, h->batch_M > 0) : leaf_config(in.M);
     if (!in.adv && in.scan && in.lc.pt > 2 && in.M % in.lc.pt == 0)
@@ -816,7 +855,8 @@ int setup_instance(fracsolve_ctx *h, Inst &in)
         HIPCHK(h, launch_adv_factor(h->st, in.lc, in.coef, in.h, in.adv == 2, in.fac));
     } else if (in.scan) {
         if ((rc = dalloc(h, &in.fac, scan_table_doubles(in.lc)))) return rc;
-        HIPCHK(h, launch_scan_factor(h->st, in.lc, in.M, in.coef, in.e, in.fac));
+        // averaged variant: diagonal block a_0 I + K/2
+        HIPCHK(h, launch_scan_factor(h->st, in.lc, in.M, in.coef, in.cn ? 0.5 * in.e : in.e, in.fac));
     } else {
         if ((rc = dalloc(h, &in.fac, leaf_table_doubles(in.lc)))) return rc;
         HIPCHK(h, launch_leaf_factor(h->st, in.lc, in.M, in.coef, in.e, in.fac));
@@ -885,6 +925,11 @@ int solve_all(fracsolve_ctx *h, const double *const *f, const double *const *u0,
         const double *ph = (in.regime == 1) ? opt_ptr(phi, k) : nullptr;
         HIPCHK(h, launch_rhs(h->st, f[k], opt_ptr(u0, k), ph, in.rho, in.psi, u[k], in.M, in.N));
         h->kernels++;
+        if (in.cn && opt_ptr(u0, k)) {
+            // step 1 of the averaged variant carries -(K/2) u0
+            HIPCHK(h, launch_halfK_rows(h->st, opt_ptr(u0, k), u[k], in.M, 1, -0.5 * in.e, ColPerm{0, 0}));
+            h->kernels++;
+        }
         // to the internal column order (in place)
         if (in.perm.mfull > 0) {
             HIPCHK(h, launch_permute(h->st, u[k], u[k], in.M, in.N, in.perm, true, false));
@@ -1040,6 +1085,10 @@ int gmres_one(fracsolve_ctx *h, int k, const double *f, const double *u0, const 
     const double *ph = (in.regime == 1) ? phi : nullptr;
     HIPCHK(h, launch_rhs(h->st, f, u0, ph, in.rho, in.psi, b, in.M, in.N));
     h->kernels++;
+    if (in.cn && u0) {
+        HIPCHK(h, launch_halfK_rows(h->st, u0, b, in.M, 1, -0.5 * in.e, ColPerm{0, 0}));
+        h->kernels++;
+    }
     double bnorm = 0.0;
     if ((rc = dev_norm2(h, b, n, &bnorm))) return rc;
     if (!o.use_guess || bnorm == 0.0) {
@@ -1160,9 +1209,22 @@ int fracsolve_create(const fracsolve_problem *probs, int32_t count, const fracso
         return fail(nullptr, FRACSOLVE_E_ARG, "leaf_solver must be 0 or 1, got %d", (int)o.leaf_solver);
     if (o.leaf != 0 && o.leaf != 4 && o.leaf != 8 && o.leaf != 16)
         return fail(nullptr, FRACSOLVE_E_ARG, "leaf must be 0, 4, 8 or 16, got %d", (int)o.leaf);
-    if (o.equation != FRACSOLVE_DIFFUSION && o.equation != FRACSOLVE_ADVECTION)
-        return fail(nullptr, FRACSOLVE_E_ARG, "equation must be 0 (diffusion) or 1 (advection), got %d",
+    if (o.equation != FRACSOLVE_DIFFUSION && o.equation != FRACSOLVE_ADVECTION &&
+        o.equation != FRACSOLVE_DIFFUSION_CN)
+        return fail(nullptr, FRACSOLVE_E_ARG,
+                    "equation must be 0 (diffusion), 1 (advection) or 2 (diffusion, averaged spatial term), got %d",
                     (int)o.equation);
+    if (o.equation == FRACSOLVE_DIFFUSION_CN) {
+        for (int k = 0; k < count; ++k)
+            if (!(probs[k].gamma > 1.0))
+                return fail(nullptr, FRACSOLVE_E_ARG,
+                            "instance %d: the averaged spatial term is for 1 < gamma < 2, got gamma %g", k,
+                            probs[k].gamma);
+        if (o.precision != FRACSOLVE_FP64)
+            return fail(nullptr, FRACSOLVE_E_ARG, "the averaged spatial term is solved in float64 only (precision 0)");
+        if (o.leaf_solver != 0)
+            return fail(nullptr, FRACSOLVE_E_ARG, "the averaged spatial term needs the scan leaf (leaf_solver 0)");
+    }
     if (o.equation == FRACSOLVE_ADVECTION) {
         if (o.precision != FRACSOLVE_FP64)
             return fail(nullptr, FRACSOLVE_E_ARG, "the advection equations are solved in float64 only (precision 0)");
@@ -1319,7 +1381,7 @@ int fracsolve_solve(fracsolve_t h, const double *const *f, const double *const *
 int fracsolve_apply(fracsolve_t h, const double *const *u, double *const *y)
 {
     if (!h) return fail(nullptr, FRACSOLVE_E_ARG, "handle is NULL");
-    if (h->opts.equation != FRACSOLVE_DIFFUSION)
+    if (h->opts.equation == FRACSOLVE_ADVECTION)
         return fail(h, FRACSOLVE_E_ARG, "not available for the advection equations");
     int rc;
     if ((rc = check_fields(h, (const void *const *)u, "u", true))) return rc;
@@ -1336,7 +1398,7 @@ int fracsolve_adjoint(fracsolve_t h, const double *const *g, const double *const
                       const double *const *phi, double *const *dL_df, double *dL_dgamma)
 {
     if (!h) return fail(nullptr, FRACSOLVE_E_ARG, "handle is NULL");
-    if (h->opts.equation != FRACSOLVE_DIFFUSION)
+    if (h->opts.equation == FRACSOLVE_ADVECTION)
         return fail(h, FRACSOLVE_E_ARG, "not available for the advection equations");
     int rc;
     if ((rc = check_fields(h, (const void *const *)g, "g", true))) return rc;
@@ -1389,7 +1451,7 @@ int fracsolve_gmres(fracsolve_t h, const double *const *f, const double *const *
                     double *hist, int32_t hist_cap)
 {
     if (!h) return fail(nullptr, FRACSOLVE_E_ARG, "handle is NULL");
-    if (h->opts.equation != FRACSOLVE_DIFFUSION)
+    if (h->opts.equation == FRACSOLVE_ADVECTION)
         return fail(h, FRACSOLVE_E_ARG, "not available for the advection equations");
     int rc;
     if ((rc = check_fields(h, (const void *const *)f, "f", true))) return rc;

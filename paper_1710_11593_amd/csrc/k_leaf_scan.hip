@@ -44,7 +44,7 @@ struct slog2<1> {
 };
 
 // Table layout (doubles):
-//   [0] K0, [1] rho,
+//   [0] K0, [1] rho, [2] e,
 //   [8 + s]  m^(2^s), m = rho^PT, s < 16,
 //   [24 + k] rho^(k+1), k < 16,
 //   [SCAN_TAB_ALPHA + r] alpha of row r+1 (r < NT*PT, 0 beyond M), then beta.
@@ -61,6 +61,7 @@ __global__ __launch_bounds__(NT) void k_scan_factor(int64_t M, double a0, double
     if (t == 0) {
         double gam = -expm1(-2.0 * (double)(M + 1) * th);
         tab[0] = 1.0 / (e * 2.0 * sinh(th) * gam);
+        tab[2] = e;  // the coefficient of tridiag(-1, 2, -1) in the block
         tab[1] = exp(-th);
         for (int s = 0; s < 16; ++s) tab[8 + s] = exp(-(double)PT * (double)(1 << s) * th);
         for (int k = 0; k < 16; ++k) tab[SCAN_TAB_POW + k] = exp(-(double)(k + 1) * th);
@@ -133,7 +134,12 @@ __device__ __forceinline__ void row_scans(double &f, double &b, const double *cp
     }
 }
 
-template <int NT, int PT, int L, bool MIXED, int VEC>
+// CN: the lag-1 block is a_1 I + e tridiag(-1, 2, -1) (the spatial term
+// averaged over two time levels; the diagonal block is then a_0 I + e
+// tridiag(-1, 2, -1) with the same e): pushing x_r into the next row also
+// subtracts e (2 x_i - x_{i-1} - x_{i+1}), with the neighbours across
+// threads exchanged through LDS (one more barrier per step).
+template <int NT, int PT, int L, bool MIXED, int VEC, bool CN = false>
 __global__ __launch_bounds__(NT) void k_leaf_scan(TaskRef<LeafTask> tr)
 {
     static_assert(PT % 2 == 0 && PT <= 16, "rows per thread must be even and at most 16");
@@ -142,6 +148,7 @@ __global__ __launch_bounds__(NT) void k_leaf_scan(TaskRef<LeafTask> tr)
     constexpr int MP = NT * PT;
     constexpr int UT = PT / 2;
     __shared__ double sR[2][2][NR];  // [parity][forward/backward][row]
+    __shared__ double sE[CN ? 2 : 1][2][CN ? NT : 1];  // CN: [parity][first/last][thread]
 
     const LeafTask tk = get_task(tr, blockIdx.x);
     const int t = threadIdx.x;
@@ -356,6 +363,21 @@ __global__ __launch_bounds__(NT) void k_leaf_scan(TaskRef<LeafTask> tr)
         if (r + 1 < L) {
 #pragma unroll
             for (int k = 0; k < PT; ++k) acc[r + 1][k] = fma(-aw[1], xp[k], acc[r + 1][k]);
+            if constexpr (CN) {
+                // columns past M hold x = 0 (their alpha and beta are 0), as do the Dirichlet ends
+                sE[par][0][t] = xp[0];
+                sE[par][1][t] = xp[PT - 1];
+                __syncthreads();
+                const double xl = (t > 0) ? sE[par][1][t - 1] : 0.0;
+                const double xr = (t + 1 < NT) ? sE[par][0][t + 1] : 0.0;
+                const double ec = tab[2];
+#pragma unroll
+                for (int k = 0; k < PT; ++k) {
+                    const double lft = (k > 0) ? xp[k - 1] : xl;
+                    const double rgt = (k < PT - 1) ? xp[k + 1] : xr;
+                    acc[r + 1][k] = fma(-ec, 2.0 * xp[k] - lft - rgt, acc[r + 1][k]);
+                }
+            }
         }
     }
 }
@@ -578,21 +600,26 @@ hipError_t launch_scan_factor(hipStream_t st, const LeafCfg &c, int64_t M, doubl
     return hipErrorInvalidValue;
 }
 
-template <int NT, int PT, int L, bool MIXED>
+template <int NT, int PT, int L, bool MIXED, bool CN = false>
 static void scan_go_m(hipStream_t st, int vec, const TaskRef<LeafTask> &d_tasks, int ntasks)
 {
     if (vec == 1)
-        hipLaunchKernelGGL((k_leaf_scan<NT, PT, L, MIXED, 1>), dim3(ntasks), dim3(NT), 0, st, d_tasks);
+        hipLaunchKernelGGL((k_leaf_scan<NT, PT, L, MIXED, 1, CN>), dim3(ntasks), dim3(NT), 0, st, d_tasks);
     else if (vec == 2)
-        hipLaunchKernelGGL((k_leaf_scan<NT, PT, L, MIXED, 2>), dim3(ntasks), dim3(NT), 0, st, d_tasks);
+        hipLaunchKernelGGL((k_leaf_scan<NT, PT, L, MIXED, 2, CN>), dim3(ntasks), dim3(NT), 0, st, d_tasks);
     else
-        hipLaunchKernelGGL((k_leaf_scan<NT, PT, L, MIXED, 0>), dim3(ntasks), dim3(NT), 0, st, d_tasks);
+        hipLaunchKernelGGL((k_leaf_scan<NT, PT, L, MIXED, 0, CN>), dim3(ntasks), dim3(NT), 0, st, d_tasks);
 }
 
+// cn: float64 only (the averaged spatial term is not offered with float32 products)
 template <int NT, int PT, int L>
-static hipError_t scan_go(hipStream_t st, bool mixed, int vec, const TaskRef<LeafTask> &d_tasks, int ntasks)
+static hipError_t scan_go(hipStream_t st, bool mixed, int vec, const TaskRef<LeafTask> &d_tasks, int ntasks,
+                          bool cn)
 {
-    if (mixed)
+    if (cn) {
+        if (mixed) return hipErrorInvalidValue;
+        scan_go_m<NT, PT, L, false, true>(st, vec, d_tasks, ntasks);
+    } else if (mixed)
         scan_go_m<NT, PT, L, true>(st, vec, d_tasks, ntasks);
     else
         scan_go_m<NT, PT, L, false>(st, vec, d_tasks, ntasks);
@@ -600,23 +627,24 @@ static hipError_t scan_go(hipStream_t st, bool mixed, int vec, const TaskRef<Lea
 }
 
 template <int NT, int PT>
-static hipError_t scan_go16(hipStream_t st, bool mixed, int vec, const TaskRef<LeafTask> &d_tasks, int ntasks)
+static hipError_t scan_go16(hipStream_t st, bool mixed, int vec, const TaskRef<LeafTask> &d_tasks, int ntasks,
+                            bool cn)
 {
     if constexpr (PT <= 2)
-        return scan_go<NT, PT, 16>(st, mixed, vec, d_tasks, ntasks);
+        return scan_go<NT, PT, 16>(st, mixed, vec, d_tasks, ntasks, cn);
     else
         return hipErrorInvalidValue;
 }
 
 hipError_t launch_leaf_scan(hipStream_t st, const LeafCfg &c, int L, const TaskRef<LeafTask> &d_tasks, int ntasks,
-                            bool mixed, int vec)
+                            bool mixed, int vec, bool cn)
 {
-#define FS_SL(NT_, PT_)                                                                        \
-    if (c.nt == NT_ && c.pt == PT_) {                                                          \
-        if (L == 4) return scan_go<NT_, PT_, 4>(st, mixed, vec, d_tasks, ntasks);              \
-        if (L == 8) return scan_go<NT_, PT_, 8>(st, mixed, vec, d_tasks, ntasks);              \
-        if (L == 16 && PT_ <= 2) return scan_go16<NT_, PT_>(st, mixed, vec, d_tasks, ntasks);  \
-        return hipErrorInvalidValue;                                                           \
+#define FS_SL(NT_, PT_)                                                                            \
+    if (c.nt == NT_ && c.pt == PT_) {                                                              \
+        if (L == 4) return scan_go<NT_, PT_, 4>(st, mixed, vec, d_tasks, ntasks, cn);              \
+        if (L == 8) return scan_go<NT_, PT_, 8>(st, mixed, vec, d_tasks, ntasks, cn);              \
+        if (L == 16 && PT_ <= 2) return scan_go16<NT_, PT_>(st, mixed, vec, d_tasks, ntasks, cn);  \
+        return hipErrorInvalidValue;                                                               \
     }
     FS_SL(64, 2)
     FS_SL(64, 4)

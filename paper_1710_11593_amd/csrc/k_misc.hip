@@ -13,6 +13,53 @@ static inline unsigned nblocks_for(int64_t n, int bs)
     return (unsigned)nb;
 }
 
+// y[r][i] += coef (2 x[r][i] - x[r][i-1] - x[r][i+1]), r < nrows; the spatial
+// neighbours of memory column i through the column order perm, 0 past the
+// ends (the lag-1 block of the averaged diffusion-wave variant).
+__device__ __forceinline__ double tri_row(const double *__restrict__ xr, int64_t i, int64_t M, ColPerm perm)
+{
+    const int64_t xs = perm_m2s(i, perm);
+    const double left = (xs > 0) ? xr[perm_s2m(xs - 1, perm)] : 0.0;
+    const double right = (xs + 1 < M) ? xr[perm_s2m(xs + 1, perm)] : 0.0;
+    return 2.0 * xr[i] - left - right;
+}
+
+__global__ void k_halfK_rows(const double *__restrict__ x, double *__restrict__ y, int64_t M, int64_t nrows,
+                             double coef, ColPerm perm)
+{
+    const int64_t total = M * nrows;
+    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t r = idx / M, i = idx - r * M;
+        y[idx] += coef * tri_row(x + r * M, i, M, perm);
+    }
+}
+
+hipError_t launch_halfK_rows(hipStream_t st, const double *x, double *y, int64_t M, int64_t nrows, double coef,
+                             ColPerm perm)
+{
+    const int64_t total = M * nrows;
+    if (total == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_halfK_rows, dim3(nblocks_for(total, 256)), dim3(256), 0, st, x, y, M, nrows, coef, perm);
+    return hipGetLastError();
+}
+
+__global__ void k_halfK_tasks(const Lag1Task *__restrict__ tasks)
+{
+    const Lag1Task tk = tasks[blockIdx.y];
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= tk.M) return;
+    tk.y[i] += tk.coef * tri_row(tk.x, i, tk.M, tk.perm);
+}
+
+hipError_t launch_halfK_tasks(hipStream_t st, const Lag1Task *d_tasks, int ntasks, int64_t maxM)
+{
+    if (ntasks == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_halfK_tasks, dim3((unsigned)((maxM + 255) / 256), (unsigned)ntasks), dim3(256), 0, st,
+                       d_tasks);
+    return hipGetLastError();
+}
+
 // Scheme 2 of the advection equation, twice the scheme's right-hand side in
 // the unknowns W = B U: y[n][i] = 2 f[n][i] - rho_n (u0[i] + u0[i-1]), with
 // u0 at the inflow point taken as 0.

@@ -115,3 +115,44 @@ def solve_adv(gamma, M, N, F, u0=None, phi=None, T=1.0, x0=0.0, x1=1.0):
             U[n, i] = (r[i] - lo * pv) / di
             pv = U[n, i]
     return U
+
+
+def solve_cn(gamma, M, N, F, u0=None, phi=None, T=1.0, x0=0.0, x1=1.0):
+    """The oracle's stepping of the diffusion-wave variant with the spatial
+    term averaged over t_n and t_{n-1}, in extended precision."""
+    a, rho, psi = weights(gamma, N, T)
+    h = (np.longdouble(x1) - np.longdouble(x0)) / np.longdouble(M + 1)
+    e = 1 / (h * h)
+    he = e / 2
+    d = a[0] + e
+    cp = np.zeros(M, dtype=np.longdouble)
+    inv = np.zeros(M, dtype=np.longdouble)
+    prev = np.longdouble(0)
+    for i in range(M):
+        piv = d + he * prev
+        inv[i] = 1 / piv
+        cp[i] = -he * inv[i]
+        prev = cp[i]
+    Fl = np.asarray(F, dtype=np.longdouble)
+    u0l = np.zeros(M, dtype=np.longdouble) if u0 is None else np.asarray(u0, dtype=np.longdouble)
+    phil = np.zeros(M, dtype=np.longdouble) if phi is None else np.asarray(phi, dtype=np.longdouble)
+
+    def K(v):
+        left = np.concatenate(([np.longdouble(0)], v[:-1]))
+        right = np.concatenate((v[1:], [np.longdouble(0)]))
+        return e * (2 * v - left - right)
+
+    U = np.zeros((N, M), dtype=np.longdouble)
+    for n in range(N):
+        r = Fl[n] - rho[n] * u0l + psi[n] * phil - K(u0l if n == 0 else U[n - 1]) / 2
+        for j in range(n):
+            r = r - a[n - j] * U[j]
+        x = np.zeros(M, dtype=np.longdouble)
+        pv = np.longdouble(0)
+        for i in range(M):
+            x[i] = (r[i] + he * pv) * inv[i]
+            pv = x[i]
+        for i in range(M - 2, -1, -1):
+            x[i] -= cp[i] * x[i + 1]
+        U[n] = x
+    return U

@@ -82,7 +82,8 @@ def test_invalid_problem_is_rejected_before_device_work(lib, prob, pattern):
     ((1, 9, 0, 0, 0, None), "refine_steps"),
     ((0, 0, 5, 0, 0, None), "leaf"),
     ((0, 0, 0, 0, 2, None), "leaf_solver"),
-    ((0, 0, 0, 0, 0, None, 2), "equation"),
+    ((0, 0, 0, 0, 0, None, 3), "equation"),
+    ((0, 0, 0, 0, 0, None, 2), "1 < gamma < 2"),
     ((1, 1, 0, 0, 0, None, 1), "float64"),
     ((0, 0, 0, 0, 1, None, 1), "leaf_solver"),
     ((0, 0, 16, 0, 0, None, 1), "leaf"),
