@@ -44,8 +44,10 @@ static ld dser(int64_t m, ld p, int order)
     return powl((ld)m, p) * sum;
 }
 
-/* v[n-1], n = 1..N: (a_0 + lam) v^n = g^n - rho_n v0 + psi_n phihat - sum_{j<n} a_{n-j} v^j */
-int ext_mode(double gamma, double T, int64_t N, double lam, const double *g, double v0, double phihat, double *vout)
+/* v[n-1], n = 1..N: (a_0 + lam) v^n = g^n - rho_n v0 + psi_n phihat - sum_{j<n} a_{n-j} v^j
+ * (cn: (a_0 + lam/2) v^n = ... - (lam/2) v^{n-1}, v^0 = v0) */
+static int ext_mode_any(double gamma, double T, int64_t N, double lam, const double *g, double v0, double phihat,
+                        double *vout, int cn)
 {
     int wave = gamma > 1.0;
     ld G = (ld)gamma, p = wave ? 2.0L - G : 1.0L - G;
@@ -69,13 +71,26 @@ int ext_mode(double gamma, double T, int64_t N, double lam, const double *g, dou
             psi[n - 1] = coef * tau * bk(n - 1, p);
         }
     }
-    ld d0 = a[0] + (ld)lam;
+    /* cn: the spatial term averaged over t_n and t_{n-1} (lam/2 on both) */
+    ld d0 = a[0] + (cn ? 0.5L : 1.0L) * (ld)lam;
     for (int64_t n = 1; n <= N; ++n) {
         ld s = (ld)g[n - 1] - rho[n - 1] * (ld)v0 + psi[n - 1] * (ld)phihat;
         for (int64_t j = 1; j < n; ++j) s -= a[n - j] * v[j - 1];
+        if (cn) s -= 0.5L * (ld)lam * (n == 1 ? (ld)v0 : v[n - 2]);
         v[n - 1] = s / d0;
         vout[n - 1] = (double)v[n - 1];
     }
     free(a); free(rho); free(psi); free(v);
     return 0;
+}
+
+int ext_mode(double gamma, double T, int64_t N, double lam, const double *g, double v0, double phihat, double *vout)
+{
+    return ext_mode_any(gamma, T, N, lam, g, v0, phihat, vout, 0);
+}
+
+int ext_mode_cn(double gamma, double T, int64_t N, double lam, const double *g, double v0, double phihat,
+                double *vout)
+{
+    return ext_mode_any(gamma, T, N, lam, g, v0, phihat, vout, 1);
 }
