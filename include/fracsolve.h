@@ -82,8 +82,8 @@ typedef struct {
     double T;       /* final time, > 0                                         */
     double x0, x1;  /* spatial interval, x1 > x0                               */
     int64_t M;      /* interior points, 1 <= M <= 4096                         */
-    int64_t N;      /* time steps, N >= 1 (padded internally to a power of 2;
-                       exact, because the system is causal)                   */
+    int64_t N;      /* time steps, 1 <= N <= 2^17 (padded internally to a
+                       power of 2; exact, because the system is causal)       */
 } fracsolve_problem;
 
 /* Equation of every instance of a handle. */
@@ -132,7 +132,8 @@ typedef struct {
 
 /*
  * Create a handle for `count` instances (probs[0..count-1]).  Validates every
- * problem (gamma in (0,1) or (1,2), T > 0, x1 > x0, 1 <= M <= 4096, N >= 1),
+ * problem (gamma in (0,1) or (1,2), T > 0, x1 > x0, 1 <= M <= 4096,
+ * 1 <= N <= 2^17),
  * computes the weights (section 3: G_k / M_k in cancellation-free form),
  * the FFT spectra of the Toeplitz column for every FFT level (circulant
  * embedding, section 3.1) and the factor tables of a_0 I + K, on the device.

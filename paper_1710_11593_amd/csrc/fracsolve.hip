@@ -789,8 +789,11 @@ int validate_problem(const fracsolve_problem &p, int k)
         return fail(nullptr, FRACSOLVE_E_ARG, "%s: need x1 > x0, got [%g, %g]", what, p.x0, p.x1);
     if (p.M < 1 || p.M > 4096)
         return fail(nullptr, FRACSOLVE_E_ARG, "%s: M must lie in [1, 4096], got %lld", what, (long long)p.M);
-    if (p.N < 1 || p.N > (1LL << 24))
-        return fail(nullptr, FRACSOLVE_E_ARG, "%s: N must lie in [1, 2^24], got %lld", what, (long long)p.N);
+    // the largest level product is an FFT of 2 Np / 2 = Np points: one
+    // single-pass transform of at most 8192 points times an outer digit of
+    // at most 16 (multi-pass route), so Np <= 2^17
+    if (p.N < 1 || p.N > (1LL << 17))
+        return fail(nullptr, FRACSOLVE_E_ARG, "%s: N must lie in [1, 2^17], got %lld", what, (long long)p.N);
     return FRACSOLVE_OK;
 }
 

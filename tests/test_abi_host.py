@@ -70,6 +70,7 @@ GOOD = (0.5, 1.0, 0.0, 1.0, 64, 256)
     ((0.5, 1.0, 0.0, 1.0, 0, 256), "M"),
     ((0.5, 1.0, 0.0, 1.0, 4097, 256), "M"),
     ((0.5, 1.0, 0.0, 1.0, 64, 0), "N"),
+    ((0.5, 1.0, 0.0, 1.0, 64, 131073), "N"),
 ])
 def test_invalid_problem_is_rejected_before_device_work(lib, prob, pattern):
     rc, h, msg = create(lib, [GOOD, prob])
