@@ -205,7 +205,7 @@ size_t adv_table_doubles();
 hipError_t launch_leaf_adv(hipStream_t st, const LeafCfg &c, int L, const TaskRef<AdvTask> &d_tasks, int ntasks,
                            bool wsum);
 hipError_t launch_leaf_scan(hipStream_t st, const LeafCfg &c, int L, const TaskRef<LeafTask> &tr, int ntasks,
-                            bool mixed, int vec, bool cn = false);
+                            bool mixed, int vec, bool cn = false, bool pair = false);
 
 hipError_t launch_twiddles(hipStream_t st, int64_t nmax, cplx<double> *w64, cplx<float> *w32);
 

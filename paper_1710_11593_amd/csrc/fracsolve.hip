@@ -133,6 +133,9 @@ struct fracsolve_ctx {
     // batches: every instance uses the leaf configuration of the widest one,
     // so that one launch per step covers all leaves (0: single instance)
     int64_t batch_M = 0;
+    // leaves in pairs with the level product of half-size L inside the leaf
+    // kernel (dense levels at s = L, scan leaves, L <= 8, diffusion)
+    bool pair = false;
     // GMRES: zero history weights (block-diagonal solves through the leaf
     // kernels), multi-dot partials and results
     double *zeros = nullptr;
@@ -238,6 +241,7 @@ struct Op {
     int lead = 0;        // dense levels of a solve: rows the next leaf reads first
     bool wsum = false;   // advection leaves: Scheme 2 (X = B U, U to its own field)
     bool cn = false;     // scan leaves: the lag-1 spatial term of the averaged variant
+    bool pair = false;   // scan leaves: two leaves and the level of half-size L between them
 };
 
 // Flat column-group offsets of the tasks of a single-pass FFT level (see
@@ -303,7 +307,7 @@ int run_ops(fracsolve_ctx *h, const std::vector<Op> &ops)
                 break;
             case OP_LEAF_SCAN:
                 e = launch_leaf_scan(h->st, op.lc, h->L, task_ref<LeafTask>(h, op), op.ntasks, op.mixed, op.lc.vec,
-                                     op.cn);
+                                     op.cn, op.pair);
                 break;
             case OP_LAG1:
                 e = launch_halfK_tasks(h->st, dptr<Lag1Task>(h, op.off), op.ntasks, op.maxM);
@@ -342,7 +346,7 @@ int run_ops(fracsolve_ctx *h, const std::vector<Op> &ops)
                        : op.kind == OP_FFT64    ? 3
                        : op.kind == OP_LAG1     ? 5
                                                 : 4;
-            h->recs.push_back({kind, lf ? h->L : op.s, op.ntasks, op.bytes, evi});
+            h->recs.push_back({kind, lf ? h->L * (op.pair ? 2 : 1) : op.s, op.ntasks, op.bytes, evi});
             // the near-corner band of an FFT level as a group of its own:
             // X rows s-31..s-1, Y rows 0..30 read and written
             const bool fft = op.kind == OP_FFT64 || op.kind == OP_FFT32;
@@ -399,6 +403,7 @@ uint64_t ops_key(const std::vector<Op> &ops, const void *d_desc)
         mix((uint64_t)op.lc.vec);
         mix((uint64_t)op.wsum);
         mix((uint64_t)op.cn);
+        mix((uint64_t)op.pair);
     }
     mix((uint64_t)ops.size());
     return hsh;
@@ -467,10 +472,13 @@ void build_solve(fracsolve_ctx *h, const std::vector<int> &sel, const std::vecto
     int64_t K = 0;
     for (int i : sel) K = std::max(K, h->inst[i].Np / L);
     for (int64_t k = 0; k < K; ++k) {
-        // leaves, one launch per leaf configuration
+        // leaves, one launch per leaf configuration; in pair mode leaf k + 1
+        // (k even) runs in the launch of leaf k
+        const bool pair_first = h->pair && (k % 2 == 0);
+        const bool pair_second = h->pair && (k % 2 == 1);
         std::vector<std::pair<int, LeafTask>> lt;
         std::vector<std::pair<int, AdvTask>> at;
-        for (size_t q = 0; q < sel.size(); ++q) {
+        for (size_t q = 0; q < sel.size() && !pair_second; ++q) {
             const Inst &in = h->inst[sel[q]];
             int64_t lo = k * L;
             if (lo >= in.N) continue;
@@ -494,7 +502,7 @@ void build_solve(fracsolve_ctx *h, const std::vector<int> &sel, const std::vecto
             t.x32 = mixed ? fld[q].x32 : nullptr;
             t.M = in.M;
             t.lo = lo;
-            t.nrows = (int)std::min<int64_t>(L, in.N - lo);
+            t.nrows = (int)std::min<int64_t>(pair_first ? 2 * L : L, in.N - lo);
             t.flags = (in.perm.pt > 2 && in.perm.mfull > 0) ? LEAF_PERM : 0;
             // whole 16-byte row units for the scan leaf
             if (in.scan && (in.M % in.lc.pt) == 0 && ((uintptr_t)t.u & 15) == 0) t.flags |= LEAF_VEC;
@@ -535,12 +543,15 @@ void build_solve(fracsolve_ctx *h, const std::vector<int> &sel, const std::vecto
             lc.vec = nvec == (int)v.size() ? 1 : (nvec == 0 ? 0 : 2);
             Op op{lt[b].first >= 1000000 ? OP_LEAF_SCAN : OP_LEAF, off, (int)v.size(), 0, 0, lc, mixed};
             op.cn = (h->opts.equation == FRACSOLVE_DIFFUSION_CN);
+            op.pair = pair_first;
             for (auto &t : v) op.bytes += (double)t.nrows * (double)t.M * (mixed ? 24.0 : 16.0);
             ops.push_back(op);
             b = e;
         }
-        // level product after leaf k
+        // level product after leaf k (of half-size L after an even leaf:
+        // inside the pair's launch in pair mode)
         if (k + 1 >= K) break;
+        if (pair_first) continue;
         int64_t kk = k + 1;
         int64_t s = (int64_t)L * (kk & -kk);
         int64_t mid = kk * L, lo = mid - s;
@@ -1250,6 +1261,11 @@ int fracsolve_create(const fracsolve_problem *probs, int32_t count, const fracso
     h->L = o.leaf ? o.leaf : 8;
     // dense products are limited to s <= 1024 (k_gemm.hip)
     h->crossover = (o.crossover > 0) ? std::min(o.crossover, 1024) : (o.crossover < 0 ? 0 : 64);
+    {
+        const char *pv = getenv("FRACSOLVE_PAIR");
+        h->pair = !(pv && pv[0] == '0') && o.equation == FRACSOLVE_DIFFUSION && o.leaf_solver == 0 && h->L <= 8 &&
+                  h->L <= h->crossover;
+    }
     int64_t npmax = 0;
     for (int k = 0; k < count; ++k) npmax = std::max(npmax, std::max<int64_t>(next_pow2(probs[k].N), h->L));
     h->nmax = std::max<int64_t>(npmax, 16384);

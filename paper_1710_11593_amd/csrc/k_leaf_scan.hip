@@ -139,7 +139,12 @@ __device__ __forceinline__ void row_scans(double &f, double &b, const double *cp
 // tridiag(-1, 2, -1) with the same e): pushing x_r into the next row also
 // subtracts e (2 x_i - x_{i-1} - x_{i+1}), with the neighbours across
 // threads exchanged through LDS (one more barrier per step).
-template <int NT, int PT, int L, bool MIXED, int VEC, bool CN = false>
+// PAIR: the task covers two leaves (up to 2L rows) and applies between them
+// the level product of half-size L (rows L..2L-1 minus the Toeplitz block
+// a_{L+p-q} times rows 0..L-1), so one launch replaces leaf, dense level
+// product, leaf.  Each thread re-reads its own columns of the first leaf's
+// solution rows, which it has just stored.
+template <int NT, int PT, int L, bool MIXED, int VEC, bool CN = false, bool PAIR = false>
 __global__ __launch_bounds__(NT) void k_leaf_scan(TaskRef<LeafTask> tr)
 {
     static_assert(PT % 2 == 0 && PT <= 16, "rows per thread must be even and at most 16");
@@ -158,10 +163,10 @@ __global__ __launch_bounds__(NT) void k_leaf_scan(TaskRef<LeafTask> tr)
     FS_G const double *__restrict__ tab = gptr(tk.fac);
     const int64_t M = tk.M;
     const int c0 = t * PT;
-    const int nrows = tk.nrows;
-    FS_G double *__restrict__ u = gptr(tk.u) + tk.lo * M;
-    FS_G const float *__restrict__ hist = MIXED ? gptr(tk.hist) + tk.lo * M : nullptr;
-    FS_G float *__restrict__ x32 = MIXED ? gptr(tk.x32) + tk.lo * M : nullptr;
+    const int nrows_all = tk.nrows;
+    FS_G double *__restrict__ u_base = gptr(tk.u) + tk.lo * M;
+    FS_G const float *__restrict__ hist_base = MIXED ? gptr(tk.hist) + tk.lo * M : nullptr;
+    FS_G float *__restrict__ x32_base = MIXED ? gptr(tk.x32) + tk.lo * M : nullptr;
     // vec: M is a multiple of PT and the field is 16-byte aligned, so a
     // thread's rows are either all inside [0, M) or all outside.  VEC = 2
     // takes it from the task flags (batches mixing both kinds in one launch).
@@ -183,6 +188,49 @@ __global__ __launch_bounds__(NT) void k_leaf_scan(TaskRef<LeafTask> tr)
         al[k] = tab[SCAN_TAB_ALPHA + c0 + k];
         be[k] = tab[SCAN_TAB_ALPHA + MP + c0 + k];
     }
+    // uniform constants
+    const double K0 = tab[0];
+    // K0 alpha and K0 beta for the final product of each row (one multiply
+    // less per row and step) where the registers allow it (float64 mode)
+    constexpr bool KFOLD = !MIXED && (VEC != 0 || PT < 8) && !((PAIR || CN) && PT >= 8);
+    double kal[KFOLD ? PT : 1], kbe[KFOLD ? PT : 1];
+    if constexpr (KFOLD) {
+#pragma unroll
+        for (int k = 0; k < PT; ++k) {
+            kal[k] = K0 * al[k];
+            kbe[k] = K0 * be[k];
+        }
+    }
+    const double rho = tab[1];
+    double mp[4];  // m^(1,2,4,8): lane steps inside a row
+#pragma unroll
+    for (int s = 0; s < 4; ++s) mp[s] = tab[8 + s];
+    double cp[5];  // c^(2^s), c = m^16: row steps
+#pragma unroll
+    for (int s = 0; s < 5; ++s) cp[s] = tab[12 + s];
+    double rp[PT];  // rho^(k+1)
+#pragma unroll
+    for (int k = 0; k < PT; ++k) rp[k] = tab[SCAN_TAB_POW + k];
+    double aw[L];
+#pragma unroll
+    for (int m = 0; m < L; ++m) aw[m] = (m > 0) ? gptr(tk.a)[m] : 0.0;
+    // lane multipliers: m^rl and m^(15-rl) (row carries into a thread);
+    // c^((lane&15)+1) for the row_bcast:15 step and c^(16-lane) for the
+    // backward step of the row scan (both used only on lanes < NR)
+    double mpw[5] = {mp[0], mp[1], mp[2], mp[3], 0.0};
+    const double m_lo = pow_bits(mpw, rl);
+    const double m_hi = pow_bits(mpw, 15 - rl);
+    const double c_b15 = pow_bits(cp, (lane & 15) + 1);
+    const double c_bk = pow_bits(cp, 16 - (lane & 15));
+
+    constexpr int NH = PAIR ? 2 : 1;
+#pragma unroll 1
+    for (int hf = 0; hf < NH; ++hf) {
+    const int nrows = (hf == 0) ? (nrows_all < L ? nrows_all : L) : nrows_all - L;
+    if (nrows <= 0) break;  // whole workgroup
+    FS_G double *__restrict__ u = u_base + (int64_t)(hf * L) * M;
+    FS_G const float *__restrict__ hist = MIXED ? hist_base + (int64_t)(hf * L) * M : nullptr;
+    FS_G float *__restrict__ x32 = MIXED ? x32_base + (int64_t)(hf * L) * M : nullptr;
     // right-hand sides of the leaf's rows (row r of the leaf in acc[r])
     double acc[L][PT];
 #pragma unroll
@@ -224,42 +272,40 @@ __global__ __launch_bounds__(NT) void k_leaf_scan(TaskRef<LeafTask> tr)
             for (int k = 0; k < PT; ++k) hv[k] = (r < nrows && c0 + k < M) ? hrow[col(k)] : 0.f;
         }
     };
-    if (MIXED) load_hist(0);
-
-    // uniform constants
-    const double K0 = tab[0];
-    // K0 alpha and K0 beta for the final product of each row (one multiply
-    // less per row and step) where the registers allow it (float64 mode)
-    constexpr bool KFOLD = !MIXED && (VEC != 0 || PT < 8);
-    double kal[KFOLD ? PT : 1], kbe[KFOLD ? PT : 1];
-    if constexpr (KFOLD) {
+    if constexpr (PAIR) {
+        if (hf == 1) {
+            // the level product of half-size L from the first leaf's rows
+            // (this thread's own columns, stored by it in the first half)
+            auto load_x = [&](int q, double *xq) {
+                FS_G const double *xrow = u_base + (int64_t)q * M;
+                if (vec) {
 #pragma unroll
-        for (int k = 0; k < PT; ++k) {
-            kal[k] = K0 * al[k];
-            kbe[k] = K0 * be[k];
+                    for (int i = 0; i < UT; ++i) {
+                        double2 v = double2{0.0, 0.0};
+                        if (act) v = *reinterpret_cast<FS_G const double2 *>(xrow + col(2 * i));
+                        xq[2 * i] = v.x;
+                        xq[2 * i + 1] = v.y;
+                    }
+                } else {
+#pragma unroll
+                    for (int k = 0; k < PT; ++k) xq[k] = (c0 + k < M) ? xrow[col(k)] : 0.0;
+                }
+            };
+            // one row of X in registers at a time (more rows spill at 512 x 8)
+#pragma unroll 1
+            for (int q = 0; q < L; ++q) {
+                double xq[PT];
+                load_x(q, xq);
+#pragma unroll
+                for (int p = 0; p < L; ++p) {
+                    const double w = gptr(tk.a)[L + p - q];
+#pragma unroll
+                    for (int k = 0; k < PT; ++k) acc[p][k] = fma(-w, xq[k], acc[p][k]);
+                }
+            }
         }
     }
-    const double rho = tab[1];
-    double mp[4];  // m^(1,2,4,8): lane steps inside a row
-#pragma unroll
-    for (int s = 0; s < 4; ++s) mp[s] = tab[8 + s];
-    double cp[5];  // c^(2^s), c = m^16: row steps
-#pragma unroll
-    for (int s = 0; s < 5; ++s) cp[s] = tab[12 + s];
-    double rp[PT];  // rho^(k+1)
-#pragma unroll
-    for (int k = 0; k < PT; ++k) rp[k] = tab[SCAN_TAB_POW + k];
-    double aw[L];
-#pragma unroll
-    for (int m = 0; m < L; ++m) aw[m] = (m > 0) ? gptr(tk.a)[m] : 0.0;
-    // lane multipliers: m^rl and m^(15-rl) (row carries into a thread);
-    // c^((lane&15)+1) for the row_bcast:15 step and c^(16-lane) for the
-    // backward step of the row scan (both used only on lanes < NR)
-    double mpw[5] = {mp[0], mp[1], mp[2], mp[3], 0.0};
-    const double m_lo = pow_bits(mpw, rl);
-    const double m_hi = pow_bits(mpw, 15 - rl);
-    const double c_b15 = pow_bits(cp, (lane & 15) + 1);
-    const double c_bk = pow_bits(cp, 16 - (lane & 15));
+    if (MIXED) load_hist(0);
 
     double xp[PT];  // solution of the previous step, pushed and stored during this step
 #pragma unroll
@@ -380,6 +426,7 @@ __global__ __launch_bounds__(NT) void k_leaf_scan(TaskRef<LeafTask> tr)
             }
         }
     }
+    }  // halves
 }
 
 // ---- leaf of the advection equations (Schemes 2 and 3) ----
@@ -600,25 +647,36 @@ hipError_t launch_scan_factor(hipStream_t st, const LeafCfg &c, int64_t M, doubl
     return hipErrorInvalidValue;
 }
 
-template <int NT, int PT, int L, bool MIXED, bool CN = false>
+template <int NT, int PT, int L, bool MIXED, bool CN = false, bool PAIR = false>
 static void scan_go_m(hipStream_t st, int vec, const TaskRef<LeafTask> &d_tasks, int ntasks)
 {
     if (vec == 1)
-        hipLaunchKernelGGL((k_leaf_scan<NT, PT, L, MIXED, 1, CN>), dim3(ntasks), dim3(NT), 0, st, d_tasks);
+        hipLaunchKernelGGL((k_leaf_scan<NT, PT, L, MIXED, 1, CN, PAIR>), dim3(ntasks), dim3(NT), 0, st, d_tasks);
     else if (vec == 2)
-        hipLaunchKernelGGL((k_leaf_scan<NT, PT, L, MIXED, 2, CN>), dim3(ntasks), dim3(NT), 0, st, d_tasks);
+        hipLaunchKernelGGL((k_leaf_scan<NT, PT, L, MIXED, 2, CN, PAIR>), dim3(ntasks), dim3(NT), 0, st, d_tasks);
     else
-        hipLaunchKernelGGL((k_leaf_scan<NT, PT, L, MIXED, 0, CN>), dim3(ntasks), dim3(NT), 0, st, d_tasks);
+        hipLaunchKernelGGL((k_leaf_scan<NT, PT, L, MIXED, 0, CN, PAIR>), dim3(ntasks), dim3(NT), 0, st, d_tasks);
 }
 
 // cn: float64 only (the averaged spatial term is not offered with float32 products)
+// pair: two leaves per task with the level product of half-size L between
+// them (not with cn, and not for L = 16)
 template <int NT, int PT, int L>
 static hipError_t scan_go(hipStream_t st, bool mixed, int vec, const TaskRef<LeafTask> &d_tasks, int ntasks,
-                          bool cn)
+                          bool cn, bool pair)
 {
     if (cn) {
-        if (mixed) return hipErrorInvalidValue;
+        if (mixed || pair) return hipErrorInvalidValue;
         scan_go_m<NT, PT, L, false, true>(st, vec, d_tasks, ntasks);
+    } else if (pair) {
+        if constexpr (L <= 8) {
+            if (mixed)
+                scan_go_m<NT, PT, L, true, false, true>(st, vec, d_tasks, ntasks);
+            else
+                scan_go_m<NT, PT, L, false, false, true>(st, vec, d_tasks, ntasks);
+        } else {
+            return hipErrorInvalidValue;
+        }
     } else if (mixed)
         scan_go_m<NT, PT, L, true>(st, vec, d_tasks, ntasks);
     else
@@ -628,23 +686,23 @@ static hipError_t scan_go(hipStream_t st, bool mixed, int vec, const TaskRef<Lea
 
 template <int NT, int PT>
 static hipError_t scan_go16(hipStream_t st, bool mixed, int vec, const TaskRef<LeafTask> &d_tasks, int ntasks,
-                            bool cn)
+                            bool cn, bool pair)
 {
     if constexpr (PT <= 2)
-        return scan_go<NT, PT, 16>(st, mixed, vec, d_tasks, ntasks, cn);
+        return scan_go<NT, PT, 16>(st, mixed, vec, d_tasks, ntasks, cn, pair);
     else
         return hipErrorInvalidValue;
 }
 
 hipError_t launch_leaf_scan(hipStream_t st, const LeafCfg &c, int L, const TaskRef<LeafTask> &d_tasks, int ntasks,
-                            bool mixed, int vec, bool cn)
+                            bool mixed, int vec, bool cn, bool pair)
 {
-#define FS_SL(NT_, PT_)                                                                            \
-    if (c.nt == NT_ && c.pt == PT_) {                                                              \
-        if (L == 4) return scan_go<NT_, PT_, 4>(st, mixed, vec, d_tasks, ntasks, cn);              \
-        if (L == 8) return scan_go<NT_, PT_, 8>(st, mixed, vec, d_tasks, ntasks, cn);              \
-        if (L == 16 && PT_ <= 2) return scan_go16<NT_, PT_>(st, mixed, vec, d_tasks, ntasks, cn);  \
-        return hipErrorInvalidValue;                                                               \
+#define FS_SL(NT_, PT_)                                                                                  \
+    if (c.nt == NT_ && c.pt == PT_) {                                                                    \
+        if (L == 4) return scan_go<NT_, PT_, 4>(st, mixed, vec, d_tasks, ntasks, cn, pair);              \
+        if (L == 8) return scan_go<NT_, PT_, 8>(st, mixed, vec, d_tasks, ntasks, cn, pair);              \
+        if (L == 16 && PT_ <= 2) return scan_go16<NT_, PT_>(st, mixed, vec, d_tasks, ntasks, cn, pair);  \
+        return hipErrorInvalidValue;                                                                     \
     }
     FS_SL(64, 2)
     FS_SL(64, 4)
