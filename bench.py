@@ -15,7 +15,8 @@ the path), timed live with HIP events around each launch on the solver's
 stream during one extra solve; achieved = its algorithmic bytes (24 B per
 X-row entry: read X, read and write Y) / its time, against the 8 TB/s HBM
 peak.  critical_path: the sequential chain of leaf solves (one workgroup
-each), which sets most of the solve time.
+per launch, two leaves per launch where they run in pairs), which sets most
+of the solve time.
 forms (unless --no-forms): mixed precision and the variant with the spatial
 term averaged over t_n and t_{n-1} (c3), batching (c4), the adjoint (c5) and
 the paper's own iterative method, restarted GMRES(m), on its
@@ -626,7 +627,10 @@ def main():
     timed_ms = sum(g["ms"] for g in ks)
     # the sequential chain of leaf solves (one workgroup each) and the level
     # products between them, as shares of the per-group event times
-    critical = {"kernel": "k_leaf_scan (one workgroup per leaf, L=%d steps)" % st["leaf"],
+    leaf_s = max((g["s"] for g in groups if g["kind"] == "leaf"), default=st["leaf"])
+    critical = {"kernel": "k_leaf_scan (one workgroup per launch, %d time steps of L=%d%s)" % (
+                    leaf_s, st["leaf"], ": two leaves and the level product between them" if leaf_s > st["leaf"]
+                    else ""),
                 "launches": leaf_launches, "avg_us": round(leaf_ms * 1e3 / max(leaf_launches, 1), 2),
                 "leaf_share": round(leaf_ms / timed_ms, 3) if timed_ms else None,
                 "groups": [{"kind": g["kind"], "s": g["s"], "launches": g["launches"], "ms": round(g["ms"], 3)}
