@@ -134,7 +134,7 @@ struct fracsolve_ctx {
     // so that one launch per step covers all leaves (0: single instance)
     int64_t batch_M = 0;
     // leaves in pairs with the level product of half-size L inside the leaf
-    // kernel (dense levels at s = L, scan leaves, L <= 8, diffusion)
+    // kernel (dense levels at s = L, scan leaves, L <= 8, not advection)
     bool pair = false;
     // GMRES: zero history weights (block-diagonal solves through the leaf
     // kernels), multi-dot partials and results
@@ -1263,7 +1263,7 @@ int fracsolve_create(const fracsolve_problem *probs, int32_t count, const fracso
     h->crossover = (o.crossover > 0) ? std::min(o.crossover, 1024) : (o.crossover < 0 ? 0 : 64);
     {
         const char *pv = getenv("FRACSOLVE_PAIR");
-        h->pair = !(pv && pv[0] == '0') && o.equation == FRACSOLVE_DIFFUSION && o.leaf_solver == 0 && h->L <= 8 &&
+        h->pair = !(pv && pv[0] == '0') && o.equation != FRACSOLVE_ADVECTION && o.leaf_solver == 0 && h->L <= 8 &&
                   h->L <= h->crossover;
     }
     int64_t npmax = 0;

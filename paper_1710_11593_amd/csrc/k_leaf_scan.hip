@@ -302,6 +302,24 @@ __global__ __launch_bounds__(NT) void k_leaf_scan(TaskRef<LeafTask> tr)
 #pragma unroll
                     for (int k = 0; k < PT; ++k) acc[p][k] = fma(-w, xq[k], acc[p][k]);
                 }
+                if constexpr (CN) {
+                    if (q == L - 1) {
+                        // the lag-1 spatial term from the first leaf's last row;
+                        // sE[1] has not been read since the last step's barrier
+                        sE[1][0][t] = xq[0];
+                        sE[1][1][t] = xq[PT - 1];
+                        __syncthreads();
+                        const double xl = (t > 0) ? sE[1][1][t - 1] : 0.0;
+                        const double xr = (t + 1 < NT) ? sE[1][0][t + 1] : 0.0;
+                        const double ec = tab[2];
+#pragma unroll
+                        for (int k = 0; k < PT; ++k) {
+                            const double lft = (k > 0) ? xq[k - 1] : xl;
+                            const double rgt = (k < PT - 1) ? xq[k + 1] : xr;
+                            acc[0][k] = fma(-ec, 2.0 * xq[k] - lft - rgt, acc[0][k]);
+                        }
+                    }
+                }
             }
         }
     }
@@ -660,14 +678,21 @@ static void scan_go_m(hipStream_t st, int vec, const TaskRef<LeafTask> &d_tasks,
 
 // cn: float64 only (the averaged spatial term is not offered with float32 products)
 // pair: two leaves per task with the level product of half-size L between
-// them (not with cn, and not for L = 16)
+// them (not for L = 16)
 template <int NT, int PT, int L>
 static hipError_t scan_go(hipStream_t st, bool mixed, int vec, const TaskRef<LeafTask> &d_tasks, int ntasks,
                           bool cn, bool pair)
 {
     if (cn) {
-        if (mixed || pair) return hipErrorInvalidValue;
-        scan_go_m<NT, PT, L, false, true>(st, vec, d_tasks, ntasks);
+        if (mixed) return hipErrorInvalidValue;
+        if (pair) {
+            if constexpr (L <= 8)
+                scan_go_m<NT, PT, L, false, true, true>(st, vec, d_tasks, ntasks);
+            else
+                return hipErrorInvalidValue;
+        } else {
+            scan_go_m<NT, PT, L, false, true>(st, vec, d_tasks, ntasks);
+        }
     } else if (pair) {
         if constexpr (L <= 8) {
             if (mixed)
