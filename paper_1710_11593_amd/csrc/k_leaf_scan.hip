@@ -47,7 +47,9 @@ struct slog2<1> {
 //   [0] K0, [1] rho, [2] e,
 //   [8 + s]  m^(2^s), m = rho^PT, s < 16,
 //   [24 + k] rho^(k+1), k < 16,
-//   [SCAN_TAB_ALPHA + r] alpha of row r+1 (r < NT*PT, 0 beyond M), then beta.
+//   [SCAN_TAB_ALPHA + r] sqrt(K0) alpha of row r+1 (r < NT*PT, 0 beyond M),
+//   then sqrt(K0) beta: with both scaled, the prefix and suffix sums carry a
+//   factor sqrt(K0) each and x = beta' P' + alpha' Q' needs no product with K0.
 constexpr int SCAN_TAB_POW = 24;
 constexpr int SCAN_TAB_ALPHA = 40;
 
@@ -58,9 +60,10 @@ __global__ __launch_bounds__(NT) void k_scan_factor(int64_t M, double a0, double
     const double dlt = a0 / (2.0 * e);
     const double th = log1p(dlt + sqrt(dlt * (2.0 + dlt)));
     const int t = threadIdx.x;
+    const double K0 = 1.0 / (e * 2.0 * sinh(th) * -expm1(-2.0 * (double)(M + 1) * th));
+    const double sk = sqrt(K0);
     if (t == 0) {
-        double gam = -expm1(-2.0 * (double)(M + 1) * th);
-        tab[0] = 1.0 / (e * 2.0 * sinh(th) * gam);
+        tab[0] = K0;
         tab[2] = e;  // the coefficient of tridiag(-1, 2, -1) in the block
         tab[1] = exp(-th);
         for (int s = 0; s < 16; ++s) tab[8 + s] = exp(-(double)PT * (double)(1 << s) * th);
@@ -69,8 +72,8 @@ __global__ __launch_bounds__(NT) void k_scan_factor(int64_t M, double a0, double
     for (int r = t; r < MP; r += NT) {
         double i = (double)(r + 1);
         bool real = r < M;
-        tab[SCAN_TAB_ALPHA + r] = real ? -expm1(-2.0 * i * th) : 0.0;
-        tab[SCAN_TAB_ALPHA + MP + r] = real ? -expm1(-2.0 * ((double)(M + 1) - i) * th) : 0.0;
+        tab[SCAN_TAB_ALPHA + r] = real ? -sk * expm1(-2.0 * i * th) : 0.0;
+        tab[SCAN_TAB_ALPHA + MP + r] = real ? -sk * expm1(-2.0 * ((double)(M + 1) - i) * th) : 0.0;
     }
 }
 
@@ -189,18 +192,6 @@ __global__ __launch_bounds__(NT) void k_leaf_scan(TaskRef<LeafTask> tr)
         be[k] = tab[SCAN_TAB_ALPHA + MP + c0 + k];
     }
     // uniform constants
-    const double K0 = tab[0];
-    // K0 alpha and K0 beta for the final product of each row (one multiply
-    // less per row and step) where the registers allow it (float64 mode)
-    constexpr bool KFOLD = !MIXED && (VEC != 0 || PT < 8) && !((PAIR || CN) && PT >= 8);
-    double kal[KFOLD ? PT : 1], kbe[KFOLD ? PT : 1];
-    if constexpr (KFOLD) {
-#pragma unroll
-        for (int k = 0; k < PT; ++k) {
-            kal[k] = K0 * al[k];
-            kbe[k] = K0 * be[k];
-        }
-    }
     const double rho = tab[1];
     double mp[4];  // m^(1,2,4,8): lane steps inside a row
 #pragma unroll
@@ -418,10 +409,7 @@ __global__ __launch_bounds__(NT) void k_leaf_scan(TaskRef<LeafTask> tr)
             const double P = fma(rp[k], cf, lf[k]);
             const double Q = (k < PT - 1) ? fma(rho, sb[k + 1 < PT ? k + 1 : k], rp[PT - 2 - k >= 0 ? PT - 2 - k : 0] * cb)
                                           : cb;
-            if constexpr (KFOLD)
-                xp[k] = fma(kbe[k], P, kal[k] * Q);
-            else
-                xp[k] = K0 * fma(be[k], P, al[k] * Q);
+            xp[k] = fma(be[k], P, al[k] * Q);  // al, be carry sqrt(K0)
         }
         // the next row's right-hand side needs x_r now
         if (r + 1 < L) {
