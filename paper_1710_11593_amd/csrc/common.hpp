@@ -177,6 +177,8 @@ struct Lag1Task {
 hipError_t launch_halfK_tasks(hipStream_t st, const Lag1Task *d_tasks, int ntasks, int64_t maxM);
 hipError_t launch_halfK_rows(hipStream_t st, const double *x, double *y, int64_t M, int64_t nrows, double coef,
                              ColPerm perm);
+hipError_t launch_rhs_perm(hipStream_t st, const double *f, const double *u0, const double *phi, const double *rho,
+                           const double *psi, double *dst, int64_t M, int64_t N, ColPerm perm);
 hipError_t launch_rhs_adv2(hipStream_t st, const double *f, const double *u0, const double *rho, double *y,
                            int64_t M, int64_t N);
 hipError_t launch_rhs(hipStream_t st, const double *f, const double *u0, const double *phi,

@@ -937,6 +937,12 @@ int solve_all(fracsolve_ctx *h, const double *const *f, const double *const *u0,
             continue;
         }
         const double *ph = (in.regime == 1) ? opt_ptr(phi, k) : nullptr;
+        if (in.perm.mfull > 0 && !in.cn) {
+            // right-hand sides written straight into the internal column order
+            HIPCHK(h, launch_rhs_perm(h->st, f[k], opt_ptr(u0, k), ph, in.rho, in.psi, u[k], in.M, in.N, in.perm));
+            h->kernels++;
+            continue;
+        }
         HIPCHK(h, launch_rhs(h->st, f[k], opt_ptr(u0, k), ph, in.rho, in.psi, u[k], in.M, in.N));
         h->kernels++;
         if (in.cn && opt_ptr(u0, k)) {

@@ -197,6 +197,61 @@ __global__ __launch_bounds__(256) void k_permute(const double *src, double *dst,
     }
 }
 
+// Right-hand sides written straight into the internal column order: per row
+// block of B = 64 pt columns, f is staged in LDS (so dst == f is safe), and
+// internal column m receives f - rho_n u0 + psi_n phi at its natural column.
+// One pass over the field instead of k_rhs followed by k_permute.
+__global__ __launch_bounds__(256) void k_rhs_perm(const double *f, const double *__restrict__ u0,
+                                                  const double *__restrict__ phi, const double *__restrict__ rho,
+                                                  const double *__restrict__ psi, double *dst, int64_t M, int64_t N,
+                                                  ColPerm perm)
+{
+    __shared__ double sb[1024];
+    const int64_t B = 64 * (int64_t)perm.pt;
+    const int64_t nblk = perm.mfull / B;
+    const int64_t tail = M - perm.mfull;
+    const int64_t per = nblk + (tail > 0 ? 1 : 0);
+    const int64_t units = N * per;
+    for (int64_t u = blockIdx.x; u < units; u += gridDim.x) {
+        const int64_t n = u / per, b = u - n * per;
+        const double *fr = f + n * M;
+        double *dr = dst + n * M;
+        const double rn = rho[n], pn = psi[n];
+        if (b == nblk) {
+            // natural-order tail: each element read and written by one thread
+            for (int64_t c = perm.mfull + threadIdx.x; c < M; c += blockDim.x) {
+                double v = fr[c];
+                if (u0) v -= rn * u0[c];
+                if (phi) v += pn * phi[c];
+                dr[c] = v;
+            }
+            continue;
+        }
+        const int64_t base = b * B;
+        for (int k = threadIdx.x; k < B; k += blockDim.x) sb[k] = fr[base + k];
+        __syncthreads();
+        for (int k = threadIdx.x; k < B; k += blockDim.x) {
+            const int64_t from = perm_m2s(base + k, perm);
+            double v = sb[from - base];
+            if (u0) v -= rn * u0[from];
+            if (phi) v += pn * phi[from];
+            dr[base + k] = v;
+        }
+        __syncthreads();
+    }
+}
+
+hipError_t launch_rhs_perm(hipStream_t st, const double *f, const double *u0, const double *phi, const double *rho,
+                           const double *psi, double *dst, int64_t M, int64_t N, ColPerm perm)
+{
+    const int64_t B = 64 * (int64_t)perm.pt;
+    if (perm.pt <= 2 || perm.mfull <= 0 || B > 1024) return hipErrorInvalidValue;
+    const int64_t units = N * (perm.mfull / B + (M > perm.mfull ? 1 : 0));
+    const unsigned g = (unsigned)std::min<int64_t>(units, 65535LL * 16);
+    hipLaunchKernelGGL(k_rhs_perm, dim3(g), dim3(256), 0, st, f, u0, phi, rho, psi, dst, M, N, perm);
+    return hipGetLastError();
+}
+
 hipError_t launch_permute(hipStream_t st, const double *src, double *dst, int64_t M, int64_t N, ColPerm perm,
                           bool to_internal, bool reverse)
 {
