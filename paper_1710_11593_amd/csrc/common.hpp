@@ -205,7 +205,7 @@ hipError_t launch_scan_factor(hipStream_t st, const LeafCfg &c, int64_t M, doubl
 hipError_t launch_adv_factor(hipStream_t st, const LeafCfg &c, double a0, double h, bool scheme2, double *tab);
 size_t adv_table_doubles();
 hipError_t launch_leaf_adv(hipStream_t st, const LeafCfg &c, int L, const TaskRef<AdvTask> &d_tasks, int ntasks,
-                           bool wsum);
+                           bool wsum, bool pair = false);
 hipError_t launch_leaf_scan(hipStream_t st, const LeafCfg &c, int L, const TaskRef<LeafTask> &tr, int ntasks,
                             bool mixed, int vec, bool cn = false, bool pair = false);
 

@@ -134,7 +134,7 @@ struct fracsolve_ctx {
     // so that one launch per step covers all leaves (0: single instance)
     int64_t batch_M = 0;
     // leaves in pairs with the level product of half-size L inside the leaf
-    // kernel (dense levels at s = L, scan leaves, L <= 8, not advection)
+    // kernel (dense levels at s = L, scan or advection leaves, L <= 8)
     bool pair = false;
     // GMRES: zero history weights (block-diagonal solves through the leaf
     // kernels), multi-dot partials and results
@@ -313,7 +313,7 @@ int run_ops(fracsolve_ctx *h, const std::vector<Op> &ops)
                 e = launch_halfK_tasks(h->st, dptr<Lag1Task>(h, op.off), op.ntasks, op.maxM);
                 break;
             case OP_LEAF_ADV:
-                e = launch_leaf_adv(h->st, op.lc, h->L, task_ref<AdvTask>(h, op), op.ntasks, op.wsum);
+                e = launch_leaf_adv(h->st, op.lc, h->L, task_ref<AdvTask>(h, op), op.ntasks, op.wsum, op.pair);
                 break;
             case OP_GEMM64:
                 e = launch_gemm_update<double>(h->st, task_ref<UpdTask<double>>(h, op), op.ntasks, op.s, op.maxM,
@@ -490,7 +490,7 @@ void build_solve(fracsolve_ctx *h, const std::vector<int> &sel, const std::vecto
                 t.fac = in.fac;
                 t.M = in.M;
                 t.lo = lo;
-                t.nrows = (int)std::min<int64_t>(L, in.N - lo);
+                t.nrows = (int)std::min<int64_t>(pair_first ? 2 * L : L, in.N - lo);
                 at.push_back({(in.adv == 2 ? 100000 : 0) + in.lc.nt * 100 + in.lc.pt, t});
                 continue;
             }
@@ -519,6 +519,7 @@ void build_solve(fracsolve_ctx *h, const std::vector<int> &sel, const std::vecto
             LeafCfg lc{key / 100, key % 100, 0};
             Op op{OP_LEAF_ADV, off, (int)v.size(), 0, 0, lc, false};
             op.wsum = at[b].first >= 100000;
+            op.pair = pair_first;
             for (auto &t : v) op.bytes += (double)t.nrows * (double)t.M * (op.wsum ? 24.0 : 16.0);
             ops.push_back(op);
             b = e;
@@ -1269,8 +1270,13 @@ int fracsolve_create(const fracsolve_problem *probs, int32_t count, const fracso
     h->crossover = (o.crossover > 0) ? std::min(o.crossover, 1024) : (o.crossover < 0 ? 0 : 64);
     {
         const char *pv = getenv("FRACSOLVE_PAIR");
-        h->pair = !(pv && pv[0] == '0') && o.equation != FRACSOLVE_ADVECTION && o.leaf_solver == 0 && h->L <= 8 &&
-                  h->L <= h->crossover;
+        h->pair = !(pv && pv[0] == '0') && o.leaf_solver == 0 && h->L <= 8 && h->L <= h->crossover;
+        // the advection leaf reads its rows element by element: past M = 1024
+        // re-reading the first leaf's rows on one CU costs more than the
+        // separate level product (measured)
+        if (o.equation == FRACSOLVE_ADVECTION)
+            for (int k = 0; k < count; ++k)
+                if (probs[k].M > 1024) h->pair = false;
     }
     int64_t npmax = 0;
     for (int k = 0; k < count; ++k) npmax = std::max(npmax, std::max<int64_t>(next_pow2(probs[k].N), h->L));

@@ -499,7 +499,7 @@ __device__ __forceinline__ void row_scan_fwd(double &f, const double *cp)
 // natural order.  WSUM (Scheme 2): x holds W (right-hand sides in, W = B U
 // out) and u receives U; otherwise x is U in place.  The in-leaf history
 // pushes -a_m X into the later rows.
-template <int NT, int PT, int L, bool WSUM>
+template <int NT, int PT, int L, bool WSUM, bool PAIR = false>
 __global__ __launch_bounds__(NT) void k_leaf_adv(TaskRef<AdvTask> tr)
 {
     constexpr int NR = NT / 16;
@@ -510,15 +510,9 @@ __global__ __launch_bounds__(NT) void k_leaf_adv(TaskRef<AdvTask> tr)
     FS_G const double *__restrict__ tab = gptr(tk.fac);
     const int64_t M = tk.M;
     const int c0 = t * PT;
-    const int nrows = tk.nrows;
-    FS_G double *__restrict__ x = gptr(tk.x) + tk.lo * M;
-    FS_G double *__restrict__ u = WSUM ? gptr(tk.u) + tk.lo * M : nullptr;
-    double acc[L][PT];
-#pragma unroll
-    for (int r = 0; r < L; ++r) {
-#pragma unroll
-        for (int k = 0; k < PT; ++k) acc[r][k] = (r < nrows && c0 + k < M) ? x[(int64_t)r * M + c0 + k] : 0.0;
-    }
+    const int nrows_all = tk.nrows;
+    FS_G double *__restrict__ x_base = gptr(tk.x) + tk.lo * M;
+    FS_G double *__restrict__ u_base = WSUM ? gptr(tk.u) + tk.lo * M : nullptr;
     const double g = tab[0];
     const double kap = tab[1];
     double mp[4], cp[5], kp[PT];
@@ -535,41 +529,74 @@ __global__ __launch_bounds__(NT) void k_leaf_adv(TaskRef<AdvTask> tr)
     const double m_lo = pow_bits(mpw, rl);
     const double c_b15 = pow_bits(cp, (lane & 15) + 1);
 
+    // PAIR: two leaves per task with the level product of half-size L
+    // between them, from the first leaf's X rows re-read by their owners
+    constexpr int NH = PAIR ? 2 : 1;
+#pragma unroll 1
+    for (int hf = 0; hf < NH; ++hf) {
+        const int nrows = (hf == 0) ? (nrows_all < L ? nrows_all : L) : nrows_all - L;
+        if (nrows <= 0) break;  // whole workgroup
+        FS_G double *__restrict__ x = x_base + (int64_t)(hf * L) * M;
+        FS_G double *__restrict__ u = WSUM ? u_base + (int64_t)(hf * L) * M : nullptr;
+        double acc[L][PT];
 #pragma unroll
-    for (int r = 0; r < L; ++r) {
-        if (r >= nrows) break;
-        const int par = r & 1;
-        double lf[PT];
-        lf[0] = g * acc[r][0];
+        for (int r = 0; r < L; ++r) {
 #pragma unroll
-        for (int k = 1; k < PT; ++k) lf[k] = fma(kap, lf[k - 1], g * acc[r][k]);
-        double Sf = lf[PT - 1];
-        row_scan_fwd<16>(Sf, mp);
-        if (rl == 15) sR[par][G] = Sf;
-        __syncthreads();
-        double vf = (lane < NR) ? sR[par][lane] : 0.0;
-        row_scan_fwd<(NR < 16 ? NR : 16)>(vf, cp);
-        if constexpr (NR > 16) vf = fma(c_b15, dpp_move<0x142, 0xA>(vf), vf);
-        double Cr = lane_fetch(vf, G > 0 ? G - 1 : 0);
-        Cr = (G > 0) ? Cr : 0.0;
-        // U at the column before the thread's first one (0 at the inflow)
-        const double cf = fma(m_lo, Cr, dpp_move<0x111>(Sf));
-        double U[PT], X[PT];
+            for (int k = 0; k < PT; ++k) acc[r][k] = (r < nrows && c0 + k < M) ? x[(int64_t)r * M + c0 + k] : 0.0;
+        }
+        if constexpr (PAIR) {
+            if (hf == 1) {
+#pragma unroll 1
+                for (int q = 0; q < L; ++q) {
+                    double xq[PT];
 #pragma unroll
-        for (int k = 0; k < PT; ++k) U[k] = fma(kp[k], cf, lf[k]);
+                    for (int k = 0; k < PT; ++k) xq[k] = (c0 + k < M) ? x_base[(int64_t)q * M + c0 + k] : 0.0;
 #pragma unroll
-        for (int k = 0; k < PT; ++k) X[k] = WSUM ? U[k] + (k > 0 ? U[k - 1] : cf) : U[k];
+                    for (int p = 0; p < L; ++p) {
+                        const double w = gptr(tk.a)[L + p - q];
 #pragma unroll
-        for (int k = 0; k < PT; ++k) {
-            if (c0 + k < M) {
-                x[(int64_t)r * M + c0 + k] = X[k];
-                if (WSUM) u[(int64_t)r * M + c0 + k] = U[k];
+                        for (int k = 0; k < PT; ++k) acc[p][k] = fma(-w, xq[k], acc[p][k]);
+                    }
+                }
             }
         }
+
 #pragma unroll
-        for (int j = r + 1; j < L; ++j) {
+        for (int r = 0; r < L; ++r) {
+            if (r >= nrows) break;
+            const int par = r & 1;
+            double lf[PT];
+            lf[0] = g * acc[r][0];
 #pragma unroll
-            for (int k = 0; k < PT; ++k) acc[j][k] = fma(-aw[j - r], X[k], acc[j][k]);
+            for (int k = 1; k < PT; ++k) lf[k] = fma(kap, lf[k - 1], g * acc[r][k]);
+            double Sf = lf[PT - 1];
+            row_scan_fwd<16>(Sf, mp);
+            if (rl == 15) sR[par][G] = Sf;
+            __syncthreads();
+            double vf = (lane < NR) ? sR[par][lane] : 0.0;
+            row_scan_fwd<(NR < 16 ? NR : 16)>(vf, cp);
+            if constexpr (NR > 16) vf = fma(c_b15, dpp_move<0x142, 0xA>(vf), vf);
+            double Cr = lane_fetch(vf, G > 0 ? G - 1 : 0);
+            Cr = (G > 0) ? Cr : 0.0;
+            // U at the column before the thread's first one (0 at the inflow)
+            const double cf = fma(m_lo, Cr, dpp_move<0x111>(Sf));
+            double U[PT], X[PT];
+#pragma unroll
+            for (int k = 0; k < PT; ++k) U[k] = fma(kp[k], cf, lf[k]);
+#pragma unroll
+            for (int k = 0; k < PT; ++k) X[k] = WSUM ? U[k] + (k > 0 ? U[k - 1] : cf) : U[k];
+#pragma unroll
+            for (int k = 0; k < PT; ++k) {
+                if (c0 + k < M) {
+                    x[(int64_t)r * M + c0 + k] = X[k];
+                    if (WSUM) u[(int64_t)r * M + c0 + k] = U[k];
+                }
+            }
+#pragma unroll
+            for (int j = r + 1; j < L; ++j) {
+#pragma unroll
+                for (int k = 0; k < PT; ++k) acc[j][k] = fma(-aw[j - r], X[k], acc[j][k]);
+            }
         }
     }
 }
@@ -587,24 +614,33 @@ hipError_t launch_adv_factor(hipStream_t st, const LeafCfg &c, double a0, double
 
 size_t adv_table_doubles() { return ADV_TAB; }
 
-template <int NT, int PT, int L>
-static hipError_t adv_go(hipStream_t st, bool wsum, const TaskRef<AdvTask> &d_tasks, int ntasks)
+template <int NT, int PT, int L, bool PAIR>
+static void adv_go_p(hipStream_t st, bool wsum, const TaskRef<AdvTask> &d_tasks, int ntasks)
 {
     if (wsum)
-        hipLaunchKernelGGL((k_leaf_adv<NT, PT, L, true>), dim3(ntasks), dim3(NT), 0, st, d_tasks);
+        hipLaunchKernelGGL((k_leaf_adv<NT, PT, L, true, PAIR>), dim3(ntasks), dim3(NT), 0, st, d_tasks);
     else
-        hipLaunchKernelGGL((k_leaf_adv<NT, PT, L, false>), dim3(ntasks), dim3(NT), 0, st, d_tasks);
+        hipLaunchKernelGGL((k_leaf_adv<NT, PT, L, false, PAIR>), dim3(ntasks), dim3(NT), 0, st, d_tasks);
+}
+
+template <int NT, int PT, int L>
+static hipError_t adv_go(hipStream_t st, bool wsum, const TaskRef<AdvTask> &d_tasks, int ntasks, bool pair)
+{
+    if (pair)
+        adv_go_p<NT, PT, L, true>(st, wsum, d_tasks, ntasks);
+    else
+        adv_go_p<NT, PT, L, false>(st, wsum, d_tasks, ntasks);
     return hipGetLastError();
 }
 
 hipError_t launch_leaf_adv(hipStream_t st, const LeafCfg &c, int L, const TaskRef<AdvTask> &d_tasks, int ntasks,
-                           bool wsum)
+                           bool wsum, bool pair)
 {
-#define FS_AL(NT_, PT_)                                                             \
-    if (c.nt == NT_ && c.pt == PT_) {                                               \
-        if (L == 4) return adv_go<NT_, PT_, 4>(st, wsum, d_tasks, ntasks);          \
-        if (L == 8) return adv_go<NT_, PT_, 8>(st, wsum, d_tasks, ntasks);          \
-        return hipErrorInvalidValue;                                                \
+#define FS_AL(NT_, PT_)                                                                   \
+    if (c.nt == NT_ && c.pt == PT_) {                                                     \
+        if (L == 4) return adv_go<NT_, PT_, 4>(st, wsum, d_tasks, ntasks, pair);          \
+        if (L == 8) return adv_go<NT_, PT_, 8>(st, wsum, d_tasks, ntasks, pair);          \
+        return hipErrorInvalidValue;                                                      \
     }
     FS_AL(64, 2)
     FS_AL(64, 4)
