@@ -74,7 +74,7 @@ def lib():
     if _lib is not None:
         return _lib
     if not os.path.exists(LIBPATH):
-        raise RuntimeError("fracsolve HIP library not built: %s is missing (run __graft_entry__.build())" % LIBPATH)
+        raise RuntimeError("fracsolve HIP library not built: %s is missing (run paper_1710_11593_amd.build.build())" % LIBPATH)
     L = ctypes.CDLL(LIBPATH)
     dp = ctypes.POINTER(ctypes.c_double)
     vpp = ctypes.POINTER(ctypes.c_void_p)
