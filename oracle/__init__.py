@@ -20,6 +20,9 @@ Parity status of each function (what pins it, in tests/test_oracle_*.py):
   solve_cn, apply_cn, mode_cn
             -- exactness on (1 + t) sine modes, dense brute force, single-mode
                reduction, the convergence order 3 - gamma in tau
+  ode_column, ode_cg
+            -- Theorem 1's row identity, Table 1 of the paper, CG finite
+               termination and agreement with a Toeplitz solve
   gmres     -- finite termination at the dense solve, least-squares estimates
                equal to recomputed residuals, the one-step minimal-residual
                closed form, exact convergence in N steps with the
@@ -78,6 +81,10 @@ def _load():
     lib.oracle_apply_cn.argtypes = [d, d, d, d, i64, i64, _dp, _dp, i32]
     lib.oracle_mode_cn.restype = i32
     lib.oracle_mode_cn.argtypes = [d, d, i64, d, _dp, d, d, _dp]
+    lib.oracle_ode_column.restype = i32
+    lib.oracle_ode_column.argtypes = [d, i64, _dp]
+    lib.oracle_ode_cg.restype = i32
+    lib.oracle_ode_cg.argtypes = [d, i64, _dp, _dp, i32, d, i32, ctypes.POINTER(i32), _dp, _dp]
     lib.oracle_gmres.restype = i32
     lib.oracle_gmres.argtypes = [d, d, d, d, i64, i64, _dp, _dp, _dp, _dp, i32, i32, d, i32, i32,
                                  ctypes.POINTER(i32), _dp, _dp, i32]
@@ -213,6 +220,28 @@ def mode_cn(gamma, T, N, lam, g, v0=0.0, phihat=0.0):
     v = np.zeros(N)
     _check(lib.oracle_mode_cn(gamma, T, N, lam, _ptr(g), v0, phihat, _ptr(v)), "mode_cn")
     return v
+
+
+def ode_column(gamma, N):
+    """First column of the symmetric Toeplitz matrix of Scheme 1 (N - 1 entries)."""
+    c = np.zeros(N - 1)
+    _check(_load().oracle_ode_column(gamma, N, _ptr(c)), "ode_column")
+    return c
+
+
+def ode_cg(gamma, N, f, maxit=10000, rtol=1e-10, guess=None):
+    """Conjugate gradients for Scheme 1; returns (u [N-1], info)."""
+    lib = _load()
+    f = _f64(f, (N - 1,))
+    u = np.zeros(N - 1) if guess is None else np.array(_f64(guess, (N - 1,)))
+    out = (ctypes.c_int * 2)()
+    rel = ctypes.c_double(0.0)
+    hist = np.zeros(maxit + 1)
+    rc = lib.oracle_ode_cg(gamma, N, _ptr(f), _ptr(u), maxit, rtol, 0 if guess is None else 1, out,
+                           ctypes.byref(rel), _ptr(hist))
+    _check(rc, "ode_cg")
+    it = int(out[0])
+    return u, {"iters": it, "converged": bool(out[1]), "relres": float(rel.value), "hist": hist[: it + 1].copy()}
 
 
 def gmres(gamma, T, x0, x1, M, N, f, u0=None, phi=None, restart=30, maxit=1000, rtol=1e-10, precond=0,

@@ -35,6 +35,10 @@
  *   for Scheme 4, section 3.1), with the operator products evaluated from
  *   their definition.
  *
+ *   Scheme 1 (the two-sided fractional ODE, eq. e7) has its symmetric
+ *   Toeplitz column in oracle_ode_column and conjugate gradients in
+ *   oracle_ode_cg.
+ *
  *   Advection equations D_t^gamma u + u_x = f (Schemes 2 and 3, eq. e11-e17)
  *   are stepped by oracle_solve_adv, and the diffusion-wave variant with the
  *   spatial term averaged over t_n and t_{n-1} by oracle_solve_cn (see
@@ -623,6 +627,95 @@ int oracle_solve_adv(double gamma, double T, double x0, double x1, int64_t M, in
         }
     }
     free(a); free(rho); free(psi); free(r);
+    return ORACLE_OK;
+}
+
+static double vdot(int64_t n, const double *x, const double *y);
+
+/*
+ * Scheme 1 (eq. e7): the two-sided fractional ODE
+ *   D_t^gamma u + tD_1^gamma u + u = f on (0, 1), u(0) = u(1) = 0, 0<gamma<1,
+ * with the L1 formula from the left at t_i and its mirror from the right
+ * (eq. e4, e5), tau = 1/N, unknowns u_1 .. u_{N-1}.  The matrix is
+ * symmetric Toeplitz (Theorem 1): diagonal 1 + 2 mu G_0, and at distance k
+ * the weight mu (G_k - G_{k-1}) = a_k of the diffusion case.
+ * oracle_ode_column writes that first column c[0..N-2].
+ */
+int oracle_ode_column(double gamma, int64_t N, double *c)
+{
+    if (regime_of(gamma) != 0 || N < 2 || !c) return ORACLE_EARG;
+    double *a = (double *)malloc(sizeof(double) * (size_t)N);
+    if (!a) return ORACLE_ENOMEM;
+    oracle_weights(gamma, 1.0, N, NULL, a, NULL, NULL, NULL, NULL, NULL, NULL);
+    c[0] = 1.0 + 2.0 * a[0];
+    for (int64_t k = 1; k < N - 1; ++k) c[k] = a[k];
+    free(a);
+    return ORACLE_OK;
+}
+
+/*
+ * Conjugate gradients for Scheme 1 as listed in section 2.2: r_0 = f - A u_0,
+ * w_1 = r_0; each step takes the step length |r|^2 / <w, A w>, updates u and
+ * r, and the next direction r + (|r_new|^2 / |r_old|^2) w.  The products A w
+ * are the symmetric Toeplitz matrix from its definition (O(n^2)); the paper
+ * makes them fast by a circulant embedding (e10).  Reading: the iteration
+ * stops once |r| <= rtol |f| (the listing leaves the test open).
+ *   f, u [N-1]: u holds the initial guess when use_guess != 0
+ *   out[0] = steps, out[1] = 1 if converged; *relres = |f - A u| / |f|
+ *   recomputed; hist (NULL or maxit + 1) = |r_k| / |f| from the recurrence.
+ */
+int oracle_ode_cg(double gamma, int64_t N, const double *f, double *u, int maxit, double rtol, int use_guess,
+                  int *out, double *relres, double *hist)
+{
+    if (regime_of(gamma) != 0 || N < 2 || !f || !u || !out || !relres || maxit < 0 || !(rtol >= 0.0))
+        return ORACLE_EARG;
+    const int64_t n = N - 1;
+    double *c = (double *)malloc(sizeof(double) * (size_t)n);
+    double *r = (double *)malloc(sizeof(double) * (size_t)n);
+    double *w = (double *)malloc(sizeof(double) * (size_t)n);
+    double *Aw = (double *)malloc(sizeof(double) * (size_t)n);
+    if (!c || !r || !w || !Aw) {
+        free(c); free(r); free(w); free(Aw);
+        return ORACLE_ENOMEM;
+    }
+    oracle_ode_column(gamma, N, c);
+    if (!use_guess)
+        for (int64_t i = 0; i < n; ++i) u[i] = 0.0;
+#define TOEP_MV(x, y)                                                   \
+    for (int64_t i = 0; i < n; ++i) {                                   \
+        double s = 0.0;                                                 \
+        for (int64_t j = 0; j < n; ++j) s += c[i > j ? i - j : j - i] * (x)[j]; \
+        (y)[i] = s;                                                     \
+    }
+    TOEP_MV(u, Aw)
+    for (int64_t i = 0; i < n; ++i) r[i] = f[i] - Aw[i];
+    const double fn = sqrt(vdot(n, f, f));
+    double rr = vdot(n, r, r);
+    out[0] = 0;
+    out[1] = 0;
+    if (hist) hist[0] = fn > 0.0 ? sqrt(rr) / fn : 0.0;
+    for (int64_t i = 0; i < n; ++i) w[i] = r[i];
+    int it = 0;
+    while (it < maxit && sqrt(rr) > rtol * fn) {
+        TOEP_MV(w, Aw)
+        const double kap = rr / vdot(n, w, Aw);
+        for (int64_t i = 0; i < n; ++i) u[i] += kap * w[i];
+        for (int64_t i = 0; i < n; ++i) r[i] -= kap * Aw[i];
+        const double rn = vdot(n, r, r);
+        ++it;
+        if (hist) hist[it] = fn > 0.0 ? sqrt(rn) / fn : 0.0;
+        const double bet = rn / rr;
+        for (int64_t i = 0; i < n; ++i) w[i] = r[i] + bet * w[i];
+        rr = rn;
+    }
+    TOEP_MV(u, Aw)
+#undef TOEP_MV
+    double s = 0.0;
+    for (int64_t i = 0; i < n; ++i) s += (f[i] - Aw[i]) * (f[i] - Aw[i]);
+    out[0] = it;
+    *relres = fn > 0.0 ? sqrt(s) / fn : 0.0;
+    out[1] = *relres <= rtol * (1.0 + 1e-6) || sqrt(rr) <= rtol * fn;
+    free(c); free(r); free(w); free(Aw);
     return ORACLE_OK;
 }
 
