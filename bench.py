@@ -22,7 +22,9 @@ term averaged over t_n and t_{n-1} (c3), batching (c4), the adjoint (c5) and
 the paper's own iterative method, restarted GMRES(m), on its
 Example 4 meshes next to the recursive solve (--config gmres runs only that;
 with --N 2^k only the mesh h = tau = 2^-k), and the advection equations
-(Schemes 2 and 3) on the paper's timing meshes (--config advection).
+(Schemes 2 and 3) on the paper's timing meshes (--config advection), and
+Scheme 1, the two-sided fractional ODE by FFT conjugate gradients, on the
+meshes of its timing table (--config ode).
 cpu_baseline: the oracle (plain time stepping) on the same workload for the
 first --cpu-steps steps at full width; its wall time is scaled by
 (N / steps)^2 (the history work is quadratic in the step count) to the full
@@ -415,6 +417,50 @@ def run_gmres(dev, meshes=(8, 9, 10), rtol=1e-8):
     return res
 
 
+PAPER_FCG_S = {9: 0.01, 10: 0.06, 11: 0.09, 12: 0.57, 13: 1.29, 14: 2.24, 15: 4.58, 16: 9.81, 17: 27.2}
+PAPER_FCG_ITERS = {9: 62, 10: 75, 11: 91, 12: 110, 13: 133, 14: 159, 15: 192, 16: 230, 17: 276}
+
+
+def run_ode(dev, meshes=tuple(range(9, 18)), gamma=0.5, rtol=1e-10):
+    """Scheme 1, the two-sided fractional ODE of Example 1 (u = t(1 - t)),
+    by conjugate gradients with the FFT-embedded operator, on the timing
+    meshes tau = 2^-9 .. 2^-17 of Table 2.  The table gives neither gamma nor
+    the stop rule: gamma = 0.5 reproduces the growth of its step counts
+    (about x1.2 per halving of tau, as sqrt(cond) ~ tau^(-gamma/2)), and the
+    stop rule here is |r| <= rtol |f|.  Each call includes the set-up of the
+    operator (weights and spectra), as the paper's timings include it.  The
+    paper's FCG seconds and step counts (Matlab on a desktop) are context."""
+    import numpy as np
+    import torch
+
+    from paper_1710_11593_amd import binding
+
+    def d(s):
+        return s ** (1 - gamma) / math.gamma(2 - gamma) - 2 * s ** (2 - gamma) / math.gamma(3 - gamma)
+
+    res = {}
+    for k in meshes:
+        N = 2 ** k
+        t = np.arange(1, N) / N
+        f = torch.from_numpy(d(t) + d(1 - t) + t * (1 - t)).to(dev)
+        u = torch.empty_like(f)
+        holder = {}
+
+        def run():
+            holder["i"] = binding.ode_cg(gamma, N, f, out=u, max_iters=20000, rtol=rtol)[1]
+
+        run()
+        ms = timed(run, 3)
+        info = holder["i"]
+        err = float(np.sqrt(np.sum((u.cpu().numpy() - t * (1 - t)) ** 2) / N))
+        res["tau=2^-%d" % k] = {"N": N, "ms": round(ms, 3), "iterations": info["iterations"],
+                                "relres": info["relres"], "converged": info["converged"], "l2_error": err,
+                                "paper_fcg_cpu_s": PAPER_FCG_S.get(k), "paper_fcg_iterations": PAPER_FCG_ITERS.get(k)}
+        log("forms: scheme 1 cg tau=2^-%d: %.2f ms, %d steps, relres %.2e, L2 error %.3e" % (
+            k, ms, info["iterations"], info["relres"], err))
+    return {"gamma": gamma, "rtol": rtol, "meshes": res}
+
+
 def run_batched(args, dev):
     """--config c4: the 256 uneven instances as one batched handle; value =
     sum of M N over the batch per second; error sampled on 8 instances."""
@@ -533,6 +579,9 @@ def main():
         return run_batched(args, dev)
     if args.config == "advection":
         print(json.dumps({"advection": run_advection(dev)}))
+        return
+    if args.config == "ode":
+        print(json.dumps({"scheme1_cg": run_ode(dev)}))
         return
     if args.config == "gmres":
         # the paper's iterative method on its Example 4 meshes (a form, not the headline)

@@ -240,6 +240,40 @@ int fracsolve_gmres(fracsolve_t h, const double *const *f, const double *const *
                     double *hist, int32_t hist_cap);
 
 /*
+ * Scheme 1 (section 2, eq. e7): the two-sided fractional ODE
+ *   D_t^gamma u + tD_1^gamma u + u = f on (0, 1), u(0) = u(1) = 0, 0<gamma<1,
+ * whose matrix is symmetric Toeplitz (Theorem 1): diagonal 1 + 2 mu,
+ * distance k: mu (G_k - G_{k-1}), tau = 1/N.  Solved by conjugate gradients
+ * (section 2.2); each product goes through the circulant embedding of
+ * eq. e10 (one forward and one inverse FFT of L >= 2N - 3 points, a power of
+ * two), the paper's fast CG.  f and u are DEVICE arrays of the N - 1 values at t_i = i/N
+ * (u may not alias f).  The iteration stops when |r| <= rtol |f| (residual
+ * of the recurrence) or after max_iters steps.  opts NULL = {10000, 1e-10,
+ * 0}; info (NULL or one record, host); hist (NULL or hist_cap doubles,
+ * host): |r_k| / |f| from the recurrence, hist[0] for the start.
+ * Work runs on `stream` (NULL = null stream); the call synchronises it and
+ * holds its workspace only for its duration.  3 <= N <= 2^17 + 1.
+ * Errors (text in fracsolve_last_error(NULL)): E_ARG, E_NOMEM, E_DEVICE,
+ * E_NUMERIC (a direction with <p, A p> <= 0).
+ */
+typedef struct {
+    int32_t max_iters;  /* >= 0                                                */
+    double rtol;        /* relative residual target, finite and >= 0           */
+    int32_t use_guess;  /* 0: start from zero; 1: from the contents of u       */
+} fracsolve_cg_options;
+
+typedef struct {
+    int32_t iterations; /* CG steps taken                                      */
+    int32_t converged;  /* 1 if the recurrence residual reached rtol           */
+    double relres;      /* |f - A u| / |f| recomputed at the end               */
+    double relres_est;  /* |r| / |f| of the recurrence                         */
+} fracsolve_cg_info;
+
+int fracsolve_ode_cg(double gamma, int64_t N, const double *f, double *u,
+                     const fracsolve_cg_options *opts, fracsolve_cg_info *info,
+                     double *hist, int32_t hist_cap, void *stream);
+
+/*
  * Timing and plan details of the last call, for reporting.  Fields are -1
  * when not measured.  Filled only if timing was enabled with
  * fracsolve_set_timing(h, 1) before the call (it adds events and a

@@ -53,10 +53,19 @@ class GmresInfo(ctypes.Structure):
                 ("reserved", ctypes.c_int32), ("relres", ctypes.c_double), ("relres_est", ctypes.c_double)]
 
 
+class CgOptions(ctypes.Structure):
+    _fields_ = [("max_iters", ctypes.c_int32), ("rtol", ctypes.c_double), ("use_guess", ctypes.c_int32)]
+
+
+class CgInfo(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int32), ("converged", ctypes.c_int32), ("relres", ctypes.c_double),
+                ("relres_est", ctypes.c_double)]
+
+
 KIND_NAMES = {0: "leaf", 1: "dense_f64", 2: "dense_f32", 3: "fft_f64", 4: "fft_f32", 5: "fft_corner"}
 
 EXPORTS = ["fracsolve_create", "fracsolve_weights", "fracsolve_solve", "fracsolve_apply", "fracsolve_adjoint",
-           "fracsolve_gmres", "fracsolve_set_timing", "fracsolve_get_stats", "fracsolve_kernel_stats", "fracsolve_destroy",
+           "fracsolve_gmres", "fracsolve_ode_cg", "fracsolve_set_timing", "fracsolve_get_stats", "fracsolve_kernel_stats", "fracsolve_destroy",
            "fracsolve_last_error"]
 
 _lib = None
@@ -92,6 +101,10 @@ def lib():
     L.fracsolve_gmres.restype = ctypes.c_int
     L.fracsolve_gmres.argtypes = [ctypes.c_void_p, vpp, vpp, vpp, vpp, ctypes.POINTER(GmresOptions),
                                   ctypes.POINTER(GmresInfo), dp, ctypes.c_int32]
+    L.fracsolve_ode_cg.restype = ctypes.c_int
+    L.fracsolve_ode_cg.argtypes = [ctypes.c_double, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
+                                   ctypes.POINTER(CgOptions), ctypes.POINTER(CgInfo), dp, ctypes.c_int32,
+                                   ctypes.c_void_p]
     L.fracsolve_set_timing.restype = ctypes.c_int
     L.fracsolve_set_timing.argtypes = [ctypes.c_void_p, ctypes.c_int32]
     L.fracsolve_get_stats.restype = ctypes.c_int
@@ -258,6 +271,35 @@ class Solver:
         s = Stats()
         self._check(self._lib.fracsolve_get_stats(self.h, ctypes.byref(s)))
         return {k: getattr(s, k) for k, _ in Stats._fields_}
+
+
+def ode_cg(gamma, N, f, out=None, max_iters=10000, rtol=1e-10, use_guess=False, hist_cap=0, stream=None):
+    """Scheme 1 (the two-sided fractional ODE) by conjugate gradients with the
+    FFT operator (fracsolve_ode_cg).  f: float64 CUDA tensor of the N - 1
+    values at t_i = i/N.  Returns (u, info dict, residual history)."""
+    import numpy as np
+    import torch
+
+    L = lib()
+    if not f.is_cuda or f.dtype != torch.float64 or not f.is_contiguous() or f.numel() != N - 1:
+        raise ValueError("f must be a contiguous float64 CUDA tensor of N - 1 values")
+    if out is None:
+        out = torch.empty_like(f)
+    if stream is None:
+        stream = torch.cuda.current_stream().cuda_stream
+    opts = CgOptions(int(max_iters), float(rtol), 1 if use_guess else 0)
+    info = CgInfo()
+    hist = np.zeros(max(int(hist_cap), 1))
+    rc = L.fracsolve_ode_cg(float(gamma), int(N), ctypes.c_void_p(f.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                            ctypes.byref(opts), ctypes.byref(info),
+                            hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if hist_cap > 0 else None,
+                            int(hist_cap), ctypes.c_void_p(stream))
+    if rc != FRACSOLVE_OK:
+        raise FracsolveError(rc, L.fracsolve_last_error(None).decode())
+    d = {k: getattr(info, k) for k, _ in CgInfo._fields_}
+    d["converged"] = bool(d["converged"])
+    nh = min(int(hist_cap), d["iterations"] + 1) if hist_cap > 0 else 0
+    return out, d, hist[:nh].copy()
 
 
 _solver_cache = {}

@@ -245,6 +245,17 @@ hipError_t launch_copy_reverse(hipStream_t st, const double *src, double *dst, i
 hipError_t launch_permute(hipStream_t st, const double *src, double *dst, int64_t M, int64_t N, ColPerm perm,
                           bool to_internal, bool reverse);
 hipError_t launch_axpy(hipStream_t st, double *y, const double *x, double alpha, int64_t n);
+// symmetric Toeplitz product through its circulant embedding (k_fft1d.hip):
+// L = circ_length(n) (a power of two >= max(8, 2n - 1), at most 2^19); S
+// (L doubles) = the spectrum of the embedded column 1 + 2 a_0, a_1 .. a_{n-1}
+// divided by L (colbuf may alias S); za, zb = two complex arrays of L points.
+// y = A x for n entries (x != y).
+int64_t circ_length(int64_t n);
+int circ_launches(int64_t L);
+hipError_t launch_circ_spectrum(hipStream_t st, const double *a, int64_t n, int64_t L, double *S, double *colbuf,
+                                void *za, void *zb);
+hipError_t launch_circ_apply(hipStream_t st, const double *x, double *y, int64_t n, int64_t L, const double *S,
+                             void *za, void *zb);
 hipError_t launch_sub(hipStream_t st, double *r, const double *b, const double *y, int64_t n);
 hipError_t launch_to_f32(hipStream_t st, const double *x, float *y, int64_t n);
 hipError_t launch_zero(hipStream_t st, void *p, size_t bytes);

@@ -1206,9 +1206,130 @@ int gmres_one(fracsolve_ctx *h, int k, const double *f, const double *u0, const 
     return FRACSOLVE_OK;
 }
 
+// ---- Scheme 1 (eq. e7): conjugate gradients with the FFT operator ----
+//
+// The two-sided ODE's matrix is A = I + T + T^T with T the lower-triangular
+// Toeplitz matrix of the diffusion weights a (a_0 on the diagonal), so A is
+// symmetric Toeplitz with column c_0 = 1 + 2 a_0, c_m = a_m (Theorem 1).  A
+// handle with M = 1 computes the weights; the product A x goes through the
+// circulant embedding of length L >= 2n - 1 (eq. e10): one forward and one
+// inverse FFT of L points per product.
+
+struct OdeWork {
+    double *r, *p, *Ap;
+    double *S;       // real spectrum of the embedded column, divided by L
+    double *za, *zb;  // two complex work arrays of L points
+    int64_t L;
+};
+
+int ode_matvec(fracsolve_ctx *h, const OdeWork &w, const double *x, double *y)
+{
+    HIPCHK(h, launch_circ_apply(h->st, x, y, h->inst[0].N, w.L, w.S, w.za, w.zb));
+    h->kernels += circ_launches(w.L);
+    return FRACSOLVE_OK;
+}
+
+int ode_cg_run(fracsolve_ctx *h, const double *f, double *u, const fracsolve_cg_options &o, fracsolve_cg_info *info,
+               double *hist, int hist_cap)
+{
+    const int64_t n = h->inst[0].N;
+    OdeWork w{};
+    int rc;
+    w.L = circ_length(n);
+    for (double **q : {&w.r, &w.p, &w.Ap})
+        if ((rc = dalloc(h, q, (size_t)n))) return rc;
+    if ((rc = dalloc(h, &w.S, (size_t)w.L)) || (rc = dalloc(h, &w.za, 2 * (size_t)w.L)) ||
+        (rc = dalloc(h, &w.zb, 2 * (size_t)w.L)))
+        return rc;
+    // the embedded column is staged in S before its transform replaces it
+    HIPCHK(h, launch_circ_spectrum(h->st, h->inst[0].a, n, w.L, w.S, w.S, w.za, w.zb));
+    auto put_hist = [&](int i, double v) {
+        if (hist && i < hist_cap) hist[i] = v;
+    };
+    double fn = 0.0;
+    if ((rc = dev_norm2(h, f, n, &fn))) return rc;
+    if (!o.use_guess || fn == 0.0) HIPCHK(h, launch_zero(h->st, u, sizeof(double) * (size_t)n));
+    fracsolve_cg_info res{0, 0, 0.0, 0.0};
+    if (fn == 0.0) {
+        res.converged = 1;
+        put_hist(0, 0.0);
+        if (info) *info = res;
+        return FRACSOLVE_OK;
+    }
+    // r = f - A u, p = r
+    if ((rc = ode_matvec(h, w, u, w.Ap))) return rc;
+    HIPCHK(h, launch_sub(h->st, w.r, f, w.Ap, n));
+    HIPCHK(h, hipMemcpyAsync(w.p, w.r, sizeof(double) * (size_t)n, hipMemcpyDeviceToDevice, h->st));
+    double rr = 0.0;
+    if ((rc = dev_norm2(h, w.r, n, &rr))) return rc;
+    rr *= rr;
+    put_hist(0, std::sqrt(rr) / fn);
+    int it = 0;
+    while (it < o.max_iters && std::sqrt(rr) > o.rtol * fn) {
+        if ((rc = ode_matvec(h, w, w.p, w.Ap))) return rc;
+        double pAp = 0.0;
+        HIPCHK(h, launch_dot_partial(h->st, w.p, w.Ap, n, h->partial, kRedBlocks));
+        if ((rc = finish_sum(h, kRedBlocks, &pAp))) return rc;
+        if (!(pAp > 0.0)) return fail(h, FRACSOLVE_E_NUMERIC, "CG: <p, A p> = %g at step %d", pAp, it);
+        const double kap = rr / pAp;
+        HIPCHK(h, launch_axpy(h->st, u, w.p, kap, n));
+        HIPCHK(h, launch_axpy(h->st, w.r, w.Ap, -kap, n));
+        double rn = 0.0;
+        if ((rc = dev_norm2(h, w.r, n, &rn))) return rc;
+        rn *= rn;
+        ++it;
+        put_hist(it, std::sqrt(rn) / fn);
+        const double bet = rn / rr, one = 1.0;
+        if ((rc = lincomb(h, w.p, bet, w.r, n, 1, &one))) return rc;
+        rr = rn;
+    }
+    // the residual from its definition
+    if ((rc = ode_matvec(h, w, u, w.Ap))) return rc;
+    HIPCHK(h, launch_sub(h->st, w.r, f, w.Ap, n));
+    double tr = 0.0;
+    if ((rc = dev_norm2(h, w.r, n, &tr))) return rc;
+    res.iterations = it;
+    res.relres = tr / fn;
+    res.relres_est = std::sqrt(rr) / fn;
+    res.converged = (std::sqrt(rr) <= o.rtol * fn) ? 1 : 0;
+    if (info) *info = res;
+    return FRACSOLVE_OK;
+}
+
 }  // namespace
 
 extern "C" {
+
+int fracsolve_ode_cg(double gamma, int64_t N, const double *f, double *u, const fracsolve_cg_options *opts,
+                     fracsolve_cg_info *info, double *hist, int32_t hist_cap, void *stream)
+{
+    if (!(gamma > 0.0 && gamma < 1.0))
+        return fail(nullptr, FRACSOLVE_E_ARG, "gamma must lie in (0,1) for the two-sided ODE, got %g", gamma);
+    if (N < 3 || N - 1 > (1LL << 17))
+        return fail(nullptr, FRACSOLVE_E_ARG, "N must lie in [3, 2^17 + 1], got %lld", (long long)N);
+    if (!f || !u) return fail(nullptr, FRACSOLVE_E_ARG, "f and u must not be NULL");
+    fracsolve_cg_options o{10000, 1e-10, 0};
+    if (opts) o = *opts;
+    if (o.max_iters < 0) return fail(nullptr, FRACSOLVE_E_ARG, "max_iters must be >= 0, got %d", (int)o.max_iters);
+    if (!(o.rtol >= 0.0) || !std::isfinite(o.rtol))
+        return fail(nullptr, FRACSOLVE_E_ARG, "rtol must be finite and >= 0, got %g", o.rtol);
+    if (o.use_guess < 0 || o.use_guess > 1)
+        return fail(nullptr, FRACSOLVE_E_ARG, "use_guess must be 0 or 1, got %d", (int)o.use_guess);
+    if (hist_cap < 0 || (hist_cap > 0 && !hist))
+        return fail(nullptr, FRACSOLVE_E_ARG, "hist is NULL with hist_cap %d", (int)hist_cap);
+    // n = N - 1 unknowns, tau = 1/N: T = n / N over n steps (the handle's
+    // spatial data are unused: one point on (0, 2))
+    fracsolve_problem p{gamma, (double)(N - 1) / (double)N, 0.0, 2.0, 1, N - 1};
+    fracsolve_options ho{};
+    ho.stream = stream;
+    fracsolve_t h = nullptr;
+    int rc = fracsolve_create(&p, 1, &ho, &h);
+    if (rc) return rc;
+    rc = ode_cg_run(h, f, u, o, info, hist, hist_cap);
+    if (rc) g_create_error = h->err;
+    fracsolve_destroy(h);
+    return rc;
+}
 
 int fracsolve_create(const fracsolve_problem *probs, int32_t count, const fracsolve_options *opts, fracsolve_t *out)
 {

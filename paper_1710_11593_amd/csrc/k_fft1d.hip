@@ -1,0 +1,259 @@
+// One-dimensional complex FFT of a power-of-two length L (8 <= L <= 2^19)
+// and the symmetric-Toeplitz product built on it (Scheme 1, eq. e10): the
+// n x n symmetric Toeplitz matrix with first column c is the leading block of
+// the L-periodic circulant whose first column is c followed by zeros and by
+// c_{n-1} .. c_1 (any L >= 2n - 1), and a circulant is diagonalised by the
+// DFT, so A x = first n entries of IDFT( DFT(ĉ) * DFT(x padded with zeros) ).
+//
+// The transform is the self-sorting (Stockham) formulation: each pass takes
+// L/R butterflies of radix R (8, with one pass of 4 or 2 when log2 L is not a
+// multiple of 3); butterfly j of a pass whose sub-transforms have length Ns
+// reads the R inputs j + r L/R (consecutive threads read consecutive
+// elements), twiddles input r by w^(r k) with k = j mod Ns and w the
+// (Ns R)-th root of unity, transforms, and writes output r to
+// (j - k) R + k + r Ns, so the result comes out in natural order with no
+// bit-reversal pass.  The zero padding of x, the product with the circulant's
+// spectrum (real, the column being symmetric; pre-divided by L) and the real
+// part of the output are fused into the first forward, first inverse and last
+// inverse pass, so one product costs the passes of two transforms.
+#include <algorithm>
+#include <cmath>
+
+#include "common.hpp"
+
+namespace fs {
+
+namespace {
+
+struct c2 {
+    double x, y;
+};
+
+__device__ __forceinline__ c2 cadd(c2 a, c2 b) { return {a.x + b.x, a.y + b.y}; }
+__device__ __forceinline__ c2 csub(c2 a, c2 b) { return {a.x - b.x, a.y - b.y}; }
+__device__ __forceinline__ c2 cmul(c2 a, c2 b) { return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x}; }
+// sgn i z: +i z for sgn > 0, -i z for sgn < 0
+__device__ __forceinline__ c2 cmuli(c2 z, double sgn) { return {-sgn * z.y, sgn * z.x}; }
+
+// X_k = sum_m v_m exp(sgn 2 pi i m k / R), in place, for R = 2, 4, 8
+template <int R>
+__device__ __forceinline__ void dft_small(c2 *v, double sgn)
+{
+    if constexpr (R == 2) {
+        const c2 a = v[0], b = v[1];
+        v[0] = cadd(a, b);
+        v[1] = csub(a, b);
+    } else if constexpr (R == 4) {
+        const c2 s02 = cadd(v[0], v[2]), d02 = csub(v[0], v[2]);
+        const c2 s13 = cadd(v[1], v[3]), d13 = cmuli(csub(v[1], v[3]), sgn);
+        v[0] = cadd(s02, s13);
+        v[2] = csub(s02, s13);
+        v[1] = cadd(d02, d13);
+        v[3] = csub(d02, d13);
+    } else {
+        static_assert(R == 8, "radix 2, 4 or 8");
+        // even and odd halves by the radix-4 transform, then one radix-2 step
+        // with the eighth roots of unity w^k, w = exp(sgn i pi / 4)
+        c2 e[4] = {v[0], v[2], v[4], v[6]};
+        c2 o[4] = {v[1], v[3], v[5], v[7]};
+        dft_small<4>(e, sgn);
+        dft_small<4>(o, sgn);
+        const double h = 0.70710678118654752440;  // 1/sqrt(2)
+        o[1] = {h * (o[1].x - sgn * o[1].y), h * (o[1].y + sgn * o[1].x)};
+        o[2] = cmuli(o[2], sgn);
+        o[3] = {h * (-o[3].x - sgn * o[3].y), h * (-o[3].y + sgn * o[3].x)};
+        for (int k = 0; k < 4; ++k) {
+            v[k] = cadd(e[k], o[k]);
+            v[k + 4] = csub(e[k], o[k]);
+        }
+    }
+}
+
+// One Stockham pass.  IN_REAL: the input is the real array xr of nx entries,
+// zero beyond (first forward pass, Ns = 1).  SCALE: inputs are multiplied by
+// the real spectrum S (first inverse pass, Ns = 1).  OUT_REAL: the real parts
+// of outputs below nx go to yr and the rest is dropped (last inverse pass).
+template <int R, bool IN_REAL, bool SCALE, bool OUT_REAL>
+__global__ void __launch_bounds__(256) k_fft1d_pass(const c2 *__restrict__ in, const double *__restrict__ xr,
+                                                    const double *__restrict__ S, c2 *__restrict__ out,
+                                                    double *__restrict__ yr, int64_t L, int64_t Ns, int64_t nx,
+                                                    double sgn)
+{
+    const int64_t q = L / R;
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= q) return;
+    c2 v[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int64_t idx = j + r * q;
+        if constexpr (IN_REAL)
+            v[r] = {idx < nx ? xr[idx] : 0.0, 0.0};
+        else
+            v[r] = in[idx];
+        if constexpr (SCALE) {
+            const double s = S[idx];
+            v[r] = {v[r].x * s, v[r].y * s};
+        }
+    }
+    const int64_t k = j & (Ns - 1);
+    if (Ns > 1) {
+        // angle of w^(r k), in units of pi: sgn 2 r k / (Ns R)
+        const double a = sgn * 2.0 * (double)k / (double)(Ns * R);
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+            double sn, cs;
+            sincospi(a * r, &sn, &cs);
+            v[r] = cmul(v[r], c2{cs, sn});
+        }
+    }
+    dft_small<R>(v, sgn);
+    const int64_t base = (j - k) * R + k;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int64_t o = base + r * Ns;
+        if constexpr (OUT_REAL) {
+            if (o < nx) yr[o] = v[r].x;
+        } else {
+            out[o] = v[r];
+        }
+    }
+}
+
+template <int R, bool IN_REAL, bool SCALE, bool OUT_REAL>
+hipError_t pass_go(hipStream_t st, const c2 *in, const double *xr, const double *S, c2 *out, double *yr, int64_t L,
+                   int64_t Ns, int64_t nx, double sgn)
+{
+    const int64_t q = L / R;
+    const unsigned g = (unsigned)((q + 255) / 256);
+    hipLaunchKernelGGL((k_fft1d_pass<R, IN_REAL, SCALE, OUT_REAL>), dim3(g), dim3(256), 0, st, in, xr, S, out, yr,
+                       L, Ns, nx, sgn);
+    return hipGetLastError();
+}
+
+template <bool IN_REAL, bool SCALE, bool OUT_REAL>
+hipError_t pass_radix(int R, hipStream_t st, const c2 *in, const double *xr, const double *S, c2 *out, double *yr,
+                      int64_t L, int64_t Ns, int64_t nx, double sgn)
+{
+    switch (R) {
+    case 8: return pass_go<8, IN_REAL, SCALE, OUT_REAL>(st, in, xr, S, out, yr, L, Ns, nx, sgn);
+    case 4: return pass_go<4, IN_REAL, SCALE, OUT_REAL>(st, in, xr, S, out, yr, L, Ns, nx, sgn);
+    default: return pass_go<2, IN_REAL, SCALE, OUT_REAL>(st, in, xr, S, out, yr, L, Ns, nx, sgn);
+    }
+}
+
+// radices of the passes: 8s, with the remainder (4 or 2) first
+int radix_plan(int p, int *rad)
+{
+    int np = 0;
+    if (p % 3 == 1) rad[np++] = 2;
+    if (p % 3 == 2) rad[np++] = 4;
+    for (int b = 0; b < p / 3; ++b) rad[np++] = 8;
+    return np;
+}
+
+// mode 0: forward transform of the real xr (nx entries, zero-padded) into
+// dst; mode 1: inverse transform of S .* src (complex), real part of the
+// first nx entries into yr.  The passes alternate between the two complex
+// buffers a and b; the forward result lands in *res.
+hipError_t fft1d_run(hipStream_t st, int mode, const double *xr, const double *S, double *yr, c2 *a, c2 *b,
+                     int64_t L, int64_t nx, c2 **res)
+{
+    int p = 0;
+    while ((int64_t(1) << p) < L) ++p;
+    int rad[24];
+    const int np = radix_plan(p, rad);
+    const double sgn = mode == 0 ? -1.0 : 1.0;
+    int64_t Ns = 1;
+    c2 *src = a, *dst = b;
+    hipError_t e = hipSuccess;
+    for (int i = 0; i < np && e == hipSuccess; ++i) {
+        const bool first = i == 0, last = i == np - 1;
+        if (mode == 0) {
+            if (first)
+                e = pass_radix<true, false, false>(rad[i], st, nullptr, xr, nullptr, dst, nullptr, L, Ns, nx, sgn);
+            else
+                e = pass_radix<false, false, false>(rad[i], st, src, nullptr, nullptr, dst, nullptr, L, Ns, nx, sgn);
+        } else {
+            if (first && last)
+                e = pass_radix<false, true, true>(rad[i], st, src, nullptr, S, nullptr, yr, L, Ns, nx, sgn);
+            else if (first)
+                e = pass_radix<false, true, false>(rad[i], st, src, nullptr, S, dst, nullptr, L, Ns, nx, sgn);
+            else if (last)
+                e = pass_radix<false, false, true>(rad[i], st, src, nullptr, nullptr, nullptr, yr, L, Ns, nx, sgn);
+            else
+                e = pass_radix<false, false, false>(rad[i], st, src, nullptr, nullptr, dst, nullptr, L, Ns, nx, sgn);
+        }
+        Ns *= rad[i];
+        std::swap(src, dst);
+    }
+    if (res) *res = src;  // the buffer the last pass wrote
+    return e;
+}
+
+// ĉ: c_0 at 0, c_m and its mirror L - m for 1 <= m < n, zero elsewhere, with
+// c_0 = 1 + 2 a_0 and c_m = a_m (A = I + T + T^T, T lower-triangular Toeplitz
+// of the weights a)
+__global__ void k_circ_column(const double *__restrict__ a, double *__restrict__ ch, int64_t n, int64_t L)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= L) return;
+    double v = 0.0;
+    if (i == 0)
+        v = 1.0 + 2.0 * a[0];
+    else if (i < n)
+        v = a[i];
+    else if (i > L - n)
+        v = a[L - i];
+    ch[i] = v;
+}
+
+// S = Re(z) / L
+__global__ void k_spec_real(const c2 *__restrict__ z, double *__restrict__ S, int64_t L)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < L) S[i] = z[i].x / (double)L;
+}
+
+}  // namespace
+
+int64_t circ_length(int64_t n)
+{
+    int64_t L = 8;
+    while (L < 2 * n - 1) L *= 2;
+    return L;
+}
+
+hipError_t launch_circ_spectrum(hipStream_t st, const double *a, int64_t n, int64_t L, double *S, double *colbuf,
+                                void *za, void *zb)
+{
+    if (L < 8 || (L & (L - 1)) || L < 2 * n - 1 || L > (int64_t(1) << 19)) return hipErrorInvalidValue;
+    const unsigned g = (unsigned)((L + 255) / 256);
+    hipLaunchKernelGGL(k_circ_column, dim3(g), dim3(256), 0, st, a, colbuf, n, L);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    c2 *res = nullptr;
+    if ((e = fft1d_run(st, 0, colbuf, nullptr, nullptr, (c2 *)za, (c2 *)zb, L, L, &res)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_spec_real, dim3(g), dim3(256), 0, st, res, S, L);
+    return hipGetLastError();
+}
+
+hipError_t launch_circ_apply(hipStream_t st, const double *x, double *y, int64_t n, int64_t L, const double *S,
+                             void *za, void *zb)
+{
+    if (L < 8 || (L & (L - 1)) || L < 2 * n - 1 || L > (int64_t(1) << 19) || x == y) return hipErrorInvalidValue;
+    c2 *res = nullptr;
+    hipError_t e = fft1d_run(st, 0, x, nullptr, nullptr, (c2 *)za, (c2 *)zb, L, n, &res);
+    if (e != hipSuccess) return e;
+    c2 *other = res == (c2 *)za ? (c2 *)zb : (c2 *)za;
+    return fft1d_run(st, 1, nullptr, S, y, res, other, L, n, nullptr);
+}
+
+int circ_launches(int64_t L)
+{
+    int p = 0;
+    while ((int64_t(1) << p) < L) ++p;
+    int rad[24];
+    return 2 * radix_plan(p, rad);
+}
+
+}  // namespace fs

@@ -1,0 +1,128 @@
+"""GPU parity of fracsolve_ode_cg (Scheme 1, the two-sided fractional ODE,
+conjugate gradients with the FFT operator) against the oracle's CG, a
+Toeplitz solve and the paper's Table 1.
+
+Bars (float64): step counts within 2 of the oracle's; residual histories
+relative 1e-6 over the first 20 steps; converged iterates within
+cond(A) rtol of the Toeplitz solve; the reported residual equal to the one
+recomputed on the CPU from the oracle's Toeplitz column (relative 1e-6,
+above the rounding floor of a float64 matrix-vector product).
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+from scipy.linalg import matmul_toeplitz, solve_toeplitz
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1710_11593_amd import binding
+
+    binding.lib()
+    return torch
+
+
+def forcing(gamma, N):
+    t = np.arange(1, N) / N
+
+    def d(s):
+        return s ** (1 - gamma) / math.gamma(2 - gamma) - 2 * s ** (2 - gamma) / math.gamma(3 - gamma)
+
+    return t, d(t) + d(1 - t) + t * (1 - t)
+
+
+def gpu_cg(torch, gamma, N, f, **kw):
+    from paper_1710_11593_amd import binding
+
+    fd = torch.from_numpy(np.ascontiguousarray(f)).cuda()
+    guess = kw.pop("guess", None)
+    out = torch.from_numpy(np.ascontiguousarray(guess)).cuda() if guess is not None else None
+    u, info, hist = binding.ode_cg(gamma, N, fd, out=out, use_guess=guess is not None, **kw)
+    torch.cuda.synchronize()
+    return u.cpu().numpy(), info, hist
+
+
+@pytest.mark.parametrize("gamma,N", [(0.3, 64), (0.5, 257), (0.9, 1024), (0.7, 3000)])
+def test_matches_the_oracle_cg(torch_cuda, orc, gamma, N):
+    t, f = forcing(gamma, N)
+    u, info, hist = gpu_cg(torch_cuda, gamma, N, f, rtol=1e-12, max_iters=5000, hist_cap=5001)
+    uo, io = orc.ode_cg(gamma, N, f, maxit=5000, rtol=1e-12)
+    print("ode cg", gamma, N, info["iterations"], io["iters"], flush=True)
+    assert info["converged"] and io["converged"]
+    assert abs(info["iterations"] - io["iters"]) <= 2
+    for k in range(min(len(hist), len(io["hist"]), 21)):
+        if io["hist"][k] < 1e-8:
+            break
+        assert abs(hist[k] - io["hist"][k]) <= 1e-6 * io["hist"][k], (k, hist[k], io["hist"][k])
+    c = orc.ode_column(gamma, N)
+    ref = solve_toeplitz(c, f)
+    assert np.max(np.abs(u - ref)) <= 1e-8 * np.max(np.abs(ref))
+    rel = np.linalg.norm(f - matmul_toeplitz((c, c), u)) / np.linalg.norm(f)
+    assert abs(rel - info["relres"]) <= 1e-6 * rel + rounding_floor(c, u, f)
+
+
+def rounding_floor(c, u, f):
+    """Rounding level of a float64 residual f - A u relative to |f|: both
+    products (FFT-based here and on the GPU) carry a normwise error of a few
+    eps log2(N) |A| |u|, with |A|_2 <= |A|_1 for this symmetric matrix."""
+    N = len(f)
+    a1 = abs(c[0]) + 2 * np.sum(np.abs(c[1:]))
+    return 8 * math.log2(N) * np.finfo(float).eps * a1 * np.linalg.norm(u) / np.linalg.norm(f)
+
+
+def read_table():
+    rows = []
+    for line in open(os.path.join(GOLDEN, "table1.txt")):
+        line = line.strip()
+        if line and not line.startswith("#"):
+            g, k, p = line.split()
+            rows.append((float(g), int(k), p))
+    return rows
+
+
+def test_table1_from_gpu_solutions(torch_cuda):
+    for gamma, k, printed in read_table():
+        N = 2 ** k
+        t, f = forcing(gamma, N)
+        u, info, _ = gpu_cg(torch_cuda, gamma, N, f, rtol=1e-13, max_iters=20000)
+        err = math.sqrt(np.sum((u - t * (1 - t)) ** 2) / N)
+        target = float(printed)
+        e = math.floor(math.log10(target))
+        assert abs(err - target) <= 1.0001 * 10 ** (e - 4), (gamma, k, err, printed, info)
+
+
+def test_largest_size_and_guess(torch_cuda, orc):
+    gamma, N = 0.5, 2 ** 17 + 1
+    t, f = forcing(gamma, N)
+    u, info, _ = gpu_cg(torch_cuda, gamma, N, f, rtol=1e-10, max_iters=20000)
+    c = orc.ode_column(gamma, N)
+    rel = np.linalg.norm(f - matmul_toeplitz((c, c), u)) / np.linalg.norm(f)
+    print("ode cg n=2^17:", info, "cpu residual", rel, flush=True)
+    assert info["converged"] and rel <= 1.5e-10
+    assert abs(rel - info["relres"]) <= 1e-6 * rel + rounding_floor(c, u, f)
+    # restarting from the result takes no step
+    u2, info2, _ = gpu_cg(torch_cuda, gamma, N, f, rtol=1e-9, max_iters=10, guess=u)
+    assert info2["iterations"] == 0 and np.array_equal(u2, u)
+
+
+def test_invalid_arguments(torch_cuda):
+    from paper_1710_11593_amd import binding
+
+    f = torch_cuda.zeros(7, dtype=torch_cuda.float64, device="cuda")
+    for g, N, pat in [(1.2, 8, "gamma"), (0.0, 8, "gamma"), (0.5, 2, "N"), (0.5, 2 ** 17 + 2, "N")]:
+        ff = f if N == 8 else torch_cuda.zeros(max(N - 1, 1), dtype=torch_cuda.float64, device="cuda")
+        with pytest.raises((binding.FracsolveError, ValueError), match=pat):
+            binding.ode_cg(g, N, ff)
+    with pytest.raises(binding.FracsolveError, match="rtol"):
+        binding.ode_cg(0.5, 8, f, rtol=-1.0)
+    z, info, _ = binding.ode_cg(0.5, 8, f)
+    assert info["iterations"] == 0 and info["converged"] and not z.cpu().numpy().any()
