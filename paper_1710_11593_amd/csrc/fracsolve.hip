@@ -1264,24 +1264,41 @@ int ode_cg_run(fracsolve_ctx *h, const double *f, double *u, const fracsolve_cg_
     if ((rc = dev_norm2(h, w.r, n, &rr))) return rc;
     rr *= rr;
     put_hist(0, std::sqrt(rr) / fn);
-    int it = 0;
-    while (it < o.max_iters && std::sqrt(rr) > o.rtol * fn) {
-        if ((rc = ode_matvec(h, w, w.p, w.Ap))) return rc;
-        double pAp = 0.0;
-        HIPCHK(h, launch_dot_partial(h->st, w.p, w.Ap, n, h->partial, kRedBlocks));
-        if ((rc = finish_sum(h, kRedBlocks, &pAp))) return rc;
-        if (!(pAp > 0.0)) return fail(h, FRACSOLVE_E_NUMERIC, "CG: <p, A p> = %g at step %d", pAp, it);
-        const double kap = rr / pAp;
-        HIPCHK(h, launch_axpy(h->st, u, w.p, kap, n));
-        HIPCHK(h, launch_axpy(h->st, w.r, w.Ap, -kap, n));
-        double rn = 0.0;
-        if ((rc = dev_norm2(h, w.r, n, &rn))) return rc;
-        rn *= rn;
-        ++it;
-        put_hist(it, std::sqrt(rn) / fn);
-        const double bet = rn / rr, one = 1.0;
-        if ((rc = lincomb(h, w.p, bet, w.r, n, 1, &one))) return rc;
-        rr = rn;
+    // The scalars live on the device; the host enqueues a batch of steps and
+    // reads the state back once per batch.  Steps past the stop are no-ops.
+    CgState hs{};
+    hs.rr = rr;
+    hs.rtol_fn = o.rtol * fn;
+    hs.fn = fn;
+    hs.maxit = o.max_iters;
+    hs.done = (o.max_iters <= 0 || std::sqrt(rr) <= o.rtol * fn) ? 1 : 0;
+    CgState *ds = nullptr;
+    double *dh = nullptr;
+    if ((rc = dalloc(h, &ds, 1))) return rc;
+    if (hist_cap > 1 && (rc = dalloc(h, &dh, (size_t)hist_cap))) return rc;
+    HIPCHK(h, hipMemcpyAsync(ds, &hs, sizeof hs, hipMemcpyHostToDevice, h->st));
+    HIPCHK(h, hipStreamSynchronize(h->st));
+    const int32_t *skip = &ds->done;
+    const int batch = 8;
+    while (!hs.done) {
+        for (int b = 0; b < batch; ++b) {
+            HIPCHK(h, launch_circ_apply(h->st, w.p, w.Ap, n, w.L, w.S, w.za, w.zb, skip));
+            HIPCHK(h, launch_cg_step_tail(h->st, ds, u, w.r, w.p, w.Ap, n, h->partial, dh, hist_cap));
+            h->kernels += circ_launches(w.L) + 5;
+        }
+        HIPCHK(h, hipMemcpyAsync(&hs, ds, sizeof hs, hipMemcpyDeviceToHost, h->st));
+        HIPCHK(h, hipStreamSynchronize(h->st));
+    }
+    if (hs.bad) return fail(h, FRACSOLVE_E_NUMERIC, "CG: <p, A p> = %g at step %d", hs.pAp, (int)hs.it);
+    const int it = hs.it;
+    rr = hs.rr;
+    if (dh && hist) {
+        const int nh = std::min(hist_cap, it + 1);
+        if (nh > 1) {
+            HIPCHK(h, hipMemcpyAsync(hist + 1, dh + 1, sizeof(double) * (size_t)(nh - 1), hipMemcpyDeviceToHost,
+                                     h->st));
+            HIPCHK(h, hipStreamSynchronize(h->st));
+        }
     }
     // the residual from its definition
     if ((rc = ode_matvec(h, w, u, w.Ap))) return rc;

@@ -6,8 +6,8 @@
 // DFT, so A x = first n entries of IDFT( DFT(ĉ) * DFT(x padded with zeros) ).
 //
 // The transform is the self-sorting (Stockham) formulation: each pass takes
-// L/R butterflies of radix R (8, with one pass of 4 or 2 when log2 L is not a
-// multiple of 3); butterfly j of a pass whose sub-transforms have length Ns
+// L/R butterflies of radix R (64 for six bits of log2 L at a time, 8, 4 or 2
+// for the rest); butterfly j of a pass whose sub-transforms have length Ns
 // reads the R inputs j + r L/R (consecutive threads read consecutive
 // elements), twiddles input r by w^(r k) with k = j mod Ns and w the
 // (Ns R)-th root of unity, transforms, and writes output r to
@@ -74,11 +74,12 @@ __device__ __forceinline__ void dft_small(c2 *v, double sgn)
 // the real spectrum S (first inverse pass, Ns = 1).  OUT_REAL: the real parts
 // of outputs below nx go to yr and the rest is dropped (last inverse pass).
 template <int R, bool IN_REAL, bool SCALE, bool OUT_REAL>
-__global__ void __launch_bounds__(256) k_fft1d_pass(const c2 *__restrict__ in, const double *__restrict__ xr,
+__global__ void __launch_bounds__(64) k_fft1d_pass(const c2 *__restrict__ in, const double *__restrict__ xr,
                                                     const double *__restrict__ S, c2 *__restrict__ out,
                                                     double *__restrict__ yr, int64_t L, int64_t Ns, int64_t nx,
-                                                    double sgn)
+                                                    double sgn, const int32_t *__restrict__ skip)
 {
+    if (skip && *skip) return;
     const int64_t q = L / R;
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= q) return;
@@ -119,35 +120,121 @@ __global__ void __launch_bounds__(256) k_fft1d_pass(const c2 *__restrict__ in, c
     }
 }
 
+// Radix-64 pass: eight threads per 64-point butterfly, 8 butterflies per
+// workgroup of one wavefront (L = 2^18 gives 512 workgroups, enough to
+// reach every CU of a latency-bound pass).  Input r = 8 n1 + n2 goes to thread n2; a radix-8 transform over
+// n1 gives Y[n2][k1], which is twiddled by w64^(n2 k1), transposed through
+// LDS, and transformed over n2 by thread k1, giving output k1 + 8 k2.
+template <bool IN_REAL, bool SCALE, bool OUT_REAL>
+__global__ void __launch_bounds__(64) k_fft1d_pass64(const c2 *__restrict__ in, const double *__restrict__ xr,
+                                                      const double *__restrict__ S, c2 *__restrict__ out,
+                                                      double *__restrict__ yr, int64_t L, int64_t Ns, int64_t nx,
+                                                      double sgn, const int32_t *__restrict__ skip)
+{
+    if (skip && *skip) return;
+    __shared__ c2 lds[8 * 72];  // per butterfly 8 rows of 9 (one pad entry against bank conflicts)
+    const int t = threadIdx.x & 7, g = threadIdx.x >> 3;
+    const int64_t q = L / 64;
+    const int64_t j = (int64_t)blockIdx.x * 8 + g;
+    const bool live = j < q;
+    const int64_t k = j & (Ns - 1);
+    c2 v[8];
+    const double a = sgn * 2.0 * (double)k / (double)(Ns * 64);
+#pragma unroll
+    for (int n1 = 0; n1 < 8; ++n1) {
+        const int r = 8 * n1 + t;
+        const int64_t idx = j + r * q;
+        c2 x{0.0, 0.0};
+        if (live) {
+            if constexpr (IN_REAL)
+                x = {idx < nx ? xr[idx] : 0.0, 0.0};
+            else
+                x = in[idx];
+            if constexpr (SCALE) {
+                const double s = S[idx];
+                x = {x.x * s, x.y * s};
+            }
+        }
+        if (Ns > 1 && r > 0) {
+            double sn, cs;
+            sincospi(a * r, &sn, &cs);
+            x = cmul(x, c2{cs, sn});
+        }
+        v[n1] = x;
+    }
+    dft_small<8>(v, sgn);
+    c2 *row = lds + g * 72;
+#pragma unroll
+    for (int k1 = 0; k1 < 8; ++k1) {
+        c2 y = v[k1];
+        if (t > 0 && k1 > 0) {
+            double sn, cs;
+            sincospi(sgn * (double)(t * k1) / 32.0, &sn, &cs);
+            y = cmul(y, c2{cs, sn});
+        }
+        row[t * 9 + k1] = y;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int n2 = 0; n2 < 8; ++n2) v[n2] = row[n2 * 9 + t];
+    dft_small<8>(v, sgn);
+    if (!live) return;
+    const int64_t base = (j - k) * 64 + k;
+#pragma unroll
+    for (int k2 = 0; k2 < 8; ++k2) {
+        const int64_t o = base + (int64_t)(t + 8 * k2) * Ns;
+        if constexpr (OUT_REAL) {
+            if (o < nx) yr[o] = v[k2].x;
+        } else {
+            out[o] = v[k2];
+        }
+    }
+}
+
+template <bool IN_REAL, bool SCALE, bool OUT_REAL>
+hipError_t pass64_go(hipStream_t st, const c2 *in, const double *xr, const double *S, c2 *out, double *yr, int64_t L,
+                     int64_t Ns, int64_t nx, double sgn, const int32_t *skip)
+{
+    const int64_t q = L / 64;
+    const unsigned g = (unsigned)((q + 7) / 8);
+    hipLaunchKernelGGL((k_fft1d_pass64<IN_REAL, SCALE, OUT_REAL>), dim3(g), dim3(64), 0, st, in, xr, S, out, yr, L,
+                       Ns, nx, sgn, skip);
+    return hipGetLastError();
+}
+
 template <int R, bool IN_REAL, bool SCALE, bool OUT_REAL>
 hipError_t pass_go(hipStream_t st, const c2 *in, const double *xr, const double *S, c2 *out, double *yr, int64_t L,
-                   int64_t Ns, int64_t nx, double sgn)
+                   int64_t Ns, int64_t nx, double sgn, const int32_t *skip)
 {
     const int64_t q = L / R;
-    const unsigned g = (unsigned)((q + 255) / 256);
-    hipLaunchKernelGGL((k_fft1d_pass<R, IN_REAL, SCALE, OUT_REAL>), dim3(g), dim3(256), 0, st, in, xr, S, out, yr,
-                       L, Ns, nx, sgn);
+    const unsigned g = (unsigned)((q + 63) / 64);
+    hipLaunchKernelGGL((k_fft1d_pass<R, IN_REAL, SCALE, OUT_REAL>), dim3(g), dim3(64), 0, st, in, xr, S, out, yr,
+                       L, Ns, nx, sgn, skip);
     return hipGetLastError();
 }
 
 template <bool IN_REAL, bool SCALE, bool OUT_REAL>
 hipError_t pass_radix(int R, hipStream_t st, const c2 *in, const double *xr, const double *S, c2 *out, double *yr,
-                      int64_t L, int64_t Ns, int64_t nx, double sgn)
+                      int64_t L, int64_t Ns, int64_t nx, double sgn, const int32_t *skip)
 {
     switch (R) {
-    case 8: return pass_go<8, IN_REAL, SCALE, OUT_REAL>(st, in, xr, S, out, yr, L, Ns, nx, sgn);
-    case 4: return pass_go<4, IN_REAL, SCALE, OUT_REAL>(st, in, xr, S, out, yr, L, Ns, nx, sgn);
-    default: return pass_go<2, IN_REAL, SCALE, OUT_REAL>(st, in, xr, S, out, yr, L, Ns, nx, sgn);
+    case 64: return pass64_go<IN_REAL, SCALE, OUT_REAL>(st, in, xr, S, out, yr, L, Ns, nx, sgn, skip);
+    case 8: return pass_go<8, IN_REAL, SCALE, OUT_REAL>(st, in, xr, S, out, yr, L, Ns, nx, sgn, skip);
+    case 4: return pass_go<4, IN_REAL, SCALE, OUT_REAL>(st, in, xr, S, out, yr, L, Ns, nx, sgn, skip);
+    default: return pass_go<2, IN_REAL, SCALE, OUT_REAL>(st, in, xr, S, out, yr, L, Ns, nx, sgn, skip);
     }
 }
 
-// radices of the passes: 8s, with the remainder (4 or 2) first
+// radices of the passes: the log2 L mod 6 bits by radix 8 (and one pass of 4
+// or 2), then radix-64 passes
 int radix_plan(int p, int *rad)
 {
     int np = 0;
-    if (p % 3 == 1) rad[np++] = 2;
-    if (p % 3 == 2) rad[np++] = 4;
-    for (int b = 0; b < p / 3; ++b) rad[np++] = 8;
+    const int rem = p % 6;
+    if (rem % 3 == 1) rad[np++] = 2;
+    if (rem % 3 == 2) rad[np++] = 4;
+    for (int b = 0; b < rem / 3; ++b) rad[np++] = 8;
+    for (int b = 0; b < p / 6; ++b) rad[np++] = 64;
     return np;
 }
 
@@ -156,7 +243,7 @@ int radix_plan(int p, int *rad)
 // first nx entries into yr.  The passes alternate between the two complex
 // buffers a and b; the forward result lands in *res.
 hipError_t fft1d_run(hipStream_t st, int mode, const double *xr, const double *S, double *yr, c2 *a, c2 *b,
-                     int64_t L, int64_t nx, c2 **res)
+                     int64_t L, int64_t nx, c2 **res, const int32_t *skip)
 {
     int p = 0;
     while ((int64_t(1) << p) < L) ++p;
@@ -170,18 +257,18 @@ hipError_t fft1d_run(hipStream_t st, int mode, const double *xr, const double *S
         const bool first = i == 0, last = i == np - 1;
         if (mode == 0) {
             if (first)
-                e = pass_radix<true, false, false>(rad[i], st, nullptr, xr, nullptr, dst, nullptr, L, Ns, nx, sgn);
+                e = pass_radix<true, false, false>(rad[i], st, nullptr, xr, nullptr, dst, nullptr, L, Ns, nx, sgn, skip);
             else
-                e = pass_radix<false, false, false>(rad[i], st, src, nullptr, nullptr, dst, nullptr, L, Ns, nx, sgn);
+                e = pass_radix<false, false, false>(rad[i], st, src, nullptr, nullptr, dst, nullptr, L, Ns, nx, sgn, skip);
         } else {
             if (first && last)
-                e = pass_radix<false, true, true>(rad[i], st, src, nullptr, S, nullptr, yr, L, Ns, nx, sgn);
+                e = pass_radix<false, true, true>(rad[i], st, src, nullptr, S, nullptr, yr, L, Ns, nx, sgn, skip);
             else if (first)
-                e = pass_radix<false, true, false>(rad[i], st, src, nullptr, S, dst, nullptr, L, Ns, nx, sgn);
+                e = pass_radix<false, true, false>(rad[i], st, src, nullptr, S, dst, nullptr, L, Ns, nx, sgn, skip);
             else if (last)
-                e = pass_radix<false, false, true>(rad[i], st, src, nullptr, nullptr, nullptr, yr, L, Ns, nx, sgn);
+                e = pass_radix<false, false, true>(rad[i], st, src, nullptr, nullptr, nullptr, yr, L, Ns, nx, sgn, skip);
             else
-                e = pass_radix<false, false, false>(rad[i], st, src, nullptr, nullptr, dst, nullptr, L, Ns, nx, sgn);
+                e = pass_radix<false, false, false>(rad[i], st, src, nullptr, nullptr, dst, nullptr, L, Ns, nx, sgn, skip);
         }
         Ns *= rad[i];
         std::swap(src, dst);
@@ -232,20 +319,21 @@ hipError_t launch_circ_spectrum(hipStream_t st, const double *a, int64_t n, int6
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     c2 *res = nullptr;
-    if ((e = fft1d_run(st, 0, colbuf, nullptr, nullptr, (c2 *)za, (c2 *)zb, L, L, &res)) != hipSuccess) return e;
+    if ((e = fft1d_run(st, 0, colbuf, nullptr, nullptr, (c2 *)za, (c2 *)zb, L, L, &res, nullptr)) != hipSuccess)
+        return e;
     hipLaunchKernelGGL(k_spec_real, dim3(g), dim3(256), 0, st, res, S, L);
     return hipGetLastError();
 }
 
 hipError_t launch_circ_apply(hipStream_t st, const double *x, double *y, int64_t n, int64_t L, const double *S,
-                             void *za, void *zb)
+                             void *za, void *zb, const int32_t *skip)
 {
     if (L < 8 || (L & (L - 1)) || L < 2 * n - 1 || L > (int64_t(1) << 19) || x == y) return hipErrorInvalidValue;
     c2 *res = nullptr;
-    hipError_t e = fft1d_run(st, 0, x, nullptr, nullptr, (c2 *)za, (c2 *)zb, L, n, &res);
+    hipError_t e = fft1d_run(st, 0, x, nullptr, nullptr, (c2 *)za, (c2 *)zb, L, n, &res, skip);
     if (e != hipSuccess) return e;
     c2 *other = res == (c2 *)za ? (c2 *)zb : (c2 *)za;
-    return fft1d_run(st, 1, nullptr, S, y, res, other, L, n, nullptr);
+    return fft1d_run(st, 1, nullptr, S, y, res, other, L, n, nullptr, skip);
 }
 
 int circ_launches(int64_t L)

@@ -371,6 +371,104 @@ hipError_t launch_dot_partial(hipStream_t st, const double *x, const double *y, 
     return hipGetLastError();
 }
 
+// ---- conjugate gradients with the scalars kept on the device ----
+// Every kernel returns at once when st->done is set, so steps enqueued past
+// the stop are no-ops and the iterates are those of the step-by-step loop.
+
+__device__ double sum_partials(const double *__restrict__ partial, int nb)
+{
+    double s = 0.0;
+    for (int i = threadIdx.x; i < nb; i += 256) s += partial[i];
+    return block_sum<256>(s);
+}
+
+// partial[b] = the block's share of <p, A p>
+__global__ void __launch_bounds__(256) k_cg_pap(const CgState *__restrict__ st, const double *__restrict__ p,
+                                                const double *__restrict__ Ap, int64_t n, double *__restrict__ partial)
+{
+    if (st->done) return;
+    double s = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) s += p[i] * Ap[i];
+    const double t = block_sum<256>(s);
+    if (threadIdx.x == 0) partial[blockIdx.x] = t;
+}
+
+// kappa = r.r / <p, A p>; a direction with <p, A p> <= 0 stops with bad = 1
+__global__ void __launch_bounds__(256) k_cg_alpha(CgState *st, const double *__restrict__ partial, int nb)
+{
+    if (st->done) return;
+    const double pAp = sum_partials(partial, nb);
+    if (threadIdx.x == 0) {
+        st->pAp = pAp;
+        if (!(pAp > 0.0)) {
+            st->bad = 1;
+            st->done = 1;
+        } else {
+            st->kap = st->rr / pAp;
+        }
+    }
+}
+
+// u += kappa p, r -= kappa A p, partial[b] = the block's share of r.r
+__global__ void __launch_bounds__(256) k_cg_update(const CgState *__restrict__ st, double *__restrict__ u,
+                                                   double *__restrict__ r, const double *__restrict__ p,
+                                                   const double *__restrict__ Ap, int64_t n,
+                                                   double *__restrict__ partial)
+{
+    if (st->done) return;
+    const double kap = st->kap;
+    double s = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        u[i] += kap * p[i];
+        const double ri = r[i] - kap * Ap[i];
+        r[i] = ri;
+        s += ri * ri;
+    }
+    const double t = block_sum<256>(s);
+    if (threadIdx.x == 0) partial[blockIdx.x] = t;
+}
+
+// new r.r: count the step, record |r| / |f|, beta = new / old, stop test
+__global__ void __launch_bounds__(256) k_cg_beta(CgState *st, const double *__restrict__ partial, int nb,
+                                                 double *__restrict__ hist, int hist_cap)
+{
+    if (st->done) return;
+    const double rn = sum_partials(partial, nb);
+    if (threadIdx.x == 0) {
+        const int it = st->it + 1;
+        const double nr = sqrt(rn);
+        st->it = it;
+        if (hist && it < hist_cap) hist[it] = nr / st->fn;
+        st->bet = rn / st->rr;
+        st->rr = rn;
+        if (nr <= st->rtol_fn || it >= st->maxit) st->done = 1;
+    }
+}
+
+// p = r + beta p
+__global__ void __launch_bounds__(256) k_cg_dir(const CgState *__restrict__ st, double *__restrict__ p,
+                                                const double *__restrict__ r, int64_t n)
+{
+    if (st->done) return;
+    const double bet = st->bet;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+        p[i] = r[i] + bet * p[i];
+}
+
+int cg_blocks(int64_t n) { return (int)std::min<int64_t>(1024, std::max<int64_t>(1, (n + 255) / 256)); }
+
+hipError_t launch_cg_step_tail(hipStream_t st, CgState *cs, double *u, double *r, double *p, const double *Ap,
+                               int64_t n, double *partial, double *hist, int hist_cap)
+{
+    const int nb = cg_blocks(n);
+    hipLaunchKernelGGL(k_cg_pap, dim3(nb), dim3(256), 0, st, cs, p, Ap, n, partial);
+    hipLaunchKernelGGL(k_cg_alpha, dim3(1), dim3(256), 0, st, cs, partial, nb);
+    hipLaunchKernelGGL(k_cg_update, dim3(nb), dim3(256), 0, st, cs, u, r, p, Ap, n, partial);
+    hipLaunchKernelGGL(k_cg_beta, dim3(1), dim3(256), 0, st, cs, partial, nb, hist, hist_cap);
+    hipLaunchKernelGGL(k_cg_dir, dim3(nb), dim3(256), 0, st, cs, p, r, n);
+    return hipGetLastError();
+}
+
 // partial[b] = sum_n sum_i lam[n][i] (-rho'_n u0[i] + psi'_n phi[i])
 __global__ void k_gamma_rhs_terms(const double *__restrict__ lam, const double *__restrict__ u0,
                                   const double *__restrict__ phi, const double *__restrict__ drho,
