@@ -417,14 +417,16 @@ def run_gmres(dev, meshes=(8, 9, 10), rtol=1e-8):
     return res
 
 
-PAPER_FCG_S = {9: 0.01, 10: 0.06, 11: 0.09, 12: 0.57, 13: 1.29, 14: 2.24, 15: 4.58, 16: 9.81, 17: 27.2}
-PAPER_FCG_ITERS = {9: 62, 10: 75, 11: 91, 12: 110, 13: 133, 14: 159, 15: 192, 16: 230, 17: 276}
+PAPER_FCG_S = {9: 0.01, 10: 0.06, 11: 0.09, 12: 0.57, 13: 1.29, 14: 2.24, 15: 4.58, 16: 9.81, 17: 27.2,
+               18: 80.9, 19: 281.0, 20: 451.0, 21: 977.0, 22: 2548.0}
+PAPER_FCG_ITERS = {9: 62, 10: 75, 11: 91, 12: 110, 13: 133, 14: 159, 15: 192, 16: 230, 17: 276,
+                   18: 331, 19: 415, 20: 498, 21: 599, 22: 741}
 
 
-def run_ode(dev, meshes=tuple(range(9, 18)), gamma=0.5, rtol=1e-10):
+def run_ode(dev, meshes=tuple(range(9, 23)), gamma=0.5, rtol=1e-10):
     """Scheme 1, the two-sided fractional ODE of Example 1 (u = t(1 - t)),
     by conjugate gradients with the FFT-embedded operator, on the timing
-    meshes tau = 2^-9 .. 2^-17 of Table 2.  The table gives neither gamma nor
+    meshes tau = 2^-9 .. 2^-22 of Table 2.  The table gives neither gamma nor
     the stop rule: gamma = 0.5 reproduces the growth of its step counts
     (about x1.2 per halving of tau, as sqrt(cond) ~ tau^(-gamma/2)), and the
     stop rule here is |r| <= rtol |f|.  Each call includes the set-up of the

@@ -252,7 +252,10 @@ int fracsolve_gmres(fracsolve_t h, const double *const *f, const double *const *
  * 0}; info (NULL or one record, host); hist (NULL or hist_cap doubles,
  * host): |r_k| / |f| from the recurrence, hist[0] for the start.
  * Work runs on `stream` (NULL = null stream); the call synchronises it and
- * holds its workspace only for its duration.  3 <= N <= 2^17 + 1.
+ * holds its workspace only for its duration: 40 L + 32 (N - 1) bytes of
+ * device memory (the spectrum and two complex arrays of L < 4N points, four
+ * vectors; about 470 MB at N = 2^22).
+ * 3 <= N <= 2^22 + 1.
  * Errors (text in fracsolve_last_error(NULL)): E_ARG, E_NOMEM, E_DEVICE,
  * E_NUMERIC (a direction with <p, A p> <= 0).
  */

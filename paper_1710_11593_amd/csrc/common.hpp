@@ -246,7 +246,7 @@ hipError_t launch_permute(hipStream_t st, const double *src, double *dst, int64_
                           bool to_internal, bool reverse);
 hipError_t launch_axpy(hipStream_t st, double *y, const double *x, double alpha, int64_t n);
 // symmetric Toeplitz product through its circulant embedding (k_fft1d.hip):
-// L = circ_length(n) (a power of two >= max(8, 2n - 1), at most 2^19); S
+// L = circ_length(n) (a power of two >= max(8, 2n - 1), at most 2^23); S
 // (L doubles) = the spectrum of the embedded column 1 + 2 a_0, a_1 .. a_{n-1}
 // divided by L (colbuf may alias S); za, zb = two complex arrays of L points.
 // y = A x for n entries (x != y).

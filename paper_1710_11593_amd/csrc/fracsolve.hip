@@ -1210,10 +1210,12 @@ int gmres_one(fracsolve_ctx *h, int k, const double *f, const double *u0, const 
 //
 // The two-sided ODE's matrix is A = I + T + T^T with T the lower-triangular
 // Toeplitz matrix of the diffusion weights a (a_0 on the diagonal), so A is
-// symmetric Toeplitz with column c_0 = 1 + 2 a_0, c_m = a_m (Theorem 1).  A
-// handle with M = 1 computes the weights; the product A x goes through the
-// circulant embedding of length L >= 2n - 1 (eq. e10): one forward and one
-// inverse FFT of L points per product.
+// symmetric Toeplitz with column c_0 = 1 + 2 a_0, c_m = a_m (Theorem 1).  The
+// weights come from the diffusion path's weight kernel on tau = 1/N; the
+// product A x goes through the circulant embedding of length L >= 2n - 1
+// (eq. e10): one forward and one inverse FFT of L points per product.  The
+// handle (one point, one step) only provides the stream, the allocations and
+// the error state.
 
 struct OdeWork {
     double *r, *p, *Ap;
@@ -1222,27 +1224,34 @@ struct OdeWork {
     int64_t L;
 };
 
-int ode_matvec(fracsolve_ctx *h, const OdeWork &w, const double *x, double *y)
+int ode_matvec(fracsolve_ctx *h, const OdeWork &w, int64_t n, const double *x, double *y)
 {
-    HIPCHK(h, launch_circ_apply(h->st, x, y, h->inst[0].N, w.L, w.S, w.za, w.zb));
+    HIPCHK(h, launch_circ_apply(h->st, x, y, n, w.L, w.S, w.za, w.zb));
     h->kernels += circ_launches(w.L);
     return FRACSOLVE_OK;
 }
 
-int ode_cg_run(fracsolve_ctx *h, const double *f, double *u, const fracsolve_cg_options &o, fracsolve_cg_info *info,
-               double *hist, int hist_cap)
+int ode_cg_run(fracsolve_ctx *h, double gamma, int64_t N, const double *f, double *u, const fracsolve_cg_options &o,
+               fracsolve_cg_info *info, double *hist, int hist_cap)
 {
-    const int64_t n = h->inst[0].N;
+    const int64_t n = N - 1;
     OdeWork w{};
     int rc;
     w.L = circ_length(n);
-    for (double **q : {&w.r, &w.p, &w.Ap})
+    double *a = nullptr;
+    for (double **q : {&w.r, &w.p, &w.Ap, &a})
         if ((rc = dalloc(h, q, (size_t)n))) return rc;
     if ((rc = dalloc(h, &w.S, (size_t)w.L)) || (rc = dalloc(h, &w.za, 2 * (size_t)w.L)) ||
         (rc = dalloc(h, &w.zb, 2 * (size_t)w.L)))
         return rc;
+    // the L1 weights a_m of the left derivative (Lemma 2) on tau = 1/N,
+    // scaled by mu = tau^-gamma / Gamma(2 - gamma)
+    const double tau = 1.0 / (double)N;
+    const double mu = std::pow(tau, -gamma) / std::tgamma(2.0 - gamma);
+    HIPCHK(h, launch_weights(h->st, 0, 1.0 - gamma, mu, 0.0, tau, n, nullptr, a, nullptr, nullptr, nullptr, nullptr,
+                             nullptr));
     // the embedded column is staged in S before its transform replaces it
-    HIPCHK(h, launch_circ_spectrum(h->st, h->inst[0].a, n, w.L, w.S, w.S, w.za, w.zb));
+    HIPCHK(h, launch_circ_spectrum(h->st, a, n, w.L, w.S, w.S, w.za, w.zb));
     auto put_hist = [&](int i, double v) {
         if (hist && i < hist_cap) hist[i] = v;
     };
@@ -1257,7 +1266,7 @@ int ode_cg_run(fracsolve_ctx *h, const double *f, double *u, const fracsolve_cg_
         return FRACSOLVE_OK;
     }
     // r = f - A u, p = r
-    if ((rc = ode_matvec(h, w, u, w.Ap))) return rc;
+    if ((rc = ode_matvec(h, w, n, u, w.Ap))) return rc;
     HIPCHK(h, launch_sub(h->st, w.r, f, w.Ap, n));
     HIPCHK(h, hipMemcpyAsync(w.p, w.r, sizeof(double) * (size_t)n, hipMemcpyDeviceToDevice, h->st));
     double rr = 0.0;
@@ -1301,7 +1310,7 @@ int ode_cg_run(fracsolve_ctx *h, const double *f, double *u, const fracsolve_cg_
         }
     }
     // the residual from its definition
-    if ((rc = ode_matvec(h, w, u, w.Ap))) return rc;
+    if ((rc = ode_matvec(h, w, n, u, w.Ap))) return rc;
     HIPCHK(h, launch_sub(h->st, w.r, f, w.Ap, n));
     double tr = 0.0;
     if ((rc = dev_norm2(h, w.r, n, &tr))) return rc;
@@ -1322,8 +1331,8 @@ int fracsolve_ode_cg(double gamma, int64_t N, const double *f, double *u, const 
 {
     if (!(gamma > 0.0 && gamma < 1.0))
         return fail(nullptr, FRACSOLVE_E_ARG, "gamma must lie in (0,1) for the two-sided ODE, got %g", gamma);
-    if (N < 3 || N - 1 > (1LL << 17))
-        return fail(nullptr, FRACSOLVE_E_ARG, "N must lie in [3, 2^17 + 1], got %lld", (long long)N);
+    if (N < 3 || N - 1 > (1LL << 22))
+        return fail(nullptr, FRACSOLVE_E_ARG, "N must lie in [3, 2^22 + 1], got %lld", (long long)N);
     if (!f || !u) return fail(nullptr, FRACSOLVE_E_ARG, "f and u must not be NULL");
     fracsolve_cg_options o{10000, 1e-10, 0};
     if (opts) o = *opts;
@@ -1334,15 +1343,13 @@ int fracsolve_ode_cg(double gamma, int64_t N, const double *f, double *u, const 
         return fail(nullptr, FRACSOLVE_E_ARG, "use_guess must be 0 or 1, got %d", (int)o.use_guess);
     if (hist_cap < 0 || (hist_cap > 0 && !hist))
         return fail(nullptr, FRACSOLVE_E_ARG, "hist is NULL with hist_cap %d", (int)hist_cap);
-    // n = N - 1 unknowns, tau = 1/N: T = n / N over n steps (the handle's
-    // spatial data are unused: one point on (0, 2))
-    fracsolve_problem p{gamma, (double)(N - 1) / (double)N, 0.0, 2.0, 1, N - 1};
+    fracsolve_problem p{gamma, 1.0, 0.0, 1.0, 1, 1};
     fracsolve_options ho{};
     ho.stream = stream;
     fracsolve_t h = nullptr;
     int rc = fracsolve_create(&p, 1, &ho, &h);
     if (rc) return rc;
-    rc = ode_cg_run(h, f, u, o, info, hist, hist_cap);
+    rc = ode_cg_run(h, gamma, N, f, u, o, info, hist, hist_cap);
     if (rc) g_create_error = h->err;
     fracsolve_destroy(h);
     return rc;

@@ -1,4 +1,4 @@
-// One-dimensional complex FFT of a power-of-two length L (8 <= L <= 2^19)
+// One-dimensional complex FFT of a power-of-two length L (8 <= L <= 2^23)
 // and the symmetric-Toeplitz product built on it (Scheme 1, eq. e10): the
 // n x n symmetric Toeplitz matrix with first column c is the leading block of
 // the L-periodic circulant whose first column is c followed by zeros and by
@@ -313,7 +313,7 @@ int64_t circ_length(int64_t n)
 hipError_t launch_circ_spectrum(hipStream_t st, const double *a, int64_t n, int64_t L, double *S, double *colbuf,
                                 void *za, void *zb)
 {
-    if (L < 8 || (L & (L - 1)) || L < 2 * n - 1 || L > (int64_t(1) << 19)) return hipErrorInvalidValue;
+    if (L < 8 || (L & (L - 1)) || L < 2 * n - 1 || L > (int64_t(1) << 23)) return hipErrorInvalidValue;
     const unsigned g = (unsigned)((L + 255) / 256);
     hipLaunchKernelGGL(k_circ_column, dim3(g), dim3(256), 0, st, a, colbuf, n, L);
     hipError_t e = hipGetLastError();
@@ -328,7 +328,7 @@ hipError_t launch_circ_spectrum(hipStream_t st, const double *a, int64_t n, int6
 hipError_t launch_circ_apply(hipStream_t st, const double *x, double *y, int64_t n, int64_t L, const double *S,
                              void *za, void *zb, const int32_t *skip)
 {
-    if (L < 8 || (L & (L - 1)) || L < 2 * n - 1 || L > (int64_t(1) << 19) || x == y) return hipErrorInvalidValue;
+    if (L < 8 || (L & (L - 1)) || L < 2 * n - 1 || L > (int64_t(1) << 23) || x == y) return hipErrorInvalidValue;
     c2 *res = nullptr;
     hipError_t e = fft1d_run(st, 0, x, nullptr, nullptr, (c2 *)za, (c2 *)zb, L, n, &res, skip);
     if (e != hipSuccess) return e;

@@ -114,11 +114,29 @@ def test_largest_size_and_guess(torch_cuda, orc):
     assert info2["iterations"] == 0 and np.array_equal(u2, u)
 
 
+def test_table2_largest_mesh(torch_cuda, orc):
+    # tau = 2^-22, the last row of the paper's timing table: 2^22 - 1 unknowns
+    gamma, N = 0.5, 2 ** 22
+    t, f = forcing(gamma, N)
+    u, info, hist = gpu_cg(torch_cuda, gamma, N, f, rtol=1e-10, max_iters=20000, hist_cap=20001)
+    c = orc.ode_column(gamma, N)
+    rel = np.linalg.norm(f - matmul_toeplitz((c, c), u)) / np.linalg.norm(f)
+    err = math.sqrt(np.sum((u - t * (1 - t)) ** 2) / N)
+    print("ode cg n=2^22:", info, "cpu residual", rel, "L2 error", err, flush=True)
+    assert info["converged"] and rel <= 1.5e-10
+    assert abs(rel - info["relres"]) <= 1e-6 * rel + rounding_floor(c, u, f)
+    assert len(hist) == info["iterations"] + 1 and abs(hist[0] - 1.0) < 1e-14
+    assert abs(hist[-1] - info["relres_est"]) <= 1e-14 * hist[-1]
+    # Table 1's rate 2 - gamma continued five halvings past its last row
+    # (1.1779e-6 at tau = 2^-12, gamma = 0.5): within 10% of the extrapolation
+    assert abs(err / (1.1779e-6 * 2 ** (-10 * 1.5)) - 1) < 0.1, err
+
+
 def test_invalid_arguments(torch_cuda):
     from paper_1710_11593_amd import binding
 
     f = torch_cuda.zeros(7, dtype=torch_cuda.float64, device="cuda")
-    for g, N, pat in [(1.2, 8, "gamma"), (0.0, 8, "gamma"), (0.5, 2, "N"), (0.5, 2 ** 17 + 2, "N")]:
+    for g, N, pat in [(1.2, 8, "gamma"), (0.0, 8, "gamma"), (0.5, 2, "N"), (0.5, 2 ** 22 + 2, "N")]:
         ff = f if N == 8 else torch_cuda.zeros(max(N - 1, 1), dtype=torch_cuda.float64, device="cuda")
         with pytest.raises((binding.FracsolveError, ValueError), match=pat):
             binding.ode_cg(g, N, ff)
