@@ -132,6 +132,46 @@ def test_table2_largest_mesh(torch_cuda, orc):
     assert abs(err / (1.1779e-6 * 2 ** (-10 * 1.5)) - 1) < 0.1, err
 
 
+@pytest.mark.parametrize("maxit", [1, 5, 13])
+def test_stops_at_max_iters(torch_cuda, orc, maxit):
+    # the device-side loop runs in batches of 8 steps: a limit inside a batch
+    # must stop at exactly that step, with the iterate of that step
+    gamma, N = 0.7, 1000
+    t, f = forcing(gamma, N)
+    u, info, hist = gpu_cg(torch_cuda, gamma, N, f, rtol=1e-14, max_iters=maxit, hist_cap=3)
+    uo, io = orc.ode_cg(gamma, N, f, maxit=maxit, rtol=0.0)
+    assert info["iterations"] == maxit == io["iters"] and not info["converged"]
+    assert np.max(np.abs(u - uo)) <= 1e-10 * np.max(np.abs(uo))
+    assert len(hist) == min(3, maxit + 1)
+    assert np.allclose(hist, io["hist"][:len(hist)], rtol=1e-9, atol=0)
+
+
+def test_nearby_guess_and_smallest_sizes(torch_cuda, orc):
+    gamma, N = 0.4, 600
+    t, f = forcing(gamma, N)
+    c = orc.ode_column(gamma, N)
+    ref = solve_toeplitz(c, f)
+    cold = gpu_cg(torch_cuda, gamma, N, f, rtol=1e-12, max_iters=5000)[1]
+    guess = ref + 1e-6 * np.sin(np.arange(N - 1))
+    u, warm, _ = gpu_cg(torch_cuda, gamma, N, f, rtol=1e-12, max_iters=5000, guess=guess)
+    assert warm["converged"] and warm["iterations"] < cold["iterations"]
+    assert np.max(np.abs(u - ref)) <= 1e-9 * np.max(np.abs(ref))
+    # N = 3, 4: two and three unknowns, an 8-point embedding done in one pass;
+    # CG ends within n steps
+    for N in (3, 4, 5):
+        t, f = forcing(gamma, N)
+        u, info, _ = gpu_cg(torch_cuda, gamma, N, f, rtol=1e-14, max_iters=50)
+        ref = np.linalg.solve(orc_dense(orc, gamma, N), f)
+        assert info["converged"] and info["iterations"] <= N - 1
+        assert np.max(np.abs(u - ref)) <= 1e-13 * np.max(np.abs(ref)), (N, u, ref)
+
+
+def orc_dense(orc, gamma, N):
+    from scipy.linalg import toeplitz
+
+    return toeplitz(orc.ode_column(gamma, N))
+
+
 def test_invalid_arguments(torch_cuda):
     from paper_1710_11593_amd import binding
 
