@@ -24,7 +24,7 @@ Example 4 meshes next to the recursive solve (--config gmres runs only that;
 with --N 2^k only the mesh h = tau = 2^-k), and the advection equations
 (Schemes 2 and 3) on the paper's timing meshes (--config advection), and
 Scheme 1, the two-sided fractional ODE by FFT conjugate gradients, on the
-meshes of its timing table (--config ode).
+meshes of its timing table (--config ode; with --N 2^k only that mesh).
 cpu_baseline: the oracle (plain time stepping) on the same workload for the
 first --cpu-steps steps at full width; its wall time is scaled by
 (N / steps)^2 (the history work is quadratic in the step count) to the full
@@ -583,7 +583,9 @@ def main():
         print(json.dumps({"advection": run_advection(dev)}))
         return
     if args.config == "ode":
-        print(json.dumps({"scheme1_cg": run_ode(dev)}))
+        # Scheme 1 on Table 2's meshes (with --N 2^k only tau = 2^-k)
+        meshes = (int(round(math.log2(args.N))),) if args.N else tuple(range(9, 23))
+        print(json.dumps({"scheme1_cg": run_ode(dev, meshes)}))
         return
     if args.config == "gmres":
         # the paper's iterative method on its Example 4 meshes (a form, not the headline)
