@@ -6,8 +6,8 @@
 // DFT, so A x = first n entries of IDFT( DFT(ĉ) * DFT(x padded with zeros) ).
 //
 // The transform is the self-sorting (Stockham) formulation: each pass takes
-// L/R butterflies of radix R (64 for six bits of log2 L at a time, 8, 4 or 2
-// for the rest); butterfly j of a pass whose sub-transforms have length Ns
+// L/R butterflies of radix R (64 for six bits of log2 L at a time, one pass of
+// 2 .. 32 for the rest); butterfly j of a pass whose sub-transforms have length Ns
 // reads the R inputs j + r L/R (consecutive threads read consecutive
 // elements), twiddles input r by w^(r k) with k = j mod Ns and w the
 // (Ns R)-th root of unity, transforms, and writes output r to
@@ -120,69 +120,76 @@ __global__ void __launch_bounds__(64) k_fft1d_pass(const c2 *__restrict__ in, co
     }
 }
 
-// Radix-64 pass: eight threads per 64-point butterfly, 8 butterflies per
-// workgroup of one wavefront (L = 2^18 gives 512 workgroups, enough to
-// reach every CU of a latency-bound pass).  Input r = 8 n1 + n2 goes to thread n2; a radix-8 transform over
-// n1 gives Y[n2][k1], which is twiddled by w64^(n2 k1), transposed through
-// LDS, and transformed over n2 by thread k1, giving output k1 + 8 k2.
-template <bool IN_REAL, bool SCALE, bool OUT_REAL>
-__global__ void __launch_bounds__(64) k_fft1d_pass64(const c2 *__restrict__ in, const double *__restrict__ xr,
-                                                      const double *__restrict__ S, c2 *__restrict__ out,
-                                                      double *__restrict__ yr, int64_t L, int64_t Ns, int64_t nx,
-                                                      double sgn, const int32_t *__restrict__ skip)
+// Two-stage pass of radix R = R1 R2 (64 = 8 x 8, 32 = 4 x 8, 16 = 2 x 8):
+// eight threads per butterfly, 8 butterflies per workgroup of one wavefront
+// (L = 2^18 gives 512 workgroups at radix 64, enough to reach every CU of a
+// latency-bound pass).  Input r = R2 n1 + n2 goes to thread n2 < R2; a
+// radix-R1 transform over n1 gives Y[n2][k1], which is twiddled by
+// w_R^(n2 k1), transposed through LDS, and transformed over n2 by thread
+// k1 < R1, giving output k1 + R1 k2.
+template <int R1, int R2, bool IN_REAL, bool SCALE, bool OUT_REAL>
+__global__ void __launch_bounds__(64) k_fft1d_pass2(const c2 *__restrict__ in, const double *__restrict__ xr,
+                                                    const double *__restrict__ S, c2 *__restrict__ out,
+                                                    double *__restrict__ yr, int64_t L, int64_t Ns, int64_t nx,
+                                                    double sgn, const int32_t *__restrict__ skip)
 {
+    static_assert(R1 <= 8 && R2 <= 8 && R1 * R2 >= 16, "two stages of at most 8 points");
+    constexpr int R = R1 * R2;
     if (skip && *skip) return;
     __shared__ c2 lds[8 * 72];  // per butterfly 8 rows of 9 (one pad entry against bank conflicts)
     const int t = threadIdx.x & 7, g = threadIdx.x >> 3;
-    const int64_t q = L / 64;
+    const int64_t q = L / R;
     const int64_t j = (int64_t)blockIdx.x * 8 + g;
     const bool live = j < q;
     const int64_t k = j & (Ns - 1);
-    c2 v[8];
-    const double a = sgn * 2.0 * (double)k / (double)(Ns * 64);
-#pragma unroll
-    for (int n1 = 0; n1 < 8; ++n1) {
-        const int r = 8 * n1 + t;
-        const int64_t idx = j + r * q;
-        c2 x{0.0, 0.0};
-        if (live) {
-            if constexpr (IN_REAL)
-                x = {idx < nx ? xr[idx] : 0.0, 0.0};
-            else
-                x = in[idx];
-            if constexpr (SCALE) {
-                const double s = S[idx];
-                x = {x.x * s, x.y * s};
-            }
-        }
-        if (Ns > 1 && r > 0) {
-            double sn, cs;
-            sincospi(a * r, &sn, &cs);
-            x = cmul(x, c2{cs, sn});
-        }
-        v[n1] = x;
-    }
-    dft_small<8>(v, sgn);
     c2 *row = lds + g * 72;
+    if (t < R2) {
+        c2 v[R1];
+        const double a = sgn * 2.0 * (double)k / (double)(Ns * R);
 #pragma unroll
-    for (int k1 = 0; k1 < 8; ++k1) {
-        c2 y = v[k1];
-        if (t > 0 && k1 > 0) {
-            double sn, cs;
-            sincospi(sgn * (double)(t * k1) / 32.0, &sn, &cs);
-            y = cmul(y, c2{cs, sn});
+        for (int n1 = 0; n1 < R1; ++n1) {
+            const int r = R2 * n1 + t;
+            const int64_t idx = j + r * q;
+            c2 x{0.0, 0.0};
+            if (live) {
+                if constexpr (IN_REAL)
+                    x = {idx < nx ? xr[idx] : 0.0, 0.0};
+                else
+                    x = in[idx];
+                if constexpr (SCALE) {
+                    const double s = S[idx];
+                    x = {x.x * s, x.y * s};
+                }
+            }
+            if (Ns > 1 && r > 0) {
+                double sn, cs;
+                sincospi(a * r, &sn, &cs);
+                x = cmul(x, c2{cs, sn});
+            }
+            v[n1] = x;
         }
-        row[t * 9 + k1] = y;
+        dft_small<R1>(v, sgn);
+#pragma unroll
+        for (int k1 = 0; k1 < R1; ++k1) {
+            c2 y = v[k1];
+            if (t > 0 && k1 > 0) {
+                double sn, cs;
+                sincospi(sgn * 2.0 * (double)(t * k1) / (double)R, &sn, &cs);
+                y = cmul(y, c2{cs, sn});
+            }
+            row[t * 9 + k1] = y;
+        }
     }
     __syncthreads();
+    if (t >= R1 || !live) return;
+    c2 v[R2];
 #pragma unroll
-    for (int n2 = 0; n2 < 8; ++n2) v[n2] = row[n2 * 9 + t];
-    dft_small<8>(v, sgn);
-    if (!live) return;
-    const int64_t base = (j - k) * 64 + k;
+    for (int n2 = 0; n2 < R2; ++n2) v[n2] = row[n2 * 9 + t];
+    dft_small<R2>(v, sgn);
+    const int64_t base = (j - k) * R + k;
 #pragma unroll
-    for (int k2 = 0; k2 < 8; ++k2) {
-        const int64_t o = base + (int64_t)(t + 8 * k2) * Ns;
+    for (int k2 = 0; k2 < R2; ++k2) {
+        const int64_t o = base + (int64_t)(t + R1 * k2) * Ns;
         if constexpr (OUT_REAL) {
             if (o < nx) yr[o] = v[k2].x;
         } else {
@@ -191,14 +198,14 @@ __global__ void __launch_bounds__(64) k_fft1d_pass64(const c2 *__restrict__ in, 
     }
 }
 
-template <bool IN_REAL, bool SCALE, bool OUT_REAL>
-hipError_t pass64_go(hipStream_t st, const c2 *in, const double *xr, const double *S, c2 *out, double *yr, int64_t L,
-                     int64_t Ns, int64_t nx, double sgn, const int32_t *skip)
+template <int R1, int R2, bool IN_REAL, bool SCALE, bool OUT_REAL>
+hipError_t pass2_go(hipStream_t st, const c2 *in, const double *xr, const double *S, c2 *out, double *yr, int64_t L,
+                    int64_t Ns, int64_t nx, double sgn, const int32_t *skip)
 {
-    const int64_t q = L / 64;
+    const int64_t q = L / (R1 * R2);
     const unsigned g = (unsigned)((q + 7) / 8);
-    hipLaunchKernelGGL((k_fft1d_pass64<IN_REAL, SCALE, OUT_REAL>), dim3(g), dim3(64), 0, st, in, xr, S, out, yr, L,
-                       Ns, nx, sgn, skip);
+    hipLaunchKernelGGL((k_fft1d_pass2<R1, R2, IN_REAL, SCALE, OUT_REAL>), dim3(g), dim3(64), 0, st, in, xr, S, out,
+                       yr, L, Ns, nx, sgn, skip);
     return hipGetLastError();
 }
 
@@ -218,22 +225,21 @@ hipError_t pass_radix(int R, hipStream_t st, const c2 *in, const double *xr, con
                       int64_t L, int64_t Ns, int64_t nx, double sgn, const int32_t *skip)
 {
     switch (R) {
-    case 64: return pass64_go<IN_REAL, SCALE, OUT_REAL>(st, in, xr, S, out, yr, L, Ns, nx, sgn, skip);
+    case 64: return pass2_go<8, 8, IN_REAL, SCALE, OUT_REAL>(st, in, xr, S, out, yr, L, Ns, nx, sgn, skip);
+    case 32: return pass2_go<4, 8, IN_REAL, SCALE, OUT_REAL>(st, in, xr, S, out, yr, L, Ns, nx, sgn, skip);
+    case 16: return pass2_go<2, 8, IN_REAL, SCALE, OUT_REAL>(st, in, xr, S, out, yr, L, Ns, nx, sgn, skip);
     case 8: return pass_go<8, IN_REAL, SCALE, OUT_REAL>(st, in, xr, S, out, yr, L, Ns, nx, sgn, skip);
     case 4: return pass_go<4, IN_REAL, SCALE, OUT_REAL>(st, in, xr, S, out, yr, L, Ns, nx, sgn, skip);
     default: return pass_go<2, IN_REAL, SCALE, OUT_REAL>(st, in, xr, S, out, yr, L, Ns, nx, sgn, skip);
     }
 }
 
-// radices of the passes: the log2 L mod 6 bits by radix 8 (and one pass of 4
-// or 2), then radix-64 passes
+// radices of the passes: the log2 L mod 6 bits in one pass (radix 2 .. 32),
+// then radix-64 passes
 int radix_plan(int p, int *rad)
 {
     int np = 0;
-    const int rem = p % 6;
-    if (rem % 3 == 1) rad[np++] = 2;
-    if (rem % 3 == 2) rad[np++] = 4;
-    for (int b = 0; b < rem / 3; ++b) rad[np++] = 8;
+    if (p % 6) rad[np++] = 1 << (p % 6);
     for (int b = 0; b < p / 6; ++b) rad[np++] = 64;
     return np;
 }
