@@ -1639,10 +1639,12 @@ int fracsolve_gmres(fracsolve_t h, const double *const *f, const double *const *
     if (o.max_iters < 0) return fail(h, FRACSOLVE_E_ARG, "max_iters must be >= 0, got %d", (int)o.max_iters);
     if (!(o.rtol >= 0.0) || !std::isfinite(o.rtol))
         return fail(h, FRACSOLVE_E_ARG, "rtol must be finite and >= 0, got %g", o.rtol);
-    if (o.precond < 0 || o.precond > 1) return fail(h, FRACSOLVE_E_ARG, "precond must be 0 or 1, got %d", (int)o.precond);
+    if (o.precond < 0 || o.precond > 1)
+        return fail(h, FRACSOLVE_E_ARG, "precond must be 0 or 1, got %d", (int)o.precond);
     if (o.use_guess < 0 || o.use_guess > 1)
         return fail(h, FRACSOLVE_E_ARG, "use_guess must be 0 or 1, got %d", (int)o.use_guess);
-    if (hist_cap < 0 || (hist_cap > 0 && !hist)) return fail(h, FRACSOLVE_E_ARG, "hist is NULL with hist_cap %d", (int)hist_cap);
+    if (hist_cap < 0 || (hist_cap > 0 && !hist))
+        return fail(h, FRACSOLVE_E_ARG, "hist is NULL with hist_cap %d", (int)hist_cap);
     hipEvent_t ev[2];
     if ((rc = timed_begin(h, ev))) return rc;
     if (!h->zeros) {

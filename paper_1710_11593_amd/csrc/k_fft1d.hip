@@ -6,9 +6,9 @@
 // DFT, so A x = first n entries of IDFT( DFT(ĉ) * DFT(x padded with zeros) ).
 //
 // The transform is the self-sorting (Stockham) formulation: each pass takes
-// L/R butterflies of radix R (64 for six bits of log2 L at a time, one pass of
-// 2 .. 32 for the rest); butterfly j of a pass whose sub-transforms have length Ns
-// reads the R inputs j + r L/R (consecutive threads read consecutive
+// L/R butterflies of radix R (64 for six bits of log2 L at a time, one pass
+// of 2 .. 32 for the rest); butterfly j of a pass whose sub-transforms have
+// length Ns reads the R inputs j + r L/R (consecutive threads read consecutive
 // elements), twiddles input r by w^(r k) with k = j mod Ns and w the
 // (Ns R)-th root of unity, transforms, and writes output r to
 // (j - k) R + k + r Ns, so the result comes out in natural order with no
@@ -261,22 +261,26 @@ hipError_t fft1d_run(hipStream_t st, int mode, const double *xr, const double *S
     hipError_t e = hipSuccess;
     for (int i = 0; i < np && e == hipSuccess; ++i) {
         const bool first = i == 0, last = i == np - 1;
+        const int R = rad[i];
         if (mode == 0) {
             if (first)
-                e = pass_radix<true, false, false>(rad[i], st, nullptr, xr, nullptr, dst, nullptr, L, Ns, nx, sgn, skip);
+                e = pass_radix<true, false, false>(R, st, nullptr, xr, nullptr, dst, nullptr, L, Ns, nx, sgn, skip);
             else
-                e = pass_radix<false, false, false>(rad[i], st, src, nullptr, nullptr, dst, nullptr, L, Ns, nx, sgn, skip);
+                e = pass_radix<false, false, false>(R, st, src, nullptr, nullptr, dst, nullptr, L, Ns, nx, sgn,
+                                                    skip);
         } else {
             if (first && last)
-                e = pass_radix<false, true, true>(rad[i], st, src, nullptr, S, nullptr, yr, L, Ns, nx, sgn, skip);
+                e = pass_radix<false, true, true>(R, st, src, nullptr, S, nullptr, yr, L, Ns, nx, sgn, skip);
             else if (first)
-                e = pass_radix<false, true, false>(rad[i], st, src, nullptr, S, dst, nullptr, L, Ns, nx, sgn, skip);
+                e = pass_radix<false, true, false>(R, st, src, nullptr, S, dst, nullptr, L, Ns, nx, sgn, skip);
             else if (last)
-                e = pass_radix<false, false, true>(rad[i], st, src, nullptr, nullptr, nullptr, yr, L, Ns, nx, sgn, skip);
+                e = pass_radix<false, false, true>(R, st, src, nullptr, nullptr, nullptr, yr, L, Ns, nx, sgn,
+                                                   skip);
             else
-                e = pass_radix<false, false, false>(rad[i], st, src, nullptr, nullptr, dst, nullptr, L, Ns, nx, sgn, skip);
+                e = pass_radix<false, false, false>(R, st, src, nullptr, nullptr, dst, nullptr, L, Ns, nx, sgn,
+                                                    skip);
         }
-        Ns *= rad[i];
+        Ns *= R;
         std::swap(src, dst);
     }
     if (res) *res = src;  // the buffer the last pass wrote
