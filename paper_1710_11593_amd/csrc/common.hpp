@@ -254,9 +254,13 @@ int64_t circ_length(int64_t n);
 int circ_launches(int64_t L);
 hipError_t launch_circ_spectrum(hipStream_t st, const double *a, int64_t n, int64_t L, double *S, double *colbuf,
                                 void *za, void *zb);
-// skip (device, may be NULL): every pass returns at once while *skip != 0
+// skip (device, may be NULL): every pass returns at once while *skip != 0.
+// dotp (device, may be NULL, circ_dot_parts(L) doubles): the last pass also
+// writes partial sums of <x, y>, *ndot of them.
 hipError_t launch_circ_apply(hipStream_t st, const double *x, double *y, int64_t n, int64_t L, const double *S,
-                             void *za, void *zb, const int32_t *skip = nullptr);
+                             void *za, void *zb, const int32_t *skip = nullptr, double *dotp = nullptr,
+                             int64_t *ndot = nullptr);
+int64_t circ_dot_parts(int64_t L);
 // conjugate-gradient state kept in device memory (k_misc.hip)
 struct CgState {
     double rr;       // r.r of the current residual
@@ -266,11 +270,13 @@ struct CgState {
     double pAp;      // last <p, A p>
     int32_t it, done, maxit, bad;
 };
-// one CG step after A p is in Ap: <p, A p>, kappa, the u / r update with the
-// new r.r, beta, the stop test and p = r + beta p; no-ops once done is set.
-// hist (device, hist_cap doubles or NULL) receives |r_k| / |f| at k = it.
+// one CG step after A p is in Ap and the partial sums of <p, A p> in
+// pap[0 .. npap) (pap NULL: computed here, into partial): kappa, the u / r update with the new r.r, beta, the stop
+// test and p = r + beta p; no-ops once done is set.  hist (device, hist_cap
+// doubles or NULL) receives |r_k| / |f| at k = it.
 hipError_t launch_cg_step_tail(hipStream_t st, CgState *cs, double *u, double *r, double *p, const double *Ap,
-                               int64_t n, double *partial, double *hist, int hist_cap);
+                               int64_t n, const double *pap, int64_t npap, double *partial, double *hist,
+                               int hist_cap);
 hipError_t launch_sub(hipStream_t st, double *r, const double *b, const double *y, int64_t n);
 hipError_t launch_to_f32(hipStream_t st, const double *x, float *y, int64_t n);
 hipError_t launch_zero(hipStream_t st, void *p, size_t bytes);

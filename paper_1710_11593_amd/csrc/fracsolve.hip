@@ -1221,6 +1221,7 @@ struct OdeWork {
     double *r, *p, *Ap;
     double *S;       // real spectrum of the embedded column, divided by L
     double *za, *zb;  // two complex work arrays of L points
+    double *pap;      // partial sums of <p, A p> from the product's last pass
     int64_t L;
 };
 
@@ -1242,7 +1243,7 @@ int ode_cg_run(fracsolve_ctx *h, double gamma, int64_t N, const double *f, doubl
     for (double **q : {&w.r, &w.p, &w.Ap, &a})
         if ((rc = dalloc(h, q, (size_t)n))) return rc;
     if ((rc = dalloc(h, &w.S, (size_t)w.L)) || (rc = dalloc(h, &w.za, 2 * (size_t)w.L)) ||
-        (rc = dalloc(h, &w.zb, 2 * (size_t)w.L)))
+        (rc = dalloc(h, &w.zb, 2 * (size_t)w.L)) || (rc = dalloc(h, &w.pap, (size_t)circ_dot_parts(w.L))))
         return rc;
     // the L1 weights a_m of the left derivative (Lemma 2) on tau = 1/N,
     // scaled by mu = tau^-gamma / Gamma(2 - gamma)
@@ -1289,11 +1290,17 @@ int ode_cg_run(fracsolve_ctx *h, double gamma, int64_t N, const double *f, doubl
     HIPCHK(h, hipStreamSynchronize(h->st));
     const int32_t *skip = &ds->done;
     const int batch = 8;
+    // <p, A p> from the product's last pass saves a launch per step; above
+    // L = 2^19 its partials (one per 8 butterflies) and the gathered reads of
+    // p cost more than the separate reduction
+    const bool fused_dot = w.L <= (int64_t(1) << 19);
     while (!hs.done) {
         for (int b = 0; b < batch; ++b) {
-            HIPCHK(h, launch_circ_apply(h->st, w.p, w.Ap, n, w.L, w.S, w.za, w.zb, skip));
-            HIPCHK(h, launch_cg_step_tail(h->st, ds, u, w.r, w.p, w.Ap, n, h->partial, dh, hist_cap));
-            h->kernels += circ_launches(w.L) + 5;
+            int64_t npap = 0;
+            double *pap = fused_dot ? w.pap : nullptr;
+            HIPCHK(h, launch_circ_apply(h->st, w.p, w.Ap, n, w.L, w.S, w.za, w.zb, skip, pap, &npap));
+            HIPCHK(h, launch_cg_step_tail(h->st, ds, u, w.r, w.p, w.Ap, n, pap, npap, h->partial, dh, hist_cap));
+            h->kernels += circ_launches(w.L) + (fused_dot ? 4 : 5);
         }
         HIPCHK(h, hipMemcpyAsync(&hs, ds, sizeof hs, hipMemcpyDeviceToHost, h->st));
         HIPCHK(h, hipStreamSynchronize(h->st));

@@ -35,6 +35,14 @@ __device__ __forceinline__ c2 cmul(c2 a, c2 b) { return {a.x * b.x - a.y * b.y, 
 // sgn i z: +i z for sgn > 0, -i z for sgn < 0
 __device__ __forceinline__ c2 cmuli(c2 z, double sgn) { return {-sgn * z.y, sgn * z.x}; }
 
+// sum over the 64 lanes of a wavefront (every lane must take part)
+__device__ __forceinline__ double wave_sum(double d)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) d += __shfl_xor(d, off, 64);
+    return d;
+}
+
 // X_k = sum_m v_m exp(sgn 2 pi i m k / R), in place, for R = 2, 4, 8
 template <int R>
 __device__ __forceinline__ void dft_small(c2 *v, double sgn)
@@ -72,21 +80,27 @@ __device__ __forceinline__ void dft_small(c2 *v, double sgn)
 // One Stockham pass.  IN_REAL: the input is the real array xr of nx entries,
 // zero beyond (first forward pass, Ns = 1).  SCALE: inputs are multiplied by
 // the real spectrum S (first inverse pass, Ns = 1).  OUT_REAL: the real parts
-// of outputs below nx go to yr and the rest is dropped (last inverse pass).
+// of outputs below nx go to yr and the rest is dropped (last inverse pass);
+// with dotp, the workgroup's share of sum_o yr[o] xr[o] goes to
+// dotp[blockIdx.x] (xr is then the product's input).  Workgroups are one
+// wavefront; lanes past the end stay to the reduction.
 template <int R, bool IN_REAL, bool SCALE, bool OUT_REAL>
 __global__ void __launch_bounds__(64) k_fft1d_pass(const c2 *__restrict__ in, const double *__restrict__ xr,
                                                     const double *__restrict__ S, c2 *__restrict__ out,
                                                     double *__restrict__ yr, int64_t L, int64_t Ns, int64_t nx,
-                                                    double sgn, const int32_t *__restrict__ skip)
+                                                    double sgn, const int32_t *__restrict__ skip,
+                                                    double *__restrict__ dotp)
 {
     if (skip && *skip) return;
     const int64_t q = L / R;
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= q) return;
+    const bool live = j < q;
     c2 v[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const int64_t idx = j + r * q;
+        v[r] = {0.0, 0.0};
+        if (!live) continue;
         if constexpr (IN_REAL)
             v[r] = {idx < nx ? xr[idx] : 0.0, 0.0};
         else
@@ -109,13 +123,24 @@ __global__ void __launch_bounds__(64) k_fft1d_pass(const c2 *__restrict__ in, co
     }
     dft_small<R>(v, sgn);
     const int64_t base = (j - k) * R + k;
+    double d = 0.0;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const int64_t o = base + r * Ns;
+        if (!live) continue;
         if constexpr (OUT_REAL) {
-            if (o < nx) yr[o] = v[r].x;
+            if (o < nx) {
+                yr[o] = v[r].x;
+                if (dotp) d += v[r].x * xr[o];
+            }
         } else {
             out[o] = v[r];
+        }
+    }
+    if constexpr (OUT_REAL) {
+        if (dotp) {
+            d = wave_sum(d);
+            if (threadIdx.x == 0) dotp[blockIdx.x] = d;
         }
     }
 }
@@ -131,7 +156,8 @@ template <int R1, int R2, bool IN_REAL, bool SCALE, bool OUT_REAL>
 __global__ void __launch_bounds__(64) k_fft1d_pass2(const c2 *__restrict__ in, const double *__restrict__ xr,
                                                     const double *__restrict__ S, c2 *__restrict__ out,
                                                     double *__restrict__ yr, int64_t L, int64_t Ns, int64_t nx,
-                                                    double sgn, const int32_t *__restrict__ skip)
+                                                    double sgn, const int32_t *__restrict__ skip,
+                                                    double *__restrict__ dotp)
 {
     static_assert(R1 <= 8 && R2 <= 8 && R1 * R2 >= 16, "two stages of at most 8 points");
     constexpr int R = R1 * R2;
@@ -181,56 +207,67 @@ __global__ void __launch_bounds__(64) k_fft1d_pass2(const c2 *__restrict__ in, c
         }
     }
     __syncthreads();
-    if (t >= R1 || !live) return;
+    const bool act = t < R1 && live;
     c2 v[R2];
 #pragma unroll
-    for (int n2 = 0; n2 < R2; ++n2) v[n2] = row[n2 * 9 + t];
+    for (int n2 = 0; n2 < R2; ++n2) v[n2] = row[n2 * 9 + t];  // in the row for every t < 8
     dft_small<R2>(v, sgn);
     const int64_t base = (j - k) * R + k;
+    double d = 0.0;
 #pragma unroll
     for (int k2 = 0; k2 < R2; ++k2) {
         const int64_t o = base + (int64_t)(t + R1 * k2) * Ns;
+        if (!act) continue;
         if constexpr (OUT_REAL) {
-            if (o < nx) yr[o] = v[k2].x;
+            if (o < nx) {
+                yr[o] = v[k2].x;
+                if (dotp) d += v[k2].x * xr[o];
+            }
         } else {
             out[o] = v[k2];
+        }
+    }
+    if constexpr (OUT_REAL) {
+        if (dotp) {
+            d = wave_sum(d);
+            if (threadIdx.x == 0) dotp[blockIdx.x] = d;
         }
     }
 }
 
 template <int R1, int R2, bool IN_REAL, bool SCALE, bool OUT_REAL>
 hipError_t pass2_go(hipStream_t st, const c2 *in, const double *xr, const double *S, c2 *out, double *yr, int64_t L,
-                    int64_t Ns, int64_t nx, double sgn, const int32_t *skip)
+                    int64_t Ns, int64_t nx, double sgn, const int32_t *skip, double *dotp)
 {
     const int64_t q = L / (R1 * R2);
     const unsigned g = (unsigned)((q + 7) / 8);
     hipLaunchKernelGGL((k_fft1d_pass2<R1, R2, IN_REAL, SCALE, OUT_REAL>), dim3(g), dim3(64), 0, st, in, xr, S, out,
-                       yr, L, Ns, nx, sgn, skip);
+                       yr, L, Ns, nx, sgn, skip, dotp);
     return hipGetLastError();
 }
 
 template <int R, bool IN_REAL, bool SCALE, bool OUT_REAL>
 hipError_t pass_go(hipStream_t st, const c2 *in, const double *xr, const double *S, c2 *out, double *yr, int64_t L,
-                   int64_t Ns, int64_t nx, double sgn, const int32_t *skip)
+                   int64_t Ns, int64_t nx, double sgn, const int32_t *skip, double *dotp)
 {
     const int64_t q = L / R;
     const unsigned g = (unsigned)((q + 63) / 64);
     hipLaunchKernelGGL((k_fft1d_pass<R, IN_REAL, SCALE, OUT_REAL>), dim3(g), dim3(64), 0, st, in, xr, S, out, yr,
-                       L, Ns, nx, sgn, skip);
+                       L, Ns, nx, sgn, skip, dotp);
     return hipGetLastError();
 }
 
 template <bool IN_REAL, bool SCALE, bool OUT_REAL>
 hipError_t pass_radix(int R, hipStream_t st, const c2 *in, const double *xr, const double *S, c2 *out, double *yr,
-                      int64_t L, int64_t Ns, int64_t nx, double sgn, const int32_t *skip)
+                      int64_t L, int64_t Ns, int64_t nx, double sgn, const int32_t *skip, double *dotp = nullptr)
 {
     switch (R) {
-    case 64: return pass2_go<8, 8, IN_REAL, SCALE, OUT_REAL>(st, in, xr, S, out, yr, L, Ns, nx, sgn, skip);
-    case 32: return pass2_go<4, 8, IN_REAL, SCALE, OUT_REAL>(st, in, xr, S, out, yr, L, Ns, nx, sgn, skip);
-    case 16: return pass2_go<2, 8, IN_REAL, SCALE, OUT_REAL>(st, in, xr, S, out, yr, L, Ns, nx, sgn, skip);
-    case 8: return pass_go<8, IN_REAL, SCALE, OUT_REAL>(st, in, xr, S, out, yr, L, Ns, nx, sgn, skip);
-    case 4: return pass_go<4, IN_REAL, SCALE, OUT_REAL>(st, in, xr, S, out, yr, L, Ns, nx, sgn, skip);
-    default: return pass_go<2, IN_REAL, SCALE, OUT_REAL>(st, in, xr, S, out, yr, L, Ns, nx, sgn, skip);
+    case 64: return pass2_go<8, 8, IN_REAL, SCALE, OUT_REAL>(st, in, xr, S, out, yr, L, Ns, nx, sgn, skip, dotp);
+    case 32: return pass2_go<4, 8, IN_REAL, SCALE, OUT_REAL>(st, in, xr, S, out, yr, L, Ns, nx, sgn, skip, dotp);
+    case 16: return pass2_go<2, 8, IN_REAL, SCALE, OUT_REAL>(st, in, xr, S, out, yr, L, Ns, nx, sgn, skip, dotp);
+    case 8: return pass_go<8, IN_REAL, SCALE, OUT_REAL>(st, in, xr, S, out, yr, L, Ns, nx, sgn, skip, dotp);
+    case 4: return pass_go<4, IN_REAL, SCALE, OUT_REAL>(st, in, xr, S, out, yr, L, Ns, nx, sgn, skip, dotp);
+    default: return pass_go<2, IN_REAL, SCALE, OUT_REAL>(st, in, xr, S, out, yr, L, Ns, nx, sgn, skip, dotp);
     }
 }
 
@@ -244,12 +281,21 @@ int radix_plan(int p, int *rad)
     return np;
 }
 
+// workgroups of a pass of radix R over L points
+int64_t pass_blocks(int R, int64_t L)
+{
+    return R >= 16 ? (L / R + 7) / 8 : (L / R + 63) / 64;
+}
+
 // mode 0: forward transform of the real xr (nx entries, zero-padded) into
 // dst; mode 1: inverse transform of S .* src (complex), real part of the
-// first nx entries into yr.  The passes alternate between the two complex
-// buffers a and b; the forward result lands in *res.
+// first nx entries into yr, and with dotp the partial sums of
+// sum_o yr[o] xr[o] (one per workgroup of the last pass, their count in
+// *ndot).  The passes alternate between the two complex buffers a and b; the
+// forward result lands in *res.
 hipError_t fft1d_run(hipStream_t st, int mode, const double *xr, const double *S, double *yr, c2 *a, c2 *b,
-                     int64_t L, int64_t nx, c2 **res, const int32_t *skip)
+                     int64_t L, int64_t nx, c2 **res, const int32_t *skip, double *dotp = nullptr,
+                     int64_t *ndot = nullptr)
 {
     int p = 0;
     while ((int64_t(1) << p) < L) ++p;
@@ -269,13 +315,14 @@ hipError_t fft1d_run(hipStream_t st, int mode, const double *xr, const double *S
                 e = pass_radix<false, false, false>(R, st, src, nullptr, nullptr, dst, nullptr, L, Ns, nx, sgn,
                                                     skip);
         } else {
+            if (last && ndot) *ndot = pass_blocks(R, L);
             if (first && last)
-                e = pass_radix<false, true, true>(R, st, src, nullptr, S, nullptr, yr, L, Ns, nx, sgn, skip);
+                e = pass_radix<false, true, true>(R, st, src, xr, S, nullptr, yr, L, Ns, nx, sgn, skip, dotp);
             else if (first)
                 e = pass_radix<false, true, false>(R, st, src, nullptr, S, dst, nullptr, L, Ns, nx, sgn, skip);
             else if (last)
-                e = pass_radix<false, false, true>(R, st, src, nullptr, nullptr, nullptr, yr, L, Ns, nx, sgn,
-                                                   skip);
+                e = pass_radix<false, false, true>(R, st, src, xr, nullptr, nullptr, yr, L, Ns, nx, sgn, skip,
+                                                   dotp);
             else
                 e = pass_radix<false, false, false>(R, st, src, nullptr, nullptr, dst, nullptr, L, Ns, nx, sgn,
                                                     skip);
@@ -336,15 +383,17 @@ hipError_t launch_circ_spectrum(hipStream_t st, const double *a, int64_t n, int6
 }
 
 hipError_t launch_circ_apply(hipStream_t st, const double *x, double *y, int64_t n, int64_t L, const double *S,
-                             void *za, void *zb, const int32_t *skip)
+                             void *za, void *zb, const int32_t *skip, double *dotp, int64_t *ndot)
 {
     if (L < 8 || (L & (L - 1)) || L < 2 * n - 1 || L > (int64_t(1) << 23) || x == y) return hipErrorInvalidValue;
     c2 *res = nullptr;
     hipError_t e = fft1d_run(st, 0, x, nullptr, nullptr, (c2 *)za, (c2 *)zb, L, n, &res, skip);
     if (e != hipSuccess) return e;
     c2 *other = res == (c2 *)za ? (c2 *)zb : (c2 *)za;
-    return fft1d_run(st, 1, nullptr, S, y, res, other, L, n, nullptr, skip);
+    return fft1d_run(st, 1, x, S, y, res, other, L, n, nullptr, skip, dotp, ndot);
 }
+
+int64_t circ_dot_parts(int64_t L) { return L / 128 + 1; }
 
 int circ_launches(int64_t L)
 {

@@ -375,10 +375,10 @@ hipError_t launch_dot_partial(hipStream_t st, const double *x, const double *y, 
 // Every kernel returns at once when st->done is set, so steps enqueued past
 // the stop are no-ops and the iterates are those of the step-by-step loop.
 
-__device__ double sum_partials(const double *__restrict__ partial, int nb)
+__device__ double sum_partials(const double *__restrict__ partial, int64_t nb)
 {
     double s = 0.0;
-    for (int i = threadIdx.x; i < nb; i += 256) s += partial[i];
+    for (int64_t i = threadIdx.x; i < nb; i += 256) s += partial[i];
     return block_sum<256>(s);
 }
 
@@ -394,7 +394,7 @@ __global__ void __launch_bounds__(256) k_cg_pap(const CgState *__restrict__ st, 
 }
 
 // kappa = r.r / <p, A p>; a direction with <p, A p> <= 0 stops with bad = 1
-__global__ void __launch_bounds__(256) k_cg_alpha(CgState *st, const double *__restrict__ partial, int nb)
+__global__ void __launch_bounds__(256) k_cg_alpha(CgState *st, const double *__restrict__ partial, int64_t nb)
 {
     if (st->done) return;
     const double pAp = sum_partials(partial, nb);
@@ -429,7 +429,7 @@ __global__ void __launch_bounds__(256) k_cg_update(const CgState *__restrict__ s
 }
 
 // new r.r: count the step, record |r| / |f|, beta = new / old, stop test
-__global__ void __launch_bounds__(256) k_cg_beta(CgState *st, const double *__restrict__ partial, int nb,
+__global__ void __launch_bounds__(256) k_cg_beta(CgState *st, const double *__restrict__ partial, int64_t nb,
                                                  double *__restrict__ hist, int hist_cap)
 {
     if (st->done) return;
@@ -458,13 +458,18 @@ __global__ void __launch_bounds__(256) k_cg_dir(const CgState *__restrict__ st, 
 int cg_blocks(int64_t n) { return (int)std::min<int64_t>(1024, std::max<int64_t>(1, (n + 255) / 256)); }
 
 hipError_t launch_cg_step_tail(hipStream_t st, CgState *cs, double *u, double *r, double *p, const double *Ap,
-                               int64_t n, double *partial, double *hist, int hist_cap)
+                               int64_t n, const double *pap, int64_t npap, double *partial, double *hist,
+                               int hist_cap)
 {
     const int nb = cg_blocks(n);
-    hipLaunchKernelGGL(k_cg_pap, dim3(nb), dim3(256), 0, st, cs, p, Ap, n, partial);
-    hipLaunchKernelGGL(k_cg_alpha, dim3(1), dim3(256), 0, st, cs, partial, nb);
+    if (!pap) {
+        hipLaunchKernelGGL(k_cg_pap, dim3(nb), dim3(256), 0, st, cs, p, Ap, n, partial);
+        pap = partial;
+        npap = nb;
+    }
+    hipLaunchKernelGGL(k_cg_alpha, dim3(1), dim3(256), 0, st, cs, pap, npap);
     hipLaunchKernelGGL(k_cg_update, dim3(nb), dim3(256), 0, st, cs, u, r, p, Ap, n, partial);
-    hipLaunchKernelGGL(k_cg_beta, dim3(1), dim3(256), 0, st, cs, partial, nb, hist, hist_cap);
+    hipLaunchKernelGGL(k_cg_beta, dim3(1), dim3(256), 0, st, cs, partial, (int64_t)nb, hist, hist_cap);
     hipLaunchKernelGGL(k_cg_dir, dim3(nb), dim3(256), 0, st, cs, p, r, n);
     return hipGetLastError();
 }
