@@ -146,26 +146,28 @@ __global__ void __launch_bounds__(64) k_fft1d_pass(const c2 *__restrict__ in, co
 }
 
 // Two-stage pass of radix R = R1 R2 (64 = 8 x 8, 32 = 4 x 8, 16 = 2 x 8):
-// eight threads per butterfly, 8 butterflies per workgroup of one wavefront
-// (L = 2^18 gives 512 workgroups at radix 64, enough to reach every CU of a
-// latency-bound pass).  Input r = R2 n1 + n2 goes to thread n2 < R2; a
+// eight threads per butterfly, BPW butterflies per workgroup: 8, one
+// wavefront (L = 2^18 gives 512 workgroups at radix 64, enough to reach
+// every CU of a latency-bound pass), or 16 for the real-array passes at
+// large L.  Input r = R2 n1 + n2 goes to thread n2 < R2; a
 // radix-R1 transform over n1 gives Y[n2][k1], which is twiddled by
 // w_R^(n2 k1), transposed through LDS, and transformed over n2 by thread
 // k1 < R1, giving output k1 + R1 k2.
-template <int R1, int R2, bool IN_REAL, bool SCALE, bool OUT_REAL>
-__global__ void __launch_bounds__(64) k_fft1d_pass2(const c2 *__restrict__ in, const double *__restrict__ xr,
+template <int R1, int R2, bool IN_REAL, bool SCALE, bool OUT_REAL, int BPW>
+__global__ void __launch_bounds__(8 * BPW) k_fft1d_pass2(const c2 *__restrict__ in, const double *__restrict__ xr,
                                                     const double *__restrict__ S, c2 *__restrict__ out,
                                                     double *__restrict__ yr, int64_t L, int64_t Ns, int64_t nx,
                                                     double sgn, const int32_t *__restrict__ skip,
                                                     double *__restrict__ dotp)
 {
     static_assert(R1 <= 8 && R2 <= 8 && R1 * R2 >= 16, "two stages of at most 8 points");
+    static_assert(BPW == 8 || (BPW == 16 && !OUT_REAL), "the partial sums assume one wavefront per workgroup");
     constexpr int R = R1 * R2;
     if (skip && *skip) return;
-    __shared__ c2 lds[8 * 72];  // per butterfly 8 rows of 9 (one pad entry against bank conflicts)
+    __shared__ c2 lds[BPW * 72];  // per butterfly 8 rows of 9 (one pad entry against bank conflicts)
     const int t = threadIdx.x & 7, g = threadIdx.x >> 3;
     const int64_t q = L / R;
-    const int64_t j = (int64_t)blockIdx.x * 8 + g;
+    const int64_t j = (int64_t)blockIdx.x * BPW + g;
     const bool live = j < q;
     const int64_t k = j & (Ns - 1);
     c2 *row = lds + g * 72;
@@ -235,13 +237,24 @@ __global__ void __launch_bounds__(64) k_fft1d_pass2(const c2 *__restrict__ in, c
     }
 }
 
+// Passes that read a real array (x, or the spectrum) take 16 butterflies per
+// workgroup for L >= 2^20, where HBM bounds them: with 8, a wavefront covers
+// 64 B of that array, half a cache line, and the line is fetched twice.
 template <int R1, int R2, bool IN_REAL, bool SCALE, bool OUT_REAL>
 hipError_t pass2_go(hipStream_t st, const c2 *in, const double *xr, const double *S, c2 *out, double *yr, int64_t L,
                     int64_t Ns, int64_t nx, double sgn, const int32_t *skip, double *dotp)
 {
     const int64_t q = L / (R1 * R2);
+    if constexpr ((IN_REAL || SCALE) && !OUT_REAL) {
+        if (L >= (int64_t(1) << 20)) {
+            const unsigned g = (unsigned)((q + 15) / 16);
+            hipLaunchKernelGGL((k_fft1d_pass2<R1, R2, IN_REAL, SCALE, OUT_REAL, 16>), dim3(g), dim3(128), 0, st, in,
+                               xr, S, out, yr, L, Ns, nx, sgn, skip, dotp);
+            return hipGetLastError();
+        }
+    }
     const unsigned g = (unsigned)((q + 7) / 8);
-    hipLaunchKernelGGL((k_fft1d_pass2<R1, R2, IN_REAL, SCALE, OUT_REAL>), dim3(g), dim3(64), 0, st, in, xr, S, out,
+    hipLaunchKernelGGL((k_fft1d_pass2<R1, R2, IN_REAL, SCALE, OUT_REAL, 8>), dim3(g), dim3(64), 0, st, in, xr, S, out,
                        yr, L, Ns, nx, sgn, skip, dotp);
     return hipGetLastError();
 }
