@@ -142,3 +142,45 @@ def test_recorded_traffic_lines_parse():
         assert m.group(1) in names
         s, b = int(m.group(2)), int(m.group(3))
         assert 0.5 * 24 * s * 4096 <= b <= 2.0 * 24 * s * 4096  # within 2x of the algorithmic bytes
+
+
+def ode_cg(lib, gamma, N, f=1, u=2, opts=None, hist=None, hist_cap=0):
+    from paper_1710_11593_amd import binding
+
+    o = binding.CgOptions(*opts) if opts else None
+    info = binding.CgInfo()
+    fn = lib.fracsolve_ode_cg
+    fn.restype = ctypes.c_int
+    rc = fn(ctypes.c_double(gamma), ctypes.c_int64(N), ctypes.c_void_p(f), ctypes.c_void_p(u),
+            ctypes.byref(o) if o is not None else None, ctypes.byref(info), hist, ctypes.c_int32(hist_cap), None)
+    return rc, lib.fracsolve_last_error(None).decode()
+
+
+@pytest.mark.parametrize("gamma, N, kw, pattern", [
+    (1.0, 64, {}, "gamma"),
+    (0.0, 64, {}, "gamma"),
+    (1.5, 64, {}, "gamma"),
+    (0.5, 2, {}, "N must"),
+    (0.5, 2 ** 22 + 2, {}, "N must"),
+    (0.5, 64, {"f": 0}, "NULL"),
+    (0.5, 64, {"u": 0}, "NULL"),
+    (0.5, 64, {"opts": (-1, 1e-10, 0)}, "max_iters"),
+    (0.5, 64, {"opts": (10, -1.0, 0)}, "rtol"),
+    (0.5, 64, {"opts": (10, float("nan"), 0)}, "rtol"),
+    (0.5, 64, {"opts": (10, 1e-10, 2)}, "use_guess"),
+    (0.5, 64, {"hist_cap": 5}, "hist"),
+])
+def test_ode_cg_rejects_bad_arguments_before_device_work(lib, gamma, N, kw, pattern):
+    # every check runs on the host before any device call, so the dummy
+    # pointers are never touched
+    rc, msg = ode_cg(lib, gamma, N, **kw)
+    assert rc == E_ARG, (rc, msg)
+    assert pattern in msg, msg
+
+
+def test_ode_cg_valid_arguments_without_gpu_report_no_device(lib):
+    torch = pytest.importorskip("torch")
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    rc, msg = ode_cg(lib, 0.5, 2 ** 22 + 1)
+    assert rc == E_DEVICE, (rc, msg)
