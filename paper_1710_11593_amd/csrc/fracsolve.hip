@@ -1294,16 +1294,57 @@ int ode_cg_run(fracsolve_ctx *h, double gamma, int64_t N, const double *f, doubl
     // L = 2^19 its partials (one per 8 butterflies) and the gathered reads of
     // p cost more than the separate reduction
     const bool fused_dot = w.L <= (int64_t(1) << 19);
-    while (!hs.done) {
+    auto enqueue_batch = [&](hipStream_t st) -> hipError_t {
         for (int b = 0; b < batch; ++b) {
             int64_t npap = 0;
             double *pap = fused_dot ? w.pap : nullptr;
-            HIPCHK(h, launch_circ_apply(h->st, w.p, w.Ap, n, w.L, w.S, w.za, w.zb, skip, pap, &npap));
-            HIPCHK(h, launch_cg_step_tail(h->st, ds, u, w.r, w.p, w.Ap, n, pap, npap, h->partial, dh, hist_cap));
-            h->kernels += circ_launches(w.L) + (fused_dot ? 4 : 5);
+            hipError_t e = launch_circ_apply(st, w.p, w.Ap, n, w.L, w.S, w.za, w.zb, skip, pap, &npap);
+            if (e == hipSuccess)
+                e = launch_cg_step_tail(st, ds, u, w.r, w.p, w.Ap, n, pap, npap, h->partial, dh, hist_cap);
+            if (e != hipSuccess) return e;
         }
-        HIPCHK(h, hipMemcpyAsync(&hs, ds, sizeof hs, hipMemcpyDeviceToHost, h->st));
-        HIPCHK(h, hipStreamSynchronize(h->st));
+        return hipSuccess;
+    };
+    const int per_batch = batch * (circ_launches(w.L) + (fused_dot ? 4 : 5));
+    // Up to L = 2^19 a step is launch-bound: one batch is captured once and
+    // replayed as a graph on a stream of this call (default priority).  The
+    // caller's stream is idle here (synchronised above) and every batch ends
+    // with a host synchronisation, so no events are needed.
+    struct OdeGraph {
+        hipStream_t st = nullptr;
+        hipGraphExec_t exec = nullptr;
+        ~OdeGraph()
+        {
+            if (exec) hipGraphExecDestroy(exec);
+            if (st) hipStreamDestroy(st);
+        }
+    } og;
+    const char *genv = getenv("FRACSOLVE_ODE_GRAPH");
+    if (!hs.done && w.L <= (int64_t(1) << 19) && !(genv && genv[0] == '0')) {
+        HIPCHK(h, hipStreamCreateWithFlags(&og.st, hipStreamNonBlocking));
+        hipGraph_t graph = nullptr;
+        HIPCHK(h, hipStreamBeginCapture(og.st, hipStreamCaptureModeThreadLocal));
+        const hipError_t e1 = enqueue_batch(og.st);
+        const hipError_t e2 = hipStreamEndCapture(og.st, &graph);
+        if (e1 != hipSuccess || e2 != hipSuccess) {
+            if (graph) hipGraphDestroy(graph);
+            return fail(h, FRACSOLVE_E_DEVICE, "CG graph capture failed: %s",
+                        hipGetErrorString(e1 != hipSuccess ? e1 : e2));
+        }
+        const hipError_t e3 = hipGraphInstantiate(&og.exec, graph, nullptr, nullptr, 0);
+        hipGraphDestroy(graph);
+        if (e3 != hipSuccess)
+            return fail(h, FRACSOLVE_E_DEVICE, "CG graph instantiate failed: %s", hipGetErrorString(e3));
+    }
+    hipStream_t bst = og.exec ? og.st : h->st;
+    while (!hs.done) {
+        if (og.exec)
+            HIPCHK(h, hipGraphLaunch(og.exec, bst));
+        else
+            HIPCHK(h, enqueue_batch(bst));
+        h->kernels += per_batch;
+        HIPCHK(h, hipMemcpyAsync(&hs, ds, sizeof hs, hipMemcpyDeviceToHost, bst));
+        HIPCHK(h, hipStreamSynchronize(bst));
     }
     if (hs.bad) return fail(h, FRACSOLVE_E_NUMERIC, "CG: <p, A p> = %g at step %d", hs.pAp, (int)hs.it);
     const int it = hs.it;

@@ -172,6 +172,20 @@ def orc_dense(orc, gamma, N):
     return toeplitz(orc.ode_column(gamma, N))
 
 
+@pytest.mark.parametrize("gamma, N", [(0.9, 1024), (0.5, 2 ** 17 + 1)])
+def test_graph_replay_matches_direct_launches(torch_cuda, monkeypatch, gamma, N):
+    # up to L = 2^19 a batch of steps is replayed as a graph (many replays per
+    # call, with host reads and synchronisation between them); the same
+    # kernels launched directly must give bit-identical iterates
+    t, f = forcing(gamma, N)
+    u_g, i_g, h_g = gpu_cg(torch_cuda, gamma, N, f, rtol=1e-11, max_iters=5000, hist_cap=5001)
+    monkeypatch.setenv("FRACSOLVE_ODE_GRAPH", "0")
+    u_d, i_d, h_d = gpu_cg(torch_cuda, gamma, N, f, rtol=1e-11, max_iters=5000, hist_cap=5001)
+    print("graph vs direct", N, i_g["iterations"], i_d["iterations"], flush=True)
+    assert i_g["iterations"] == i_d["iterations"] > 16
+    assert np.array_equal(u_g, u_d) and np.array_equal(h_g, h_d)
+
+
 def test_invalid_arguments(torch_cuda):
     from paper_1710_11593_amd import binding
 
