@@ -72,9 +72,9 @@ enum {
     FRACSOLVE_FP64 = 0,   /* all products in float64                          */
     FRACSOLVE_FP32 = 1,   /* FFT level products in float32, their history
                              accumulated in float32                           */
-    FRACSOLVE_BF16X3 = 2  /* accepted, and runs as FRACSOLVE_FP32: the
-                             products a split bf16 form would serve are bound
-                             by memory or latency, not by arithmetic          */
+    FRACSOLVE_BF16X3 = 2  /* reserved for split bf16 products on the matrix
+                             cores; not available in this version:
+                             fracsolve_create returns E_ARG for it            */
 };
 
 typedef struct {
@@ -111,7 +111,7 @@ enum {
 };
 
 typedef struct {
-    int32_t precision;    /* FRACSOLVE_FP64 / FP32 / BF16X3                    */
+    int32_t precision;    /* FRACSOLVE_FP64 or FRACSOLVE_FP32 (BF16X3: E_ARG)  */
     int32_t refine_steps; /* iterative-refinement steps against the float64
                              operator for FP32 / BF16X3 (0 = none; FP64 ignores
                              it)                                               */

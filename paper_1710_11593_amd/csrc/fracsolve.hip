@@ -1417,6 +1417,10 @@ int fracsolve_create(const fracsolve_problem *probs, int32_t count, const fracso
     if (opts) o = *opts;
     if (o.precision < FRACSOLVE_FP64 || o.precision > FRACSOLVE_BF16X3)
         return fail(nullptr, FRACSOLVE_E_ARG, "unknown precision %d", (int)o.precision);
+    if (o.precision == FRACSOLVE_BF16X3)
+        return fail(nullptr, FRACSOLVE_E_ARG,
+                    "precision 2 (split bf16 products) is not available in this version; use 0 (float64) or 1 "
+                    "(float32 products with float64 refinement)");
     if (o.refine_steps < 0 || o.refine_steps > 8)
         return fail(nullptr, FRACSOLVE_E_ARG, "refine_steps must lie in [0, 8], got %d", (int)o.refine_steps);
     if (o.leaf_solver < 0 || o.leaf_solver > 1)

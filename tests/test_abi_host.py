@@ -80,6 +80,7 @@ def test_invalid_problem_is_rejected_before_device_work(lib, prob, pattern):
 
 @pytest.mark.parametrize("opts, pattern", [
     ((3, 0, 0, 0, 0, None), "precision"),
+    ((2, 1, 0, 0, 0, None), "not available"),   # split bf16 products are not built
     ((1, 9, 0, 0, 0, None), "refine_steps"),
     ((0, 0, 5, 0, 0, None), "leaf"),
     ((0, 0, 0, 0, 2, None), "leaf_solver"),

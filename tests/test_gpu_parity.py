@@ -46,20 +46,12 @@ def rand_case(gamma, M, N, seed=0):
     return f, u0, phi
 
 
-def level_factor(N, L=8):
-    """Bound on how many more rounded partial sums the recursive solve adds to
-    a row's history than sequential time stepping: one per recursion level."""
-    import math
-
-    return 1.0 + max(0.0, math.log2(max(N, L) / L))
-
-
 def assert_parity64(u, ref, gamma, M, N, f, u0, phi):
     """float64 bar: <= 1e-11 against the oracle.  Where the oracle's own
     float64 error exceeds that (its distance to an extended-precision solve
     of the same system), the GPU result's distance to the extended-precision
-    solve must stay within the oracle's, times the number of recursion levels
-    (each level adds one rounded partial sum to a row's history)."""
+    solve must be at most twice the oracle's (and the oracle within 1e-8 of
+    it)."""
     e = relerr(u, ref)
     if e <= TOL64:
         return
@@ -67,7 +59,8 @@ def assert_parity64(u, ref, gamma, M, N, f, u0, phi):
 
     ext = np.asarray(ext_reference.solve(gamma, M, N, f, u0, phi), dtype=np.float64)
     e_gpu, e_orc = relerr(u, ext), relerr(ref, ext)
-    assert e_gpu <= max(TOL64, level_factor(N) * e_orc), (e, e_gpu, e_orc)
+    print("  extended-precision check: gpu %.2e oracle %.2e" % (e_gpu, e_orc), flush=True)
+    ext_reference.assert_within_floor(e, e_gpu, e_orc, TOL64)
 
 
 def gpu_solve(torch, gamma, M, N, f, u0=None, phi=None, **opts):
@@ -171,8 +164,11 @@ def test_multipass_fft_level(torch_cuda, orc, gamma, crossover):
     err = float((u - ref).abs().max() / ref.abs().max())
     if err > TOL64:
         # float64 floor of the diffusion-wave recurrence: measure it
+        from tests import ext_reference
+
         e_gpu, e_orc = ext_mode_check(torch_cuda, orc, inst, u)
-        assert e_gpu <= max(TOL64, level_factor(inst.N) * e_orc), (err, e_gpu, e_orc)
+        print("  extended-precision check: gpu %.2e oracle %.2e" % (e_gpu, e_orc), flush=True)
+        ext_reference.assert_within_floor(err, e_gpu, e_orc, TOL64)
 
 
 @pytest.mark.parametrize("gamma,M,N", [(0.6, 33, 100), (1.5, 64, 128), (0.9, 300, 77)])
@@ -211,7 +207,8 @@ def test_adjoint_parity(torch_cuda, orc, gamma, M, N):
 
         ext = np.asarray(ext_reference.solve(gamma, M, N, g[::-1]), dtype=np.float64)[::-1]
         e_gpu, e_orc = relerr(lam, ext), relerr(lam_ref, ext)
-        assert e_gpu <= max(TOL64, level_factor(N) * e_orc), (e, e_gpu, e_orc)
+        print("  extended-precision check: gpu %.2e oracle %.2e" % (e_gpu, e_orc), flush=True)
+        ext_reference.assert_within_floor(e, e_gpu, e_orc, TOL64)
     assert abs(dg[0] - dg_ref) <= 1e-10 * abs(dg_ref)
 
 
@@ -349,44 +346,20 @@ def mode_reference(torch, orc, inst):
     return f, u0, phi, ref
 
 
-def ext_mode_lib():
-    """Build and load tests/ext_mode.c (long double single-mode recurrence)."""
-    import ctypes
-    import os
-    import subprocess
-
-    here = os.path.dirname(os.path.abspath(__file__))
-    out = os.path.join(os.path.dirname(here), "_build", "libext_mode.so")
-    os.makedirs(os.path.dirname(out), exist_ok=True)
-    src = os.path.join(here, "ext_mode.c")
-    if not os.path.exists(out) or os.path.getmtime(out) < os.path.getmtime(src):
-        subprocess.check_call(["gcc", "-O2", "-fPIC", "-shared", "-o", out, src, "-lm"])
-    lib = ctypes.CDLL(out)
-    dp = ctypes.POINTER(ctypes.c_double)
-    lib.ext_mode.restype = ctypes.c_int
-    lib.ext_mode.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_int64, ctypes.c_double, dp,
-                             ctypes.c_double, ctypes.c_double, dp]
-    return lib
-
-
 def ext_mode_check(torch, orc, inst, u):
     """(GPU error, float64 oracle recurrence error), both against the
     extended-precision recurrence, for a sum-of-sine-modes instance."""
-    import ctypes
     import math
+
+    from tests import ext_reference
 
     series = wl.modal_time_series(inst)
     x, _, h, _ = wl.grid(inst.M, inst.N)
-    dp = ctypes.POINTER(ctypes.c_double)
-    lib = ext_mode_lib()
     uext = None
     e_orc = 0.0
     for j, (g, v0, ph) in series.items():
         lam = 4.0 / h ** 2 * math.sin(j * math.pi * h / 2) ** 2
-        g = np.ascontiguousarray(g)
-        vx = np.zeros(inst.N)
-        assert lib.ext_mode(inst.gamma, inst.T, inst.N, lam, g.ctypes.data_as(dp), v0, ph,
-                            vx.ctypes.data_as(dp)) == 0
+        vx = ext_reference.mode(inst.gamma, inst.T, inst.N, lam, g, v0, ph)
         v64 = orc.mode(inst.gamma, inst.T, inst.N, lam, g, v0, ph)
         e_orc = max(e_orc, float(np.max(np.abs(v64 - vx)) / np.max(np.abs(vx))))
         term = torch.from_numpy(vx).cuda()[:, None] * torch.from_numpy(np.sin(j * math.pi * x)).cuda()[None, :]
@@ -404,10 +377,10 @@ def test_full_size_mode_reduction(torch_cuda, orc, which):
     N = 2^17 (the history sum cancels several times the result at every
     step); there the floor is measured with an extended-precision recurrence
     and the GPU must be at least as close to it as the float64 oracle."""
-    import ctypes
     import math
 
     from paper_1710_11593_amd import binding
+    from tests import ext_reference
 
     if which.startswith("c2"):
         inst = wl.c2(gamma=float(which.split("-")[1]), build=False)
@@ -428,15 +401,11 @@ def test_full_size_mode_reduction(torch_cuda, orc, which):
     g, v0, ph = series[1]
     x, _, h, _ = wl.grid(inst.M, inst.N)
     lam = 4.0 / h ** 2 * math.sin(math.pi * h / 2) ** 2
-    vx = np.zeros(inst.N)
-    dp = ctypes.POINTER(ctypes.c_double)
-    g = np.ascontiguousarray(g)
-    assert ext_mode_lib().ext_mode(inst.gamma, inst.T, inst.N, lam, g.ctypes.data_as(dp), v0, ph,
-                                   vx.ctypes.data_as(dp)) == 0
+    vx = ext_reference.mode(inst.gamma, inst.T, inst.N, lam, g, v0, ph)
     v64 = orc.mode(inst.gamma, inst.T, inst.N, lam, g, v0, ph)
     e_orc = float(np.max(np.abs(v64 - vx)) / np.max(np.abs(vx)))
     s1 = torch_cuda.from_numpy(np.sin(math.pi * x)).cuda()
     uext = torch_cuda.from_numpy(vx).cuda()[:, None] * s1[None, :]
     e_gpu = float((u - uext).abs().max() / uext.abs().max())
     print("c3: GPU vs extended %.3e, float64 oracle recurrence vs extended %.3e" % (e_gpu, e_orc))
-    assert e_gpu <= max(TOL64, 2.0 * e_orc)
+    ext_reference.assert_within_floor(err, e_gpu, e_orc, TOL64)
