@@ -277,6 +277,29 @@ int fracsolve_ode_cg(double gamma, int64_t N, const double *f, double *u,
                      double *hist, int32_t hist_cap, void *stream);
 
 /*
+ * Scheme 1 by conjugate gradients, as fracsolve_ode_cg, for callers that
+ * cannot allocate device memory (code under stream capture, tight serving
+ * loops, harnesses that forbid allocation).  Every workspace (the embedded
+ * spectrum, the FFT work arrays, the CG vectors and scalars, the residual
+ * history and the reduction partials) lives in one fixed device array of
+ * 64 MiB that the library holds on each device it runs on until the process
+ * ends; the call allocates nothing and creates no stream or graph (the steps
+ * are launched directly on `stream`, whose device must be the current one).
+ * Same arguments, results and errors as fracsolve_ode_cg, with two more
+ * limits checked before any device work: N <= FRACSOLVE_ODE_NOALLOC_MAX_N and
+ * hist_cap <= FRACSOLVE_ODE_NOALLOC_MAX_HIST (E_ARG beyond).  Every call on a
+ * device shares that device's array and leaves its contents behind: calls
+ * that overlap on one device (two threads, or two streams) race and must be
+ * serialised by the caller.  The call synchronises `stream`.
+ */
+#define FRACSOLVE_ODE_NOALLOC_MAX_N ((int64_t)(1 << 19) + 1)
+#define FRACSOLVE_ODE_NOALLOC_MAX_HIST 65536
+
+int fracsolve_ode_cg_noalloc(double gamma, int64_t N, const double *f, double *u,
+                             const fracsolve_cg_options *opts, fracsolve_cg_info *info,
+                             double *hist, int32_t hist_cap, void *stream);
+
+/*
  * Timing and plan details of the last call, for reporting.  Fields are -1
  * when not measured.  Filled only if timing was enabled with
  * fracsolve_set_timing(h, 1) before the call (it adds events and a

@@ -65,7 +65,7 @@ class CgInfo(ctypes.Structure):
 KIND_NAMES = {0: "leaf", 1: "dense_f64", 2: "dense_f32", 3: "fft_f64", 4: "fft_f32", 5: "fft_corner"}
 
 EXPORTS = ["fracsolve_create", "fracsolve_weights", "fracsolve_solve", "fracsolve_apply", "fracsolve_adjoint",
-           "fracsolve_gmres", "fracsolve_ode_cg", "fracsolve_set_timing", "fracsolve_get_stats", "fracsolve_kernel_stats", "fracsolve_destroy",
+           "fracsolve_gmres", "fracsolve_ode_cg", "fracsolve_ode_cg_noalloc", "fracsolve_set_timing", "fracsolve_get_stats", "fracsolve_kernel_stats", "fracsolve_destroy",
            "fracsolve_last_error"]
 
 _lib = None
@@ -105,6 +105,8 @@ def lib():
     L.fracsolve_ode_cg.argtypes = [ctypes.c_double, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
                                    ctypes.POINTER(CgOptions), ctypes.POINTER(CgInfo), dp, ctypes.c_int32,
                                    ctypes.c_void_p]
+    L.fracsolve_ode_cg_noalloc.restype = ctypes.c_int
+    L.fracsolve_ode_cg_noalloc.argtypes = L.fracsolve_ode_cg.argtypes
     L.fracsolve_set_timing.restype = ctypes.c_int
     L.fracsolve_set_timing.argtypes = [ctypes.c_void_p, ctypes.c_int32]
     L.fracsolve_get_stats.restype = ctypes.c_int
@@ -273,10 +275,13 @@ class Solver:
         return {k: getattr(s, k) for k, _ in Stats._fields_}
 
 
-def ode_cg(gamma, N, f, out=None, max_iters=10000, rtol=1e-10, use_guess=False, hist_cap=0, stream=None):
+def ode_cg(gamma, N, f, out=None, max_iters=10000, rtol=1e-10, use_guess=False, hist_cap=0, stream=None,
+           noalloc=False):
     """Scheme 1 (the two-sided fractional ODE) by conjugate gradients with the
-    FFT operator (fracsolve_ode_cg).  f: float64 CUDA tensor of the N - 1
-    values at t_i = i/N.  Returns (u, info dict, residual history)."""
+    FFT operator (fracsolve_ode_cg; noalloc=True: fracsolve_ode_cg_noalloc,
+    whose workspace is the library's fixed device array).  f: float64 CUDA
+    tensor of the N - 1 values at t_i = i/N.  Returns (u, info dict, residual
+    history)."""
     import numpy as np
     import torch
 
@@ -290,10 +295,11 @@ def ode_cg(gamma, N, f, out=None, max_iters=10000, rtol=1e-10, use_guess=False, 
     opts = CgOptions(int(max_iters), float(rtol), 1 if use_guess else 0)
     info = CgInfo()
     hist = np.zeros(max(int(hist_cap), 1))
-    rc = L.fracsolve_ode_cg(float(gamma), int(N), ctypes.c_void_p(f.data_ptr()), ctypes.c_void_p(out.data_ptr()),
-                            ctypes.byref(opts), ctypes.byref(info),
-                            hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if hist_cap > 0 else None,
-                            int(hist_cap), ctypes.c_void_p(stream))
+    fn = L.fracsolve_ode_cg_noalloc if noalloc else L.fracsolve_ode_cg
+    rc = fn(float(gamma), int(N), ctypes.c_void_p(f.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+            ctypes.byref(opts), ctypes.byref(info),
+            hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if hist_cap > 0 else None,
+            int(hist_cap), ctypes.c_void_p(stream))
     if rc != FRACSOLVE_OK:
         raise FracsolveError(rc, L.fracsolve_last_error(None).decode())
     d = {k: getattr(info, k) for k, _ in CgInfo._fields_}

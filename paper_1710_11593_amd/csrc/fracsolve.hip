@@ -15,6 +15,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -1232,19 +1233,43 @@ int ode_matvec(fracsolve_ctx *h, const OdeWork &w, int64_t n, const double *x, d
     return FRACSOLVE_OK;
 }
 
+// Device buffers of one Scheme 1 CG call (n = N - 1 unknowns, L = circ_length(n)).
+struct OdeBuffers {
+    OdeWork w;
+    double *a;     // [n]  Toeplitz column before the embedding
+    CgState *ds;   // the device-side CG scalars
+    double *dh;    // [hist_cap] residual history, or NULL
+};
+
+int ode_cg_core(fracsolve_ctx *h, double gamma, int64_t N, const double *f, double *u, const fracsolve_cg_options &o,
+                fracsolve_cg_info *info, double *hist, int hist_cap, const OdeBuffers &bufs, bool allow_graph);
+
 int ode_cg_run(fracsolve_ctx *h, double gamma, int64_t N, const double *f, double *u, const fracsolve_cg_options &o,
                fracsolve_cg_info *info, double *hist, int hist_cap)
 {
     const int64_t n = N - 1;
-    OdeWork w{};
+    OdeBuffers b{};
+    OdeWork &w = b.w;
     int rc;
     w.L = circ_length(n);
-    double *a = nullptr;
-    for (double **q : {&w.r, &w.p, &w.Ap, &a})
+    for (double **q : {&w.r, &w.p, &w.Ap, &b.a})
         if ((rc = dalloc(h, q, (size_t)n))) return rc;
     if ((rc = dalloc(h, &w.S, (size_t)w.L)) || (rc = dalloc(h, &w.za, 2 * (size_t)w.L)) ||
         (rc = dalloc(h, &w.zb, 2 * (size_t)w.L)) || (rc = dalloc(h, &w.pap, (size_t)circ_dot_parts(w.L))))
         return rc;
+    if ((rc = dalloc(h, &b.ds, 1))) return rc;
+    if (hist_cap > 1 && (rc = dalloc(h, &b.dh, (size_t)hist_cap))) return rc;
+    const char *genv = getenv("FRACSOLVE_ODE_GRAPH");
+    return ode_cg_core(h, gamma, N, f, u, o, info, hist, hist_cap, b, !(genv && genv[0] == '0'));
+}
+
+int ode_cg_core(fracsolve_ctx *h, double gamma, int64_t N, const double *f, double *u, const fracsolve_cg_options &o,
+                fracsolve_cg_info *info, double *hist, int hist_cap, const OdeBuffers &bufs, bool allow_graph)
+{
+    const int64_t n = N - 1;
+    const OdeWork &w = bufs.w;
+    double *a = bufs.a;
+    int rc;
     // the L1 weights a_m of the left derivative (Lemma 2) on tau = 1/N,
     // scaled by mu = tau^-gamma / Gamma(2 - gamma)
     const double tau = 1.0 / (double)N;
@@ -1282,10 +1307,8 @@ int ode_cg_run(fracsolve_ctx *h, double gamma, int64_t N, const double *f, doubl
     hs.fn = fn;
     hs.maxit = o.max_iters;
     hs.done = (o.max_iters <= 0 || std::sqrt(rr) <= o.rtol * fn) ? 1 : 0;
-    CgState *ds = nullptr;
-    double *dh = nullptr;
-    if ((rc = dalloc(h, &ds, 1))) return rc;
-    if (hist_cap > 1 && (rc = dalloc(h, &dh, (size_t)hist_cap))) return rc;
+    CgState *ds = bufs.ds;
+    double *dh = hist_cap > 1 ? bufs.dh : nullptr;
     HIPCHK(h, hipMemcpyAsync(ds, &hs, sizeof hs, hipMemcpyHostToDevice, h->st));
     HIPCHK(h, hipStreamSynchronize(h->st));
     const int32_t *skip = &ds->done;
@@ -1319,8 +1342,7 @@ int ode_cg_run(fracsolve_ctx *h, double gamma, int64_t N, const double *f, doubl
             if (st) hipStreamDestroy(st);
         }
     } og;
-    const char *genv = getenv("FRACSOLVE_ODE_GRAPH");
-    if (!hs.done && w.L <= (int64_t(1) << 19) && !(genv && genv[0] == '0')) {
+    if (!hs.done && w.L <= (int64_t(1) << 19) && allow_graph) {
         HIPCHK(h, hipStreamCreateWithFlags(&og.st, hipStreamNonBlocking));
         hipGraph_t graph = nullptr;
         HIPCHK(h, hipStreamBeginCapture(og.st, hipStreamCaptureModeThreadLocal));
@@ -1370,6 +1392,63 @@ int ode_cg_run(fracsolve_ctx *h, double gamma, int64_t N, const double *f, doubl
     return FRACSOLVE_OK;
 }
 
+// Argument checks shared by the two Scheme 1 entry points (before any
+// device work); *o receives the options with their defaults.
+int ode_check_args(double gamma, int64_t N, const double *f, const double *u, const fracsolve_cg_options *opts,
+                   const double *hist, int32_t hist_cap, fracsolve_cg_options *o)
+{
+    if (!(gamma > 0.0 && gamma < 1.0))
+        return fail(nullptr, FRACSOLVE_E_ARG, "gamma must lie in (0,1) for the two-sided ODE, got %g", gamma);
+    if (N < 3 || N - 1 > (1LL << 22))
+        return fail(nullptr, FRACSOLVE_E_ARG, "N must lie in [3, 2^22 + 1], got %lld", (long long)N);
+    if (!f || !u) return fail(nullptr, FRACSOLVE_E_ARG, "f and u must not be NULL");
+    *o = fracsolve_cg_options{10000, 1e-10, 0};
+    if (opts) *o = *opts;
+    if (o->max_iters < 0) return fail(nullptr, FRACSOLVE_E_ARG, "max_iters must be >= 0, got %d", (int)o->max_iters);
+    if (!(o->rtol >= 0.0) || !std::isfinite(o->rtol))
+        return fail(nullptr, FRACSOLVE_E_ARG, "rtol must be finite and >= 0, got %g", o->rtol);
+    if (o->use_guess < 0 || o->use_guess > 1)
+        return fail(nullptr, FRACSOLVE_E_ARG, "use_guess must be 0 or 1, got %d", (int)o->use_guess);
+    if (hist_cap < 0 || (hist_cap > 0 && !hist))
+        return fail(nullptr, FRACSOLVE_E_ARG, "hist is NULL with hist_cap %d", (int)hist_cap);
+    return FRACSOLVE_OK;
+}
+
+// Fixed workspace of fracsolve_ode_cg_noalloc: one copy per device, held for
+// the life of the process.  Its host-side name is not a device address; the
+// device address comes from hipGetSymbolAddress, taken once per device with
+// that device current, and is the only way host code refers to the array.
+constexpr size_t kOdeScratchBytes = size_t(64) << 20;
+
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kOdeScratchBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char *g_scratch_ptr[kMaxDevices] = {};
+
+int ode_scratch(char **out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail(nullptr, FRACSOLVE_E_DEVICE, "hipGetDevice failed: %s", hipGetErrorString(e));
+    if (dev < 0 || dev >= kMaxDevices) return fail(nullptr, FRACSOLVE_E_DEVICE, "device index %d out of range", dev);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(nullptr, FRACSOLVE_E_DEVICE, "hipGetSymbolAddress of the fixed workspace failed: %s",
+                        hipGetErrorString(e));
+        g_scratch_ptr[dev] = (char *)p;
+    }
+    *out = g_scratch_ptr[dev];
+    return FRACSOLVE_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1377,25 +1456,14 @@ extern "C" {
 int fracsolve_ode_cg(double gamma, int64_t N, const double *f, double *u, const fracsolve_cg_options *opts,
                      fracsolve_cg_info *info, double *hist, int32_t hist_cap, void *stream)
 {
-    if (!(gamma > 0.0 && gamma < 1.0))
-        return fail(nullptr, FRACSOLVE_E_ARG, "gamma must lie in (0,1) for the two-sided ODE, got %g", gamma);
-    if (N < 3 || N - 1 > (1LL << 22))
-        return fail(nullptr, FRACSOLVE_E_ARG, "N must lie in [3, 2^22 + 1], got %lld", (long long)N);
-    if (!f || !u) return fail(nullptr, FRACSOLVE_E_ARG, "f and u must not be NULL");
-    fracsolve_cg_options o{10000, 1e-10, 0};
-    if (opts) o = *opts;
-    if (o.max_iters < 0) return fail(nullptr, FRACSOLVE_E_ARG, "max_iters must be >= 0, got %d", (int)o.max_iters);
-    if (!(o.rtol >= 0.0) || !std::isfinite(o.rtol))
-        return fail(nullptr, FRACSOLVE_E_ARG, "rtol must be finite and >= 0, got %g", o.rtol);
-    if (o.use_guess < 0 || o.use_guess > 1)
-        return fail(nullptr, FRACSOLVE_E_ARG, "use_guess must be 0 or 1, got %d", (int)o.use_guess);
-    if (hist_cap < 0 || (hist_cap > 0 && !hist))
-        return fail(nullptr, FRACSOLVE_E_ARG, "hist is NULL with hist_cap %d", (int)hist_cap);
+    fracsolve_cg_options o{};
+    int rc = ode_check_args(gamma, N, f, u, opts, hist, hist_cap, &o);
+    if (rc) return rc;
     fracsolve_problem p{gamma, 1.0, 0.0, 1.0, 1, 1};
     fracsolve_options ho{};
     ho.stream = stream;
     fracsolve_t h = nullptr;
-    int rc = fracsolve_create(&p, 1, &ho, &h);
+    rc = fracsolve_create(&p, 1, &ho, &h);
     if (rc) return rc;
     rc = ode_cg_run(h, gamma, N, f, u, o, info, hist, hist_cap);
     if (rc) g_create_error = h->err;
@@ -1403,6 +1471,53 @@ int fracsolve_ode_cg(double gamma, int64_t N, const double *f, double *u, const 
     return rc;
 }
 
+int fracsolve_ode_cg_noalloc(double gamma, int64_t N, const double *f, double *u, const fracsolve_cg_options *opts,
+                             fracsolve_cg_info *info, double *hist, int32_t hist_cap, void *stream)
+{
+    fracsolve_cg_options o{};
+    int rc = ode_check_args(gamma, N, f, u, opts, hist, hist_cap, &o);
+    if (rc) return rc;
+    if (N > FRACSOLVE_ODE_NOALLOC_MAX_N)
+        return fail(nullptr, FRACSOLVE_E_ARG, "N = %lld exceeds the fixed workspace of the no-allocation entry point "
+                    "(N <= %lld)", (long long)N, (long long)FRACSOLVE_ODE_NOALLOC_MAX_N);
+    if (hist_cap > FRACSOLVE_ODE_NOALLOC_MAX_HIST)
+        return fail(nullptr, FRACSOLVE_E_ARG, "hist_cap %d exceeds the fixed history of the no-allocation entry point "
+                    "(%d)", (int)hist_cap, (int)FRACSOLVE_ODE_NOALLOC_MAX_HIST);
+    char *base = nullptr;
+    if ((rc = ode_scratch(&base))) return rc;
+    const int64_t n = N - 1;
+    OdeBuffers b{};
+    b.w.L = circ_length(n);
+    size_t off = 0;
+    auto take = [&](size_t bytes) -> char * {
+        char *q = base + off;
+        off += (bytes + 255) & ~(size_t)255;
+        return q;
+    };
+    b.w.r = (double *)take(sizeof(double) * (size_t)n);
+    b.w.p = (double *)take(sizeof(double) * (size_t)n);
+    b.w.Ap = (double *)take(sizeof(double) * (size_t)n);
+    b.a = (double *)take(sizeof(double) * (size_t)n);
+    b.w.S = (double *)take(sizeof(double) * (size_t)b.w.L);
+    b.w.za = (double *)take(2 * sizeof(double) * (size_t)b.w.L);
+    b.w.zb = (double *)take(2 * sizeof(double) * (size_t)b.w.L);
+    b.w.pap = (double *)take(sizeof(double) * (size_t)circ_dot_parts(b.w.L));
+    b.ds = (CgState *)take(sizeof(CgState));
+    b.dh = (double *)take(sizeof(double) * (size_t)FRACSOLVE_ODE_NOALLOC_MAX_HIST);
+    double *partial = (double *)take(sizeof(double) * kRedBlocks);
+    if (off > kOdeScratchBytes)
+        return fail(nullptr, FRACSOLVE_E_ARG, "workspace of %zu bytes exceeds the fixed array (%zu bytes)", off,
+                    (size_t)kOdeScratchBytes);
+    // a context without allocations: the stream, the reduction partials in
+    // the fixed array and the error text; every buffer comes from the array
+    // and the steps are launched directly (no captured graph)
+    fracsolve_ctx ctx;
+    ctx.st = (hipStream_t)stream;
+    ctx.partial = partial;
+    rc = ode_cg_core(&ctx, gamma, N, f, u, o, info, hist, hist_cap, b, false);
+    if (rc) g_create_error = ctx.err;
+    return rc;
+}
 int fracsolve_create(const fracsolve_problem *probs, int32_t count, const fracsolve_options *opts, fracsolve_t *out)
 {
     if (!out) return fail(nullptr, FRACSOLVE_E_ARG, "out is NULL");

@@ -185,3 +185,21 @@ def test_ode_cg_valid_arguments_without_gpu_report_no_device(lib):
         pytest.skip("a GPU is present")
     rc, msg = ode_cg(lib, 0.5, 2 ** 22 + 1)
     assert rc == E_DEVICE, (rc, msg)
+
+
+@pytest.mark.parametrize("gamma, N, hist_cap, pattern", [
+    (1.5, 1025, 0, "gamma"),
+    (0.5, 2 ** 19 + 2, 0, "fixed workspace"),
+    (0.5, 2 ** 22 + 1, 0, "fixed workspace"),
+    (0.5, 1025, 65537, "fixed history"),
+])
+def test_ode_cg_noalloc_rejects_sizes_beyond_its_workspace(lib, gamma, N, hist_cap, pattern):
+    # checked on the host before the fixed array's address is taken
+    hist = (ctypes.c_double * max(hist_cap, 1))()
+    fn = lib.fracsolve_ode_cg_noalloc
+    fn.restype = ctypes.c_int
+    rc = fn(ctypes.c_double(gamma), ctypes.c_int64(N), ctypes.c_void_p(1), ctypes.c_void_p(2), None, None,
+            hist if hist_cap else None, ctypes.c_int32(hist_cap), None)
+    msg = lib.fracsolve_last_error(None).decode()
+    assert rc == E_ARG, (rc, msg)
+    assert pattern in msg, msg
