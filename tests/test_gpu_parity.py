@@ -93,6 +93,20 @@ def test_weights_vs_oracle(torch_cuda, orc, gamma):
     for k in ("da", "drho", "dpsi"):
         sc = np.max(np.abs(o[k])) + 1e-300
         assert np.max(np.abs(w[k] - o[k])) <= 1e-12 * sc, k
+    # each a_m to a few ulp of itself against 40-digit decimal (the
+    # diffusion-wave recurrence turns a relative weight error of 1e-16 into
+    # about 1e-12 on the solution at N = 8192, so the weights must not lose
+    # bits to cancellation)
+    from tests import ext_reference
+
+    a_dec, rho_dec, psi_dec = ext_reference.weights(gamma, N)
+    rel = np.abs((np.asarray(w["a"], dtype=np.longdouble) - a_dec) / a_dec)
+    assert float(np.max(rel)) <= 16 * eps, (int(np.argmax(rel)), float(np.max(rel)))
+    for k, ref in (("rho", rho_dec), ("psi", psi_dec)):
+        ref = np.asarray(ref, dtype=np.longdouble)
+        nz = ref != 0
+        if np.any(nz):
+            assert float(np.max(np.abs((w[k][nz] - ref[nz]) / ref[nz]))) <= 16 * eps, k
 
 
 @pytest.mark.parametrize("leaf_solver", [0, 1])
