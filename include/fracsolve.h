@@ -115,10 +115,10 @@ typedef struct {
     int32_t refine_steps; /* iterative-refinement steps against the float64
                              operator for FP32 / BF16X3 (0 = none; FP64 ignores
                              it)                                               */
-    int32_t leaf;         /* leaf size L (4, 8 or 16); 0 = default             */
+    int32_t leaf;         /* leaf size L (4, 8 or 16); 0 = tuned plan          */
     int32_t crossover;    /* largest half-block size s done as a dense product;
-                             FFT above it.  0 = tuned default, < 0 = FFT at
-                             every level                                       */
+                             FFT above it.  0 = tuned plan (fracsolve_plan),
+                             < 0 = FFT at every level                          */
     int32_t leaf_solver;  /* tridiagonal solve of a_0 I + K in the leaves:
                              0 = closed-form inverse by parallel scan (default),
                              1 = block Thomas + parallel cyclic reduction      */
@@ -143,6 +143,25 @@ typedef struct {
  */
 int fracsolve_create(const fracsolve_problem *probs, int32_t count,
                      const fracsolve_options *opts, fracsolve_t *out);
+
+/*
+ * The plan fracsolve_create would choose for these problems and options: the
+ * leaf size L and the crossover s* (largest half-block size done as a dense
+ * product; -1 = FFT at every level).  Options leaf / crossover > 0 (or
+ * crossover < 0) are taken as given; zeros are looked up, first in the plan
+ * cache written by the tuner (paper_1710_11593_amd/tune.py: a JSON file at
+ * $FRACSOLVE_TUNE_CACHE, else $XDG_CACHE_HOME/fracsolve/plan.json, else
+ * ~/.cache/fracsolve/plan.json; not read when FRACSOLVE_TUNE=0), then in the
+ * library's built-in table.  A missing,
+ * unreadable or malformed cache file falls back to the built-in table.
+ * *source (any output may be NULL) tells which: FRACSOLVE_PLAN_OPTIONS,
+ * FRACSOLVE_PLAN_CACHE or FRACSOLVE_PLAN_BUILTIN.  Host only: no device is
+ * needed.  Errors: E_ARG (as fracsolve_create's problem checks).
+ */
+enum { FRACSOLVE_PLAN_OPTIONS = 0, FRACSOLVE_PLAN_CACHE = 1, FRACSOLVE_PLAN_BUILTIN = 2 };
+
+int fracsolve_plan(const fracsolve_problem *probs, int32_t count, const fracsolve_options *opts,
+                   int32_t *leaf, int32_t *crossover, int32_t *source);
 
 /*
  * Copy instance `inst`'s weights to host arrays of length N (any may be NULL):

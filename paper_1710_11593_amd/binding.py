@@ -65,7 +65,7 @@ class CgInfo(ctypes.Structure):
 KIND_NAMES = {0: "leaf", 1: "dense_f64", 2: "dense_f32", 3: "fft_f64", 4: "fft_f32", 5: "fft_corner"}
 
 EXPORTS = ["fracsolve_create", "fracsolve_weights", "fracsolve_solve", "fracsolve_apply", "fracsolve_adjoint",
-           "fracsolve_gmres", "fracsolve_ode_cg", "fracsolve_ode_cg_noalloc", "fracsolve_set_timing", "fracsolve_get_stats", "fracsolve_kernel_stats", "fracsolve_destroy",
+           "fracsolve_gmres", "fracsolve_ode_cg", "fracsolve_ode_cg_noalloc", "fracsolve_plan", "fracsolve_set_timing", "fracsolve_get_stats", "fracsolve_kernel_stats", "fracsolve_destroy",
            "fracsolve_last_error"]
 
 _lib = None
@@ -105,6 +105,10 @@ def lib():
     L.fracsolve_ode_cg.argtypes = [ctypes.c_double, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
                                    ctypes.POINTER(CgOptions), ctypes.POINTER(CgInfo), dp, ctypes.c_int32,
                                    ctypes.c_void_p]
+    L.fracsolve_plan.restype = ctypes.c_int
+    L.fracsolve_plan.argtypes = [ctypes.POINTER(Problem), ctypes.c_int32, ctypes.POINTER(Options),
+                                 ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                                 ctypes.POINTER(ctypes.c_int32)]
     L.fracsolve_ode_cg_noalloc.restype = ctypes.c_int
     L.fracsolve_ode_cg_noalloc.argtypes = L.fracsolve_ode_cg.argtypes
     L.fracsolve_set_timing.restype = ctypes.c_int
@@ -139,6 +143,32 @@ def _ptrs(tensors, required=True, name="field"):
     return ctypes.cast(arr, ctypes.POINTER(ctypes.c_void_p))
 
 
+PLAN_SOURCE = {0: "options", 1: "cache", 2: "builtin"}
+
+
+def _problems(problems):
+    arr = (Problem * len(problems))()
+    for k, p in enumerate(problems):
+        arr[k] = Problem(float(p["gamma"]), float(p.get("T", 1.0)), float(p.get("x0", 0.0)),
+                         float(p.get("x1", 1.0)), int(p["M"]), int(p["N"]))
+    return arr
+
+
+def plan(problems: Sequence[dict], precision="fp64", leaf=0, crossover=0, leaf_solver=0, equation="diffusion"):
+    """(leaf, crossover, source) that fracsolve_create would choose
+    (fracsolve_plan; host only, no device needed)."""
+    L = lib()
+    opts = Options(PRECISION[precision] if isinstance(precision, str) else int(precision), 0, int(leaf),
+                   int(crossover), int(leaf_solver), None,
+                   EQUATION[equation] if isinstance(equation, str) else int(equation))
+    lf, cr, src = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    rc = L.fracsolve_plan(_problems(problems), len(problems), ctypes.byref(opts), ctypes.byref(lf), ctypes.byref(cr),
+                          ctypes.byref(src))
+    if rc != FRACSOLVE_OK:
+        raise FracsolveError(rc, L.fracsolve_last_error(None).decode())
+    return lf.value, cr.value, PLAN_SOURCE.get(src.value, src.value)
+
+
 class Solver:
     """One handle over `len(problems)` instances (see fracsolve_create)."""
 
@@ -147,10 +177,7 @@ class Solver:
         L = lib()
         self._lib = L
         self.problems = [dict(p) for p in problems]
-        arr = (Problem * len(problems))()
-        for k, p in enumerate(problems):
-            arr[k] = Problem(float(p["gamma"]), float(p.get("T", 1.0)), float(p.get("x0", 0.0)),
-                             float(p.get("x1", 1.0)), int(p["M"]), int(p["N"]))
+        arr = _problems(problems)
         if stream is None:
             import torch
 
@@ -342,6 +369,7 @@ def _make_function():
             f = f.contiguous()
             u = s.solve([f], [u0] if u0 is not None else None, [phi] if phi is not None else None)[0]
             ctx.solver = s
+            ctx.gamma_device = gamma.device if isinstance(gamma, torch.Tensor) else None
             ctx.save_for_backward(u, u0 if u0 is not None else None, phi if phi is not None else None)
             ctx.has = (u0 is not None, phi is not None)
             return u
@@ -352,7 +380,9 @@ def _make_function():
             s = ctx.solver
             g = grad_u.contiguous()
             lam, dg = s.adjoint([g], [u], [u0] if ctx.has[0] else None, [phi] if ctx.has[1] else None)
-            dgamma = torch.tensor(dg[0], dtype=torch.float64, device=grad_u.device)
+            dgamma = None
+            if ctx.gamma_device is not None:
+                dgamma = torch.tensor(dg[0], dtype=torch.float64, device=ctx.gamma_device)
             return lam[0], dgamma, None, None, None, None, None
 
     return FracSolve

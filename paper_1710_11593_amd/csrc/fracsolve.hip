@@ -21,6 +21,7 @@
 
 #include "../../include/fracsolve.h"
 #include "common.hpp"
+#include "plan.hpp"
 
 using namespace fs;
 
@@ -142,6 +143,7 @@ struct fracsolve_ctx {
     double *zeros = nullptr;
     double *gpart = nullptr, *gdots = nullptr;
     int gcap = 0;
+    int plan_source = 0;  // where L and the crossover came from (FRACSOLVE_PLAN_*)
 };
 
 namespace {
@@ -789,6 +791,27 @@ int finish_max(fracsolve_ctx *h, int nb, double *out)
 }
 
 constexpr int kRedBlocks = 1024;
+
+// Leaf size and crossover of a handle: options, plan cache or built-in table
+// (plan.hip).  A looked-up leaf size the leaf kernels cannot take for some
+// instance (L = 16 needs at most two rows per leaf thread, and the advection
+// leaf at most 8) falls back to 8.
+Plan plan_for(const fracsolve_problem *probs, int32_t count, const fracsolve_options &o)
+{
+    int64_t mmax = 0;
+    for (int k = 0; k < count; ++k) mmax = std::max<int64_t>(mmax, probs[k].M);
+    Plan pl = resolve_plan(o.precision, o.equation, mmax, o.leaf, o.crossover);
+    if (o.leaf == 0 && pl.leaf > 8) {
+        bool ok = o.equation != FRACSOLVE_ADVECTION;
+        for (int k = 0; k < count && ok; ++k) {
+            const bool scan = o.leaf_solver == 0;
+            const LeafCfg lc = scan ? scan_config(count > 1 ? mmax : probs[k].M, count > 1) : leaf_config(probs[k].M);
+            if ((scan && lc.pt > 2) || (!scan && lc.pt == 16)) ok = false;
+        }
+        if (!ok) pl.leaf = 8;
+    }
+    return pl;
+}
 
 int validate_problem(const fracsolve_problem &p, int k)
 {
@@ -1577,9 +1600,13 @@ int fracsolve_create(const fracsolve_problem *probs, int32_t count, const fracso
         delete h;
         return fail(nullptr, FRACSOLVE_E_DEVICE, "hipGetDevice failed");
     }
-    h->L = o.leaf ? o.leaf : 8;
-    // dense products are limited to s <= 1024 (k_gemm.hip)
-    h->crossover = (o.crossover > 0) ? std::min(o.crossover, 1024) : (o.crossover < 0 ? 0 : 64);
+    {
+        const Plan pl = plan_for(probs, count, o);
+        h->L = pl.leaf;
+        // dense products are limited to s <= 1024 (k_gemm.hip)
+        h->crossover = (pl.crossover > 0) ? std::min(pl.crossover, 1024) : 0;
+        h->plan_source = pl.source;
+    }
     {
         const char *pv = getenv("FRACSOLVE_PAIR");
         h->pair = !(pv && pv[0] == '0') && o.leaf_solver == 0 && h->L <= 8 && h->L <= h->crossover;
@@ -1645,6 +1672,26 @@ int fracsolve_create(const fracsolve_problem *probs, int32_t count, const fracso
     h->stats.crossover = h->crossover;
     h->stats.levels = ilog2i(h->inst[0].Np / h->L);
     *out = h;
+    return FRACSOLVE_OK;
+}
+
+int fracsolve_plan(const fracsolve_problem *probs, int32_t count, const fracsolve_options *opts, int32_t *leaf,
+                   int32_t *crossover, int32_t *source)
+{
+    if (!probs) return fail(nullptr, FRACSOLVE_E_ARG, "probs is NULL");
+    if (count < 1) return fail(nullptr, FRACSOLVE_E_ARG, "count must be >= 1, got %d", (int)count);
+    for (int k = 0; k < count; ++k) {
+        int rc = validate_problem(probs[k], k);
+        if (rc) return rc;
+    }
+    fracsolve_options o{};
+    if (opts) o = *opts;
+    if (o.leaf != 0 && o.leaf != 4 && o.leaf != 8 && o.leaf != 16)
+        return fail(nullptr, FRACSOLVE_E_ARG, "leaf must be 0, 4, 8 or 16, got %d", (int)o.leaf);
+    const Plan pl = plan_for(probs, count, o);
+    if (leaf) *leaf = pl.leaf;
+    if (crossover) *crossover = pl.crossover > 0 ? std::min(pl.crossover, 1024) : -1;
+    if (source) *source = pl.source;
     return FRACSOLVE_OK;
 }
 
