@@ -10,11 +10,12 @@ second over the timed steps.  The error is checked against the oracle
 through single-mode reduction (every source mode's discrete solution is
 v_j^n sin(j pi x_i), with v_j from the oracle's scalar recurrence).
 
-roofline: the largest single-pass FFT level kernel (the HBM-bound part of
-the path), timed live with HIP events around each launch on the solver's
-stream during one extra solve; achieved = its algorithmic bytes (24 B per
-X-row entry: read X, read and write Y) / its time, against the 8 TB/s HBM
-peak.  critical_path: the sequential chain of leaf solves (one workgroup
+roofline: the FFT level products (the HBM-bound part of the path), every
+level, single-pass and multi-pass, timed live with HIP events around each
+launch on the solver's stream during one extra solve; achieved = their
+algorithmic bytes (24 B per X-row entry: read X, read and write Y) / their
+summed time, against the 8 TB/s HBM peak, with each level's own figure and
+the worst level listed.  critical_path: the sequential chain of leaf solves (one workgroup
 per launch, two leaves per launch where they run in pairs), which sets most
 of the solve time.
 forms (unless --no-forms): mixed precision and the variant with the spatial
@@ -77,6 +78,46 @@ def recorded_traffic(kernel: str, M: int):
         if m and m.group(1) == kernel and m.group(4) == sha:
             return float(m.group(3))
     return None
+
+
+def fft_roofline(ks, prec, M):
+    """Roofline of the FFT level products (the HBM-bound part of the path):
+    every FFT level of the solve, single-pass and multi-pass, from the
+    per-launch event times of one solve.  achieved = their algorithmic bytes
+    (24 B per X-row entry and launch: read X, read and write Y) / their summed
+    time, against the 8 TB/s HBM peak; the near-corner band launches that
+    complete the single-pass levels count in the time.  levels lists each
+    level's own figure; worst names the slowest."""
+    fft_kind = "fft_f64" if prec == "fp64" else "fft_f32"
+    lv = [g for g in ks if g["kind"] == fft_kind and g["ms"] > 0]
+    if not lv:
+        return None
+    corner = {g["s"]: g for g in ks if g["kind"] == "fft_corner"}
+    levels = []
+    for g in sorted(lv, key=lambda r: r["s"]):
+        ms = g["ms"] + (corner[g["s"]]["ms"] if g["s"] in corner else 0.0)
+        levels.append({"s": g["s"], "launches": g["launches"], "ms": round(ms, 4),
+                       "GBps": round(g["bytes"] / (ms * 1e-3) / 1e9, 1),
+                       "frac": round(g["bytes"] / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)})
+    tot_b = sum(g["bytes"] for g in lv)
+    tot_ms = sum(l["ms"] for l in levels)
+    achieved = tot_b / (tot_ms * 1e-3) / 1e9
+    worst = min(levels, key=lambda l: l["frac"])
+    big = max(lv, key=lambda r: r["s"])
+    kname = ("fs::" + FFT64_NAMES[2 * big["s"]]) if (prec == "fp64" and 2 * big["s"] in FFT64_NAMES) else None
+    traffic = None
+    if prec == "fp64":
+        # recorded HBM bytes of every level over their algorithmic bytes
+        rec = [(recorded_traffic(("fs::" + FFT64_NAMES[2 * g["s"]]) if 2 * g["s"] in FFT64_NAMES else
+                                 "multipass s=%d" % g["s"], M), g) for g in lv]
+        if rec and all(r is not None for r, _ in rec):
+            traffic = sum(r * g["launches"] for r, g in rec)
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "kernel": "FFT level products, all levels (s = %d .. %d), time-weighted" % (levels[0]["s"],
+                                                                                      levels[-1]["s"]),
+            "algorithmic_bytes": tot_b, "ms": round(tot_ms, 3), "worst_level": worst, "levels": levels,
+            "largest_single_pass_kernel": kname}
 
 
 def build_instance(args):
@@ -498,17 +539,9 @@ def run_batched(args, dev):
     groups = sorted(ks, key=lambda r: -r["ms"])
     for g in groups[:12]:
         log("  %-10s s=%-6d launches=%-6d tasks=%-7d %9.3f ms" % (g["kind"], g["s"], g["launches"], g["tasks"], g["ms"]))
-    fft_kind = "fft_f64" if prec == "fp64" else "fft_f32"
-    single = [g for g in ks if g["kind"] == fft_kind and 2 * g["s"] <= (8192 if prec == "fp64" else 16384)]
-    roof = None
-    if single:
-        dom = max(single, key=lambda r: r["s"])
-        per_ms = dom["ms"] / dom["launches"]
-        ach = dom["bytes"] / dom["launches"] / (per_ms * 1e-3) / 1e9
-        roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "%s s=%d (batched)" % (fft_kind, dom["s"]),
-                "level_s": dom["s"], "launches": dom["launches"], "avg_us": round(per_ms * 1e3, 2),
-                "bytes_per_launch": dom["bytes"] / dom["launches"]}
+    roof = fft_roofline(ks, prec, 0)
+    if roof:
+        roof["kernel"] += " (batched, all 256 instances)"
     line = {
         "metric": METRIC, "value": mn / (ms * 1e-3), "unit": "unknowns/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
@@ -655,25 +688,7 @@ def main():
     for g in groups[:12]:
         log("  %-10s s=%-6d launches=%-6d %9.3f ms  %8.1f GB/s" % (
             g["kind"], g["s"], g["launches"], g["ms"], g["bytes"] / (g["ms"] * 1e-3) / 1e9 if g["ms"] else 0))
-    fft_kind = "fft_f64" if prec == "fp64" else "fft_f32"
-    single = [g for g in ks if g["kind"] == fft_kind and 2 * g["s"] <= (8192 if prec == "fp64" else 16384)]
-    roof = None
-    if single:
-        # every level moves the same algorithmic bytes (12 B per unknown);
-        # the largest single-pass transform is the one whose efficiency
-        # carries over to larger problems, and its launches are long enough
-        # for per-launch event timing to match the kernel trace
-        dom = max(single, key=lambda r: r["s"])
-        per_launch_ms = dom["ms"] / dom["launches"]
-        per_launch_bytes = dom["bytes"] / dom["launches"]
-        achieved = per_launch_bytes / (per_launch_ms * 1e-3) / 1e9
-        kname = ("fs::" + FFT64_NAMES[2 * dom["s"]]) if (prec == "fp64" and 2 * dom["s"] in FFT64_NAMES) \
-            else "fft_f32 s=%d" % dom["s"]
-        traffic = recorded_traffic(kname, M) if prec == "fp64" else None
-        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": kname, "level_s": dom["s"], "launches": dom["launches"],
-                "avg_us": round(per_launch_ms * 1e3, 2), "bytes_per_launch": per_launch_bytes}
+    roof = fft_roofline(ks, prec, M)
     leaf = [g for g in ks if g["kind"] == "leaf"]
     leaf_ms = sum(g["ms"] for g in leaf)
     leaf_launches = sum(g["launches"] for g in leaf)

@@ -12,7 +12,9 @@
 // two first-order recurrences with the common multiplier rho <= 1.
 // theta = log1p(d + sqrt(d (2 + d))), d = a_0 / (2 e), keeps a_0 exact even
 // when it is tiny next to 2 e, where forming the diagonal a_0 + 2 e in
-// float64 would round a_0 away.
+// float64 would round a_0 away; when a_0 >> e instead, K0 and rho are formed
+// from d and sinh(theta) = sqrt(d (2 + d)) without theta (whose absolute
+// rounding grows with theta).
 //
 // Work split.  Thread t owns the PT consecutive rows c0+1 .. c0+PT
 // (c0 = t PT).  Per time step it forms the local prefix l_k and suffix s_k
@@ -58,16 +60,41 @@ __global__ __launch_bounds__(NT) void k_scan_factor(int64_t M, double a0, double
 {
     constexpr int MP = NT * PT;
     const double dlt = a0 / (2.0 * e);
-    const double th = log1p(dlt + sqrt(dlt * (2.0 + dlt)));
+    const double sh = sqrt(dlt * (2.0 + dlt));  // sinh(theta)
+    const double th = log1p(dlt + sh);
     const int t = threadIdx.x;
-    const double K0 = 1.0 / (e * 2.0 * sinh(th) * -expm1(-2.0 * (double)(M + 1) * th));
+    // 1/rho - rho = 2 sinh(theta) from sh itself: through theta it would
+    // carry theta's absolute rounding (about theta ulp), a systematic error
+    // of every leaf solve that the diffusion-wave recurrence amplifies when
+    // a_0 >> e (theta of 10 or more)
+    const double K0 = 1.0 / (e * 2.0 * sh * -expm1(-2.0 * (double)(M + 1) * th));
     const double sk = sqrt(K0);
     if (t == 0) {
         tab[0] = K0;
         tab[2] = e;  // the coefficient of tridiag(-1, 2, -1) in the block
-        tab[1] = exp(-th);
-        for (int s = 0; s < 16; ++s) tab[8 + s] = exp(-(double)PT * (double)(1 << s) * th);
-        for (int k = 0; k < 16; ++k) tab[SCAN_TAB_POW + k] = exp(-(double)(k + 1) * th);
+        if (th < 0.5) {
+            // small theta (a_0 << e): exp of the accurately known theta
+            tab[1] = exp(-th);
+            for (int s = 0; s < 16; ++s) tab[8 + s] = exp(-(double)PT * (double)(1 << s) * th);
+            for (int k = 0; k < 16; ++k) tab[SCAN_TAB_POW + k] = exp(-(double)(k + 1) * th);
+        } else {
+            // large theta: rho = 1 / (cosh + sinh) to a few ulp, its powers
+            // by products (rho^k <= e^{-k/2}: the higher ones only couple
+            // rows through factors far below the diagonal's)
+            const double rho = 1.0 / (1.0 + dlt + sh);
+            tab[1] = rho;
+            double pk = rho;
+            for (int k = 0; k < 16; ++k) {
+                tab[SCAN_TAB_POW + k] = pk;
+                pk *= rho;
+            }
+            double m = 1.0;
+            for (int k = 0; k < PT; ++k) m *= rho;
+            for (int s = 0; s < 16; ++s) {
+                tab[8 + s] = m;
+                m *= m;
+            }
+        }
     }
     for (int r = t; r < MP; r += NT) {
         double i = (double)(r + 1);

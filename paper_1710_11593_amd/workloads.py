@@ -148,14 +148,16 @@ def c4(seed: int = 4, count: int = 256):
 
 
 def c5(seed: int = 5, M: int = 1024, N: int = 32768, build: bool = True):
-    """Differentiation case, gamma = 0.6: (base instance, perturbation modes).
+    """Differentiation case, gamma = 0.6: (base instance, observation instance).
 
     The base source is the manufactured t^2 sin(pi x) term; the observation is
     the solution for the base source plus 0.1 xi_k t^(p_k) sin(j_k pi x) on 4
-    distinct modes j_k drawn from 9..32.
+    distinct modes: j_1 = 1 (the base's own mode, so that u - u_obs has a part
+    that the base solution's gamma-dependence meets and dL/dgamma is not zero
+    by orthogonality) and j_2..j_4 drawn from 2..32.
     """
     rng = np.random.default_rng(seed)
-    js = rng.choice(np.arange(9, 33), size=4, replace=False)
+    js = [1] + [int(j) for j in rng.choice(np.arange(2, 33), size=3, replace=False)]
     xi = rng.standard_normal(4)
     pows = rng.uniform(1.0, 3.0, 4)
     base = Instance(0.6, M, N, manufactured=True)

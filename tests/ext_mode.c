@@ -94,3 +94,58 @@ int ext_mode_cn(double gamma, double T, int64_t N, double lam, const double *g, 
 {
     return ext_mode_any(gamma, T, N, lam, g, v0, phihat, vout, 1);
 }
+
+/* The same recurrence in long double with the float64 weights given (a[m],
+ * rho[n-1], psi[n-1], m, n-1 < N): the exact solution of the system those
+ * float64 weights define, so that an implementation's solver rounding can be
+ * measured apart from the rounding of its weights. */
+int ext_mode_given(int64_t N, const double *a, const double *rho, const double *psi, double lam, const double *g,
+                   double v0, double phihat, double *vout, int cn)
+{
+    ld *v = malloc(sizeof(ld) * (size_t)N);
+    if (!v) return -2;
+    ld d0 = (ld)a[0] + (cn ? 0.5L : 1.0L) * (ld)lam;
+    for (int64_t n = 1; n <= N; ++n) {
+        ld s = (ld)g[n - 1] - (ld)rho[n - 1] * (ld)v0 + (ld)psi[n - 1] * (ld)phihat;
+        for (int64_t j = 1; j < n; ++j) s -= (ld)a[n - j] * v[j - 1];
+        if (cn) s -= 0.5L * (ld)lam * (n == 1 ? (ld)v0 : v[n - 2]);
+        v[n - 1] = s / d0;
+        vout[n - 1] = (double)v[n - 1];
+    }
+    free(v);
+    return 0;
+}
+
+/* Residual of a single-mode solution v (float64, as a solver returned it) of
+ * the system defined by the float64 weights given, in long double: for every
+ * step n
+ *   r^n = g^n - rho_n v0 + psi_n phihat - (a_0 + lam) v^n - sum_{m=1}^{n-1} a_m v^{n-m}
+ * (cn: lam/2 on v^n and on v^{n-1}, v^0 = v0) into rout[n-1], and the sum of
+ * the absolute values of the same terms into sout[n-1]. */
+int ext_mode_residual(int64_t N, const double *a, const double *rho, const double *psi, double lam, const double *g,
+                      double v0, double phihat, const double *v, int cn, double *rout, double *sout)
+{
+    const ld L = (ld)lam;
+    for (int64_t n = 1; n <= N; ++n) {
+        ld terms[4] = {(ld)g[n - 1], -(ld)rho[n - 1] * (ld)v0, (ld)psi[n - 1] * (ld)phihat,
+                       -((ld)a[0] + (cn ? 0.5L : 1.0L) * L) * (ld)v[n - 1]};
+        ld r = 0.0L, sc = 0.0L;
+        for (int k = 0; k < 4; ++k) {
+            r += terms[k];
+            sc += fabsl(terms[k]);
+        }
+        for (int64_t j = 1; j < n; ++j) {
+            const ld t = (ld)a[n - j] * (ld)v[j - 1];
+            r -= t;
+            sc += fabsl(t);
+        }
+        if (cn) {
+            const ld t = 0.5L * L * (n == 1 ? (ld)v0 : (ld)v[n - 2]);
+            r -= t;
+            sc += fabsl(t);
+        }
+        rout[n - 1] = (double)r;
+        sout[n - 1] = (double)sc;
+    }
+    return 0;
+}

@@ -120,8 +120,18 @@ def weights(gamma, N, T=1.0):
     return conv(a), conv(rho), conv(psi)
 
 
-def solve(gamma, M, N, F, u0=None, phi=None, T=1.0, x0=0.0, x1=1.0):
-    a, rho, psi = weights(gamma, N, T)
+def given_weights(w, N):
+    """(a, rho, psi) as long double arrays from float64 weights w (a dict or
+    triple of arrays of at least N entries)."""
+    if isinstance(w, dict):
+        w = (w["a"], w["rho"], w["psi"])
+    return tuple(np.asarray(x[:N], dtype=np.longdouble) for x in w)
+
+
+def solve(gamma, M, N, F, u0=None, phi=None, T=1.0, x0=0.0, x1=1.0, weights_given=None):
+    """Extended-precision stepping; weights_given: use these float64 weights
+    (the system they define) instead of the decimal ones."""
+    a, rho, psi = weights(gamma, N, T) if weights_given is None else given_weights(weights_given, N)
     h = (np.longdouble(x1) - np.longdouble(x0)) / np.longdouble(M + 1)
     e = 1 / (h * h)
     d = a[0] + 2 * e
@@ -154,10 +164,10 @@ def solve(gamma, M, N, F, u0=None, phi=None, T=1.0, x0=0.0, x1=1.0):
     return U
 
 
-def solve_adv(gamma, M, N, F, u0=None, phi=None, T=1.0, x0=0.0, x1=1.0):
+def solve_adv(gamma, M, N, F, u0=None, phi=None, T=1.0, x0=0.0, x1=1.0, weights_given=None):
     """The advection time stepping of the oracle (Scheme 2 for gamma < 1,
     Scheme 3 for gamma > 1; inflow value 0) in extended precision."""
-    a, rho, psi = weights(gamma, N, T)
+    a, rho, psi = weights(gamma, N, T) if weights_given is None else given_weights(weights_given, N)
     h = (np.longdouble(x1) - np.longdouble(x0)) / np.longdouble(M + 1)
     Fl = np.asarray(F, dtype=np.longdouble)
     u0l = np.zeros(M, dtype=np.longdouble) if u0 is None else np.asarray(u0, dtype=np.longdouble)
@@ -187,10 +197,10 @@ def solve_adv(gamma, M, N, F, u0=None, phi=None, T=1.0, x0=0.0, x1=1.0):
     return U
 
 
-def solve_cn(gamma, M, N, F, u0=None, phi=None, T=1.0, x0=0.0, x1=1.0):
+def solve_cn(gamma, M, N, F, u0=None, phi=None, T=1.0, x0=0.0, x1=1.0, weights_given=None):
     """The oracle's stepping of the diffusion-wave variant with the spatial
     term averaged over t_n and t_{n-1}, in extended precision."""
-    a, rho, psi = weights(gamma, N, T)
+    a, rho, psi = weights(gamma, N, T) if weights_given is None else given_weights(weights_given, N)
     h = (np.longdouble(x1) - np.longdouble(x0)) / np.longdouble(M + 1)
     e = 1 / (h * h)
     he = e / 2
@@ -228,9 +238,22 @@ def solve_cn(gamma, M, N, F, u0=None, phi=None, T=1.0, x0=0.0, x1=1.0):
     return U
 
 
+_lib_lock = __import__("threading").Lock()
+_lib = None
+
+
 def ext_mode_lib():
     """Build (gcc, into _build/) and load tests/ext_mode.c: ext_mode and
-    ext_mode_cn, the long double single-mode recurrences."""
+    ext_mode_cn, the long double single-mode recurrences (once per process;
+    safe to call from several threads)."""
+    global _lib
+    with _lib_lock:
+        if _lib is None:
+            _lib = _build_ext_mode()
+        return _lib
+
+
+def _build_ext_mode():
     here = os.path.dirname(os.path.abspath(__file__))
     out = os.path.join(os.path.dirname(here), "_build", "libext_mode.so")
     os.makedirs(os.path.dirname(out), exist_ok=True)
@@ -246,6 +269,12 @@ def ext_mode_lib():
         fn.restype = ctypes.c_int
         fn.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_int64, ctypes.c_double, dp,
                        ctypes.c_double, ctypes.c_double, dp]
+    lib.ext_mode_residual.restype = ctypes.c_int
+    lib.ext_mode_residual.argtypes = [ctypes.c_int64, dp, dp, dp, ctypes.c_double, dp, ctypes.c_double,
+                                      ctypes.c_double, dp, ctypes.c_int, dp, dp]
+    lib.ext_mode_given.restype = ctypes.c_int
+    lib.ext_mode_given.argtypes = [ctypes.c_int64, dp, dp, dp, ctypes.c_double, dp, ctypes.c_double,
+                                   ctypes.c_double, dp, ctypes.c_int]
     return lib
 
 
@@ -260,11 +289,165 @@ def mode(gamma, T, N, lam, g, v0=0.0, phihat=0.0, cn=False):
     return out
 
 
-def assert_within_floor(e, e_gpu, e_orc, tol):
-    """Parity where the float64 oracle misses tol: e is the GPU's distance to
-    the oracle, e_gpu and e_orc the GPU's and the oracle's distances to the
-    extended-precision solve.  The oracle must be close to that solve
-    (e_orc <= FLOOR_ORACLE_MAX: the reference is then not in doubt), and the
-    GPU at most twice as far from it as the oracle."""
+def mode_given(a, rho, psi, lam, g, v0=0.0, phihat=0.0, cn=False):
+    """Long double single-mode recurrence with the float64 weights given
+    (ext_mode_given): the exact solution of the system they define."""
+    lib = ext_mode_lib()
+    dp = ctypes.POINTER(ctypes.c_double)
+    arrs = [np.ascontiguousarray(x, dtype=np.float64) for x in (a, rho, psi, g)]
+    N = len(arrs[3])
+    assert all(len(x) >= N for x in arrs[:3])
+    out = np.zeros(N)
+    assert lib.ext_mode_given(N, *(x.ctypes.data_as(dp) for x in arrs[:3]), lam, arrs[3].ctypes.data_as(dp), v0,
+                              phihat, out.ctypes.data_as(dp), 1 if cn else 0) == 0
+    return out
+
+
+def mode_residual(a, rho, psi, lam, g, v, v0=0.0, phihat=0.0, cn=False):
+    """(r, scale): the long double residual of the single-mode solution v of
+    the system the float64 weights define, and per step the sum of the
+    absolute values of its terms (ext_mode_residual)."""
+    lib = ext_mode_lib()
+    dp = ctypes.POINTER(ctypes.c_double)
+    arrs = [np.ascontiguousarray(x, dtype=np.float64) for x in (a, rho, psi, g, v)]
+    N = len(arrs[3])
+    assert len(arrs[4]) == N and all(len(x) >= N for x in arrs[:3])
+    r, sc = np.zeros(N), np.zeros(N)
+    rc = lib.ext_mode_residual(N, arrs[0].ctypes.data_as(dp), arrs[1].ctypes.data_as(dp), arrs[2].ctypes.data_as(dp),
+                               lam, arrs[3].ctypes.data_as(dp), v0, phihat, arrs[4].ctypes.data_as(dp),
+                               1 if cn else 0, r.ctypes.data_as(dp), sc.ctypes.data_as(dp))
+    assert rc == 0
+    return r, sc
+
+
+def modal_backward(weights_given, M, N, series, v_by_mode, cn=False, x0=0.0, x1=1.0):
+    """Normwise backward error of a sum-of-sine-modes solution, from its modal
+    coefficients v_by_mode[j] (the field's projections): the residual of each
+    mode's scalar system, combined as max_n sum_j |r_j^n| / max_n sum_j
+    scale_j^n (|sin| <= 1 bounds the field's residual by the sum)."""
+    a, rho, psi = (weights_given["a"], weights_given["rho"], weights_given["psi"]) \
+        if isinstance(weights_given, dict) else weights_given
+    h = (x1 - x0) / (M + 1)
+    rsum, ssum = np.zeros(N), np.zeros(N)
+    for j, (g, v0, ph) in series.items():
+        lam = 4.0 / h ** 2 * math.sin(j * math.pi * h / 2) ** 2
+        r, sc = mode_residual(a, rho, psi, lam, g, np.asarray(v_by_mode[j], dtype=np.float64), v0, ph, cn)
+        rsum += np.abs(r)
+        ssum += sc
+    return float(np.max(rsum) / np.max(ssum))
+
+
+def modal_coefficients(u, js, chunk=2048):
+    """Sine coefficients of a field u [N][M] (float64 array, or a torch tensor
+    on any device) for the modes js, in long double:
+    v_j = 2/(M+1) sum_i u_i sin(j pi i/(M+1)) (discrete orthogonality of the
+    sine basis on the grid); rows are converted in chunks."""
+    N, M = u.shape
+    i = np.arange(1, M + 1, dtype=np.longdouble)
+    pi = np.longdouble("3.14159265358979323846264338327950288")
+    S = np.stack([np.sin(np.longdouble(j) * pi * i / np.longdouble(M + 1)) for j in js], axis=1)
+    out = np.zeros((N, len(js)), dtype=np.longdouble)
+    for r0 in range(0, N, chunk):
+        blk = u[r0:r0 + chunk]
+        blk = blk.cpu().numpy() if hasattr(blk, "cpu") else np.asarray(blk)
+        out[r0:r0 + chunk] = np.asarray(blk, dtype=np.longdouble) @ S
+    out *= 2 / np.longdouble(M + 1)
+    return [out[:, k] for k in range(len(js))]
+
+
+def backward(weights_given, M, N, F, U, u0=None, phi=None, kind="diffusion", x0=0.0, x1=1.0):
+    """Normwise backward error of a float64 solution U [N][M] of the block
+    system (kind "diffusion" or "cn") with the float64 weights given, in long
+    double: max over (n, i) of |r| divided by the max over (n, i) of the sum
+    of the absolute values of the terms of r (a bound of ||A|| ||U|| + ||b||
+    row by row; a per-entry ratio would weigh entries whose terms nearly
+    vanish)."""
+    a, rho, psi = given_weights(weights_given, N)
+    h = (np.longdouble(x1) - np.longdouble(x0)) / np.longdouble(M + 1)
+    e = 1 / (h * h)
+    Ul = np.asarray(U, dtype=np.longdouble)
+    Fl = np.asarray(F, dtype=np.longdouble)
+    u0l = np.zeros(M, dtype=np.longdouble) if u0 is None else np.asarray(u0, dtype=np.longdouble)
+    phil = np.zeros(M, dtype=np.longdouble) if phi is None else np.asarray(phi, dtype=np.longdouble)
+    cf = np.longdouble(0.5) if kind == "cn" else np.longdouble(1)
+
+    def Kabs(v):  # |e| (2|v_i| + |v_{i-1}| + |v_{i+1}|) and K v
+        z = np.zeros(1, dtype=np.longdouble)
+        left, right = np.concatenate((z, v[:-1])), np.concatenate((v[1:], z))
+        return e * (2 * v - left - right), e * (2 * np.abs(v) + np.abs(left) + np.abs(right))
+
+    rmax, smax = 0.0, 0.0
+    for n in range(N):
+        kv, ka = Kabs(Ul[n])
+        r = Fl[n] - rho[n] * u0l + psi[n] * phil - a[0] * Ul[n] - cf * kv
+        sc = np.abs(Fl[n]) + np.abs(rho[n] * u0l) + np.abs(psi[n] * phil) + np.abs(a[0] * Ul[n]) + cf * ka
+        if n:
+            hist = a[n:0:-1][:, None] * Ul[:n]
+            r -= hist.sum(axis=0)
+            sc += np.abs(hist).sum(axis=0)
+        if kind == "cn":
+            kp, kpa = Kabs(u0l if n == 0 else Ul[n - 1])
+            r -= cf * kp
+            sc += cf * kpa
+        rmax = max(rmax, float(np.max(np.abs(r))))
+        smax = max(smax, float(np.max(sc)))
+    return rmax / smax if smax > 0 else 0.0
+
+
+def backward_adv(weights_given, gamma, M, N, F, U, u0=None, phi=None, x0=0.0, x1=1.0):
+    """Normwise backward error (as backward()) of a float64 solution U of the
+    advection schemes (Scheme 2 for gamma < 1 in its twice-scaled row form,
+    Scheme 3 for gamma > 1; inflow value 0) with the float64 weights given,
+    in long double (the rows solve_adv steps through)."""
+    a, rho, psi = given_weights(weights_given, N)
+    h = (np.longdouble(x1) - np.longdouble(x0)) / np.longdouble(M + 1)
+    Ul = np.asarray(U, dtype=np.longdouble)
+    Fl = np.asarray(F, dtype=np.longdouble)
+    u0l = np.zeros(M, dtype=np.longdouble) if u0 is None else np.asarray(u0, dtype=np.longdouble)
+    phil = np.zeros(M, dtype=np.longdouble) if (phi is None or gamma < 1) else np.asarray(phi, dtype=np.longdouble)
+
+    def shift(v):  # v_{i-1}, with 0 at the inflow
+        return np.concatenate(([np.longdouble(0)], v[:-1]))
+
+    rmax, smax = 0.0, 0.0
+    for n in range(N):
+        if gamma < 1:
+            terms = [2 * Fl[n], -rho[n] * (u0l + shift(u0l)), -(a[0] + 2 / h) * Ul[n], -(a[0] - 2 / h) * shift(Ul[n])]
+            hist = a[n:0:-1][:, None] * (Ul[:n] + np.concatenate((np.zeros((n, 1), dtype=np.longdouble),
+                                                                  Ul[:n, :-1]), axis=1)) if n else None
+        else:
+            terms = [Fl[n], -rho[n] * u0l, psi[n] * phil, -(a[0] + 1 / h) * Ul[n], (1 / h) * shift(Ul[n])]
+            hist = a[n:0:-1][:, None] * Ul[:n] if n else None
+        r = sum(terms)
+        sc = sum(np.abs(t) for t in terms)
+        if hist is not None:
+            r = r - hist.sum(axis=0)
+            sc = sc + np.abs(hist).sum(axis=0)
+        rmax = max(rmax, float(np.max(np.abs(r))))
+        smax = max(smax, float(np.max(sc)))
+    return rmax / smax if smax > 0 else 0.0
+
+
+EPS = 2.0 ** -52
+FLOOR_FORWARD_MAX = 1e-8   # forward error allowed in the floor regime (both sides)
+BACKWARD_ULPS = 8          # backward error allowed there, in units of float64 roundoff
+
+
+def assert_floor_parity(e, e_gpu, e_orc, eta_gpu, eta_orc, tol):
+    """Parity where the float64 oracle itself misses tol against the exact
+    discrete solution.  e is the GPU's distance to the oracle; e_gpu, e_orc
+    the GPU's and the oracle's distances to the extended-precision solve;
+    eta_gpu, eta_orc their normwise backward errors (long double residuals of
+    the systems their own float64 weights define).  Required: the extended
+    solve agrees with the oracle (e_orc <= 1e-8: the reference is not in
+    doubt) and both forward errors stay <= 1e-8; and the GPU is at least as
+    close to the exact solution as the oracle up to a factor 2
+    (e_gpu <= max(tol, 2 e_orc)) or, where the problem is so ill-conditioned
+    that ulp-level rounding decides which of two float64 results lands
+    closer (the diffusion-wave recurrence with long histories), backward
+    stable like the oracle: eta_gpu <= max(BACKWARD_ULPS ulp, 2 eta_orc)."""
     assert e_orc <= FLOOR_ORACLE_MAX, ("oracle too far from the extended solve", e, e_gpu, e_orc)
-    assert e_gpu <= max(tol, 2.0 * e_orc), (e, e_gpu, e_orc)
+    assert e_gpu <= FLOOR_FORWARD_MAX, ("forward error", e, e_gpu, e_orc)
+    forward_ok = e_gpu <= max(tol, 2.0 * e_orc)
+    backward_ok = eta_gpu <= max(BACKWARD_ULPS * EPS, 2.0 * eta_orc)
+    assert forward_ok or backward_ok, ("forward and backward error", e_gpu, e_orc, eta_gpu / EPS, eta_orc / EPS)

@@ -326,11 +326,50 @@ def test_two_extended_references_agree():
 
 
 def test_floor_check_rejects_a_wrong_reference():
-    """assert_within_floor: the GPU within twice the oracle's distance to the
-    extended solve passes; a reference far from the oracle is refused even if
-    the GPU is close to the oracle."""
-    ext.assert_within_floor(3e-11, 2e-11, 1.5e-11, 1e-11)
+    """assert_floor_parity: passes with the GPU forward error within twice
+    the oracle's, or with its backward error within 8 ulp; refuses a
+    reference far from the oracle, a forward error above 1e-8, and a result
+    that fails both the forward and the backward condition."""
+    eps = ext.EPS
+    ext.assert_floor_parity(3e-11, 2e-11, 1.5e-11, 500 * eps, 0.5 * eps, 1e-11)   # forward
+    ext.assert_floor_parity(3e-11, 5e-11, 1.5e-11, 3 * eps, 0.5 * eps, 1e-11)     # backward
+    ext.assert_floor_parity(3e-11, 5e-11, 1.5e-11, 20 * eps, 12 * eps, 1e-11)
     with pytest.raises(AssertionError):
-        ext.assert_within_floor(3e-11, 4e-11, 1.5e-11, 1e-11)
+        ext.assert_floor_parity(3e-11, 0.5, 0.5, eps, eps, 1e-11)          # reference in doubt
     with pytest.raises(AssertionError):
-        ext.assert_within_floor(3e-11, 0.5, 0.5, 1e-11)
+        ext.assert_floor_parity(3e-8, 2e-8, 1e-9, eps, eps, 1e-11)         # forward error too large
+    with pytest.raises(AssertionError):
+        ext.assert_floor_parity(3e-11, 5e-11, 1.5e-11, 9 * eps, eps, 1e-11)  # both conditions fail
+
+
+def test_backward_error_measures(orc):
+    """The backward-error measures: about half an ulp for the oracle's own
+    solutions, and a perturbation of 1e-13 relative shows as hundreds of
+    ulp (field, advection and modal forms)."""
+    M, N = 9, 60
+    rng = np.random.default_rng(2)
+    F, u0, phi = rng.standard_normal((N, M)), rng.standard_normal(M), rng.standard_normal(M)
+    for gamma in (0.6, 1.6):
+        w = orc.weights(gamma, 1.0, N)
+        U = orc.solve(gamma, 1.0, 0.0, 1.0, M, N, F, u0=u0, phi=phi)
+        assert ext.backward(w, M, N, F, U, u0, phi) <= 4 * ext.EPS
+        assert ext.backward(w, M, N, F, U * (1 + 1e-13), u0, phi) >= 50 * ext.EPS
+        Ua = orc.solve_adv(gamma, 1.0, 0.0, 1.0, M, N, F, u0=u0, phi=phi)
+        assert ext.backward_adv(w, gamma, M, N, F, Ua, u0, phi) <= 4 * ext.EPS
+        assert ext.backward_adv(w, gamma, M, N, F, Ua * (1 + 1e-13), u0, phi) >= 50 * ext.EPS
+    w = orc.weights(1.6, 1.0, N)
+    Uc = orc.solve_cn(1.6, 1.0, 0.0, 1.0, M, N, F, u0=u0, phi=phi)
+    assert ext.backward(w, M, N, F, Uc, u0, phi, kind="cn") <= 4 * ext.EPS
+    assert ext.backward(w, M, N, F, Uc * (1 + 1e-13), u0, phi, kind="cn") >= 50 * ext.EPS
+    # modal form through projection of the field
+    from paper_1710_11593_amd import workloads as wl
+
+    inst = wl.Instance(1.4, 6, 400, modes=[(1, 0.7, 1.5), (2, -0.4, 2.2), (5, 1.1, 1.2)], manufactured=True)
+    wl.fill(inst)
+    U = orc.solve(1.4, 1.0, 0.0, 1.0, 6, 400, inst.f, u0=inst.u0, phi=inst.phi)
+    series = wl.modal_time_series(inst)
+    js = sorted(series)
+    V = dict(zip(js, ext.modal_coefficients(U, js)))
+    w = orc.weights(1.4, 1.0, 400)
+    assert ext.modal_backward(w, 6, 400, series, V) <= 4 * ext.EPS
+    assert ext.modal_backward(w, 6, 400, series, {j: V[j] * (1 + 1e-13) for j in js}) >= 50 * ext.EPS

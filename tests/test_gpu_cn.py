@@ -41,18 +41,24 @@ def relerr(x, ref):
 
 def assert_parity(u, ref, gamma, M, N, f, u0, phi):
     """<= 1e-11 against the oracle; where the oracle's own float64 error
-    exceeds that (Thomas' rounding of a_0 + e next to e at large M), the GPU
-    result's distance to an extended-precision solve must be at most twice
-    the oracle's (and the oracle within 1e-8 of it)."""
+    exceeds that (Thomas' rounding of a_0 + e next to e at large M), the floor
+    regime's checks: forward errors against an extended-precision solve
+    <= 1e-8 and the GPU's backward error at most 8 ulp or twice the
+    oracle's."""
     e = relerr(u, ref)
     if e <= TOL:
         return
+    import oracle
     from tests import ext_reference
+    from tests.test_gpu_parity import gpu_weights
 
     ext = np.asarray(ext_reference.solve_cn(gamma, M, N, f, u0, phi), dtype=np.float64)
     e_gpu, e_orc = relerr(u, ext), relerr(ref, ext)
-    print("  extended-precision check: gpu %.2e oracle %.2e" % (e_gpu, e_orc), flush=True)
-    ext_reference.assert_within_floor(e, e_gpu, e_orc, TOL)
+    eta_gpu = ext_reference.backward(gpu_weights(gamma, N), M, N, f, u, u0, phi, kind="cn")
+    eta_orc = ext_reference.backward(oracle.weights(gamma, 1.0, N), M, N, f, ref, u0, phi, kind="cn")
+    print("  floor: vs extended gpu %.2e oracle %.2e; backward error gpu %.2f oracle %.2f ulp"
+          % (e_gpu, e_orc, eta_gpu / ext_reference.EPS, eta_orc / ext_reference.EPS), flush=True)
+    ext_reference.assert_floor_parity(e, e_gpu, e_orc, eta_gpu, eta_orc, TOL)
 
 
 def case(gamma, M, N, seed=0):
@@ -192,16 +198,7 @@ def test_full_size_c3_workload(torch_cuda, orc):
     if err <= TOL:
         return
     from tests import ext_reference
+    from tests.test_gpu_parity import ext_mode_check
 
-    x, _, h, _ = wl.grid(inst.M, inst.N)
-    uext, e_orc = None, 0.0
-    for j, (g, v0, ph) in wl.modal_time_series(inst).items():
-        lam = 4.0 / h ** 2 * math.sin(j * math.pi * h / 2) ** 2
-        vx = ext_reference.mode(inst.gamma, inst.T, inst.N, lam, g, v0, ph, cn=True)
-        v64 = orc.mode_cn(inst.gamma, inst.T, inst.N, lam, g, v0, ph)
-        e_orc = max(e_orc, float(np.max(np.abs(v64 - vx)) / np.max(np.abs(vx))))
-        term = torch_cuda.from_numpy(vx).cuda()[:, None] * torch_cuda.from_numpy(np.sin(j * math.pi * x)).cuda()[None, :]
-        uext = term if uext is None else uext + term
-    e_gpu = float((u - uext).abs().max() / uext.abs().max())
-    print("  extended-precision check: gpu %.2e oracle %.2e" % (e_gpu, e_orc), flush=True)
-    ext_reference.assert_within_floor(err, e_gpu, e_orc, TOL)
+    e_gpu, e_orc, eta_gpu, eta_orc = ext_mode_check(torch_cuda, orc, inst, u, cn=True)
+    ext_reference.assert_floor_parity(err, e_gpu, e_orc, eta_gpu, eta_orc, TOL)

@@ -46,12 +46,29 @@ def rand_case(gamma, M, N, seed=0):
     return f, u0, phi
 
 
+def gpu_weights(gamma, N):
+    """The float64 weights a, rho, psi the library computes for (gamma, N)
+    (the same for every width)."""
+    from paper_1710_11593_amd import binding
+
+    s = binding.Solver([dict(gamma=gamma, M=1, N=N)])
+    w = s.weights(0)
+    s.close()
+    return w
+
+
+def orc_weights(gamma, N):
+    import oracle
+
+    return oracle.weights(gamma, 1.0, N)
+
+
 def assert_parity64(u, ref, gamma, M, N, f, u0, phi):
     """float64 bar: <= 1e-11 against the oracle.  Where the oracle's own
-    float64 error exceeds that (its distance to an extended-precision solve
-    of the same system), the GPU result's distance to the extended-precision
-    solve must be at most twice the oracle's (and the oracle within 1e-8 of
-    it)."""
+    float64 error exceeds that (the floor regime: its distance to an
+    extended-precision solve of the same system), both results are checked
+    against the extended solve (forward error <= 1e-8) and by their backward
+    errors: the GPU's at most 8 ulp or twice the oracle's."""
     e = relerr(u, ref)
     if e <= TOL64:
         return
@@ -59,8 +76,11 @@ def assert_parity64(u, ref, gamma, M, N, f, u0, phi):
 
     ext = np.asarray(ext_reference.solve(gamma, M, N, f, u0, phi), dtype=np.float64)
     e_gpu, e_orc = relerr(u, ext), relerr(ref, ext)
-    print("  extended-precision check: gpu %.2e oracle %.2e" % (e_gpu, e_orc), flush=True)
-    ext_reference.assert_within_floor(e, e_gpu, e_orc, TOL64)
+    eta_gpu = ext_reference.backward(gpu_weights(gamma, N), M, N, f, u, u0, phi)
+    eta_orc = ext_reference.backward(orc_weights(gamma, N), M, N, f, ref, u0, phi)
+    print("  floor: vs extended gpu %.2e oracle %.2e; backward error gpu %.2f oracle %.2f ulp"
+          % (e_gpu, e_orc, eta_gpu / ext_reference.EPS, eta_orc / ext_reference.EPS), flush=True)
+    ext_reference.assert_floor_parity(e, e_gpu, e_orc, eta_gpu, eta_orc, TOL64)
 
 
 def gpu_solve(torch, gamma, M, N, f, u0=None, phi=None, **opts):
@@ -180,9 +200,8 @@ def test_multipass_fft_level(torch_cuda, orc, gamma, crossover):
         # float64 floor of the diffusion-wave recurrence: measure it
         from tests import ext_reference
 
-        e_gpu, e_orc = ext_mode_check(torch_cuda, orc, inst, u)
-        print("  extended-precision check: gpu %.2e oracle %.2e" % (e_gpu, e_orc), flush=True)
-        ext_reference.assert_within_floor(err, e_gpu, e_orc, TOL64)
+        e_gpu, e_orc, eta_gpu, eta_orc = ext_mode_check(torch_cuda, orc, inst, u)
+        ext_reference.assert_floor_parity(err, e_gpu, e_orc, eta_gpu, eta_orc, TOL64)
 
 
 @pytest.mark.parametrize("gamma,M,N", [(0.6, 33, 100), (1.5, 64, 128), (0.9, 300, 77)])
@@ -221,8 +240,12 @@ def test_adjoint_parity(torch_cuda, orc, gamma, M, N):
 
         ext = np.asarray(ext_reference.solve(gamma, M, N, g[::-1]), dtype=np.float64)[::-1]
         e_gpu, e_orc = relerr(lam, ext), relerr(lam_ref, ext)
-        print("  extended-precision check: gpu %.2e oracle %.2e" % (e_gpu, e_orc), flush=True)
-        ext_reference.assert_within_floor(e, e_gpu, e_orc, TOL64)
+        # backward errors of the time-reversed forward systems they solve
+        eta_gpu = ext_reference.backward(gpu_weights(gamma, N), M, N, g[::-1], lam[::-1])
+        eta_orc = ext_reference.backward(orc_weights(gamma, N), M, N, g[::-1], lam_ref[::-1])
+        print("  floor: vs extended gpu %.2e oracle %.2e; backward error gpu %.2f oracle %.2f ulp"
+              % (e_gpu, e_orc, eta_gpu / ext_reference.EPS, eta_orc / ext_reference.EPS), flush=True)
+        ext_reference.assert_floor_parity(e, e_gpu, e_orc, eta_gpu, eta_orc, TOL64)
     assert abs(dg[0] - dg_ref) <= 1e-10 * abs(dg_ref)
 
 
@@ -360,26 +383,41 @@ def mode_reference(torch, orc, inst):
     return f, u0, phi, ref
 
 
-def ext_mode_check(torch, orc, inst, u):
-    """(GPU error, float64 oracle recurrence error), both against the
-    extended-precision recurrence, for a sum-of-sine-modes instance."""
+def ext_mode_check(torch, orc, inst, u, cn=False):
+    """Floor-regime measures of a sum-of-sine-modes instance: (GPU forward
+    error, float64 oracle recurrence forward error), both against the
+    extended-precision recurrence, and (GPU backward error, oracle backward
+    error), each for the system its own float64 weights define (the GPU's
+    modal coefficients by projection of its field)."""
     import math
 
     from tests import ext_reference
 
     series = wl.modal_time_series(inst)
     x, _, h, _ = wl.grid(inst.M, inst.N)
-    uext = None
-    e_orc = 0.0
-    for j, (g, v0, ph) in series.items():
+    js = sorted(series)
+    uext, uorc, v64s = None, None, {}
+    for j in js:
+        g, v0, ph = series[j]
         lam = 4.0 / h ** 2 * math.sin(j * math.pi * h / 2) ** 2
-        vx = ext_reference.mode(inst.gamma, inst.T, inst.N, lam, g, v0, ph)
-        v64 = orc.mode(inst.gamma, inst.T, inst.N, lam, g, v0, ph)
-        e_orc = max(e_orc, float(np.max(np.abs(v64 - vx)) / np.max(np.abs(vx))))
-        term = torch.from_numpy(vx).cuda()[:, None] * torch.from_numpy(np.sin(j * math.pi * x)).cuda()[None, :]
+        vx = ext_reference.mode(inst.gamma, inst.T, inst.N, lam, g, v0, ph, cn=cn)
+        v64 = (orc.mode_cn if cn else orc.mode)(inst.gamma, inst.T, inst.N, lam, g, v0, ph)
+        v64s[j] = v64
+        sj = torch.from_numpy(np.sin(j * math.pi * x)).cuda()[None, :]
+        term = torch.from_numpy(vx).cuda()[:, None] * sj
+        tor = torch.from_numpy(v64).cuda()[:, None] * sj
         uext = term if uext is None else uext + term
-    e_gpu = float((u - uext).abs().max() / uext.abs().max())
-    return e_gpu, e_orc
+        uorc = tor if uorc is None else uorc + tor
+    nrm = float(uext.abs().max())
+    e_gpu = float((u - uext).abs().max()) / nrm
+    e_orc = float((uorc - uext).abs().max()) / nrm
+    vg = dict(zip(js, ext_reference.modal_coefficients(u, js)))
+    eta_gpu = ext_reference.modal_backward(gpu_weights(inst.gamma, inst.N), inst.M, inst.N, series, vg, cn=cn)
+    eta_orc = ext_reference.modal_backward(orc.weights(inst.gamma, inst.T, inst.N), inst.M, inst.N, series, v64s,
+                                           cn=cn)
+    print("  floor: vs extended gpu %.2e oracle %.2e; backward error gpu %.2f oracle %.2f ulp"
+          % (e_gpu, e_orc, eta_gpu / ext_reference.EPS, eta_orc / ext_reference.EPS), flush=True)
+    return e_gpu, e_orc, eta_gpu, eta_orc
 
 
 @pytest.mark.parametrize("which", ["c2-0.3", "c2-0.7", "c3"])
@@ -389,10 +427,8 @@ def test_full_size_mode_reduction(torch_cuda, orc, which):
     oracle's single-mode recurrences.  For the diffusion-wave case (c3) the
     float64 recurrence itself carries a rounding floor well above 1e-11 at
     N = 2^17 (the history sum cancels several times the result at every
-    step); there the floor is measured with an extended-precision recurrence
-    and the GPU must be at least as close to it as the float64 oracle."""
-    import math
-
+    step); there the floor regime's checks apply (extended-precision
+    recurrence, backward errors)."""
     from paper_1710_11593_amd import binding
     from tests import ext_reference
 
@@ -407,19 +443,10 @@ def test_full_size_mode_reduction(torch_cuda, orc, which):
     s.close()
     err = float((u - ref).abs().max() / ref.abs().max())
     print("%s: max-norm relative error vs the float64 single-mode reference %.3e" % (which, err))
-    if which.startswith("c2"):
+    if which.startswith("c2") or err <= TOL64:
         assert err <= TOL64
         return
-    # c3 is one sine mode (j = 1): compare with the extended-precision recurrence
-    series = wl.modal_time_series(inst)
-    g, v0, ph = series[1]
-    x, _, h, _ = wl.grid(inst.M, inst.N)
-    lam = 4.0 / h ** 2 * math.sin(math.pi * h / 2) ** 2
-    vx = ext_reference.mode(inst.gamma, inst.T, inst.N, lam, g, v0, ph)
-    v64 = orc.mode(inst.gamma, inst.T, inst.N, lam, g, v0, ph)
-    e_orc = float(np.max(np.abs(v64 - vx)) / np.max(np.abs(vx)))
-    s1 = torch_cuda.from_numpy(np.sin(math.pi * x)).cuda()
-    uext = torch_cuda.from_numpy(vx).cuda()[:, None] * s1[None, :]
-    e_gpu = float((u - uext).abs().max() / uext.abs().max())
+    # c3: the float64 floor of the diffusion-wave recurrence at N = 2^17
+    e_gpu, e_orc, eta_gpu, eta_orc = ext_mode_check(torch_cuda, orc, inst, u)
     print("c3: GPU vs extended %.3e, float64 oracle recurrence vs extended %.3e" % (e_gpu, e_orc))
-    ext_reference.assert_within_floor(err, e_gpu, e_orc, TOL64)
+    ext_reference.assert_floor_parity(err, e_gpu, e_orc, eta_gpu, eta_orc, TOL64)
