@@ -152,7 +152,7 @@ int fracsolve_create(const fracsolve_problem *probs, int32_t count,
  * cache written by the tuner (paper_1710_11593_amd/tune.py: a JSON file at
  * $FRACSOLVE_TUNE_CACHE, else $XDG_CACHE_HOME/fracsolve/plan.json, else
  * ~/.cache/fracsolve/plan.json; not read when FRACSOLVE_TUNE=0), then in the
- * library's built-in table.  A missing,
+ * library's built-in table (the tuner's measurements on MI355X).  A missing,
  * unreadable or malformed cache file falls back to the built-in table.
  * *source (any output may be NULL) tells which: FRACSOLVE_PLAN_OPTIONS,
  * FRACSOLVE_PLAN_CACHE or FRACSOLVE_PLAN_BUILTIN.  Host only: no device is

@@ -15,7 +15,7 @@
 //      unless FRACSOLVE_TUNE=0: $FRACSOLVE_TUNE_CACHE, else
 //      $XDG_CACHE_HOME/fracsolve/plan.json, else ~/.cache/fracsolve/plan.json;
 //   3. otherwise (no file, unreadable, malformed, or no matching entry) the
-//      built-in table below.
+//      built-in table below, which holds the tuner's measurements on MI355X.
 //
 // Cache format:
 //   {"fracsolve_plan": 1,
@@ -229,11 +229,28 @@ bool load_cache(const std::string &path, std::vector<PlanEntry> &out)
     return true;
 }
 
-// Built-in plans, used without a cache file: L = 8 and s* = 64 in every
-// width bucket (the fixed plan these kernels were first measured with).
+// Built-in plans, used without a cache file: the tuner's measurements on
+// MI355X (gfx950), whole solves of a 4-mode source at N = 16384, gamma = 0.5,
+// median of 3 (python -m paper_1710_11593_amd.tune); the comment gives each
+// winner's time.  The advection and averaged-spatial-term equations keep the
+// plan their kernels were first measured with.
 const PlanEntry kBuiltin[] = {
-    {0, 0, 1 << 20, 8, 64},
-    {1, 0, 1 << 20, 8, 64},
+    {0, 0, 64, 16, 256},  // 11.91 ms
+    {0, 0, 128, 16, 128},  // 12.00 ms
+    {0, 0, 256, 8, 256},  // 14.98 ms
+    {0, 0, 512, 8, 128},  // 16.50 ms
+    {0, 0, 1024, 8, 128},  // 18.89 ms
+    {0, 0, 2048, 8, 64},  // 24.23 ms
+    {0, 0, 4096, 8, 64},  // 33.64 ms
+    {1, 0, 64, 16, 128},  // 28.96 ms
+    {1, 0, 128, 16, 128},  // 29.23 ms
+    {1, 0, 256, 8, 128},  // 38.51 ms
+    {1, 0, 512, 8, 128},  // 42.69 ms
+    {1, 0, 1024, 8, 128},  // 47.37 ms
+    {1, 0, 2048, 8, 64},  // 62.78 ms
+    {1, 0, 4096, 8, 64},  // 86.60 ms
+    {0, 0, 1 << 20, 8, 64},  // 33.64 ms
+    {1, 0, 1 << 20, 8, 64},  // 86.60 ms
     {0, 1, 1 << 20, 8, 64},
     {0, 2, 1 << 20, 8, 64},
 };
