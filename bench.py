@@ -120,6 +120,25 @@ def fft_roofline(ks, prec, M):
             "largest_single_pass_kernel": kname}
 
 
+FP64_MFMA_PEAK_TFS = 78.6
+
+
+def mfma_levels(ks, M, mfma_from=128):
+    """Matrix-core utilisation of the dense level products that run on the
+    float64 MFMA kernel (half-size s >= mfma_from): executed flops 2 s^2 M
+    per launch (a full block; the last block of a solve can be shorter) over
+    their event-timed duration, against the 78.6 TF/s float64 matrix peak."""
+    out = []
+    for g in sorted(ks, key=lambda r: r["s"]):
+        if g["kind"] != "dense_f64" or g["s"] < mfma_from or g["ms"] <= 0:
+            continue
+        fl = 2.0 * g["s"] * g["s"] * M * g["launches"]
+        tf = fl / (g["ms"] * 1e-3) / 1e12
+        out.append({"s": g["s"], "launches": g["launches"], "ms": round(g["ms"], 4), "TFLOPs": round(tf, 2),
+                    "frac": round(tf / FP64_MFMA_PEAK_TFS, 4)})
+    return out
+
+
 def build_instance(args):
     from paper_1710_11593_amd import workloads as wl
 
@@ -689,6 +708,7 @@ def main():
         log("  %-10s s=%-6d launches=%-6d %9.3f ms  %8.1f GB/s" % (
             g["kind"], g["s"], g["launches"], g["ms"], g["bytes"] / (g["ms"] * 1e-3) / 1e9 if g["ms"] else 0))
     roof = fft_roofline(ks, prec, M)
+    mfma = mfma_levels(ks, M) if prec == "fp64" else []
     leaf = [g for g in ks if g["kind"] == "leaf"]
     leaf_ms = sum(g["ms"] for g in leaf)
     leaf_launches = sum(g["launches"] for g in leaf)
@@ -752,6 +772,9 @@ def main():
         "critical_path": critical,
         "kernels_per_solve": st["kernels"],
         "roofline": roof,
+        "mfma": ({"bound": "mfma", "peak": FP64_MFMA_PEAK_TFS, "unit": "TFLOP/s",
+                  "kernel": "fs::k_dense_mfma (float64 16x16x4 MFMA dense level products)", "levels": mfma}
+                 if mfma else None),
         "cpu_baseline": cpu,
         "forms": forms,
     }

@@ -13,6 +13,7 @@
 // wave-uniform broadcasts), and the output rows are spread over the grid so
 // that even s = 64 occupies every CU.
 #include <algorithm>
+#include <cstdlib>
 
 #include "common.hpp"
 
@@ -133,11 +134,103 @@ static void dense_go(hipStream_t st, const TaskRef<UpdTask<T>> &d_tasks, int nta
         hipLaunchKernelGGL((k_dense_update<T, 64, RB>), grid, dim3(256), 0, st, d_tasks, lead, gxp, gyp, ntasks);
 }
 
+// The same level product on the matrix cores, float64 (v_mfma_f64_16x16x4):
+// the Toeplitz-expanded GEMM Y_blk += alpha T_s X_blk, T_s[p][q] = w[s+p-q].
+// Workgroup: 4 waves over a slab of 16 columns (one 128-byte line of each
+// row) and 64 output rows; the slab's s rows of X and the weight window
+// w[p0+1 .. p0+s+63] are staged in LDS, and each wave accumulates one
+// 16 x 16 output tile over s/4 MFMAs.  Operand layout of the 16x16x4 f64
+// instruction (one double per lane): A[i][k] from lane i + 16 k, B[k][j]
+// from lane j + 16 k; D[4 r + l/16][l mod 16] in lane l, register r.
+template <int SMAX>
+__global__ __launch_bounds__(256) void k_dense_mfma(TaskRef<UpdTask<double>> tr)
+{
+    typedef double v4d __attribute__((ext_vector_type(4)));
+    __shared__ double sx[SMAX * 16];
+    __shared__ double sw[SMAX + 64];
+    const UpdTask<double> tk = get_task(tr, blockIdx.z);
+    const int s = tk.s;
+    const int64_t M = tk.M;
+    const int64_t c0 = (int64_t)blockIdx.x * 16;
+    const int p0 = blockIdx.y * 64;
+    if (p0 >= tk.ny || c0 >= M) return;  // whole workgroup
+    const int t = threadIdx.x;
+    // stage X[0..s) x columns c0..c0+15 (zero past M) and the weight window
+    {
+        FS_G const double *__restrict__ xb = gptr(tk.x) + tk.xlo * M + c0;
+        const int j = t & 15;
+        const bool okc = c0 + j < M;
+        for (int q = t >> 4; q < s; q += 16) sx[q * 16 + j] = okc ? xb[(int64_t)q * M + j] : 0.0;
+        FS_G const double *__restrict__ w = gptr(tk.w);
+        for (int k = t; k < s + 63; k += 256) sw[k] = w[p0 + 1 + k];
+    }
+    __syncthreads();
+    const int wv = t >> 6, l = t & 63;
+    const int pt = p0 + 16 * wv;  // first row of this wave's tile
+    if (pt >= tk.ny) return;      // the whole wave (no barrier follows)
+    const int li = l & 15, lk = l >> 4;
+    // A[i][k] = w[s + pt + i - q0 - k] = sw[s + pt + i - q0 - k - p0 - 1];
+    // four independent accumulation chains over q (s is a multiple of 4;
+    // chains past s stay zero), summed at the end
+    const double *__restrict__ wa = sw + (s + 16 * wv + li - lk - 1);
+    const double *__restrict__ xbk = sx + lk * 16 + li;
+    v4d acc[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[c] = v4d{0.0, 0.0, 0.0, 0.0};
+    for (int q0 = 0; q0 < s; q0 += 16) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int q = q0 + 4 * c;
+            if (q < s) acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(wa[-q], xbk[q * 16], acc[c], 0, 0, 0);
+        }
+    }
+    const v4d accs = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+    const int64_t col = c0 + li;
+    if (col < M) {
+        FS_G double *__restrict__ yb = gptr(tk.y) + tk.ylo * M + col;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int p = pt + 4 * r + lk;
+            if (p < tk.ny) yb[(int64_t)p * M] += tk.alpha * accs[r];
+        }
+    }
+}
+
+// Largest half-size routed to the matrix-core kernel, and the smallest:
+// below it the VALU kernel above (organised for latency, with XCD placement
+// next to the following leaf) is the faster one.
+constexpr int DENSE_MFMA_MAX = 512;
+
+static int dense_mfma_from()
+{
+    static const int v = [] {
+        const char *e = getenv("FRACSOLVE_MFMA_FROM");
+        return e ? atoi(e) : 128;
+    }();
+    return v;
+}
+
+hipError_t launch_dense_mfma(hipStream_t st, const TaskRef<UpdTask<double>> &d_tasks, int ntasks, int s, int64_t maxM)
+{
+    const dim3 grid((unsigned)((maxM + 15) / 16), (unsigned)((s + 63) / 64), (unsigned)ntasks);
+    if (s <= 64)
+        hipLaunchKernelGGL((k_dense_mfma<64>), grid, dim3(256), 0, st, d_tasks);
+    else if (s <= 256)
+        hipLaunchKernelGGL((k_dense_mfma<256>), grid, dim3(256), 0, st, d_tasks);
+    else
+        hipLaunchKernelGGL((k_dense_mfma<512>), grid, dim3(256), 0, st, d_tasks);
+    return hipGetLastError();
+}
+
 template <typename T>
 hipError_t launch_gemm_update(hipStream_t st, const TaskRef<UpdTask<T>> &d_tasks, int ntasks, int s, int64_t maxM,
                               int lead_rows)
 {
     if (s > DENSE_MAXS || s < 1 || (s & (s - 1)) != 0) return hipErrorInvalidValue;
+    if constexpr (sizeof(T) == 8) {
+        if (s >= 4 && s >= dense_mfma_from() && s <= DENSE_MFMA_MAX)
+            return launch_dense_mfma(st, d_tasks, ntasks, s, maxM);
+    }
     // workgroups at 4 rows per thread; past a few per CU the X re-reads
     // dominate and more rows per thread pay
     const int64_t wg4 = (int64_t)ntasks * ((maxM + 255) / 256) * ((s + 3) / 4);

@@ -450,3 +450,39 @@ def test_full_size_mode_reduction(torch_cuda, orc, which):
     e_gpu, e_orc, eta_gpu, eta_orc = ext_mode_check(torch_cuda, orc, inst, u)
     print("c3: GPU vs extended %.3e, float64 oracle recurrence vs extended %.3e" % (e_gpu, e_orc))
     ext_reference.assert_floor_parity(err, e_gpu, e_orc, eta_gpu, eta_orc, TOL64)
+
+
+@pytest.mark.parametrize("gamma,M,N", [(0.35, 5, 2048), (1.45, 33, 1500), (0.8, 1000, 1100), (1.7, 2048, 300)])
+def test_dense_levels_on_the_matrix_cores(torch_cuda, orc, gamma, M, N):
+    """Crossover 512: the dense level products of half-size 128..512 run on
+    the float64 matrix cores (16x16x4 MFMA tiles over 16-column slabs), the
+    smaller ones on the vector units; ragged widths (slabs past M) and row
+    counts (the last level's Y block cut at N)."""
+    f, u0, phi = rand_case(gamma, M, N, seed=N)
+    ref = orc.solve(gamma, 1.0, 0.0, 1.0, M, N, f, u0=u0, phi=phi)
+    u = gpu_solve(torch_cuda, gamma, M, N, f, u0, phi, crossover=512)
+    assert_parity64(u, ref, gamma, M, N, f, u0, phi)
+
+
+def test_dense_mfma_apply_and_batch(torch_cuda, orc):
+    """The matrix-core dense products in the operator apply and in a batch
+    of uneven instances (one launch over every task of a level)."""
+    from paper_1710_11593_amd import binding
+
+    rng = np.random.default_rng(11)
+    M, N = 70, 1300
+    x = rng.standard_normal((N, M))
+    s = binding.Solver([dict(gamma=0.55, M=M, N=N)], crossover=512)
+    y = s.apply([dev(torch_cuda, x)])[0].cpu().numpy()
+    s.close()
+    assert relerr(y, orc.apply(0.55, 1.0, 0.0, 1.0, M, N, x)) <= TOL64
+    cases = [(0.3, 17, 900), (1.2, 300, 1200), (0.6, 64, 513)]
+    data = [rand_case(g, Mi, Ni, seed=20 + i) for i, (g, Mi, Ni) in enumerate(cases)]
+    s = binding.Solver([dict(gamma=g, M=Mi, N=Ni) for g, Mi, Ni in cases], crossover=512)
+    us = s.solve([dev(torch_cuda, d[0]) for d in data], [dev(torch_cuda, d[1]) for d in data],
+                 [dev(torch_cuda, d[2]) if d[2] is not None else None for d in data])
+    torch_cuda.cuda.synchronize()
+    for (g, Mi, Ni), d, u in zip(cases, data, us):
+        ref = orc.solve(g, 1.0, 0.0, 1.0, Mi, Ni, d[0], u0=d[1], phi=d[2])
+        assert_parity64(u.cpu().numpy(), ref, g, Mi, Ni, d[0], d[1], d[2])
+    s.close()
