@@ -61,10 +61,12 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def recorded_traffic(kernel: str, M: int):
-    """HBM bytes per launch of `kernel` recorded in profiles/ (FETCH_SIZE and
-    WRITE_SIZE passes scaled by the copy calibration), or None when there is no
-    record for this M or the FFT source changed since it was taken."""
+def recorded_traffic(s: int, M: int):
+    """HBM bytes per level product of half-size s (every kernel of that level:
+    the transform kernel and the near-corner band, or the three multi-pass
+    kernels) recorded in profiles/ (FETCH_SIZE and WRITE_SIZE passes scaled by
+    the copy calibration), or None when there is no record for this M or the
+    FFT source changed since it was taken."""
     import hashlib
     import re
 
@@ -74,9 +76,9 @@ def recorded_traffic(kernel: str, M: int):
         return None
     sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
     for line in open(path):
-        m = re.match(r'traffic: kernel="(.*)" s=(\d+) bytes_per_launch=(\d+) k_fft_sha=(\w+)', line.strip())
-        if m and m.group(1) == kernel and m.group(4) == sha:
-            return float(m.group(3))
+        m = re.match(r'traffic: s=(\d+) bytes_per_launch=(\d+) k_fft_sha=(\w+)', line.strip())
+        if m and int(m.group(1)) == s and m.group(3) == sha:
+            return float(m.group(2))
     return None
 
 
@@ -108,8 +110,7 @@ def fft_roofline(ks, prec, M):
     traffic = None
     if prec == "fp64":
         # recorded HBM bytes of every level over their algorithmic bytes
-        rec = [(recorded_traffic(("fs::" + FFT64_NAMES[2 * g["s"]]) if 2 * g["s"] in FFT64_NAMES else
-                                 "multipass s=%d" % g["s"], M), g) for g in lv]
+        rec = [(recorded_traffic(g["s"], M), g) for g in lv]
         if rec and all(r is not None for r, _ in rec):
             traffic = sum(r * g["launches"] for r, g in rec)
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -599,6 +600,9 @@ def main():
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the mixed-precision (c3), batched (c4) and adjoint (c5) comparisons")
     ap.add_argument("--out", default="")
+    ap.add_argument("--solve-once", action="store_true",
+                    help="only build the inputs and run one solve of the configuration (the program "
+                         "profiled by the HBM counter passes, whose dispatches are then one solve's)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of 512 MiB (3 times), the reference kernel for "
                          "scaling HBM counters (FETCH_SIZE / WRITE_SIZE) taken with rocprofv3 --pmc")
@@ -669,6 +673,11 @@ def main():
     def step():
         solver.solve([f], [u0], [phi] if wave else None, out=[u])
 
+    if args.solve_once:
+        step()
+        torch.cuda.synchronize()
+        log("bench: one solve done")
+        return
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
