@@ -339,6 +339,16 @@ typedef struct {
 /* on = 0: off; 1: total time and residual norm; 2: also per-kernel-group
  * times (an event pair around every launch; adds overhead). */
 int fracsolve_set_timing(fracsolve_t h, int32_t on);
+
+/* Output check (failure detection, off by default).  With on = 1, every
+ * later fracsolve_solve, fracsolve_apply and fracsolve_adjoint of the handle
+ * scans its output fields (u, y, dL_df; and dL_dgamma) for NaN and
+ * infinities after the work and returns FRACSOLVE_E_NUMERIC, naming the
+ * field, the instance and the count, if it finds any; the outputs are left
+ * as computed.  The scan reads each output once more (8 bytes per unknown)
+ * and synchronises the handle's stream.  on = 0 turns it off.  E_ARG for a
+ * NULL handle. */
+int fracsolve_set_check(fracsolve_t h, int32_t on);
 int fracsolve_get_stats(fracsolve_t h, fracsolve_stats *out);
 
 /* Per-kernel-group timing of the last call (timing level 2).  One record per

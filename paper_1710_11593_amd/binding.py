@@ -65,8 +65,9 @@ class CgInfo(ctypes.Structure):
 KIND_NAMES = {0: "leaf", 1: "dense_f64", 2: "dense_f32", 3: "fft_f64", 4: "fft_f32", 5: "fft_corner"}
 
 EXPORTS = ["fracsolve_create", "fracsolve_weights", "fracsolve_solve", "fracsolve_apply", "fracsolve_adjoint",
-           "fracsolve_gmres", "fracsolve_ode_cg", "fracsolve_ode_cg_noalloc", "fracsolve_plan", "fracsolve_set_timing", "fracsolve_get_stats", "fracsolve_kernel_stats", "fracsolve_destroy",
-           "fracsolve_last_error"]
+           "fracsolve_gmres", "fracsolve_ode_cg", "fracsolve_ode_cg_noalloc", "fracsolve_plan",
+           "fracsolve_set_timing", "fracsolve_set_check", "fracsolve_get_stats", "fracsolve_kernel_stats",
+           "fracsolve_destroy", "fracsolve_last_error"]
 
 _lib = None
 
@@ -113,6 +114,8 @@ def lib():
     L.fracsolve_ode_cg_noalloc.argtypes = L.fracsolve_ode_cg.argtypes
     L.fracsolve_set_timing.restype = ctypes.c_int
     L.fracsolve_set_timing.argtypes = [ctypes.c_void_p, ctypes.c_int32]
+    L.fracsolve_set_check.restype = ctypes.c_int
+    L.fracsolve_set_check.argtypes = [ctypes.c_void_p, ctypes.c_int32]
     L.fracsolve_get_stats.restype = ctypes.c_int
     L.fracsolve_get_stats.argtypes = [ctypes.c_void_p, ctypes.POINTER(Stats)]
     L.fracsolve_kernel_stats.restype = ctypes.c_int
@@ -292,6 +295,10 @@ class Solver:
         self._check(self._lib.fracsolve_kernel_stats(self.h, arr, cap, ctypes.byref(n)))
         return [dict(kind=KIND_NAMES[arr[k].kind], s=arr[k].s, launches=arr[k].launches, tasks=arr[k].tasks,
                      ms=arr[k].ms, bytes=arr[k].bytes) for k in range(min(n.value, cap))]
+
+    def set_check(self, on=True):
+        """Scan every later call's outputs for NaN / infinities (E_NUMERIC)."""
+        self._check(self._lib.fracsolve_set_check(self.h, 1 if on else 0))
 
     def set_timing_level(self, level):
         self._check(self._lib.fracsolve_set_timing(self.h, int(level)))

@@ -297,5 +297,6 @@ hipError_t launch_gamma_rhs_terms(hipStream_t st, const double *lam, const doubl
                                   const double *drho, const double *dpsi, int64_t M, int64_t N, double *partial,
                                   int nblocks);
 hipError_t launch_absmax_partial(hipStream_t st, const double *x, int64_t n, double *partial, int nblocks);
+hipError_t launch_nonfinite_partial(hipStream_t st, const double *x, int64_t n, double *partial, int nblocks);
 
 }  // namespace fs

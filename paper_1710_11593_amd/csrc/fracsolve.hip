@@ -111,6 +111,7 @@ struct fracsolve_ctx {
     double *partial = nullptr;  // reduction partials
     std::string err;
     int timing = 0;
+    int check = 0;  // scan outputs for non-finite values (fracsolve_set_check)
     fracsolve_stats stats{};
     std::vector<hipEvent_t> evpool;
     struct Rec {
@@ -1711,6 +1712,23 @@ int fracsolve_weights(fracsolve_t h, int32_t inst, double *b, double *a, double 
     return FRACSOLVE_OK;
 }
 
+// With checking on (fracsolve_set_check): E_NUMERIC if a field of the call's
+// output holds a NaN or an infinity.
+static int check_outputs(fracsolve_ctx *h, const double *const *x, const char *name, int rc)
+{
+    if (rc || !h->check) return rc;
+    for (size_t k = 0; k < h->inst.size(); ++k) {
+        const Inst &in = h->inst[k];
+        double cnt = 0.0;
+        HIPCHK(h, launch_nonfinite_partial(h->st, x[k], in.M * in.N, h->partial, kRedBlocks));
+        if ((rc = finish_sum(h, kRedBlocks, &cnt))) return rc;
+        if (cnt > 0.0)
+            return fail(h, FRACSOLVE_E_NUMERIC, "%s[%zu] holds %.0f non-finite values (of %lld)", name, k, cnt,
+                        (long long)(in.M * in.N));
+    }
+    return FRACSOLVE_OK;
+}
+
 static int timed_begin(fracsolve_ctx *h, hipEvent_t *ev)
 {
     h->kernels = 0;
@@ -1765,6 +1783,7 @@ int fracsolve_solve(fracsolve_t h, const double *const *f, const double *const *
     hipEvent_t ev[2];
     if ((rc = timed_begin(h, ev))) return rc;
     rc = solve_all(h, f, u0, phi, u);
+    rc = check_outputs(h, (const double *const *)u, "u", rc);
     return timed_end(h, ev, rc);
 }
 
@@ -1781,6 +1800,7 @@ int fracsolve_apply(fracsolve_t h, const double *const *u, double *const *y)
     hipEvent_t ev[2];
     if ((rc = timed_begin(h, ev))) return rc;
     for (size_t k = 0; k < h->inst.size() && !rc; ++k) rc = apply_op(h, (int)k, u[k], y[k], false, ColPerm{0, 0});
+    rc = check_outputs(h, (const double *const *)y, "y", rc);
     return timed_end(h, ev, rc);
 }
 
@@ -1831,8 +1851,11 @@ int fracsolve_adjoint(fracsolve_t h, const double *const *g, const double *const
                                              h->partial, kRedBlocks));
             if ((rc = finish_sum(h, kRedBlocks, &t2))) break;
             dL_dgamma[k] = t2 - t1;
+            if (h->check && !std::isfinite(dL_dgamma[k]))
+                rc = fail(h, FRACSOLVE_E_NUMERIC, "dL_dgamma[%zu] is not finite", k);
         }
     }
+    rc = check_outputs(h, (const double *const *)dL_df, "dL_df", rc);
     return timed_end(h, ev, rc);
 }
 
@@ -1889,6 +1912,13 @@ int fracsolve_set_timing(fracsolve_t h, int32_t on)
 {
     if (!h) return fail(nullptr, FRACSOLVE_E_ARG, "handle is NULL");
     h->timing = on;
+    return FRACSOLVE_OK;
+}
+
+int fracsolve_set_check(fracsolve_t h, int32_t on)
+{
+    if (!h) return fail(nullptr, FRACSOLVE_E_ARG, "handle is NULL");
+    h->check = on ? 1 : 0;
     return FRACSOLVE_OK;
 }
 

@@ -523,6 +523,29 @@ hipError_t launch_absmax_partial(hipStream_t st, const double *x, int64_t n, dou
     return hipGetLastError();
 }
 
+// Number of non-finite entries (NaN or +-Inf) of x, as per-block partial
+// counts (exact in float64 for any n below 2^53).
+__global__ void k_nonfinite_partial(const double *__restrict__ x, int64_t n, double *__restrict__ partial)
+{
+    __shared__ double red[256];
+    double c = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        c += isfinite(x[i]) ? 0.0 : 1.0;
+    red[threadIdx.x] = c;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+hipError_t launch_nonfinite_partial(hipStream_t st, const double *x, int64_t n, double *partial, int nblocks)
+{
+    hipLaunchKernelGGL(k_nonfinite_partial, dim3(nblocks), dim3(256), 0, st, x, n, partial);
+    return hipGetLastError();
+}
+
 
 // ---- Krylov-basis kernels of the restarted GMRES(m) (section 3.1) ----
 // The basis V is stored as nv vectors of length n, vector k at V + k ldv.

@@ -101,6 +101,7 @@ def test_empty_batch_and_null_handle(lib):
     assert rc == E_ARG and "count" in msg
     lib.fracsolve_destroy(None)  # NULL-safe
     assert lib.fracsolve_solve(None, None, None, None, None) == E_ARG
+    assert lib.fracsolve_set_check(None, 1) == E_ARG
 
 
 def test_valid_problem_without_gpu_reports_no_device(lib):

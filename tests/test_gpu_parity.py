@@ -486,3 +486,34 @@ def test_dense_mfma_apply_and_batch(torch_cuda, orc):
         ref = orc.solve(g, 1.0, 0.0, 1.0, Mi, Ni, d[0], u0=d[1], phi=d[2])
         assert_parity64(u.cpu().numpy(), ref, g, Mi, Ni, d[0], d[1], d[2])
     s.close()
+
+
+def test_output_check_reports_non_finite_values(torch_cuda, orc):
+    """fracsolve_set_check: a finite solve passes unchanged (and equals the
+    oracle); a NaN in one source row makes every later row non-finite, which
+    the scan reports as E_NUMERIC naming the field and instance; apply and
+    adjoint are checked the same way; off again, the same call returns OK."""
+    from paper_1710_11593_amd import binding
+
+    gamma, M, N = 0.6, 40, 96
+    f, u0, _ = rand_case(gamma, M, N, seed=5)
+    ref = orc.solve(gamma, 1.0, 0.0, 1.0, M, N, f, u0=u0)
+    s = binding.Solver([dict(gamma=gamma, M=M, N=N)])
+    s.set_check(True)
+    u = s.solve([dev(torch_cuda, f)], [dev(torch_cuda, u0)])[0]
+    assert relerr(u.cpu().numpy(), ref) <= TOL64
+    bad = f.copy()
+    bad[N // 2, M // 3] = np.nan
+    with pytest.raises(binding.FracsolveError, match=r"E_NUMERIC.*u\[0\] holds \d+ non-finite"):
+        s.solve([dev(torch_cuda, bad)], [dev(torch_cuda, u0)])
+    x = np.ones((N, M))
+    x[3, 4] = np.inf
+    with pytest.raises(binding.FracsolveError, match=r"E_NUMERIC.*y\[0\]"):
+        s.apply([dev(torch_cuda, x)])
+    with pytest.raises(binding.FracsolveError, match=r"E_NUMERIC.*dL_df\[0\]"):
+        s.adjoint([dev(torch_cuda, bad)], want_gamma=False)
+    with pytest.raises(binding.FracsolveError, match=r"E_NUMERIC.*dL_dgamma\[0\] is not finite"):
+        s.adjoint([dev(torch_cuda, bad)], [u], [dev(torch_cuda, u0)], None)
+    s.set_check(False)
+    s.solve([dev(torch_cuda, bad)], [dev(torch_cuda, u0)])
+    s.close()

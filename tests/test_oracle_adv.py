@@ -130,3 +130,35 @@ def test_dense_bruteforce(orc, gamma, M, N):
     ref = np.linalg.solve(A, R.ravel()).reshape(N, M)
     U = orc.solve_adv(gamma, 1.0, 0.0, 1.0, M, N, F, u0=u0, phi=phi)
     assert np.max(np.abs(U - ref)) <= 1e-11 * np.max(np.abs(ref))
+
+
+def test_scheme3_example3_diverges_past_2e_10(orc):
+    """Scheme 3 on Example 3 at gamma = 1.5 and h = tau = 2^-k (the meshes
+    of the paper's timing table, which prints no errors there): the L2 error
+    at T is 2.4e-2 at k = 10 and grows past 5e2 at k = 11, while Scheme 2 on
+    Example 2 keeps converging at k = 11.  This is the printed scheme's own
+    growth, which the GPU solve reproduces; bench.py marks such rows as
+    diverged."""
+    def scheme3(k):
+        Mp = N = 2 ** k
+        h = 1.0 / Mp
+        x = h * np.arange(1, Mp)
+        th = (np.arange(1, N + 1) - 0.5) / N
+        f = (np.outer(6 * th ** 1.5 / math.gamma(2.5), x - x * x) + np.outer(th ** 3, 1 - 2 * x))
+        U = orc.solve_adv(1.5, 1.0, 0.0, 1.0, Mp - 1, N, f)
+        return math.sqrt(h * np.sum((U[-1] - x * (1 - x)) ** 2))
+
+    def scheme2(k):
+        Mp = N = 2 ** k
+        h = 1.0 / Mp
+        x = h * np.arange(1, Mp)
+        t = np.arange(1, N + 1) / N
+        xm = x - h / 2
+        f = (np.outer(t ** 0.1 / math.gamma(1.1), np.sin(np.pi * xm)) + np.outer(np.pi * t, np.cos(np.pi * xm)))
+        U = orc.solve_adv(0.9, 1.0, 0.0, 1.0, Mp - 1, N, f)
+        return math.sqrt(h * np.sum((U[-1] - np.sin(np.pi * x)) ** 2))
+
+    assert scheme3(10) < 0.05
+    assert scheme3(11) > 1.0
+    e10, e11 = scheme2(10), scheme2(11)
+    assert e11 < e10 < 1e-5
