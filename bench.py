@@ -533,6 +533,44 @@ def run_ode(dev, meshes=tuple(range(9, 23)), gamma=0.5, rtol=1e-10):
     return {"gamma": gamma, "rtol": rtol, "meshes": res}
 
 
+def run_cpu_full(args):
+    """The oracle on the whole configuration, as consecutive row ranges of
+    --cpu-block steps (a run split that way computes exactly what one call
+    does), each printed when done: the measured full-run time that the
+    default cpu_baseline (a bounded sample scaled by (N/steps)^2) estimates."""
+    import numpy as np
+
+    import oracle
+    from paper_1710_11593_amd import workloads as wl
+
+    inst, desc = build_instance(args)
+    M, N, gamma = inst.M, inst.N, inst.gamma
+    js, G, c_u0, c_phi = modal_factors(inst)
+    x, _, _, _ = wl.grid(M, N)
+    S = np.stack([np.sin(j * math.pi * x) for j in js])
+    f = np.ascontiguousarray(G @ S)
+    u0 = np.asarray(c_u0) @ S
+    phi = (np.asarray(c_phi) @ S) if gamma > 1 else None
+    u = np.zeros((N, M))
+    th = oracle.threads()
+    log("cpu-full: %s, oracle on %d threads, blocks of %d steps" % (desc, th, args.cpu_block))
+    blocks, t_all = [], 0.0
+    for a in range(0, N, args.cpu_block):
+        b = min(N, a + args.cpu_block)
+        t0 = time.perf_counter()
+        oracle.solve_rows(gamma, inst.T, 0.0, 1.0, M, N, f, u, a, b, u0=u0, phi=phi)
+        dt = time.perf_counter() - t0
+        t_all += dt
+        blocks.append({"rows": [a, b], "s": round(dt, 3)})
+        log("cpu-full: rows %d..%d in %.2f s (total %.1f s)" % (a, b - 1, dt, t_all))
+    sample = sum(bl["s"] for bl in blocks if bl["rows"][1] <= 8192)
+    print(json.dumps({"oracle_full_run_s": round(t_all, 2), "threads": th, "M": M, "N": N, "gamma": gamma,
+                      "unknowns_per_s": M * N / t_all, "first_8192_steps_s": round(sample, 2),
+                      "estimate_from_first_8192_s": round(sample * (N / 8192) ** 2, 1) if N > 8192 else None,
+                      "blocks": blocks}),
+          flush=True)
+
+
 def run_batched(args, dev):
     """--config c4: the 256 uneven instances as one batched handle; value =
     sum of M N over the batch per second; error sampled on 8 instances."""
@@ -609,6 +647,11 @@ def main():
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the mixed-precision (c3), batched (c4) and adjoint (c5) comparisons")
     ap.add_argument("--out", default="")
+    ap.add_argument("--cpu-full", action="store_true",
+                    help="only time the oracle on the whole configuration (CPU, no GPU), in consecutive "
+                         "blocks of --cpu-block time steps, printing each block; the check of the "
+                         "cpu_baseline scaling")
+    ap.add_argument("--cpu-block", type=int, default=4096)
     ap.add_argument("--solve-once", action="store_true",
                     help="only build the inputs and run one solve of the configuration (the program "
                          "profiled by the HBM counter passes, whose dispatches are then one solve's)")
@@ -627,6 +670,9 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8, "launches": 3}))
         return
+
+    if args.cpu_full:
+        return run_cpu_full(args)
 
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (instances would shard "

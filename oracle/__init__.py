@@ -67,6 +67,8 @@ def _load():
     lib.oracle_weights.argtypes = [d, d, i64] + [_dp] * 8
     lib.oracle_solve.restype = i32
     lib.oracle_solve.argtypes = [d, d, d, d, i64, i64, i64, _dp, _dp, _dp, _dp, i32]
+    lib.oracle_solve_rows.restype = i32
+    lib.oracle_solve_rows.argtypes = [d, d, d, d, i64, i64, i64, i64, _dp, _dp, _dp, _dp, i32]
     lib.oracle_apply.restype = i32
     lib.oracle_apply.argtypes = [d, d, d, d, i64, i64, _dp, _dp, i32]
     lib.oracle_adjoint.restype = i32
@@ -142,6 +144,21 @@ def solve(gamma, T, x0, x1, M, N, f, u0=None, phi=None, nsteps=None, nthreads=0)
     rc = lib.oracle_solve(gamma, T, x0, x1, M, N, N if nsteps is None else nsteps,
                           _ptr(f), _ptr(u0), _ptr(phi), _ptr(u), nthreads)
     _check(rc, "solve")
+    return u
+
+
+def solve_rows(gamma, T, x0, x1, M, N, f, u, nfirst, nsteps, u0=None, phi=None, nthreads=0):
+    """Continue a forward run in place: rows nfirst..nsteps-1 of u (float64
+    [N][M], C order; rows below nfirst already solved by earlier calls)."""
+    lib = _load()
+    f = _f64(f, (N, M))
+    u0 = _f64(u0, (M,))
+    phi = _f64(phi, (M,))
+    if not (isinstance(u, np.ndarray) and u.dtype == np.float64 and u.shape == (N, M) and u.flags.c_contiguous):
+        raise ValueError("u must be a C-contiguous float64 array of shape (N, M)")
+    rc = lib.oracle_solve_rows(gamma, T, x0, x1, M, N, nfirst, nsteps, _ptr(f), _ptr(u0), _ptr(phi), _ptr(u),
+                               nthreads)
+    _check(rc, "solve_rows")
     return u
 
 

@@ -265,20 +265,23 @@ int oracle_threads(void)
 }
 
 /*
- * Forward time stepping for n = 1..nsteps (nsteps <= N; the grid and the
- * weights are those of the full N-step problem).
+ * Forward time stepping for n = nfirst+1..nsteps (0 <= nfirst <= nsteps <= N;
+ * the grid and the weights are those of the full N-step problem).  Rows
+ * below nfirst must already hold the solution (from an earlier call with the
+ * same arguments): each step reads only earlier rows, so a run split into
+ * consecutive ranges computes exactly what one call does.
  *   f   [N][M]  source sampled at t_n (gamma<1) or t_{n-1/2} (gamma>1)
  *   u0  [M]     initial value (NULL = 0)
  *   phi [M]     initial velocity, used for gamma>1 only (NULL = 0)
- *   u   [N][M]  output; rows >= nsteps are left untouched
+ *   u   [N][M]  output; rows outside nfirst..nsteps-1 are left untouched
  */
-int oracle_solve(double gamma, double T, double x0, double x1, int64_t M, int64_t N,
-                 int64_t nsteps, const double *f, const double *u0, const double *phi,
-                 double *u, int nthreads)
+int oracle_solve_rows(double gamma, double T, double x0, double x1, int64_t M, int64_t N,
+                      int64_t nfirst, int64_t nsteps, const double *f, const double *u0, const double *phi,
+                      double *u, int nthreads)
 {
     if (regime_of(gamma) < 0 || !(T > 0.0) || !(x1 > x0) || M < 1 || N < 1 || !f || !u)
         return ORACLE_EARG;
-    if (nsteps < 0 || nsteps > N) return ORACLE_EARG;
+    if (nsteps < 0 || nsteps > N || nfirst < 0 || nfirst > nsteps) return ORACLE_EARG;
     set_threads(nthreads);
     double h = (x1 - x0) / (double)(M + 1);
     double e = 1.0 / (h * h);
@@ -294,7 +297,7 @@ int oracle_solve(double gamma, double T, double x0, double x1, int64_t M, int64_
     oracle_weights(gamma, T, N, NULL, a, rho, psi, NULL, NULL, NULL, NULL);
     thomas_factor(M, a[0] + 2.0 * e, -e, cp, inv);
 
-    for (int64_t n = 1; n <= nsteps; ++n) {
+    for (int64_t n = nfirst + 1; n <= nsteps; ++n) {
         double *r = u + (size_t)(n - 1) * (size_t)M;
         const double *fn = f + (size_t)(n - 1) * (size_t)M;
         /* right-hand side: F^n - rho_n u^0 + psi_n phi - sum_j a_{n-j} U^j */
@@ -319,6 +322,14 @@ int oracle_solve(double gamma, double T, double x0, double x1, int64_t M, int64_
     }
     free(a); free(rho); free(psi); free(cp); free(inv);
     return ORACLE_OK;
+}
+
+/* The whole run n = 1..nsteps (rows >= nsteps are left untouched). */
+int oracle_solve(double gamma, double T, double x0, double x1, int64_t M, int64_t N,
+                 int64_t nsteps, const double *f, const double *u0, const double *phi,
+                 double *u, int nthreads)
+{
+    return oracle_solve_rows(gamma, T, x0, x1, M, N, 0, nsteps, f, u0, phi, u, nthreads);
 }
 
 /* y = A u for the Toeplitz column a and e = 1/h^2 (the definition, row by

@@ -243,3 +243,23 @@ def test_c1_oracle_error_vs_exact(orc):
     _, _, _, exact = wl.manufactured_source(inst.gamma, inst.M, inst.N)
     rel = np.max(np.abs(U - exact)) / np.max(np.abs(exact))
     assert 1e-6 < rel < 1e-3
+
+
+@pytest.mark.parametrize("gamma", [0.3, 1.6])
+def test_solve_in_row_ranges_is_the_same_run(orc, gamma):
+    """A run continued in consecutive row ranges (oracle_solve_rows, the form
+    the full-length CPU timing uses) is bit-identical to one call, and rows
+    outside the range are untouched."""
+    M, N = 37, 50
+    rng = np.random.default_rng(4)
+    f = rng.standard_normal((N, M))
+    u0 = rng.standard_normal(M)
+    phi = rng.standard_normal(M) if gamma > 1 else None
+    ref = orc.solve(gamma, 1.0, 0.0, 1.0, M, N, f, u0=u0, phi=phi)
+    u = np.full((N, M), 7.0)
+    for a, b in ((0, 13), (13, 13), (13, 31), (31, 50)):
+        orc.solve_rows(gamma, 1.0, 0.0, 1.0, M, N, f, u, a, b, u0=u0, phi=phi)
+        assert np.all(u[b:] == 7.0)
+    assert np.array_equal(u, ref)
+    with pytest.raises(Exception):
+        orc.solve_rows(gamma, 1.0, 0.0, 1.0, M, N, f, u, 20, 10, u0=u0, phi=phi)
