@@ -27,9 +27,11 @@ with --N 2^k only the mesh h = tau = 2^-k), and the advection equations
 Scheme 1, the two-sided fractional ODE by FFT conjugate gradients, on the
 meshes of its timing table (--config ode; with --N 2^k only that mesh).
 cpu_baseline: the oracle (plain time stepping) on the same workload for the
-first --cpu-steps steps at full width; its wall time is scaled by
-(N / steps)^2 (the history work is quadratic in the step count) to the full
-run and reported as unknowns per second.
+first --cpu-steps steps at full width; its wall time is scaled to the full
+run, by the ratio measured once for this workload on the GPU host
+(bench.py --cpu-full, recorded in profiles/) where there is one, otherwise by
+(N / steps)^2 (the history work is quadratic in the step count), and
+reported as unknowns per second.
 """
 from __future__ import annotations
 
@@ -79,6 +81,22 @@ def recorded_traffic(s: int, M: int):
         m = re.match(r'traffic: s=(\d+) bytes_per_launch=(\d+) k_fft_sha=(\w+)', line.strip())
         if m and int(m.group(1)) == s and m.group(3) == sha:
             return float(m.group(2))
+    return None
+
+
+def recorded_full_run(config: str, M: int, N: int, gamma: float, n_s: int):
+    """The whole-run oracle time recorded in profiles/ for this workload
+    (bench.py --cpu-full on the GPU host), or None."""
+    import re
+
+    path = os.path.join(ROOT, "profiles", "oracle_c2_full_run.md")
+    if config != "c2" or n_s != 8192 or not os.path.exists(path):
+        return None
+    for line in open(path):
+        m = re.match(r"full_run: workload=c2 M=(\d+) N=(\d+) gamma=([\d.]+) threads=(\d+) total_s=([\d.]+) "
+                     r"first_8192_s=([\d.]+)$", line.strip())
+        if m and int(m.group(1)) == M and int(m.group(2)) == N and abs(float(m.group(3)) - gamma) < 1e-12:
+            return {"threads": int(m.group(4)), "total_s": float(m.group(5)), "first_s": float(m.group(6))}
     return None
 
 
@@ -801,10 +819,21 @@ def main():
         oracle.solve(gamma, inst.T, 0.0, 1.0, M, N, fpad, u0=np.asarray(c_u0) @ S,
                      phi=(np.asarray(c_phi) @ S) if wave else None, nsteps=n_s)
         c1 = time.perf_counter()
-        t_full = (c1 - c0) * (N / n_s) ** 2
+        rec = recorded_full_run(args.config, M, N, gamma, n_s)
+        if rec:
+            # the measured ratio of a whole run to this sample on the GPU host
+            ratio = rec["total_s"] / rec["first_s"]
+            how = ("time scaled by %.2f, the ratio of the whole run (%.1f s on %d threads, measured once, "
+                   "profiles/oracle_c2_full_run.md) to its first %d steps" % (ratio, rec["total_s"], rec["threads"],
+                                                                             n_s))
+        else:
+            ratio = (N / n_s) ** 2
+            how = "time scaled by (N/%d)^2 to the full run" % n_s
+        t_full = (c1 - c0) * ratio
         cpu = {"value": M * N / t_full, "unit": "unknowns/s", "cores": th, "kind": "oracle",
-               "sample": "first %d of %d time steps at full M=%d (%.2f s wall); time scaled by (N/%d)^2 to the "
-                         "full run" % (n_s, N, M, c1 - c0, n_s)}
+               "sample": "first %d of %d time steps at full M=%d (%.2f s wall); %s" % (n_s, N, M, c1 - c0, how)}
+        if rec:
+            cpu["full_run_measured_s"] = rec["total_s"]
         log("bench: oracle sample %.2f s on %d threads -> %.4g unknowns/s (full-run estimate)" % (
             c1 - c0, th, cpu["value"]))
 

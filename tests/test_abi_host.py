@@ -215,3 +215,18 @@ def test_ode_cg_noalloc_rejects_sizes_beyond_its_workspace(lib, gamma, N, hist_c
     msg = lib.fracsolve_last_error(None).decode()
     assert rc == E_ARG, (rc, msg)
     assert pattern in msg, msg
+
+
+def test_recorded_full_run_parses():
+    """The whole-run oracle time behind the cpu_baseline scaling is recorded
+    for the c2 workload, with a ratio above the quadratic 64 (its later
+    blocks run slower than a quadratic cost predicts) and is not applied to
+    other workloads or sample sizes."""
+    import bench
+
+    rec = bench.recorded_full_run("c2", 4096, 65536, 0.3, 8192)
+    assert rec and rec["threads"] >= 1
+    assert 64.0 <= rec["total_s"] / rec["first_s"] <= 100.0
+    assert bench.recorded_full_run("c2", 4096, 65536, 0.7, 8192) is None
+    assert bench.recorded_full_run("c2", 4096, 65536, 0.3, 4096) is None
+    assert bench.recorded_full_run("c3", 2048, 131072, 1.5, 8192) is None
