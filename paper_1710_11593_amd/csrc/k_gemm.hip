@@ -74,24 +74,33 @@ __global__ __launch_bounds__(256) void k_dense_update(TaskRef<UpdTask<T>> tr, in
 
     FS_G const T *__restrict__ xp = gptr(tk.x) + tk.xlo * M + cl;
     FS_G T *__restrict__ yp = gptr(tk.y) + (tk.ylo + p0) * M + cl;
-    // Y rows of this thread (rows past ny read row ny - 1 and are not stored)
+    // Loads in the order they are waited for, all before the first wait: the
+    // thread's first weight of the window sw[k] = w[p0 + 1 + k],
+    // k < s + DENSE_RB - 1 (clamped, so unconditional), the Y rows (rows
+    // past ny read row ny - 1 and are not stored), the first batch of X.
+    FS_G const double *__restrict__ w = gptr(tk.w) + p0 + 1;
+    const int nwin = s + DENSE_RB - 1;
+    const double w_first = w[(int)threadIdx.x < nwin ? (int)threadIdx.x : nwin - 1];
     T yv[DENSE_RB];
 #pragma unroll
     for (int r = 0; r < DENSE_RB; ++r) yv[r] = yp[(int64_t)(r < np ? r : np - 1) * M];
-    // weight window: sw[k] = w[p0 + 1 + k], k < s + DENSE_RB - 1
-    FS_G const double *__restrict__ w = gptr(tk.w);
-    for (int k = threadIdx.x; k < s + DENSE_RB - 1; k += 256) sw[k] = w[p0 + 1 + k];
+    T xv[QC];
+#pragma unroll
+    for (int j = 0; j < QC; ++j) xv[j] = xp[(int64_t)j * M];
+    if ((int)threadIdx.x < nwin) sw[threadIdx.x] = w_first;
+    for (int k = threadIdx.x + 256; k < nwin; k += 256) sw[k] = w[k];  // windows past 256 (s > 240)
+    __syncthreads();  // weight window ready
 
     T acc[DENSE_RB];
 #pragma unroll
     for (int r = 0; r < DENSE_RB; ++r) acc[r] = (T)0;
     // w[s + p - q] with p = p0 + r: sw[s - 1 + r - q]
     for (int q0 = 0; q0 < s; q0 += QC) {
-        T xv[QC];
-        FS_G const T *__restrict__ xq = xp + (int64_t)q0 * M;
+        if (q0 > 0) {
+            FS_G const T *__restrict__ xq = xp + (int64_t)q0 * M;
 #pragma unroll
-        for (int j = 0; j < QC; ++j) xv[j] = xq[(int64_t)j * M];
-        if (q0 == 0) __syncthreads();  // weight window ready
+            for (int j = 0; j < QC; ++j) xv[j] = xq[(int64_t)j * M];
+        }
         const double *__restrict__ wq = sw + (s - 1 - q0);
 #pragma unroll
         for (int j = 0; j < QC; ++j) {
@@ -146,6 +155,8 @@ template <int SMAX>
 __global__ __launch_bounds__(256) void k_dense_mfma(TaskRef<UpdTask<double>> tr)
 {
     typedef double v4d __attribute__((ext_vector_type(4)));
+    constexpr int NQ = SMAX / 16;            // X rows staged per thread
+    constexpr int NW = (SMAX + 63 + 255) / 256;  // weights staged per thread
     __shared__ double sx[SMAX * 16];
     __shared__ double sw[SMAX + 64];
     const UpdTask<double> tk = get_task(tr, blockIdx.z);
@@ -155,43 +166,84 @@ __global__ __launch_bounds__(256) void k_dense_mfma(TaskRef<UpdTask<double>> tr)
     const int p0 = blockIdx.y * 64;
     if (p0 >= tk.ny || c0 >= M) return;  // whole workgroup
     const int t = threadIdx.x;
-    // stage X[0..s) x columns c0..c0+15 (zero past M) and the weight window
-    {
-        FS_G const double *__restrict__ xb = gptr(tk.x) + tk.xlo * M + c0;
-        const int j = t & 15;
-        const bool okc = c0 + j < M;
-        for (int q = t >> 4; q < s; q += 16) sx[q * 16 + j] = okc ? xb[(int64_t)q * M + j] : 0.0;
-        FS_G const double *__restrict__ w = gptr(tk.w);
-        for (int k = t; k < s + 63; k += 256) sw[k] = w[p0 + 1 + k];
+    const int wv = t >> 6, l = t & 63;
+    const int li = l & 15, lk = l >> 4;
+    const int pt = p0 + 16 * wv;  // first row of this wave's tile
+    // Every global load of the workgroup is issued before the first wait:
+    // the lane's four Y entries, its NQ rows of the X slab and its share of
+    // the weight window.  Loads are unconditional (indices past the data are
+    // clamped to a valid element whose value is then discarded), so no
+    // branch serialises them.
+    const int64_t col = c0 + li;
+    const int64_t colc = col < M ? col : M - 1;
+    FS_G double *__restrict__ yb = gptr(tk.y) + tk.ylo * M;
+    double yv[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int p = pt + 4 * r + lk;
+        yv[r] = yb[(int64_t)(p < tk.ny ? p : tk.ny - 1) * M + colc];
+    }
+    const int j = t & 15;
+    const bool okc = c0 + j < M;
+    FS_G const double *__restrict__ xb = gptr(tk.x) + tk.xlo * M + (okc ? c0 + j : M - 1);
+    double xv[NQ];
+#pragma unroll
+    for (int i = 0; i < NQ; ++i) {
+        const int q = (t >> 4) + 16 * i;
+        xv[i] = xb[(int64_t)(q < s ? q : s - 1) * M];
+    }
+    FS_G const double *__restrict__ w = gptr(tk.w) + p0 + 1;
+    const int nw = s + 63;  // window w[p0+1 .. p0+s+63]; w has at least p0 + s + 64 entries
+    double wvv[NW];
+#pragma unroll
+    for (int i = 0; i < NW; ++i) {
+        const int k = t + 256 * i;
+        wvv[i] = w[k < nw ? k : nw - 1];
+    }
+#pragma unroll
+    for (int i = 0; i < NQ; ++i) {
+        const int q = (t >> 4) + 16 * i;
+        if (q < s) sx[q * 16 + j] = okc ? xv[i] : 0.0;
+    }
+#pragma unroll
+    for (int i = 0; i < NW; ++i) {
+        const int k = t + 256 * i;
+        if (k < nw) sw[k] = wvv[i];
     }
     __syncthreads();
-    const int wv = t >> 6, l = t & 63;
-    const int pt = p0 + 16 * wv;  // first row of this wave's tile
-    if (pt >= tk.ny) return;      // the whole wave (no barrier follows)
-    const int li = l & 15, lk = l >> 4;
+    if (pt >= tk.ny) return;  // the whole wave (no barrier follows)
     // A[i][k] = w[s + pt + i - q0 - k] = sw[s + pt + i - q0 - k - p0 - 1];
-    // four independent accumulation chains over q (s is a multiple of 4;
-    // chains past s stay zero), summed at the end
+    // four independent accumulation chains over q, summed at the end
     const double *__restrict__ wa = sw + (s + 16 * wv + li - lk - 1);
     const double *__restrict__ xbk = sx + lk * 16 + li;
     v4d acc[4];
 #pragma unroll
     for (int c = 0; c < 4; ++c) acc[c] = v4d{0.0, 0.0, 0.0, 0.0};
-    for (int q0 = 0; q0 < s; q0 += 16) {
+    if (s % 16 == 0) {
+#pragma unroll 2
+        for (int q0 = 0; q0 < s; q0 += 16) {
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            const int q = q0 + 4 * c;
-            if (q < s) acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(wa[-q], xbk[q * 16], acc[c], 0, 0, 0);
+            for (int c = 0; c < 4; ++c) {
+                const int q = q0 + 4 * c;
+                acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(wa[-q], xbk[q * 16], acc[c], 0, 0, 0);
+            }
+        }
+    } else {
+        // s = 4 or 8 (chains past s stay zero)
+        for (int q0 = 0; q0 < s; q0 += 16) {
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const int q = q0 + 4 * c;
+                if (q < s) acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(wa[-q], xbk[q * 16], acc[c], 0, 0, 0);
+            }
         }
     }
     const v4d accs = (acc[0] + acc[1]) + (acc[2] + acc[3]);
-    const int64_t col = c0 + li;
     if (col < M) {
-        FS_G double *__restrict__ yb = gptr(tk.y) + tk.ylo * M + col;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int p = pt + 4 * r + lk;
-            if (p < tk.ny) yb[(int64_t)p * M] += tk.alpha * accs[r];
+            if (p < tk.ny) yb[(int64_t)p * M + col] = yv[r] + tk.alpha * accs[r];
         }
     }
 }
