@@ -373,9 +373,18 @@ __global__ __launch_bounds__(NT) void k_leaf_scan(TaskRef<LeafTask> tr)
             if (rl == 15) sR[par][0][G] = Sf;
             if (rl == 0) sR[par][1][G] = Sb;
         }
+        // the step's barrier, then the reads of the row totals
+        double vf = 0.0, vb = 0.0;
+        if (run) {
+            __syncthreads();
+            vf = (lane < NR) ? sR[par][0][lane] : 0.0;
+            vb = (lane < NR) ? sR[par][1][lane] : 0.0;
+        }
         // deferred work of the previous step: store its solution row and
         // push it into the right-hand sides beyond the next row (the next
-        // row itself was updated right after the solve)
+        // row itself was updated right after the solve).  It sits after the
+        // barrier, where it fills the wait for the row totals' reads and
+        // scans instead of delaying every wave's arrival at the barrier.
         if (r > 0 && r - 1 < nrows) {
             FS_G double *row = u + (int64_t)(r - 1) * M;
             if (vec) {
@@ -411,10 +420,7 @@ __global__ __launch_bounds__(NT) void k_leaf_scan(TaskRef<LeafTask> tr)
             }
         }
         if (!run) break;
-        __syncthreads();
         // scan of the NR row totals (multiplier c = m^16 per row) on lanes < NR
-        double vf = (lane < NR) ? sR[par][0][lane] : 0.0;
-        double vb = (lane < NR) ? sR[par][1][lane] : 0.0;
         row_scans<(NR < 16 ? NR : 16)>(vf, vb, cp);
         if constexpr (NR > 16) {
             // rows 0-15 -> 16-31: forward by row_bcast:15 into lanes 16..31,
