@@ -385,13 +385,27 @@ __global__ __launch_bounds__(NT) void k_leaf_scan(TaskRef<LeafTask> tr)
         // row itself was updated right after the solve).  It sits after the
         // barrier, where it fills the wait for the row totals' reads and
         // scans instead of delaying every wave's arrival at the barrier.
+        // The row's 16-byte stores are spread over this phase of the step
+        // (one part at each of STORE_PARTS points, pinned by scheduling
+        // barriers) instead of leaving the CU in one burst of 32 KB, which
+        // stalls the issuing waves and, through the next barrier, all of them.
+        constexpr int STORE_PARTS = (UT % 4 == 0) ? 4 : 1;
+        const bool store_row = r > 0 && r - 1 < nrows;
+        FS_G double *const srow = u + (int64_t)(r > 0 ? r - 1 : 0) * M;
+        auto store_part = [&](int part) {
+            if (store_row && vec && act) {
+#pragma unroll
+                for (int i = part * (UT / STORE_PARTS); i < (part + 1) * (UT / STORE_PARTS); ++i)
+                    *reinterpret_cast<FS_G double2 *>(srow + col(2 * i)) = double2{xp[2 * i], xp[2 * i + 1]};
+            }
+        };
         if (r > 0 && r - 1 < nrows) {
             FS_G double *row = u + (int64_t)(r - 1) * M;
             if (vec) {
-                if (act) {
+                store_part(0);
+                if (STORE_PARTS == 1 || !run) {
 #pragma unroll
-                    for (int i = 0; i < UT; ++i)
-                        *reinterpret_cast<FS_G double2 *>(row + col(2 * i)) = double2{xp[2 * i], xp[2 * i + 1]};
+                    for (int part = 1; part < STORE_PARTS; ++part) store_part(part);
                 }
             } else {
 #pragma unroll
@@ -420,8 +434,14 @@ __global__ __launch_bounds__(NT) void k_leaf_scan(TaskRef<LeafTask> tr)
             }
         }
         if (!run) break;
+        if constexpr (STORE_PARTS > 1) __builtin_amdgcn_sched_barrier(0);
         // scan of the NR row totals (multiplier c = m^16 per row) on lanes < NR
         row_scans<(NR < 16 ? NR : 16)>(vf, vb, cp);
+        if constexpr (STORE_PARTS > 1) {
+            __builtin_amdgcn_sched_barrier(0);
+            store_part(1);
+            __builtin_amdgcn_sched_barrier(0);
+        }
         if constexpr (NR > 16) {
             // rows 0-15 -> 16-31: forward by row_bcast:15 into lanes 16..31,
             // backward by the uniform suffix at lane 16 into lanes 0..15
@@ -432,10 +452,20 @@ __global__ __launch_bounds__(NT) void k_leaf_scan(TaskRef<LeafTask> tr)
         // carries: P at the row before the thread's rows, Q at its last row
         double Cr = lane_fetch(vf, G > 0 ? G - 1 : 0);
         double Dr = lane_fetch(vb, G < NR - 1 ? G + 1 : 0);
+        if constexpr (STORE_PARTS > 1) {
+            __builtin_amdgcn_sched_barrier(0);
+            store_part(2);
+            __builtin_amdgcn_sched_barrier(0);
+        }
         Cr = (G > 0) ? Cr : 0.0;
         Dr = (G < NR - 1) ? Dr : 0.0;
         const double cf = fma(m_lo, Cr, dpp_move<0x111>(Sf));
         const double cb = fma(m_hi, Dr, dpp_move<0x101>(Sb));
+        if constexpr (STORE_PARTS > 1) {
+            __builtin_amdgcn_sched_barrier(0);
+            store_part(3);
+            __builtin_amdgcn_sched_barrier(0);
+        }
         // unfold
 #pragma unroll
         for (int k = 0; k < PT; ++k) {
