@@ -433,7 +433,8 @@ def test_full_size_mode_reduction(torch_cuda, orc, which):
     from tests import ext_reference
 
     if which.startswith("c2"):
-        inst = wl.c2(gamma=float(which.split("-")[1]), build=False)
+        g = float(which.split("-")[1])
+        inst = wl.c2(gamma=g, seed=3 if g == 0.7 else 2, build=False)  # the recipe's seeds
     else:
         inst = wl.c3(build=False)
     f, u0, phi, ref = mode_reference(torch_cuda, orc, inst)
