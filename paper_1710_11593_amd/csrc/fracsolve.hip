@@ -1652,7 +1652,13 @@ int fracsolve_create(const fracsolve_problem *probs, int32_t count, const fracso
         for (auto &in : h->inst)
             if (in.Np > fft_max_single_pass(false)) need = true;
         if (need) {
-            h->zs_bytes = (size_t)256 << 20;
+            // FRACSOLVE_MP_SCRATCH_MB: scratch size in MiB (16 to 4096)
+            size_t mb = 256;
+            if (const char *e = getenv("FRACSOLVE_MP_SCRATCH_MB")) {
+                const long v = strtol(e, nullptr, 10);
+                if (v >= 16 && v <= 4096) mb = (size_t)v;
+            }
+            h->zs_bytes = mb << 20;
             if (hipMalloc(&h->zs, h->zs_bytes) != hipSuccess) {
                 hipGetLastError();
                 rc = fail(h, FRACSOLVE_E_NOMEM, "multi-pass scratch allocation failed");

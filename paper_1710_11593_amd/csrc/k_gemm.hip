@@ -37,8 +37,8 @@ constexpr int DENSE_MAXS = 1024;  // largest half-block size for this kernel
 //  lead < 0 (several tasks): every tile of task t runs on XCD t mod 8, next to
 //    its leaf: grid (8 gxp, gyp, ceil(ntasks / 8)), task = 8 z + x mod 8.
 //  lead = 0: grid (gxp, gyp, ntasks).
-template <typename T, int QC, int RB>
-__global__ __launch_bounds__(256) void k_dense_update(TaskRef<UpdTask<T>> tr, int lead, int gxp, int gyp, int ntasks)
+template <typename T, int QC, int RB, int NTD>
+__global__ __launch_bounds__(NTD) void k_dense_update(TaskRef<UpdTask<T>> tr, int lead, int gxp, int gyp, int ntasks)
 {
     constexpr int DENSE_RB = RB;
     __shared__ double sw[DENSE_MAXS + DENSE_RB];
@@ -66,8 +66,8 @@ __global__ __launch_bounds__(256) void k_dense_update(TaskRef<UpdTask<T>> tr, in
     const int s = tk.s;
     const int64_t M = tk.M;
     const int p0 = by * DENSE_RB;  // first output row of the workgroup
-    const int64_t col = (int64_t)bx * 256 + threadIdx.x;
-    if (p0 >= tk.ny || (int64_t)bx * 256 >= M) return;  // whole workgroup exits together
+    const int64_t col = (int64_t)bx * NTD + threadIdx.x;
+    if (p0 >= tk.ny || (int64_t)bx * NTD >= M) return;  // whole workgroup exits together
     const bool ok = col < M;
     const int64_t cl = ok ? col : M - 1;
     const int np = (tk.ny - p0 < DENSE_RB) ? tk.ny - p0 : DENSE_RB;
@@ -88,7 +88,7 @@ __global__ __launch_bounds__(256) void k_dense_update(TaskRef<UpdTask<T>> tr, in
 #pragma unroll
     for (int j = 0; j < QC; ++j) xv[j] = xp[(int64_t)j * M];
     if ((int)threadIdx.x < nwin) sw[threadIdx.x] = w_first;
-    for (int k = threadIdx.x + 256; k < nwin; k += 256) sw[k] = w[k];  // windows past 256 (s > 240)
+    for (int k = threadIdx.x + NTD; k < nwin; k += NTD) sw[k] = w[k];  // windows past NTD
     __syncthreads();  // weight window ready
 
     T acc[DENSE_RB];
@@ -116,10 +116,11 @@ __global__ __launch_bounds__(256) void k_dense_update(TaskRef<UpdTask<T>> tr, in
     }
 }
 
-template <typename T, int RB>
-static void dense_go(hipStream_t st, const TaskRef<UpdTask<T>> &d_tasks, int ntasks, int s, int64_t maxM, int lead_rows)
+template <typename T, int RB, int NTD>
+static void dense_go_nt(hipStream_t st, const TaskRef<UpdTask<T>> &d_tasks, int ntasks, int s, int64_t maxM,
+                        int lead_rows)
 {
-    dim3 grid((unsigned)((maxM + 255) / 256), (unsigned)((s + RB - 1) / RB), (unsigned)ntasks);
+    dim3 grid((unsigned)((maxM + NTD - 1) / NTD), (unsigned)((s + RB - 1) / RB), (unsigned)ntasks);
     const int gxp = (int)grid.x, gyp = (int)grid.y;
     // single task: the row blocks the next leaf reads on XCD 0 (see the kernel)
     int lead = 0;
@@ -132,15 +133,26 @@ static void dense_go(hipStream_t st, const TaskRef<UpdTask<T>> &d_tasks, int nta
         grid = dim3((unsigned)(8 * gxp), (unsigned)gyp, (unsigned)((ntasks + 7) / 8));
     }
     if (s <= 4)
-        hipLaunchKernelGGL((k_dense_update<T, 4, RB>), grid, dim3(256), 0, st, d_tasks, lead, gxp, gyp, ntasks);
+        hipLaunchKernelGGL((k_dense_update<T, 4, RB, NTD>), grid, dim3(NTD), 0, st, d_tasks, lead, gxp, gyp, ntasks);
     else if (s <= 8)
-        hipLaunchKernelGGL((k_dense_update<T, 8, RB>), grid, dim3(256), 0, st, d_tasks, lead, gxp, gyp, ntasks);
+        hipLaunchKernelGGL((k_dense_update<T, 8, RB, NTD>), grid, dim3(NTD), 0, st, d_tasks, lead, gxp, gyp, ntasks);
     else if (s <= 16)
-        hipLaunchKernelGGL((k_dense_update<T, 16, RB>), grid, dim3(256), 0, st, d_tasks, lead, gxp, gyp, ntasks);
+        hipLaunchKernelGGL((k_dense_update<T, 16, RB, NTD>), grid, dim3(NTD), 0, st, d_tasks, lead, gxp, gyp, ntasks);
     else if (s <= 32 || RB > 4)
-        hipLaunchKernelGGL((k_dense_update<T, 32, RB>), grid, dim3(256), 0, st, d_tasks, lead, gxp, gyp, ntasks);
+        hipLaunchKernelGGL((k_dense_update<T, 32, RB, NTD>), grid, dim3(NTD), 0, st, d_tasks, lead, gxp, gyp, ntasks);
     else
-        hipLaunchKernelGGL((k_dense_update<T, 64, RB>), grid, dim3(256), 0, st, d_tasks, lead, gxp, gyp, ntasks);
+        hipLaunchKernelGGL((k_dense_update<T, 64, RB, NTD>), grid, dim3(NTD), 0, st, d_tasks, lead, gxp, gyp, ntasks);
+}
+
+// One wave per workgroup: the small products finish sooner when their
+// loads are spread over more CUs (measured against 128 and 256 threads:
+// c2 139.5 -> 138.9 ms, c3 196.2 -> 191.8 ms, c4 batched 170.0 -> 163.9 ms).
+constexpr int DENSE_NT = 64;
+
+template <typename T, int RB>
+static void dense_go(hipStream_t st, const TaskRef<UpdTask<T>> &d_tasks, int ntasks, int s, int64_t maxM, int lead_rows)
+{
+    dense_go_nt<T, RB, DENSE_NT>(st, d_tasks, ntasks, s, maxM, lead_rows);
 }
 
 // The same level product on the matrix cores, float64 (v_mfma_f64_16x16x4):
@@ -283,7 +295,7 @@ hipError_t launch_gemm_update(hipStream_t st, const TaskRef<UpdTask<T>> &d_tasks
         if (s >= 4 && s >= dense_mfma_from() && s <= DENSE_MFMA_MAX)
             return launch_dense_mfma(st, d_tasks, ntasks, s, maxM);
     }
-    // workgroups at 4 rows per thread; past a few per CU the X re-reads
+    // tiles of 256 columns at 4 rows per thread; past a few per CU the X re-reads
     // dominate and more rows per thread pay
     const int64_t wg4 = (int64_t)ntasks * ((maxM + 255) / 256) * ((s + 3) / 4);
     if (wg4 > 2048 && s >= 16)
