@@ -43,6 +43,20 @@
  *     Argument errors are detected before any device work.  The text of the
  *     last error is available from fracsolve_last_error(h) (or with h = NULL
  *     for errors of fracsolve_create).
+ *
+ * Environment (read once per process or per handle; none changes a result
+ * beyond rounding order):
+ *   FRACSOLVE_TUNE=0, FRACSOLVE_TUNE_CACHE   plan cache (fracsolve_plan)
+ *   FRACSOLVE_PAIR=0          leaves one at a time instead of in pairs
+ *   FRACSOLVE_MFMA_FROM=s     smallest dense level size on the matrix cores
+ *                             (default 128)
+ *   FRACSOLVE_MP_SCRATCH_MB   multi-pass FFT scratch in MiB (16..4096,
+ *                             default 256)
+ *   FRACSOLVE_GRAPH=1         record the recursive solve's launch
+ *                             sequences as HIP graphs and replay them
+ *   FRACSOLVE_ODE_GRAPH=0     launch the conjugate-gradient steps of
+ *                             fracsolve_ode_cg directly instead of replaying
+ *                             a recorded graph
  */
 #ifndef FRACSOLVE_H
 #define FRACSOLVE_H
