@@ -229,9 +229,11 @@ hipError_t launch_fft_update_ex(hipStream_t st, const UpdTask<T> *d_tasks, const
                                 bool even, bool corner = true);
 int fft_update_cc(int n, bool fp32);
 // near-corner band of a single-pass FFT level (no-op for multi-pass levels,
-// which add it inside their last pass)
+// which add it inside their last pass, and where fft_band_in_update holds:
+// the float64 three-digit update kernels add it when they store Y)
 template <typename T>
 hipError_t launch_fft_corner(hipStream_t st, const UpdTask<T> *d_tasks, int ntasks, int s, int64_t maxM);
+bool fft_band_in_update(int s, bool fp32);
 hipError_t launch_spectrum(hipStream_t st, const double *w, int s, cplx<double> *spec64, cplx<float> *spec32,
                            const cplx<double> *tw, int64_t nmax, cplx<double> *scratch);
 int fft_max_single_pass(bool fp32);

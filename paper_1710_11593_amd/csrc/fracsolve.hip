@@ -354,7 +354,8 @@ int run_ops(fracsolve_ctx *h, const std::vector<Op> &ops)
             // the near-corner band of an FFT level as a group of its own:
             // X rows s-31..s-1, Y rows 0..30 read and written
             const bool fft = op.kind == OP_FFT64 || op.kind == OP_FFT32;
-            if (fft && 2 * op.s <= fft_max_single_pass(op.kind == OP_FFT32) && corner_width(op.s) >= 2) {
+            if (fft && 2 * op.s <= fft_max_single_pass(op.kind == OP_FFT32) && corner_width(op.s) >= 2 &&
+                !fft_band_in_update(op.s, op.kind == OP_FFT32)) {
                 const size_t evj = 2 * h->recs.size();
                 hipEvent_t e1;
                 int rc = get_event(h, evj + 1, &e1);

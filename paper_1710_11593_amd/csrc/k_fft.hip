@@ -530,6 +530,8 @@ struct GroupView {
     int64_t g;  // group within the task
     int ny;
     T scale;
+    FS_G const double *w;  // Toeplitz column (near-corner band)
+    double alpha;
 };
 
 template <typename T>
@@ -544,6 +546,8 @@ __device__ __forceinline__ GroupView<T> group_view(const GroupCursor<T> &c, int6
     v.g = f - c.gbase[c.t];
     v.ny = tk.ny;
     v.scale = (T)(tk.alpha / (double)n);
+    v.w = gptr(tk.w);
+    v.alpha = tk.alpha;
     return v;
 }
 
@@ -671,6 +675,14 @@ __global__ __launch_bounds__(NT) void k_fft3u(const UpdTask<T> *__restrict__ tas
     constexpr int NA = GR::NA, H = GR::H;
     constexpr int NB = (CC * N1 * N3 + NT - 1) / NT;  // items per thread of stages B and D
     __shared__ cplx<T> sd[N1 * N2 * RS];
+    // Near-corner band in float64 (the sum of k_corner, added where Y rows
+    // 0..30 are stored): stage A keeps the group's raw X rows s-1-k,
+    // k < KB, in sB[k][c]; stage C the weights w_0..w_KB in sWb.
+    constexpr bool BAND = sizeof(T) == 8;
+    constexpr int KB = 31;  // corner_width(s) - 1 for every s of these kernels
+    static_assert(!BAND || N2 * N3 >= KB, "the band rows come from the last outer digit");
+    __shared__ cplx<T> sB[BAND ? KB * CC : 1];
+    __shared__ double sWb[BAND ? KB + 1 : 1];
     const int t = threadIdx.x;
     const int64_t tws = nmax / n;
     const int64_t P = gridDim.x;
@@ -704,6 +716,9 @@ __global__ __launch_bounds__(NT) void k_fft3u(const UpdTask<T> *__restrict__ tas
                     cplx<T> v[N1];
 #pragma unroll
                     for (int q1 = 0; q1 < H; ++q1) v[q1] = xc.v[a][q1];
+                    // X row (H-1) R + r = s-1-k with k = R-1-r
+                    if constexpr (BAND)
+                        if (r >= N2 * N3 - KB) sB[(N2 * N3 - 1 - r) * CC + c] = v[H - 1];
                     dft_reg<N1, false, true>(v);
                     apply_twiddles_b<N1, false>(v, pa[a]);
 #pragma unroll
@@ -733,7 +748,11 @@ __global__ __launch_bounds__(NT) void k_fft3u(const UpdTask<T> *__restrict__ tas
             }
         }
         __syncthreads();
-        // C: q3 -> k3, spectrum, k3 -> q3 (no other loads in flight)
+        // C: q3 -> k3, spectrum, k3 -> q3 (no other loads in flight; the
+        // band weights are loaded with the spectrum)
+        double wband = 0.0;
+        if constexpr (BAND)
+            if (t <= KB) wband = gv.w[t];
 #pragma unroll 1
         for (int it = t; it < CC * N1 * N2; it += NT) {
             const int c = it % CC, r = it / CC, k2 = r % N2, k1 = r / N2;
@@ -750,6 +769,8 @@ __global__ __launch_bounds__(NT) void k_fft3u(const UpdTask<T> *__restrict__ tas
 #pragma unroll
             for (int q3 = 0; q3 < N3; ++q3) sd[at(k1, k2, q3, c)] = v[q3];
         }
+        if constexpr (BAND)
+            if (t <= KB) sWb[t] = wband;
         __syncthreads();
         // the next group (possibly of the next task)
         const int64_t fn = f + P;
@@ -801,13 +822,30 @@ __global__ __launch_bounds__(NT) void k_fft3u(const UpdTask<T> *__restrict__ tas
                     apply_twiddles_b<N1, true>(v, pa[a]);
                     dft_reg<N1, true, false>(v);
                     const int64_t col = 2 * (gv.g * CC + c);
+                    // band of output row p = r < KB (q1 = H):
+                    //   sum_{k <= KB-1-r} w_{r+1+k} X[s-1-k]
+                    cplx<T> bnd{0, 0};
+                    if constexpr (BAND) {
+                        if (r < KB) {
+                            for (int k = 0; k < KB - r; ++k) {
+                                const double wk = sWb[r + 1 + k];
+                                const cplx<T> xk = sB[k * CC + c];
+                                bnd.x = fma(wk, xk.x, bnd.x);
+                                bnd.y = fma(wk, xk.y, bnd.y);
+                            }
+                        }
+                    }
 #pragma unroll
                     for (int q1 = H; q1 < N1; ++q1) {
                         const int p = (q1 - H) * N2 * N3 + r;
                         if (p < gv.ny) {
                             const cplx<T> y0 = yc.v[a][q1 - H];
-                            st_pair<EVEN>(gv.yb + (int64_t)p * gv.M, col, gv.M,
-                                          cplx<T>{y0.x + gv.scale * v[q1].x, y0.y + gv.scale * v[q1].y});
+                            cplx<T> yv{y0.x + gv.scale * v[q1].x, y0.y + gv.scale * v[q1].y};
+                            if (BAND && q1 == H) {
+                                yv.x = fma((T)gv.alpha, bnd.x, yv.x);
+                                yv.y = fma((T)gv.alpha, bnd.y, yv.y);
+                            }
+                            st_pair<EVEN>(gv.yb + (int64_t)p * gv.M, col, gv.M, yv);
                         }
                     }
                 }
@@ -1176,10 +1214,15 @@ static hipError_t multipass(hipStream_t st, const UpdTask<T> *d_task, int n, int
 
 // Entry: tasks of one level (all with the same s).  Multi-pass levels take
 // exactly one task and need the scratch buffer zs (zs_elems complex entries).
+// Float64 level products of the three-digit kernels (2s >= 512, single pass)
+// add the near-corner band themselves.
+bool fft_band_in_update(int s, bool fp32) { return !fp32 && 2 * s >= 512 && 2 * s <= fft_max_single_pass(false); }
+
 template <typename T>
 hipError_t launch_fft_corner(hipStream_t st, const UpdTask<T> *d_tasks, int ntasks, int s, int64_t maxM)
 {
-    if (2 * s > fft_max_single_pass(sizeof(T) == 4) || corner_width(s) < 2) return hipSuccess;
+    if (2 * s > fft_max_single_pass(sizeof(T) == 4) || corner_width(s) < 2 || fft_band_in_update(s, sizeof(T) == 4))
+        return hipSuccess;
     hipLaunchKernelGGL((k_corner<T>), dim3((unsigned)((maxM + 255) / 256), (unsigned)(corner_width(s) - 1),
                                            (unsigned)ntasks),
                        dim3(256), 0, st, d_tasks);
