@@ -65,8 +65,8 @@ def log(*a):
 
 def recorded_traffic(s: int, M: int):
     """HBM bytes per level product of half-size s (every kernel of that level:
-    the transform kernel and the near-corner band, or the three multi-pass
-    kernels) recorded in profiles/ (FETCH_SIZE and WRITE_SIZE passes scaled by
+    the transform kernel, with the near-corner band kernel where the band has
+    one, or the three multi-pass kernels) recorded in profiles/ (FETCH_SIZE and WRITE_SIZE passes scaled by
     the copy calibration), or None when there is no record for this M or the
     FFT source changed since it was taken."""
     import hashlib
