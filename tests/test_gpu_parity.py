@@ -252,10 +252,12 @@ def test_adjoint_parity(torch_cuda, orc, gamma, M, N):
 @pytest.mark.parametrize("precision", ["fp32"])
 @pytest.mark.parametrize("gamma,M,N", [(0.5, 64, 256), (1.5, 128, 512), (0.3, 1000, 300)])
 def test_mixed_precision_refined(torch_cuda, orc, precision, gamma, M, N):
+    # crossover 16: the levels from s = 32 up are float32 FFT products (the
+    # tuned plan keeps every level of sizes this small dense, in float64)
     f, u0, phi = rand_case(gamma, M, N, seed=5)
     ref = orc.solve(gamma, 1.0, 0.0, 1.0, M, N, f, u0=u0, phi=phi)
-    u0r = gpu_solve(torch_cuda, gamma, M, N, f, u0, phi, precision=precision, refine_steps=0)
-    u1 = gpu_solve(torch_cuda, gamma, M, N, f, u0, phi, precision=precision, refine_steps=1)
+    u0r = gpu_solve(torch_cuda, gamma, M, N, f, u0, phi, precision=precision, refine_steps=0, crossover=16)
+    u1 = gpu_solve(torch_cuda, gamma, M, N, f, u0, phi, precision=precision, refine_steps=1, crossover=16)
     e0, e1 = relerr(u0r, ref), relerr(u1, ref)
     assert e1 <= 1e-5, (e0, e1)
     assert e1 <= e0
