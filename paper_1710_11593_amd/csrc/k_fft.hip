@@ -867,7 +867,9 @@ __global__ __launch_bounds__(NT) void k_fft3u(const UpdTask<T> *__restrict__ tas
 // One thread per (output row p = blockIdx.y, column): all its X loads are
 // issued together (the rows are shared through the cache by the threads of
 // the other p), so a launch costs about two memory round trips.  It runs
-// after the transform kernel on the same stream.
+// after the transform kernel on the same stream, for the levels whose
+// transform kernel does not add the band itself (float32, and the two-digit
+// sizes below 512 points).
 template <typename T>
 __global__ __launch_bounds__(256) void k_corner(const UpdTask<T> *__restrict__ tasks)
 {
@@ -1013,7 +1015,8 @@ __global__ void k_spec_store(const cplx<double> *__restrict__ in, int64_t n, cpl
 }
 
 // spec = DFT_{2s}(w'), w'_j = w_j for j >= corner_width(s), 0 below (the
-// near-corner terms are added exactly by the FFT kernels' last stage);
+// near-corner terms are added exactly: by the float64 three-digit update
+// kernels as they store Y, by the last multipass pass, else by k_corner);
 // scratch holds 2*2s complex entries.
 hipError_t launch_spectrum(hipStream_t st, const double *w, int s, cplx<double> *spec64, cplx<float> *spec32,
                            const cplx<double> *tw, int64_t nmax, cplx<double> *scratch)
