@@ -204,6 +204,29 @@ def test_multipass_fft_level(torch_cuda, orc, gamma, crossover):
         ext_reference.assert_floor_parity(err, e_gpu, e_orc, eta_gpu, eta_orc, TOL64)
 
 
+def test_multipass_levels_in_small_column_chunks(torch_cuda, orc, monkeypatch):
+    """The multi-pass levels (2s = 16384, 32768 at N = 20000) of a width
+    whose complex columns (500) split into ragged chunks of the smallest
+    scratch (16 MiB: 64 and 32 columns per chunk): the same bits as one
+    chunk per level, and the mode-reduction reference."""
+    from paper_1710_11593_amd import binding
+
+    rng = np.random.default_rng(11)
+    inst = wl.Instance(0.4, 1000, 20000, modes=[(j, float(a), float(p)) for j, a, p in zip(
+        (1, 3, 7), rng.standard_normal(3), rng.uniform(1, 3, 3))], manufactured=True)
+    f, u0, phi, ref = mode_reference(torch_cuda, orc, inst)
+    us = []
+    for mb in ("4096", "16"):
+        monkeypatch.setenv("FRACSOLVE_MP_SCRATCH_MB", mb)
+        s = binding.Solver([dict(gamma=inst.gamma, M=inst.M, N=inst.N)], crossover=-1)
+        us.append(s.solve([f], [u0])[0])
+        torch_cuda.cuda.synchronize()
+        s.close()
+    assert torch_cuda.equal(us[0], us[1])
+    err = float((us[1] - ref).abs().max() / ref.abs().max())
+    assert err <= TOL64, err
+
+
 @pytest.mark.parametrize("gamma,M,N", [(0.6, 33, 100), (1.5, 64, 128), (0.9, 300, 77)])
 def test_apply_parity(torch_cuda, orc, gamma, M, N):
     from paper_1710_11593_amd import binding
