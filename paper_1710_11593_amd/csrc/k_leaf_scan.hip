@@ -242,6 +242,23 @@ __global__ __launch_bounds__(NT) void k_leaf_scan(TaskRef<LeafTask> tr)
     const double c_bk = pow_bits(cp, 16 - (lane & 15));
 
     constexpr int NH = PAIR ? 2 : 1;
+    // PUSH2 (512 x 4, the configuration of batches up to M = 2048): the
+    // second leaf's right-hand sides are loaded with the first leaf's, and
+    // each solved row x_q of the first leaf is pushed into them,
+    //   acc2[p] -= a_{L+p-q} x_q,  p < L,
+    // in the deferred phase of the step after its solve (where the second
+    // wave of each SIMD fills the gaps), instead of re-reading the first
+    // leaf's rows between the halves.  Measured: c4 batch 161.3 -> 157.4 ms;
+    // with one wave per SIMD (256 x 8, c3) the pushes lengthen every step
+    // (191 -> 221 ms), and 512 x 8 has no registers left for them.
+    constexpr bool PUSH2 = PAIR && !MIXED && !CN && NT == 512 && PT == 4;
+    constexpr int L2 = PUSH2 ? L : 1;
+    double acc2[L2][PT];
+    double ax[PUSH2 ? 2 * L : 1];  // a_0 .. a_{2L-1}
+    if constexpr (PUSH2) {
+#pragma unroll
+        for (int m = 0; m < 2 * L; ++m) ax[m] = gptr(tk.a)[m];
+    }
 #pragma unroll 1
     for (int hf = 0; hf < NH; ++hf) {
     const int nrows = (hf == 0) ? (nrows_all < L ? nrows_all : L) : nrows_all - L;
@@ -251,24 +268,36 @@ __global__ __launch_bounds__(NT) void k_leaf_scan(TaskRef<LeafTask> tr)
     FS_G float *__restrict__ x32 = MIXED ? x32_base + (int64_t)(hf * L) * M : nullptr;
     // right-hand sides of the leaf's rows (row r of the leaf in acc[r])
     double acc[L][PT];
-#pragma unroll
-    for (int r = 0; r < L; ++r) {
-        FS_G const double *row = u + (int64_t)r * M;
+    auto load_rows = [&](double (&dst)[PT], FS_G const double *row, bool in) {
         if (vec) {
-            if (r < nrows && act) {
+            if (in && act) {
 #pragma unroll
                 for (int i = 0; i < UT; ++i) {
                     const double2 v = *reinterpret_cast<FS_G const double2 *>(row + col(2 * i));
-                    acc[r][2 * i] = v.x;
-                    acc[r][2 * i + 1] = v.y;
+                    dst[2 * i] = v.x;
+                    dst[2 * i + 1] = v.y;
                 }
             } else {
 #pragma unroll
-                for (int k = 0; k < PT; ++k) acc[r][k] = 0.0;
+                for (int k = 0; k < PT; ++k) dst[k] = 0.0;
             }
         } else {
 #pragma unroll
-            for (int k = 0; k < PT; ++k) acc[r][k] = (r < nrows && c0 + k < M) ? row[col(k)] : 0.0;
+            for (int k = 0; k < PT; ++k) dst[k] = (in && c0 + k < M) ? row[col(k)] : 0.0;
+        }
+    };
+    if (PUSH2 && hf == 1) {
+#pragma unroll
+        for (int r = 0; r < L; ++r)
+#pragma unroll
+            for (int k = 0; k < PT; ++k) acc[r][k] = acc2[PUSH2 ? r : 0][k];
+    } else {
+#pragma unroll
+        for (int r = 0; r < L; ++r) load_rows(acc[r], u + (int64_t)r * M, r < nrows);
+        if constexpr (PUSH2) {
+            // the second leaf's rows (none past the task's rows)
+#pragma unroll
+            for (int r = 0; r < L; ++r) load_rows(acc2[r], u + (int64_t)(L + r) * M, L + r < nrows_all);
         }
     }
     // float32 history rows (mixed mode): row r is loaded one step ahead, in
@@ -290,7 +319,7 @@ __global__ __launch_bounds__(NT) void k_leaf_scan(TaskRef<LeafTask> tr)
             for (int k = 0; k < PT; ++k) hv[k] = (r < nrows && c0 + k < M) ? hrow[col(k)] : 0.f;
         }
     };
-    if constexpr (PAIR) {
+    if constexpr (PAIR && !PUSH2) {
         if (hf == 1) {
             // the level product of half-size L from the first leaf's rows
             // (this thread's own columns, stored by it in the first half)
@@ -432,6 +461,16 @@ __global__ __launch_bounds__(NT) void k_leaf_scan(TaskRef<LeafTask> tr)
             for (int j = r + 1; j < L; ++j) {
 #pragma unroll
                 for (int k = 0; k < PT; ++k) acc[j][k] = fma(-aw[j - r + 1], xp[k], acc[j][k]);
+            }
+            if constexpr (PUSH2) {
+                if (hf == 0) {
+                    // x_{r-1} into the second leaf: a_{L+p-(r-1)}
+#pragma unroll
+                    for (int p = 0; p < L; ++p)
+#pragma unroll
+                        for (int k = 0; k < PT; ++k)
+                            acc2[p][k] = fma(-ax[PUSH2 ? L + p - r + 1 : 0], xp[k], acc2[p][k]);
+                }
             }
         }
         if (!run) break;
