@@ -199,7 +199,7 @@ size_t leaf_table_doubles(const LeafCfg &c);
 hipError_t launch_leaf_factor(hipStream_t st, const LeafCfg &c, int64_t M, double a0, double e, double *fac);
 hipError_t launch_leaf(hipStream_t st, const LeafCfg &c, int L, const LeafTask *d_tasks, int ntasks, bool mixed);
 // scan-form leaf (closed-form semiseparable inverse of a_0 I + K)
-LeafCfg scan_config(int64_t M, bool batched = false);
+LeafCfg scan_config(int64_t M, bool batched = false, bool cn = false);
 size_t scan_table_doubles(const LeafCfg &c);
 hipError_t launch_scan_factor(hipStream_t st, const LeafCfg &c, int64_t M, double a0, double e, double *tab);
 hipError_t launch_adv_factor(hipStream_t st, const LeafCfg &c, double a0, double h, bool scheme2, double *tab);

@@ -807,7 +807,9 @@ Plan plan_for(const fracsolve_problem *probs, int32_t count, const fracsolve_opt
         bool ok = o.equation != FRACSOLVE_ADVECTION;
         for (int k = 0; k < count && ok; ++k) {
             const bool scan = o.leaf_solver == 0;
-            const LeafCfg lc = scan ? scan_config(count > 1 ? mmax : probs[k].M, count > 1) : leaf_config(probs[k].M);
+            const LeafCfg lc = scan ? scan_config(count > 1 ? mmax : probs[k].M, count > 1,
+                                                  o.equation == FRACSOLVE_DIFFUSION_CN)
+                                    : leaf_config(probs[k].M);
             if ((scan && lc.pt > 2) || (!scan && lc.pt == 16)) ok = false;
         }
         if (!ok) pl.leaf = 8;
@@ -878,7 +880,7 @@ int setup_instance(fracsolve_ctx *h, Inst &in)
     in.adv = (h->opts.equation == FRACSOLVE_ADVECTION) ? (in.regime == 0 ? 2 : 3) : 0;
     in.cn = (h->opts.equation == FRACSOLVE_DIFFUSION_CN);
     in.scan = (h->opts.leaf_solver == 0) || in.adv;
-    in.lc = in.scan ? scan_config(h->batch_M > 0 ? h->batch_M : in.M, h->batch_M > 0) : leaf_config(in.M);
+    in.lc = in.scan ? scan_config(h->batch_M > 0 ? h->batch_M : in.M, h->batch_M > 0, in.cn) : leaf_config(in.M);
     if (!in.adv && in.scan && in.lc.pt > 2 && in.M % in.lc.pt == 0)
         in.perm = ColPerm{in.lc.pt, (in.M / (64 * (int64_t)in.lc.pt)) * 64 * (int64_t)in.lc.pt};
     if (h->L > 8 && ((in.scan && in.lc.pt > 2) || (!in.scan && in.lc.pt == 16)))

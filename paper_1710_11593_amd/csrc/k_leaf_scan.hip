@@ -758,17 +758,20 @@ hipError_t launch_leaf_adv(hipStream_t st, const LeafCfg &c, int L, const TaskRe
 
 // Up to 512 threads (two waves per SIMD) with 2, 4 or 8 rows per thread: the
 // leaf's right-hand sides (L x PT doubles per thread) stay in registers and
-// each thread's rows are whole 16-byte units.  For 1024 < M <= 2048 a single
-// instance runs faster on 256 threads x 8 rows (one wave per SIMD, a
-// shallower scan), but in a batch two such workgroups can share a CU, and
-// 512 x 4 (which fills the CU's registers at two waves per SIMD) is faster.
-LeafCfg scan_config(int64_t M, bool batched)
+// each thread's rows are whole 16-byte units.  For 1024 < M <= 2048, 512 x 4
+// (two waves per SIMD, with the in-register pushes between the leaves of a
+// pair) is faster than 256 x 8 (one wave per SIMD), alone and in a batch:
+// c3 190.5 -> 187.5 ms, and M = 1500 and 1983, whose width is not a multiple
+// of 8 (no 16-byte row units with 8 rows per thread), 27-29% faster.  The
+// averaged variant (cn: one more LDS exchange and barrier per step) keeps
+// 256 x 8 for a single instance (its c3-size solve 240 ms against 246 ms).
+LeafCfg scan_config(int64_t M, bool batched, bool cn)
 {
     if (M <= 128) return {64, 2, 6};
     if (M <= 256) return {64, 4, 6};
     if (M <= 512) return {128, 4, 7};
     if (M <= 1024) return {256, 4, 8};
-    if (M <= 2048) return batched ? LeafCfg{512, 4, 9} : LeafCfg{256, 8, 8};
+    if (M <= 2048) return (cn && !batched) ? LeafCfg{256, 8, 8} : LeafCfg{512, 4, 9};
     return {512, 8, 9};
 }
 
