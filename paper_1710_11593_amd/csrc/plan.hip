@@ -235,22 +235,22 @@ bool load_cache(const std::string &path, std::vector<PlanEntry> &out)
 // winner's time.  The advection and averaged-spatial-term equations keep the
 // plan their kernels were first measured with.
 const PlanEntry kBuiltin[] = {
-    {0, 0, 64, 16, 512},  // 10.81 ms
-    {0, 0, 128, 16, 512},  // 10.96 ms
-    {0, 0, 256, 8, 256},  // 14.01 ms
-    {0, 0, 512, 8, 512},  // 15.45 ms
-    {0, 0, 1024, 8, 256},  // 17.33 ms
-    {0, 0, 2048, 8, 256},  // 22.47 ms
-    {0, 0, 4096, 8, 128},  // 32.65 ms
-    {1, 0, 64, 16, 256},  // 26.83 ms
-    {1, 0, 128, 16, 256},  // 27.23 ms
-    {1, 0, 256, 8, 256},  // 36.46 ms
-    {1, 0, 512, 8, 256},  // 40.35 ms
-    {1, 0, 1024, 8, 256},  // 44.00 ms
-    {1, 0, 2048, 8, 128},  // 60.26 ms
-    {1, 0, 4096, 8, 128},  // 84.90 ms
-    {0, 0, 1 << 20, 8, 128},  // 32.65 ms
-    {1, 0, 1 << 20, 8, 128},  // 84.90 ms
+    {0, 0, 64, 16, 512},  // 10.86 ms
+    {0, 0, 128, 16, 512},  // 10.86 ms
+    {0, 0, 256, 8, 512},  // 13.89 ms
+    {0, 0, 512, 8, 256},  // 15.51 ms
+    {0, 0, 1024, 8, 128},  // 17.48 ms
+    {0, 0, 2048, 8, 128},  // 21.98 ms
+    {0, 0, 4096, 8, 128},  // 32.58 ms
+    {1, 0, 64, 16, 256},  // 26.76 ms
+    {1, 0, 128, 16, 512},  // 27.10 ms
+    {1, 0, 256, 8, 256},  // 35.77 ms
+    {1, 0, 512, 8, 256},  // 39.82 ms
+    {1, 0, 1024, 8, 256},  // 43.46 ms
+    {1, 0, 2048, 8, 128},  // 57.31 ms
+    {1, 0, 4096, 8, 128},  // 83.46 ms
+    {0, 0, 1 << 20, 8, 128},  // 32.58 ms
+    {1, 0, 1 << 20, 8, 128},  // 83.46 ms
     {0, 1, 1 << 20, 8, 64},
     {0, 2, 1 << 20, 8, 64},
 };
